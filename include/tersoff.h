@@ -1,0 +1,168 @@
+/*
+ * tersoff.h -- C ABI of libtersoff.so: Tersoff many-body energy, forces and
+ * virial on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the Tersoff potential as restated in Section 2 of Hoehnerbach,
+ * Ismail and Bientinesi, "The Tersoff many-body potential: sustainable
+ * performance through vectorization":
+ *   Eq. (1)  E = 1/2 sum_i sum_{j: r_ij < R+D} f_C(r_ij) [f_R(r_ij) + b_ij f_A(r_ij)]
+ *   Eq. (2)  b_ij = (1 + beta^eta zeta_ij^eta)^(-1/(2 eta))
+ *   Eq. (3)  zeta_ij = sum_{k != j: r_ik < R+D} f_C(r_ik) g(theta_ijk) exp((lambda3 (r_ij - r_ik))^m)
+ * with f_C(r) = 1 below R-D, 1/2 - 1/2 sin(pi/2 (r-R)/D) up to R+D, 0 beyond;
+ * f_R = A exp(-lambda1 r); f_A = -B exp(-lambda2 r);
+ * g = gamma (1 + c^2/d^2 - c^2/(d^2 + (cos theta - h)^2)).
+ * Forces follow Algorithm 1: zeta_ij over k, then V(i,j,zeta_ij) and its
+ * derivative on i and j, then dV/dzeta * d zeta(i,j,k)/dx on i, j and k.
+ * The neighbour list with a skin and the packing of in-cutoff entries are the
+ * scheme of Sections 2 and 3.
+ *
+ * Units: eV and Angstrom.  F = -dE/dx.  Virial W_ab = sum over all pair and
+ * triplet force terms of r_a F_b with r the relative vector from the centre
+ * atom (eV; positive = repulsive); reported as xx yy zz xy xz yz.
+ *
+ * Every call returns a tersoff_status (0 = OK, negative = error); no call
+ * aborts or throws across this boundary.  A context is used by one host
+ * thread at a time; the serving calls (tersoff_submit / tersoff_poll) are
+ * thread-safe.
+ */
+#ifndef TERSOFF_H
+#define TERSOFF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One parameter-table entry is 14 doubles in this order. */
+#define TERSOFF_NPARAM 14
+enum {
+    TERSOFF_P_A = 0,       /* eV                          */
+    TERSOFF_P_B = 1,       /* eV                          */
+    TERSOFF_P_LAMBDA1 = 2, /* 1/A                         */
+    TERSOFF_P_LAMBDA2 = 3, /* 1/A                         */
+    TERSOFF_P_LAMBDA3 = 4, /* 1/A                         */
+    TERSOFF_P_BETA = 5,
+    TERSOFF_P_ETA = 6,     /* Tersoff's n                 */
+    TERSOFF_P_C = 7,
+    TERSOFF_P_D = 8,
+    TERSOFF_P_H = 9,       /* cos(theta_0)                */
+    TERSOFF_P_GAMMA = 10,
+    TERSOFF_P_R = 11,      /* A, centre of the switch     */
+    TERSOFF_P_DC = 12,     /* A, half-width of the switch */
+    TERSOFF_P_M = 13       /* 1 or 3 (exponent of Eq. 3)  */
+};
+#define TERSOFF_MAX_TYPES 4
+
+typedef enum { TERSOFF_FP64 = 0, TERSOFF_MIXED = 1 } tersoff_precision;
+
+typedef enum {
+    TERSOFF_OK = 0,
+    TERSOFF_E_INVALID = -1,  /* bad argument or parameter                    */
+    TERSOFF_E_NOMEM = -2,    /* device allocation failed                     */
+    TERSOFF_E_BOX = -3,      /* a box length is below 2 (cutoff + skin)      */
+    TERSOFF_E_OVERFLOW = -4, /* an atom has more in-range neighbours than
+                                the kernel's per-batch capacity              */
+    TERSOFF_E_STALE = -5,    /* an atom moved more than skin/2 since build   */
+    TERSOFF_E_DEVICE = -6,   /* HIP runtime error                            */
+    TERSOFF_E_AGAIN = -7,    /* serving: no slot or memory free right now    */
+    TERSOFF_E_PENDING = -8,  /* serving: result not ready yet                */
+    TERSOFF_E_STATE = -9     /* call out of order (e.g. compute before build)*/
+} tersoff_status;
+
+typedef struct tersoff_ctx tersoff_ctx;
+
+/* Create a context on the current HIP device.
+ * params: host array of ntypes^3 entries (entry (ti,tj,tk) at
+ *   ((ti*ntypes + tj)*ntypes + tk) * TERSOFF_NPARAM), copied.  Pair terms and
+ *   (beta, eta) of a bond i-j use entry (t_i, t_j, t_j); the zeta term of k and
+ *   the cutoff applied to r_ik use entry (t_i, t_j, t_k).
+ * Errors: E_INVALID if ntypes is not in [1, TERSOFF_MAX_TYPES], or an entry
+ *   has A <= 0, B <= 0, D <= 0, R - D < 0, eta <= 0, beta < 0, c or d == 0,
+ *   m not 1 or 3, or a non-finite value;
+ *   E_NOMEM / E_DEVICE. */
+int tersoff_create(const double *params, int32_t ntypes, tersoff_ctx **out);
+
+/* Release every device buffer of the context.  NULL is ignored. */
+void tersoff_destroy(tersoff_ctx *ctx);
+
+/* Full neighbour list (Section 2: every j != i with minimum-image
+ * r_ij < cutoff + skin, skin atoms included), built on the GPU with a cell
+ * list; rows sorted by j.  The minimum-image displacement is, per axis,
+ * s = rint(d/L), d' = fma(-s, L, d), and r^2 = fma(dz,dz, fma(dy,dy, dx*dx)).
+ * pos: device, n x 3 float64 (row-major); types: device, n int32 in
+ *   [0, ntypes); positions need not be wrapped into the box.
+ * box: host, 3 orthorhombic periodic lengths.  cutoff must be >= the largest
+ *   R + D of the table; skin >= 0.
+ * stream: hipStream_t or NULL.  The call synchronises that stream (it reads
+ *   back the list length).  pos and types are copied; the list and the copies
+ *   stay resident in the context until the next build.
+ * Errors: E_INVALID (n < 1 or > 2^24, cutoff too small, type out of range,
+ *   non-finite position), E_BOX (a box length < 2 (cutoff + skin)), E_NOMEM,
+ *   E_DEVICE.  Rows longer than the working capacity are handled by a retry
+ *   with a larger capacity. */
+int tersoff_build_neighbors(tersoff_ctx *ctx, const double *pos, const int32_t *types,
+                            int64_t n, const double box[3], double cutoff, double skin,
+                            void *stream);
+
+/* Energy, forces and virial (Eq. 1-3, Algorithm 1) from the resident list.
+ * pos: device, n x 3 float64 for the same n atoms as the last build (they may
+ *   have moved; the minimum-image displacement is recomputed in FP64).
+ * precision: TERSOFF_FP64 (all FP64) or TERSOFF_MIXED (FP32 pair and triplet
+ *   functions; FP64 displacement, zeta -> b_ij power in log form, and energy /
+ *   force / virial accumulation).
+ * energy_virial: device, 7 float64 written: E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz.
+ * forces: device, n x 3 float64, overwritten; may be NULL.
+ * Stream-ordered on `stream`; does not synchronise.  A capacity overflow or a
+ * stale list detected on the device is reported by tersoff_check.
+ * Errors (host-side): E_STATE (no list), E_INVALID (precision), E_DEVICE. */
+int tersoff_compute(tersoff_ctx *ctx, const double *pos, int32_t precision,
+                    double *energy_virial, double *forces, void *stream);
+
+/* Synchronise `stream` and report the device-side status of every compute
+ * since the previous check: OK, E_OVERFLOW (an atom exceeded the per-batch
+ * neighbour capacity; its terms were skipped) or E_STALE (an atom moved more
+ * than skin/2 from its position at the last build).  Clears the flags. */
+int tersoff_check(tersoff_ctx *ctx, void *stream);
+
+/* Copy the resident neighbour list to host memory (synchronises).
+ * offsets: host, n+1 int64; idx: host, cap int32; *total receives the list
+ * length.  If cap < total only offsets and *total are written and
+ * E_INVALID is returned. */
+int tersoff_get_neighbors(tersoff_ctx *ctx, int64_t *offsets, int32_t *idx, int64_t cap,
+                          int64_t *total);
+
+/* Work counts of the last compute (synchronises): counts[0] = list entries S,
+ * counts[1] = in-cutoff ordered pairs P, counts[2] = ordered triplets T
+ * (centre i, j and k in cutoff, k != j). */
+int tersoff_get_counts(tersoff_ctx *ctx, int64_t counts[3]);
+
+/* Kernel timing with HIP events on the caller's stream.  While enabled, every
+ * tersoff_compute records an event pair around its main kernel launch (not the
+ * force zeroing or the final reduction) and every tersoff_build_neighbors one
+ * pair around its whole device work.  tersoff_profile_read synchronises the
+ * device and returns, then resets: out[0] = summed compute-kernel time (ms),
+ * out[1] = number of compute launches, out[2] = summed build time (ms),
+ * out[3] = number of builds. */
+int tersoff_profile(tersoff_ctx *ctx, int32_t enable);
+int tersoff_profile_read(tersoff_ctx *ctx, double out[4]);
+
+/* Nominal centre atoms per wavefront batch of the compute kernel, in
+ * [1, 64] (default 16).  Performance tuning only; results do not depend on
+ * it beyond floating-point summation order.  E_INVALID outside the range. */
+int tersoff_set_batch_atoms(tersoff_ctx *ctx, int32_t atoms);
+
+/* Number of atoms of the last build (0 if none). */
+int64_t tersoff_num_atoms(const tersoff_ctx *ctx);
+
+/* Static text for a status code. */
+const char *tersoff_strerror(int status);
+
+/* Message of the last error raised on this context ("" if none). */
+const char *tersoff_last_error(const tersoff_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TERSOFF_H */

@@ -1,0 +1,10 @@
+"""MI355X-native Tersoff energy / force / virial evaluation.
+
+The compute path lives in libtersoff.so (HIP kernels for gfx950 behind the C
+ABI of include/tersoff.h); ``Tersoff`` is its thin ctypes binding.  Importing
+this package does not load the library; the first ``Tersoff(...)`` does, and
+raises if it has not been built.
+"""
+from ._lib import FP64, MIXED, Tersoff, TersoffError, load  # noqa: F401
+
+__all__ = ["Tersoff", "TersoffError", "load", "FP64", "MIXED"]

@@ -1,0 +1,216 @@
+"""ctypes binding of libtersoff.so (argument marshalling only).
+
+Every step of the evaluation runs in the HIP kernels of the library; this
+module only checks tensor shapes, dtypes and devices and passes raw pointers
+and the current torch stream.  If the library is missing it raises: there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtersoff.so")
+
+FP64 = 0
+MIXED = 1
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+
+OK = 0
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_BOX", -4: "E_OVERFLOW", -5: "E_STALE",
+          -6: "E_DEVICE", -7: "E_AGAIN", -8: "E_PENDING", -9: "E_STATE"}
+
+# exported symbols (the declarations of include/tersoff.h)
+SYMBOLS = ("tersoff_create", "tersoff_destroy", "tersoff_build_neighbors", "tersoff_compute",
+           "tersoff_check", "tersoff_get_neighbors", "tersoff_get_counts", "tersoff_num_atoms",
+           "tersoff_strerror", "tersoff_last_error", "tersoff_profile", "tersoff_profile_read",
+           "tersoff_set_batch_atoms")
+
+_lib = None
+
+
+class TersoffError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def load():
+    """Load libtersoff.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1710_00882_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.tersoff_create.argtypes = [P, i32, ctypes.POINTER(P)]
+    lib.tersoff_create.restype = ctypes.c_int
+    lib.tersoff_destroy.argtypes = [P]
+    lib.tersoff_destroy.restype = None
+    lib.tersoff_build_neighbors.argtypes = [P, P, P, i64, P, f64, f64, P]
+    lib.tersoff_build_neighbors.restype = ctypes.c_int
+    lib.tersoff_compute.argtypes = [P, P, i32, P, P, P]
+    lib.tersoff_compute.restype = ctypes.c_int
+    lib.tersoff_check.argtypes = [P, P]
+    lib.tersoff_check.restype = ctypes.c_int
+    lib.tersoff_get_neighbors.argtypes = [P, P, P, i64, P]
+    lib.tersoff_get_neighbors.restype = ctypes.c_int
+    lib.tersoff_get_counts.argtypes = [P, P]
+    lib.tersoff_get_counts.restype = ctypes.c_int
+    lib.tersoff_num_atoms.argtypes = [P]
+    lib.tersoff_num_atoms.restype = i64
+    lib.tersoff_profile.argtypes = [P, i32]
+    lib.tersoff_profile.restype = ctypes.c_int
+    lib.tersoff_profile_read.argtypes = [P, P]
+    lib.tersoff_profile_read.restype = ctypes.c_int
+    lib.tersoff_set_batch_atoms.argtypes = [P, i32]
+    lib.tersoff_set_batch_atoms.restype = ctypes.c_int
+    lib.tersoff_strerror.argtypes = [ctypes.c_int]
+    lib.tersoff_strerror.restype = ctypes.c_char_p
+    lib.tersoff_last_error.argtypes = [P]
+    lib.tersoff_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _stream_ptr(torch, device=None) -> int:
+    return int(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_dev(t, dtype, shape_tail, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != shape_tail:
+        raise ValueError(f"{name} must have shape (n, {', '.join(map(str, shape_tail))})")
+
+
+class Tersoff:
+    """One context of libtersoff.so: parameter table, resident neighbour list."""
+
+    def __init__(self, table):
+        lib = load()
+        tab = np.ascontiguousarray(table, dtype=np.float64)
+        nt = int(round((tab.size // 14) ** (1.0 / 3.0)))
+        if nt ** 3 * 14 != tab.size:
+            raise ValueError("table must hold ntypes^3 entries of 14 values")
+        self._table = tab
+        self.ntypes = nt
+        h = ctypes.c_void_p()
+        st = lib.tersoff_create(tab.ctypes.data_as(ctypes.c_void_p), nt, ctypes.byref(h))
+        if st != OK:
+            raise TersoffError(st, "tersoff_create rejected the parameter table")
+        self._h = h
+        self._lib = lib
+        self.cutoff = float(np.max(tab.reshape(-1, 14)[:, 11] + tab.reshape(-1, 14)[:, 12]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.tersoff_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st, what):
+        msg = self._lib.tersoff_last_error(self._h).decode()
+        raise TersoffError(st, f"{what}: {msg}")
+
+    @property
+    def n(self) -> int:
+        return int(self._lib.tersoff_num_atoms(self._h))
+
+    def build_neighbors(self, pos, types, box, cutoff=None, skin=1.0):
+        import torch
+        _check_dev(pos, torch.float64, (3,), "pos")
+        _check_dev(types, torch.int32, None, "types")
+        if types.shape != (pos.shape[0],):
+            raise ValueError("types must have shape (n,)")
+        b = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(3))
+        cut = self.cutoff if cutoff is None else float(cutoff)
+        st = self._lib.tersoff_build_neighbors(self._h, pos.data_ptr(), types.data_ptr(), pos.shape[0],
+                                               b.ctypes.data_as(ctypes.c_void_p), cut, float(skin),
+                                               _stream_ptr(torch, pos.device))
+        if st != OK:
+            self._raise(st, "tersoff_build_neighbors")
+
+    def compute(self, pos, precision="mixed", forces=None, out=None, want_forces=True):
+        """Returns (out, forces): out = [E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz] (device)."""
+        import torch
+        _check_dev(pos, torch.float64, (3,), "pos")
+        if out is None:
+            out = torch.empty(7, dtype=torch.float64, device=pos.device)
+        if want_forces and forces is None:
+            forces = torch.empty_like(pos)
+        if forces is not None:
+            _check_dev(forces, torch.float64, (3,), "forces")
+        st = self._lib.tersoff_compute(self._h, pos.data_ptr(), PRECISIONS[precision], out.data_ptr(),
+                                       forces.data_ptr() if forces is not None else None,
+                                       _stream_ptr(torch, pos.device))
+        if st != OK:
+            self._raise(st, "tersoff_compute")
+        return out, forces
+
+    def check(self):
+        import torch
+        st = self._lib.tersoff_check(self._h, _stream_ptr(torch))
+        if st != OK:
+            self._raise(st, "tersoff_check")
+
+    def check_status(self) -> int:
+        import torch
+        return int(self._lib.tersoff_check(self._h, _stream_ptr(torch)))
+
+    def neighbors(self):
+        n = self.n
+        offsets = np.zeros(n + 1, dtype=np.int64)
+        total = ctypes.c_int64(0)
+        st = self._lib.tersoff_get_neighbors(self._h, offsets.ctypes.data_as(ctypes.c_void_p), None, 0,
+                                             ctypes.byref(total))
+        if total.value == 0 and st == OK:
+            return offsets, np.zeros(0, dtype=np.int32)
+        idx = np.zeros(total.value, dtype=np.int32)
+        st = self._lib.tersoff_get_neighbors(self._h, offsets.ctypes.data_as(ctypes.c_void_p),
+                                             idx.ctypes.data_as(ctypes.c_void_p), idx.size,
+                                             ctypes.byref(total))
+        if st != OK:
+            self._raise(st, "tersoff_get_neighbors")
+        return offsets, idx
+
+    def profile(self, enable: bool = True):
+        st = self._lib.tersoff_profile(self._h, 1 if enable else 0)
+        if st != OK:
+            self._raise(st, "tersoff_profile")
+
+    def profile_read(self):
+        """(compute_kernel_ms, compute_launches, build_ms, builds) since the last read."""
+        out = np.zeros(4)
+        st = self._lib.tersoff_profile_read(self._h, out.ctypes.data_as(ctypes.c_void_p))
+        if st != OK:
+            self._raise(st, "tersoff_profile_read")
+        return float(out[0]), int(out[1]), float(out[2]), int(out[3])
+
+    def set_batch_atoms(self, atoms: int):
+        st = self._lib.tersoff_set_batch_atoms(self._h, int(atoms))
+        if st != OK:
+            self._raise(st, "tersoff_set_batch_atoms")
+
+    def counts(self):
+        c = np.zeros(3, dtype=np.int64)
+        st = self._lib.tersoff_get_counts(self._h, c.ctypes.data_as(ctypes.c_void_p))
+        if st != OK:
+            self._raise(st, "tersoff_get_counts")
+        return tuple(int(v) for v in c)

@@ -1,0 +1,509 @@
+// Host runtime and C ABI of libtersoff.so (declarations and contracts in
+// include/tersoff.h).  The context owns every device buffer; positions,
+// types and the neighbour list stay resident between calls.
+#include "internal.h"
+
+#include "tersoff.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace tsf;
+
+namespace {
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t count)
+    {
+        if (count <= cap && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max<size_t>(count, 1);
+        hipError_t e = hipMalloc((void **)&p, want * sizeof(T));
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+}  // namespace
+
+struct tersoff_ctx {
+    int device = 0;
+    int ntypes = 0;
+    std::vector<double> params;
+    double max_cut = 0.0;
+    DeviceTable tab{};
+    void *d_table = nullptr;
+
+    // system of the last build
+    int n = 0;
+    double box[3] = {0, 0, 0};
+    double cutoff = 0.0, skin = 0.0;
+    bool built = false;
+    long long S = 0;
+    int ell_cap = 32;
+    int atoms_per_batch = 16;
+    int grid[2] = {0, 0};   // [fp64, mixed]
+
+    DevBuf<double> pos_build;
+    DevBuf<int> types, offsets, idx;
+    DevBuf<int> cell_of, rank, cell_count, cell_start, cell_atoms;
+    DevBuf<double> cell_pos;
+    DevBuf<int> ell, row_count, scan_tmp, misc;   // misc: [0] flags, [1] max row, [2] check flags
+    DevBuf<double> partials, force_scratch;
+    DevBuf<long long> counters, counts;
+
+    // profiling: event pairs recorded around compute / build launches
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_compute, ev_build;
+    std::vector<hipEvent_t> ev_pool;
+
+    std::string last_error;
+};
+
+namespace {
+
+int fail(tersoff_ctx *c, int status, const std::string &msg)
+{
+    if (c) c->last_error = msg;
+    return status;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? TERSOFF_E_NOMEM : TERSOFF_E_DEVICE, \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));            \
+        }                                                                               \
+    } while (0)
+
+template <typename real>
+ParamR<real> derive(const double *p)
+{
+    ParamR<real> r{};
+    double R = p[TERSOFF_P_R], D = p[TERSOFF_P_DC], c = p[TERSOFF_P_C], d = p[TERSOFF_P_D];
+    double m = p[TERSOFF_P_M], l3 = p[TERSOFF_P_LAMBDA3];
+    r.A = (real)p[TERSOFF_P_A];
+    r.B = (real)p[TERSOFF_P_B];
+    r.lam1 = (real)p[TERSOFF_P_LAMBDA1];
+    r.lam2 = (real)p[TERSOFF_P_LAMBDA2];
+    r.lam3 = (real)l3;
+    r.lam3m = (real)(m == 3.0 ? l3 * l3 * l3 : l3);
+    r.c2d2 = (real)(c * c / (d * d));
+    r.d2 = (real)(d * d);
+    r.two_c2 = (real)(2.0 * c * c);
+    r.h = (real)p[TERSOFF_P_H];
+    r.gamma = (real)p[TERSOFF_P_GAMMA];
+    r.R = (real)R;
+    r.Rin = (real)(R - D);
+    r.half_pi_D = (real)(M_PI / (2.0 * D));
+    r.m = (real)m;
+    const double lnA = std::log(p[TERSOFF_P_A]), lnB = std::log(p[TERSOFF_P_B]);
+    r.lnA = (real)lnA;
+    r.lnA_lo = (real)(lnA - (double)r.lnA);
+    r.lam1_lo = (real)(p[TERSOFF_P_LAMBDA1] - (double)r.lam1);
+    r.lnB = (real)lnB;
+    r.lnB_lo = (real)(lnB - (double)r.lnB);
+    r.lam2_lo = (real)(p[TERSOFF_P_LAMBDA2] - (double)r.lam2);
+    r.R_lo = (real)(R - (double)r.R);
+    r.half_pi_D_lo = (real)(M_PI / (2.0 * D) - (double)r.half_pi_D);
+    r.pad = (real)0;
+    return r;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+hipError_t take_event(tersoff_ctx *c, hipEvent_t *e)
+{
+    if (!c->ev_pool.empty()) {
+        *e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tersoff_strerror(int status)
+{
+    switch (status) {
+    case TERSOFF_OK: return "ok";
+    case TERSOFF_E_INVALID: return "invalid argument";
+    case TERSOFF_E_NOMEM: return "out of device memory";
+    case TERSOFF_E_BOX: return "box shorter than twice the list radius";
+    case TERSOFF_E_OVERFLOW: return "neighbour capacity exceeded";
+    case TERSOFF_E_STALE: return "neighbour list is stale (an atom moved more than skin/2)";
+    case TERSOFF_E_DEVICE: return "HIP runtime error";
+    case TERSOFF_E_AGAIN: return "no slot or memory free";
+    case TERSOFF_E_PENDING: return "result not ready";
+    case TERSOFF_E_STATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char *tersoff_last_error(const tersoff_ctx *ctx)
+{
+    return ctx ? ctx->last_error.c_str() : "";
+}
+
+int tersoff_create(const double *params, int32_t ntypes, tersoff_ctx **out)
+{
+    if (!out) return TERSOFF_E_INVALID;
+    *out = nullptr;
+    if (!params || ntypes < 1 || ntypes > TERSOFF_MAX_TYPES) return TERSOFF_E_INVALID;
+    const int ne = ntypes * ntypes * ntypes;
+    for (int e = 0; e < ne; ++e) {
+        const double *p = params + (size_t)e * TERSOFF_NPARAM;
+        for (int f = 0; f < TERSOFF_NPARAM; ++f)
+            if (!std::isfinite(p[f])) return TERSOFF_E_INVALID;
+        if (!(p[TERSOFF_P_A] > 0) || !(p[TERSOFF_P_B] > 0) ||
+            !(p[TERSOFF_P_DC] > 0) || !(p[TERSOFF_P_R] - p[TERSOFF_P_DC] >= 0) ||
+            !(p[TERSOFF_P_ETA] > 0) || !(p[TERSOFF_P_BETA] >= 0) || p[TERSOFF_P_C] == 0 ||
+            p[TERSOFF_P_D] == 0 || !(p[TERSOFF_P_M] == 1.0 || p[TERSOFF_P_M] == 3.0))
+            return TERSOFF_E_INVALID;
+    }
+    tersoff_ctx *c = new (std::nothrow) tersoff_ctx();
+    if (!c) return TERSOFF_E_NOMEM;
+    (void)hipGetDevice(&c->device);
+    c->ntypes = ntypes;
+    c->params.assign(params, params + (size_t)ne * TERSOFF_NPARAM);
+
+    std::vector<ParamR<float>> pf(ne);
+    std::vector<ParamR<double>> pd(ne);
+    std::vector<ParamX> px(ne);
+    std::vector<double> packsq((size_t)ntypes * ntypes, 0.0);
+    for (int e = 0; e < ne; ++e) {
+        const double *p = params + (size_t)e * TERSOFF_NPARAM;
+        pf[e] = derive<float>(p);
+        pd[e] = derive<double>(p);
+        double cut = p[TERSOFF_P_R] + p[TERSOFF_P_DC];
+        px[e].cutsq = cut * cut;
+        px[e].logbeta = p[TERSOFF_P_BETA] > 0 ? std::log(p[TERSOFF_P_BETA]) : -INFINITY;
+        px[e].eta = p[TERSOFF_P_ETA];
+        px[e].inv2eta = 1.0 / (2.0 * p[TERSOFF_P_ETA]);
+        c->max_cut = std::max(c->max_cut, cut);
+    }
+    // packing radius for neighbour n of centre i: any entry (ti, *, tn)
+    for (int ti = 0; ti < ntypes; ++ti)
+        for (int tj = 0; tj < ntypes; ++tj)
+            for (int tk = 0; tk < ntypes; ++tk) {
+                double cs = px[(ti * ntypes + tj) * ntypes + tk].cutsq;
+                double &slot = packsq[(size_t)ti * ntypes + tk];
+                slot = std::max(slot, cs);
+            }
+    size_t off_pf = 0;
+    size_t off_pd = off_pf + ((sizeof(ParamR<float>) * ne + 255) / 256) * 256;
+    size_t off_px = off_pd + ((sizeof(ParamR<double>) * ne + 255) / 256) * 256;
+    size_t off_pk = off_px + ((sizeof(ParamX) * ne + 255) / 256) * 256;
+    size_t total = off_pk + sizeof(double) * packsq.size();
+    std::vector<unsigned char> host(total, 0);
+    std::memcpy(host.data() + off_pf, pf.data(), sizeof(ParamR<float>) * ne);
+    std::memcpy(host.data() + off_pd, pd.data(), sizeof(ParamR<double>) * ne);
+    std::memcpy(host.data() + off_px, px.data(), sizeof(ParamX) * ne);
+    std::memcpy(host.data() + off_pk, packsq.data(), sizeof(double) * packsq.size());
+    hipError_t e = hipMalloc(&c->d_table, total);
+    if (e == hipSuccess) e = hipMemcpy(c->d_table, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        int st = e == hipErrorOutOfMemory ? TERSOFF_E_NOMEM : TERSOFF_E_DEVICE;
+        if (c->d_table) (void)hipFree(c->d_table);
+        delete c;
+        return st;
+    }
+    unsigned char *base = static_cast<unsigned char *>(c->d_table);
+    c->tab.ntypes = ntypes;
+    c->tab.pf = reinterpret_cast<const ParamR<float> *>(base + off_pf);
+    c->tab.pd = reinterpret_cast<const ParamR<double> *>(base + off_pd);
+    c->tab.px = reinterpret_cast<const ParamX *>(base + off_px);
+    c->tab.packsq = reinterpret_cast<const double *>(base + off_pk);
+    *out = c;
+    return TERSOFF_OK;
+}
+
+void tersoff_destroy(tersoff_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    c->pos_build.release(); c->types.release(); c->offsets.release(); c->idx.release();
+    c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
+    c->cell_atoms.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
+    c->scan_tmp.release(); c->misc.release(); c->partials.release(); c->force_scratch.release();
+    c->counters.release(); c->counts.release();
+    for (auto &pr : c->ev_compute) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (auto &pr : c->ev_build) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->d_table) (void)hipFree(c->d_table);
+    delete c;
+}
+
+int tersoff_profile(tersoff_ctx *c, int32_t enable)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    c->profiling = enable != 0;
+    return TERSOFF_OK;
+}
+
+int tersoff_profile_read(tersoff_ctx *c, double out[4])
+{
+    if (!c || !out) return TERSOFF_E_INVALID;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    double tc = 0.0, tb = 0.0;
+    for (auto &pr : c->ev_compute) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+        tc += ms;
+    }
+    for (auto &pr : c->ev_build) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+        tb += ms;
+    }
+    out[0] = tc;
+    out[1] = (double)c->ev_compute.size();
+    out[2] = tb;
+    out[3] = (double)c->ev_build.size();
+    for (auto &pr : c->ev_compute) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
+    for (auto &pr : c->ev_build) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
+    c->ev_compute.clear();
+    c->ev_build.clear();
+    return TERSOFF_OK;
+}
+
+int tersoff_set_batch_atoms(tersoff_ctx *c, int32_t atoms)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    if (atoms < 1 || atoms > kWave) return fail(c, TERSOFF_E_INVALID, "batch atoms must be in [1, 64]");
+    c->atoms_per_batch = atoms;
+    if (c->built) {
+        c->grid[0] = compute_grid_size(false, c->ntypes == 1, c->n, atoms);
+        c->grid[1] = compute_grid_size(true, c->ntypes == 1, c->n, atoms);
+        int gmax = std::max(c->grid[0], c->grid[1]);
+        HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
+        HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
+    }
+    return TERSOFF_OK;
+}
+
+int64_t tersoff_num_atoms(const tersoff_ctx *c)
+{
+    return (c && c->built) ? c->n : 0;
+}
+
+int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *types, int64_t n,
+                            const double box[3], double cutoff, double skin, void *stream)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    c->last_error.clear();
+    if (!pos || !types || !box) return fail(c, TERSOFF_E_INVALID, "null pointer");
+    if (n < 1 || n > (int64_t)(1 << 24)) return fail(c, TERSOFF_E_INVALID, "n must be in [1, 2^24]");
+    if (!(cutoff >= c->max_cut * (1.0 - 1e-12)) || !std::isfinite(cutoff))
+        return fail(c, TERSOFF_E_INVALID, "cutoff below the largest R + D of the table");
+    if (!(skin >= 0) || !std::isfinite(skin)) return fail(c, TERSOFF_E_INVALID, "skin must be >= 0");
+    const double rc = cutoff + skin;
+    for (int a = 0; a < 3; ++a) {
+        if (!(box[a] > 0) || !std::isfinite(box[a])) return fail(c, TERSOFF_E_INVALID, "box must be positive");
+        if (box[a] < 2.0 * rc) return fail(c, TERSOFF_E_BOX, "box length below 2 (cutoff + skin)");
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = as_stream(stream);
+    const int N = (int)n;
+    c->built = false;
+
+    hipEvent_t evb0 = nullptr, evb1 = nullptr;
+    if (c->profiling) {
+        HIP_TRY(c, take_event(c, &evb0));
+        HIP_TRY(c, take_event(c, &evb1));
+        HIP_TRY(c, hipEventRecord(evb0, s));
+    }
+    HIP_TRY(c, c->misc.ensure(4));
+    HIP_TRY(c, hipMemsetAsync(c->misc.p, 0, 4 * sizeof(int), s));
+    HIP_TRY(c, launch_check_inputs(pos, types, N, c->ntypes, c->misc.p + 2, s));
+    int chk = 0;
+    HIP_TRY(c, hipMemcpyAsync(&chk, c->misc.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (chk & 1) return fail(c, TERSOFF_E_INVALID, "non-finite position");
+    if (chk & 2) return fail(c, TERSOFF_E_INVALID, "type out of range");
+
+    CellGrid g{};
+    long long ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.L[a] = box[a];
+        g.nc[a] = std::max(1, (int)std::floor(box[a] / (rc * (1.0 + 1e-10))));
+        g.nc[a] = std::min(g.nc[a], 1024);
+        g.cell_w[a] = box[a] / g.nc[a];
+        ncell *= g.nc[a];
+    }
+    HIP_TRY(c, c->cell_of.ensure(N));
+    HIP_TRY(c, c->rank.ensure(N));
+    HIP_TRY(c, c->cell_count.ensure(ncell));
+    HIP_TRY(c, c->cell_start.ensure(ncell + 1));
+    HIP_TRY(c, c->cell_atoms.ensure(N));
+    HIP_TRY(c, c->cell_pos.ensure(3 * (size_t)N));
+    HIP_TRY(c, c->row_count.ensure(N));
+    HIP_TRY(c, c->offsets.ensure((size_t)N + 1));
+    HIP_TRY(c, c->scan_tmp.ensure(std::max(scan_tmp_size((int)ncell), scan_tmp_size(N))));
+    HIP_TRY(c, c->pos_build.ensure(3 * (size_t)N));
+    HIP_TRY(c, c->types.ensure(N));
+
+    HIP_TRY(c, hipMemsetAsync(c->cell_count.p, 0, sizeof(int) * ncell, s));
+    HIP_TRY(c, launch_bin_atoms(pos, N, g, c->cell_of.p, c->rank.p, c->cell_count.p, s));
+    HIP_TRY(c, launch_exclusive_scan(c->cell_count.p, c->cell_start.p, (int)ncell, c->scan_tmp.p, nullptr, s));
+    HIP_TRY(c, launch_scatter_cells(pos, N, c->cell_of.p, c->rank.p, c->cell_start.p,
+                                    c->cell_atoms.p, c->cell_pos.p, s));
+    int host_tot[2] = {0, 0};
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        HIP_TRY(c, c->ell.ensure((size_t)N * c->ell_cap));
+        HIP_TRY(c, launch_search(pos, N, g, rc, c->cell_of.p, c->cell_start.p, c->cell_count.p,
+                                 c->cell_atoms.p, c->cell_pos.p, c->ell_cap, c->ell.p,
+                                 c->row_count.p, s));
+        HIP_TRY(c, launch_exclusive_scan(c->row_count.p, c->offsets.p, N, c->scan_tmp.p, c->misc.p + 1, s));
+        HIP_TRY(c, hipMemcpyAsync(&host_tot[0], c->offsets.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(&host_tot[1], c->misc.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        if (host_tot[1] <= c->ell_cap) break;
+        c->ell_cap = ((host_tot[1] + 15) / 16) * 16;   // retry with the needed capacity
+        if (attempt == 3) return fail(c, TERSOFF_E_OVERFLOW, "row capacity retry failed");
+    }
+    if (host_tot[0] < 0) return fail(c, TERSOFF_E_INVALID, "list longer than 2^31 entries");
+    c->S = host_tot[0];
+    HIP_TRY(c, c->idx.ensure((size_t)std::max(c->S, 1LL)));
+    HIP_TRY(c, launch_sort_rows(c->ell.p, c->ell_cap, c->row_count.p, c->offsets.p, N, c->idx.p, s));
+    HIP_TRY(c, hipMemcpyAsync(c->pos_build.p, pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->types.p, types, sizeof(int) * (size_t)N, hipMemcpyDeviceToDevice, s));
+    if (evb1) {
+        HIP_TRY(c, hipEventRecord(evb1, s));
+        c->ev_build.emplace_back(evb0, evb1);
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+
+    c->n = N;
+    for (int a = 0; a < 3; ++a) c->box[a] = box[a];
+    c->cutoff = cutoff;
+    c->skin = skin;
+    c->grid[0] = compute_grid_size(false, c->ntypes == 1, N, c->atoms_per_batch);
+    c->grid[1] = compute_grid_size(true, c->ntypes == 1, N, c->atoms_per_batch);
+    int gmax = std::max(c->grid[0], c->grid[1]);
+    HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
+    HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
+    HIP_TRY(c, c->counts.ensure(2));
+    HIP_TRY(c, hipMemset(c->counts.p, 0, 2 * sizeof(long long)));
+    c->built = true;
+    return TERSOFF_OK;
+}
+
+int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double *energy_virial,
+                    double *forces, void *stream)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    if (!c->built) return fail(c, TERSOFF_E_STATE, "compute before build_neighbors");
+    if (!pos || !energy_virial) return fail(c, TERSOFF_E_INVALID, "null pointer");
+    if (precision != TERSOFF_FP64 && precision != TERSOFF_MIXED)
+        return fail(c, TERSOFF_E_INVALID, "precision must be TERSOFF_FP64 or TERSOFF_MIXED");
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = as_stream(stream);
+    const bool mixed = precision == TERSOFF_MIXED;
+    double *f = forces;
+    if (!f) {
+        HIP_TRY(c, c->force_scratch.ensure(3 * (size_t)c->n));
+        f = c->force_scratch.p;
+    }
+    ComputeLaunch a{};
+    a.pos = pos;
+    a.types = c->types.p;
+    a.offsets = c->offsets.p;
+    a.idx = c->idx.p;
+    a.n = c->n;
+    for (int d = 0; d < 3; ++d) {
+        a.L[d] = c->box[d];
+        a.invL[d] = 1.0 / c->box[d];
+    }
+    a.forces = f;
+    a.partials = c->partials.p;
+    a.counters = c->counters.p;
+    a.flags = c->misc.p;
+    a.pos_build = c->pos_build.p;
+    a.stale_sq = 0.25 * c->skin * c->skin;
+    a.atoms_per_batch = c->atoms_per_batch;
+    const int grid = c->grid[mixed ? 1 : 0];
+    HIP_TRY(c, launch_fill_zero(f, 3 * (size_t)c->n, s));
+    if (c->profiling) {
+        hipEvent_t e0, e1;
+        HIP_TRY(c, take_event(c, &e0));
+        HIP_TRY(c, take_event(c, &e1));
+        HIP_TRY(c, hipEventRecord(e0, s));
+        HIP_TRY(c, launch_compute(a, c->tab, mixed, grid, s));
+        HIP_TRY(c, hipEventRecord(e1, s));
+        c->ev_compute.emplace_back(e0, e1);
+    } else {
+        HIP_TRY(c, launch_compute(a, c->tab, mixed, grid, s));
+    }
+    HIP_TRY(c, launch_finalize(c->partials.p, c->counters.p, grid, energy_virial, c->counts.p, s));
+    return TERSOFF_OK;
+}
+
+int tersoff_check(tersoff_ctx *c, void *stream)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    if (!c->misc.p) return TERSOFF_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = as_stream(stream);
+    int flags = 0;
+    HIP_TRY(c, hipMemcpyAsync(&flags, c->misc.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemsetAsync(c->misc.p, 0, sizeof(int), s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (flags & kFlagOverflow) return fail(c, TERSOFF_E_OVERFLOW, "an atom exceeded the per-batch neighbour capacity");
+    if (flags & kFlagStale) return fail(c, TERSOFF_E_STALE, "an atom moved more than skin/2 since the last build");
+    return TERSOFF_OK;
+}
+
+int tersoff_get_neighbors(tersoff_ctx *c, int64_t *offsets, int32_t *idx, int64_t cap, int64_t *total)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    if (!c->built) return fail(c, TERSOFF_E_STATE, "no neighbour list");
+    if (!offsets || !total) return fail(c, TERSOFF_E_INVALID, "null pointer");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    std::vector<int> off((size_t)c->n + 1);
+    HIP_TRY(c, hipMemcpy(off.data(), c->offsets.p, sizeof(int) * off.size(), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < off.size(); ++i) offsets[i] = off[i];
+    *total = c->S;
+    if (cap < c->S || (!idx && c->S > 0)) return fail(c, TERSOFF_E_INVALID, "idx capacity below list length");
+    if (c->S > 0) HIP_TRY(c, hipMemcpy(idx, c->idx.p, sizeof(int) * (size_t)c->S, hipMemcpyDeviceToHost));
+    return TERSOFF_OK;
+}
+
+int tersoff_get_counts(tersoff_ctx *c, int64_t counts[3])
+{
+    if (!c || !counts) return TERSOFF_E_INVALID;
+    if (!c->built) return fail(c, TERSOFF_E_STATE, "no neighbour list");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    long long h[2] = {0, 0};
+    HIP_TRY(c, hipMemcpy(h, c->counts.p, sizeof(h), hipMemcpyDeviceToHost));
+    counts[0] = c->S;
+    counts[1] = h[0];
+    counts[2] = h[1];
+    return TERSOFF_OK;
+}
+
+}  // extern "C"
