@@ -72,10 +72,10 @@ def timed_run(model, pos_dev, types_dev, box, precision, nsteps, forces, out):
         model.compute(pos_dev[k], precision, forces=forces, out=out)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kms, launches, bms, builds = model.profile_read()
+    prof = model.profile_read()
     model.profile(False)
     model.check()
-    return t1 - t0, kms, launches, bms, builds
+    return t1 - t0, prof
 
 
 def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None):
@@ -99,19 +99,20 @@ def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None)
                 model.build_neighbors(pos_dev[k], types_dev, system.box)
             model.compute(pos_dev[k], prec, forces=forces, out=out)
         torch.cuda.synchronize()
-        dt, kms, launches, bms, builds = timed_run(model, pos_dev[warmup:], types_dev, system.box,
-                                                   prec, steps, forces, out)
+        dt, prof = timed_run(model, pos_dev[warmup:], types_dev, system.box, prec, steps, forces, out)
         S, P, T = model.counts()
-        kernel_s = kms / 1e3 / max(launches, 1)
+        kernel_s = prof["kernel_ms"] / 1e3 / max(prof["kernels"], 1)
         flops = algorithmic_flops(S, P, T)
         res[prec] = dict(
             seconds=dt, value=system.n * steps / dt, ms_per_step=1e3 * dt / steps,
-            kernel_ms=1e3 * kernel_s, build_ms=bms / max(builds, 1), builds=builds,
+            kernel_ms=1e3 * kernel_s, build_ms=prof["build_ms"] / max(prof["builds"], 1),
+            builds=prof["builds"], gather_ms=prof["gather_ms"] / max(prof["gathers"], 1),
             kernel_atoms_per_s=system.n / kernel_s, counts=dict(S=S, P=P, T=T),
             alg_flops_per_launch=flops, alg_tflops=flops / kernel_s / 1e12,
             energy_per_atom=float(out[0].item()) / system.n)
         log(f"[bench] {prec}: {res[prec]['value']:.4g} atoms*evals/s, {res[prec]['ms_per_step']:.3f} ms/step, "
-            f"kernel {res[prec]['kernel_ms']:.3f} ms, build {res[prec]['build_ms']:.3f} ms, "
+            f"kernel {res[prec]['kernel_ms']:.3f} ms, gather {res[prec]['gather_ms']:.3f} ms, "
+            f"build {res[prec]['build_ms']:.3f} ms, "
             f"{res[prec]['alg_tflops']:.2f} TFLOP/s alg")
     del pos_dev
     model.close()
@@ -144,6 +145,19 @@ def cpu_baseline(system, table, target_s=12.0):
                         f"{REBUILD_EVERY} evaluations"))
 
 
+def copy_probe(mib=256, reps=3):
+    """A plain elementwise copy of known size: its FETCH_SIZE / WRITE_SIZE
+    readings calibrate the HBM traffic counters."""
+    import torch
+    n = mib * 1024 * 1024 // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    log(f"[copy-probe] {reps} x elementwise copy of {mib} MiB read + {mib} MiB written")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,7 +166,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-32k", action="store_true")
     ap.add_argument("--batch-atoms", type=int, default=0)
+    ap.add_argument("--precision", choices=("both", "mixed", "fp64"), default="both",
+                    help="profiling runs may time one precision only (no JSON line then)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain 256 MiB device copy kernel (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(multi-GPU runs are not part of this build)", file=sys.stderr)
@@ -164,6 +185,9 @@ def main():
     log("[bench] generating 2,048,000-atom Si workload")
     big = W.si_2m()
     table = W.si_table()
+    if args.precision != "both":
+        measure_workload(big, table, args.steps, args.warmup, (args.precision,), args.batch_atoms)
+        return
     res = measure_workload(big, table, args.steps, args.warmup, ("mixed", "fp64"), args.batch_atoms)
     mixed, fp64 = res["mixed"], res["fp64"]
 
@@ -221,6 +245,7 @@ def main():
         "mixed_vs_fp64_speedup": mixed["value"] / fp64["value"],
         "mixed_vs_fp64_kernel_speedup": fp64["kernel_ms"] / mixed["kernel_ms"],
         "build_ms": mixed["build_ms"],
+        "gather_ms": mixed["gather_ms"],
         "counts_per_atom": {k: v / big.n for k, v in mixed["counts"].items()},
         "si_32k": extra_32k,
     }

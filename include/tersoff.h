@@ -138,14 +138,15 @@ int tersoff_get_neighbors(tersoff_ctx *ctx, int64_t *offsets, int32_t *idx, int6
 int tersoff_get_counts(tersoff_ctx *ctx, int64_t counts[3]);
 
 /* Kernel timing with HIP events on the caller's stream.  While enabled, every
- * tersoff_compute records an event pair around its main kernel launch (not the
- * force zeroing or the final reduction) and every tersoff_build_neighbors one
- * pair around its whole device work.  tersoff_profile_read synchronises the
- * device and returns, then resets: out[0] = summed compute-kernel time (ms),
- * out[1] = number of compute launches, out[2] = summed build time (ms),
- * out[3] = number of builds. */
+ * tersoff_compute records one event pair around its main (energy / force /
+ * virial) kernel and one around its force-gather kernel, and every
+ * tersoff_build_neighbors one pair around its whole device work.
+ * tersoff_profile_read synchronises the device and returns, then resets:
+ * out[0] = summed main-kernel time (ms), out[1] = its launches, out[2] = summed
+ * build time (ms), out[3] = builds, out[4] = summed gather-kernel time (ms),
+ * out[5] = its launches. */
 int tersoff_profile(tersoff_ctx *ctx, int32_t enable);
-int tersoff_profile_read(tersoff_ctx *ctx, double out[4]);
+int tersoff_profile_read(tersoff_ctx *ctx, double out[6]);
 
 /* Nominal centre atoms per wavefront batch of the compute kernel, in
  * [1, 64] (default 16).  Performance tuning only; results do not depend on

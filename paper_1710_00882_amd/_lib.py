@@ -196,12 +196,14 @@ class Tersoff:
             self._raise(st, "tersoff_profile")
 
     def profile_read(self):
-        """(compute_kernel_ms, compute_launches, build_ms, builds) since the last read."""
-        out = np.zeros(4)
+        """Since the last read: dict of summed event times (ms) and launch counts
+        of the main kernel, the neighbour builds and the force-gather kernel."""
+        out = np.zeros(6)
         st = self._lib.tersoff_profile_read(self._h, out.ctypes.data_as(ctypes.c_void_p))
         if st != OK:
             self._raise(st, "tersoff_profile_read")
-        return float(out[0]), int(out[1]), float(out[2]), int(out[3])
+        return dict(kernel_ms=float(out[0]), kernels=int(out[1]), build_ms=float(out[2]),
+                    builds=int(out[3]), gather_ms=float(out[4]), gathers=int(out[5]))
 
     def set_batch_atoms(self, atoms: int):
         st = self._lib.tersoff_set_batch_atoms(self._h, int(atoms))

@@ -131,6 +131,7 @@ struct Shared {
     real zeta[SCAP];
     real dzeta[SCAP];        // dV(i,n,zeta)/dzeta
     int j[SCAP];
+    int e[SCAP];             // entry (j, i) of the slot's reverse pair
     int tj[SCAP];
     int al[SCAP];            // centre atom (batch-local)
 };
@@ -289,6 +290,8 @@ __device__ __forceinline__ bool triplet_eval(const Shared<real, SCAP> &sh, const
 
 // ------------------------------------------------------------------ kernel -
 
+constexpr int kChunks = 4;   // 64-entry chunks whose loads phase A issues together
+
 template <typename real, bool ONE, int SCAP, int TI>
 __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable tab)
 {
@@ -326,67 +329,96 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             if (lane == 0) sh.eoff[nb] = a.offsets[a0 + nb];
             __syncthreads();
 
-            // ---- phase A: skin exclusion and packing
+            // ---- phase A: skin exclusion and packing.  The index and position
+            // loads of up to kChunks 64-entry chunks are issued together so the
+            // gathers overlap; chunks are then consumed in order.
             const int e_begin = sh.eoff[0], e_end = sh.eoff[nb];
             int npacked = 0;
             int cut = nb;
-            for (int e0 = e_begin; e0 < e_end; e0 += kWave) {
-                const int e = e0 + lane;
-                bool acc = false;
-                int al = 0, j = 0, tj = 0;
-                double dx = 0, dy = 0, dz = 0, rsq = 0;
-                if (e < e_end) {
-                    al = find_seg(sh.eoff, nb, e);
-                    j = a.idx[e];
-                    const double *pj = a.pos + 3 * (size_t)j;
-                    dx = image(pj[0] - sh.xi[al], a.L[0], a.invL[0]);
-                    dy = image(pj[1] - sh.yi[al], a.L[1], a.invL[1]);
-                    dz = image(pj[2] - sh.zi[al], a.L[2], a.invL[2]);
-                    rsq = norm2(dx, dy, dz);
-                    double psq;
-                    if (ONE) {
-                        psq = tab.packsq[0];
-                    } else {
-                        tj = a.types[j];
-                        psq = tab.packsq[sh.ti[al] * tab.ntypes + tj];
+            bool stop = false;
+            for (int eb = e_begin; eb < e_end && !stop; eb += kWave * kChunks) {
+                int jv[kChunks], rv[kChunks], tv[kChunks];
+                double xv[kChunks], yv[kChunks], zv[kChunks];
+#pragma unroll
+                for (int c = 0; c < kChunks; ++c) {
+                    const int e = eb + c * kWave + lane;
+                    int2 q = e < e_end ? a.jr[e] : make_int2(-1, 0);
+                    jv[c] = q.x;
+                    rv[c] = q.y;
+                }
+#pragma unroll
+                for (int c = 0; c < kChunks; ++c) {
+                    xv[c] = yv[c] = zv[c] = 0.0;
+                    tv[c] = 0;
+                    if (jv[c] >= 0) {
+                        const double *pj = a.pos + 3 * (size_t)jv[c];
+                        xv[c] = pj[0]; yv[c] = pj[1]; zv[c] = pj[2];
+                        if (!ONE) tv[c] = a.types[jv[c]];
                     }
-                    acc = rsq < psq;
                 }
-                unsigned long long m = __ballot(acc);
-                const int below = lanes_below(m);
-                const int cnt = __popcll(m);
-                bool stop = false;
-                if (npacked + cnt > SCAP) {
-                    // cut the batch before the first atom whose slots do not fit
-                    unsigned long long over = __ballot(acc && (npacked + below >= SCAP));
-                    int fl = __ffsll((long long)over) - 1;
-                    cut = __shfl(al, fl, kWave);
-                    acc = acc && (al < cut);
-                    stop = true;
+#pragma unroll
+                for (int c = 0; c < kChunks; ++c) {
+                    const int e0 = eb + c * kWave;
+                    if (stop || e0 >= e_end) break;
+                    const int e = e0 + lane;
+                    bool acc = false;
+                    int al = 0;
+                    double dx = 0, dy = 0, dz = 0, rsq = 0;
+                    if (e < e_end) {
+                        al = find_seg(sh.eoff, nb, e);
+                        dx = image(xv[c] - sh.xi[al], a.L[0], a.invL[0]);
+                        dy = image(yv[c] - sh.yi[al], a.L[1], a.invL[1]);
+                        dz = image(zv[c] - sh.zi[al], a.L[2], a.invL[2]);
+                        rsq = norm2(dx, dy, dz);
+                        const double psq = ONE ? tab.packsq[0] : tab.packsq[sh.ti[al] * tab.ntypes + tv[c]];
+                        acc = rsq < psq;
+                    }
+                    unsigned long long m = __ballot(acc);
+                    const int below = lanes_below(m);
+                    const int cnt = __popcll(m);
+                    if (npacked + cnt > SCAP) {
+                        // cut the batch before the first atom whose slots do not fit
+                        unsigned long long over = __ballot(acc && (npacked + below >= SCAP));
+                        int fl = __ffsll((long long)over) - 1;
+                        cut = __shfl(al, fl, kWave);
+                        acc = acc && (al < cut);
+                        stop = true;
+                    }
+                    if (e < e_end && (!stop || al < cut)) a.packed[e] = acc ? 1 : 0;
+                    if (acc) {
+                        const int s = npacked + below;
+                        real r = M<real>::sqrt((real)rsq);
+                        real ri = M<real>::rcp(r);
+                        sh.rsq[s] = rsq;
+                        sh.r[s] = r;
+                        sh.rinv[s] = ri;
+                        sh.ux[s] = (real)dx * ri;
+                        sh.uy[s] = (real)dy * ri;
+                        sh.uz[s] = (real)dz * ri;
+                        sh.zeta[s] = real(0);
+                        sh.j[s] = jv[c];
+                        sh.e[s] = rv[c];
+                        sh.tj[s] = tv[c];
+                        sh.al[s] = al;
+                        atomicAdd(&sh.pcnt[al], 1);
+                    }
+                    if (!stop) npacked += cnt;
                 }
-                if (acc) {
-                    const int s = npacked + below;
-                    real r = M<real>::sqrt((real)rsq);
-                    real ri = M<real>::rcp(r);
-                    sh.rsq[s] = rsq;
-                    sh.r[s] = r;
-                    sh.rinv[s] = ri;
-                    sh.ux[s] = (real)dx * ri;
-                    sh.uy[s] = (real)dy * ri;
-                    sh.uz[s] = (real)dz * ri;
-                    sh.zeta[s] = real(0);
-                    sh.j[s] = j;
-                    sh.tj[s] = tj;
-                    sh.al[s] = al;
-                    atomicAdd(&sh.pcnt[al], 1);
-                }
-                if (stop) break;
-                npacked += cnt;
             }
             __syncthreads();
             if (cut == 0) {
-                // a single atom has more packed neighbours than SCAP
+                // a single atom has more packed neighbours than SCAP: its terms
+                // are skipped (reported), none of its entries is marked packed
                 if (lane == 0) atomicOr(a.flags, kFlagOverflow);
+                for (int e = sh.eoff[0] + lane; e < sh.eoff[1]; e += kWave) {
+                    a.packed[e] = 0;
+                    double *f = a.contrib + 3 * (size_t)a.jr[e].y;
+                    f[0] = f[1] = f[2] = 0.0;
+                }
+                if (lane == 0) {
+                    double *o = a.own + 3 * (size_t)a0;
+                    o[0] = o[1] = o[2] = 0.0;
+                }
                 a0 += 1;
                 __syncthreads();
                 continue;
@@ -527,18 +559,21 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             }
             __syncthreads();
 
-            // ---- phase F: flush forces (FP64 global atomics)
+            // ---- phase F: write this batch's force terms (no atomics): the
+            // force on packed neighbour j goes to the entry (j, i) of j's own
+            // row, the force on each centre atom to its own slot; the gather
+            // kernel adds up each atom's row.
             for (int s = lane; s < npacked; s += kWave) {
-                double *f = a.forces + 3 * (size_t)sh.j[s];
-                unsafeAtomicAdd(f + 0, sh.fs[s][0]);
-                unsafeAtomicAdd(f + 1, sh.fs[s][1]);
-                unsafeAtomicAdd(f + 2, sh.fs[s][2]);
+                double *f = a.contrib + 3 * (size_t)sh.e[s];
+                f[0] = sh.fs[s][0];
+                f[1] = sh.fs[s][1];
+                f[2] = sh.fs[s][2];
             }
             if (lane < cut) {
-                double *f = a.forces + 3 * (size_t)(a0 + lane);
-                unsafeAtomicAdd(f + 0, sh.fi[lane][0]);
-                unsafeAtomicAdd(f + 1, sh.fi[lane][1]);
-                unsafeAtomicAdd(f + 2, sh.fi[lane][2]);
+                double *o = a.own + 3 * (size_t)(a0 + lane);
+                o[0] = sh.fi[lane][0];
+                o[1] = sh.fi[lane][1];
+                o[2] = sh.fi[lane][2];
             }
             __syncthreads();
             a0 += cut;
@@ -596,6 +631,42 @@ __global__ void k_finalize(const double *__restrict__ partials, const long long 
     }
 }
 
+// F_m = (terms of centre m) + sum over the entries (m, i) of m's row that m
+// packed of the force centre i's terms put on m.  The packing radius is
+// symmetric and r^2 of (m, i) and (i, m) is bit-identical, so m packed i
+// exactly when i packed m, and i stored that force at entry (m, i).
+// 16 lanes per row, each row read contiguously; lane partial sums reduced
+// across the 16 lanes.
+__global__ void k_gather_forces(const int *__restrict__ offsets, const unsigned char *__restrict__ packed,
+                                const double *__restrict__ contrib, const double *__restrict__ own,
+                                int n, double *__restrict__ forces)
+{
+    const int m = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
+    const int l = threadIdx.x % 16;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (m < n) {
+        const int e1 = offsets[m + 1];
+        for (int e = offsets[m] + l; e < e1; e += 16) {
+            if (packed[e]) {
+                fx += contrib[3 * (size_t)e];
+                fy += contrib[3 * (size_t)e + 1];
+                fz += contrib[3 * (size_t)e + 2];
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+        fx += __shfl_xor(fx, off, 16);
+        fy += __shfl_xor(fy, off, 16);
+        fz += __shfl_xor(fz, off, 16);
+    }
+    if (m < n && l == 0) {
+        forces[3 * (size_t)m] = own[3 * (size_t)m] + fx;
+        forces[3 * (size_t)m + 1] = own[3 * (size_t)m + 1] + fy;
+        forces[3 * (size_t)m + 2] = own[3 * (size_t)m + 2] + fz;
+    }
+}
+
 __global__ void k_fill_zero(double *p, size_t count)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -649,6 +720,15 @@ hipError_t launch_finalize(const double *partials, const long long *counters, in
                            double *out7, long long *counts_out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, counters, grid, out7, counts_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_forces(const int *offsets, const unsigned char *packed,
+                                const double *contrib, const double *own, int n, double *forces,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_forces, dim3((n + 15) / 16), dim3(256), 0, s, offsets, packed,
+                       contrib, own, n, forces);
     return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ struct DeviceTable {
     const ParamR<float> *pf;    // ntypes^3 entries
     const ParamR<double> *pd;   // ntypes^3 entries
     const ParamX *px;           // ntypes^3 entries
-    const double *packsq;       // ntypes^2: max_k cutsq(ti, tk, tn) over the middle type
+    const double *packsq;       // ntypes^2, symmetric: packing radius^2 of a (ti, tn) entry
 };
 
 // Flags raised by kernels (bitwise OR into a device int).
@@ -58,10 +58,12 @@ struct ComputeLaunch {
     const double *pos;          // n x 3
     const int *types;           // n
     const int *offsets;         // n + 1 (CSR, int32)
-    const int *idx;             // S
+    const int2 *jr;             // S: (neighbour j, entry of i in row j)
     int n;
     double L[3], invL[3];
-    double *forces;             // n x 3 (accumulated; zeroed by the launcher)
+    double *own;                // n x 3: force from the terms of each centre atom
+    double *contrib;            // S x 3: at entry (j, i), the force centre i's terms put on j
+    unsigned char *packed;      // S: 1 if centre i packed entry j in this evaluation
     double *partials;           // grid x 8
     long long *counters;        // grid x 2 (pairs, triplets)
     int *flags;
@@ -77,6 +79,9 @@ int compute_grid_size(bool mixed, bool one_type, int n, int atoms_per_batch);
 hipError_t launch_finalize(const double *partials, const long long *counters, int grid,
                            double *out7, long long *counts_out, hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
+hipError_t launch_gather_forces(const int *offsets, const unsigned char *packed,
+                                const double *contrib, const double *own, int n, double *forces,
+                                hipStream_t s);
 
 // Neighbour build (neighbors.hip)
 struct CellGrid {
@@ -95,6 +100,10 @@ hipError_t launch_search(const double *pos, int n, const CellGrid &g, double rcu
                          int *row_count, hipStream_t s);
 hipError_t launch_sort_rows(const int *ell, int cap, const int *row_count, const int *offsets,
                             int n, int *idx, hipStream_t s);
+// jr[e] = (j, rev) for entry e = (i, j), rev = the entry of i in row j (the
+// list is symmetric).  Sets *flags |= 4 if some reverse entry is missing.
+hipError_t launch_reverse_map(const int *offsets, const int *idx, int n, int2 *jr, int *flags,
+                              hipStream_t s);
 hipError_t launch_check_inputs(const double *pos, const int *types, int n, int ntypes,
                                int *flags, hipStream_t s);
 

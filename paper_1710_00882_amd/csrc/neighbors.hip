@@ -138,6 +138,31 @@ __global__ void k_sort_rows(const int *__restrict__ ell, int cap, const int *__r
     }
 }
 
+// jr[e] = (j, rev) for e = (i, j), rev = position of i in the sorted row of j.
+// The inclusion predicate is symmetric (negating t negates s and d exactly),
+// so the entry exists; a missing one raises flag 4.
+__global__ void k_reverse_map(const int *__restrict__ offsets, const int *__restrict__ idx, int n,
+                              int2 *__restrict__ jr, int *flags)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int e = offsets[i]; e < offsets[i + 1]; ++e) {
+        const int j = idx[e];
+        int lo = offsets[j], hi = offsets[j + 1] - 1, at = -1;
+        while (lo <= hi) {
+            int mid = (lo + hi) >> 1;
+            int v = idx[mid];
+            if (v == i) { at = mid; break; }
+            if (v < i) lo = mid + 1; else hi = mid - 1;
+        }
+        if (at < 0) {
+            atomicOr(flags, 4);
+            at = e;
+        }
+        jr[e] = make_int2(j, at);
+    }
+}
+
 // ---- exclusive scan (three passes) -----------------------------------------
 
 constexpr int kScanThreads = 256;
@@ -249,6 +274,14 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int n, int *tmp, int *
     hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(kScanThreads), 0, s, tile_sum, tile_max,
                        ntiles, out, n, max_out);
     hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(kScanThreads), 0, s, out, n, tile_sum);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse_map(const int *offsets, const int *idx, int n, int2 *jr, int *flags,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reverse_map, dim3(blocks_for(n, 256)), dim3(256), 0, s, offsets, idx, n, jr,
+                       flags);
     return hipGetLastError();
 }
 

@@ -62,6 +62,9 @@ struct tersoff_ctx {
 
     DevBuf<double> pos_build;
     DevBuf<int> types, offsets, idx;
+    DevBuf<int2> jr;
+    DevBuf<unsigned char> packed;
+    DevBuf<double> own, contrib;
     DevBuf<int> cell_of, rank, cell_count, cell_start, cell_atoms;
     DevBuf<double> cell_pos;
     DevBuf<int> ell, row_count, scan_tmp, misc;   // misc: [0] flags, [1] max row, [2] check flags
@@ -70,7 +73,7 @@ struct tersoff_ctx {
 
     // profiling: event pairs recorded around compute / build launches
     bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_compute, ev_build;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_compute, ev_build, ev_gather;
     std::vector<hipEvent_t> ev_pool;
 
     std::string last_error;
@@ -202,13 +205,17 @@ int tersoff_create(const double *params, int32_t ntypes, tersoff_ctx **out)
         px[e].inv2eta = 1.0 / (2.0 * p[TERSOFF_P_ETA]);
         c->max_cut = std::max(c->max_cut, cut);
     }
-    // packing radius for neighbour n of centre i: any entry (ti, *, tn)
+    // packing radius of neighbour n of centre i: every entry (ti, *, tn)
+    // (n as the bond partner or as a third atom), made symmetric in (ti, tn)
+    // so that i packs n exactly when n packs i
     for (int ti = 0; ti < ntypes; ++ti)
         for (int tj = 0; tj < ntypes; ++tj)
             for (int tk = 0; tk < ntypes; ++tk) {
                 double cs = px[(ti * ntypes + tj) * ntypes + tk].cutsq;
-                double &slot = packsq[(size_t)ti * ntypes + tk];
-                slot = std::max(slot, cs);
+                double &a = packsq[(size_t)ti * ntypes + tk];
+                double &b = packsq[(size_t)tk * ntypes + ti];
+                a = std::max(a, cs);
+                b = std::max(b, cs);
             }
     size_t off_pf = 0;
     size_t off_pd = off_pf + ((sizeof(ParamR<float>) * ne + 255) / 256) * 256;
@@ -244,12 +251,14 @@ void tersoff_destroy(tersoff_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     c->pos_build.release(); c->types.release(); c->offsets.release(); c->idx.release();
+    c->jr.release(); c->packed.release(); c->own.release(); c->contrib.release();
     c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
     c->cell_atoms.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
     c->scan_tmp.release(); c->misc.release(); c->partials.release(); c->force_scratch.release();
     c->counters.release(); c->counts.release();
     for (auto &pr : c->ev_compute) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto &pr : c->ev_build) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (auto &pr : c->ev_gather) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->d_table) (void)hipFree(c->d_table);
     delete c;
@@ -262,30 +271,25 @@ int tersoff_profile(tersoff_ctx *c, int32_t enable)
     return TERSOFF_OK;
 }
 
-int tersoff_profile_read(tersoff_ctx *c, double out[4])
+int tersoff_profile_read(tersoff_ctx *c, double out[6])
 {
     if (!c || !out) return TERSOFF_E_INVALID;
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipDeviceSynchronize());
-    double tc = 0.0, tb = 0.0;
-    for (auto &pr : c->ev_compute) {
-        float ms = 0.f;
-        HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
-        tc += ms;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> *lists[3] = {&c->ev_compute, &c->ev_build, &c->ev_gather};
+    for (int l = 0; l < 3; ++l) {
+        double t = 0.0;
+        for (auto &pr : *lists[l]) {
+            float ms = 0.f;
+            HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+            t += ms;
+        }
+        const int slot = l == 2 ? 4 : 2 * l;
+        out[slot] = t;
+        out[slot + 1] = (double)lists[l]->size();
+        for (auto &pr : *lists[l]) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
+        lists[l]->clear();
     }
-    for (auto &pr : c->ev_build) {
-        float ms = 0.f;
-        HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
-        tb += ms;
-    }
-    out[0] = tc;
-    out[1] = (double)c->ev_compute.size();
-    out[2] = tb;
-    out[3] = (double)c->ev_build.size();
-    for (auto &pr : c->ev_compute) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
-    for (auto &pr : c->ev_build) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
-    c->ev_compute.clear();
-    c->ev_build.clear();
     return TERSOFF_OK;
 }
 
@@ -388,6 +392,12 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     c->S = host_tot[0];
     HIP_TRY(c, c->idx.ensure((size_t)std::max(c->S, 1LL)));
     HIP_TRY(c, launch_sort_rows(c->ell.p, c->ell_cap, c->row_count.p, c->offsets.p, N, c->idx.p, s));
+    HIP_TRY(c, c->jr.ensure((size_t)std::max(c->S, 1LL)));
+    HIP_TRY(c, c->packed.ensure((size_t)std::max(c->S, 1LL)));
+    HIP_TRY(c, c->contrib.ensure(3 * (size_t)std::max(c->S, 1LL)));
+    HIP_TRY(c, c->own.ensure(3 * (size_t)N));
+    HIP_TRY(c, launch_reverse_map(c->offsets.p, c->idx.p, N, c->jr.p, c->misc.p + 2, s));
+    HIP_TRY(c, hipMemcpyAsync(&chk, c->misc.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(c->pos_build.p, pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->types.p, types, sizeof(int) * (size_t)N, hipMemcpyDeviceToDevice, s));
     if (evb1) {
@@ -395,6 +405,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
         c->ev_build.emplace_back(evb0, evb1);
     }
     HIP_TRY(c, hipStreamSynchronize(s));
+    if (chk & 4) return fail(c, TERSOFF_E_DEVICE, "neighbour list is not symmetric");
 
     c->n = N;
     for (int a = 0; a < 3; ++a) c->box[a] = box[a];
@@ -431,13 +442,15 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     a.pos = pos;
     a.types = c->types.p;
     a.offsets = c->offsets.p;
-    a.idx = c->idx.p;
+    a.jr = c->jr.p;
     a.n = c->n;
     for (int d = 0; d < 3; ++d) {
         a.L[d] = c->box[d];
         a.invL[d] = 1.0 / c->box[d];
     }
-    a.forces = f;
+    a.own = c->own.p;
+    a.contrib = c->contrib.p;
+    a.packed = c->packed.p;
     a.partials = c->partials.p;
     a.counters = c->counters.p;
     a.flags = c->misc.p;
@@ -445,7 +458,6 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     a.stale_sq = 0.25 * c->skin * c->skin;
     a.atoms_per_batch = c->atoms_per_batch;
     const int grid = c->grid[mixed ? 1 : 0];
-    HIP_TRY(c, launch_fill_zero(f, 3 * (size_t)c->n, s));
     if (c->profiling) {
         hipEvent_t e0, e1;
         HIP_TRY(c, take_event(c, &e0));
@@ -456,6 +468,17 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
         c->ev_compute.emplace_back(e0, e1);
     } else {
         HIP_TRY(c, launch_compute(a, c->tab, mixed, grid, s));
+    }
+    if (c->profiling) {
+        hipEvent_t e0, e1;
+        HIP_TRY(c, take_event(c, &e0));
+        HIP_TRY(c, take_event(c, &e1));
+        HIP_TRY(c, hipEventRecord(e0, s));
+        HIP_TRY(c, launch_gather_forces(c->offsets.p, c->packed.p, c->contrib.p, c->own.p, c->n, f, s));
+        HIP_TRY(c, hipEventRecord(e1, s));
+        c->ev_gather.emplace_back(e0, e1);
+    } else {
+        HIP_TRY(c, launch_gather_forces(c->offsets.p, c->packed.p, c->contrib.p, c->own.p, c->n, f, s));
     }
     HIP_TRY(c, launch_finalize(c->partials.p, c->counters.p, grid, energy_virial, c->counts.p, s));
     return TERSOFF_OK;
