@@ -138,15 +138,15 @@ int tersoff_get_neighbors(tersoff_ctx *ctx, int64_t *offsets, int32_t *idx, int6
 int tersoff_get_counts(tersoff_ctx *ctx, int64_t counts[3]);
 
 /* Kernel timing with HIP events on the caller's stream.  While enabled, every
- * tersoff_compute records one event pair around its main (energy / force /
- * virial) kernel and one around its force-gather kernel, and every
- * tersoff_build_neighbors one pair around its whole device work.
- * tersoff_profile_read synchronises the device and returns, then resets:
- * out[0] = summed main-kernel time (ms), out[1] = its launches, out[2] = summed
- * build time (ms), out[3] = builds, out[4] = summed gather-kernel time (ms),
- * out[5] = its launches. */
+ * tersoff_compute records event pairs around its packing kernel, its main
+ * (energy / force / virial) kernel, and its per-atom plus force-gather
+ * kernels, and every tersoff_build_neighbors one pair around its whole device
+ * work.  tersoff_profile_read synchronises the device and returns, then
+ * resets, summed times (ms) and counts: out[0] main kernel, out[1] its
+ * launches, out[2] builds, out[3] their number, out[4] per-atom + gather,
+ * out[5] their launches, out[6] packing, out[7] its launches. */
 int tersoff_profile(tersoff_ctx *ctx, int32_t enable);
-int tersoff_profile_read(tersoff_ctx *ctx, double out[6]);
+int tersoff_profile_read(tersoff_ctx *ctx, double out[8]);
 
 /* Nominal centre atoms per wavefront batch of the compute kernel, in
  * [1, 64] (default 16).  Performance tuning only; results do not depend on

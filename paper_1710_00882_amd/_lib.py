@@ -198,12 +198,13 @@ class Tersoff:
     def profile_read(self):
         """Since the last read: dict of summed event times (ms) and launch counts
         of the main kernel, the neighbour builds and the force-gather kernel."""
-        out = np.zeros(6)
+        out = np.zeros(8)
         st = self._lib.tersoff_profile_read(self._h, out.ctypes.data_as(ctypes.c_void_p))
         if st != OK:
             self._raise(st, "tersoff_profile_read")
         return dict(kernel_ms=float(out[0]), kernels=int(out[1]), build_ms=float(out[2]),
-                    builds=int(out[3]), gather_ms=float(out[4]), gathers=int(out[5]))
+                    builds=int(out[3]), gather_ms=float(out[4]), gathers=int(out[5]),
+                    pack_ms=float(out[6]), packs=int(out[7]))
 
     def set_batch_atoms(self, atoms: int):
         st = self._lib.tersoff_set_batch_atoms(self._h, int(atoms))

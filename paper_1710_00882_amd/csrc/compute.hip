@@ -1,24 +1,15 @@
-// Tersoff energy / force / virial kernel (Eq. 1-3, Algorithm 1).
+// Tersoff energy / force / virial evaluation (Eq. 1-3, Algorithm 1) on the
+// resident neighbour list, in three launches:
 //
-// One 64-lane wavefront per workgroup walks batches of consecutive centre
-// atoms.  Each batch goes through five phases, every phase with its lanes
-// mapped to a different kind of work item, so that the short in-cutoff lists
-// of a many-body potential do not leave lanes idle (the problem of Section 2;
-// Section 3 packs the in-cutoff entries and vectorises over (i, j) pairs):
-//
-//   A  lanes = list entries of the batch's atoms (contiguous CSR range):
-//      FP64 minimum-image displacement, r^2, skin exclusion; the entries
-//      inside the interaction range are packed (ballot + prefix count) into
-//      LDS slots, grouped by centre atom, with r, 1/r and the unit vector.
-//   C  lanes = ordered triplets (i; j, k != j) of packed slots: zeta(i,j,k)
-//      and its gradients d zeta / d x_j, d zeta / d x_k (computed once and
-//      kept in registers for the second K loop); zeta_ij summed per slot by
-//      LDS atomics.
-//   D  lanes = packed slots (i, j): f_C, f_R, f_A, the bond order b_ij and
-//      db/dzeta in FP64 log form, energy, pair force, dV/dzeta.
-//   E  lanes = triplets again: dV/dzeta * gradients, accumulated per slot and
-//      per centre atom in LDS (FP64).
-//   F  one FP64 global atomic triple per slot and per centre atom.
+//   k_pack      skin exclusion and packing (Sections 2 and 3): every list
+//               entry gets its FP64 minimum-image displacement and r^2; the
+//               entries inside the interaction range become compact per-atom
+//               records (unit vector, r, 1/r, membership bits).
+//   k_tersoff   zeta, b_ij, energy, forces and virial from the records, one
+//               wavefront per batch of centre atoms, one lane per pair (i, j).
+//   k_gather_forces
+//               F_m = (terms of centre m) + (terms of every centre i that
+//               keeps m, stored in the force plane m reserved for i).
 //
 // `real` is float for the mixed path and double for the all-FP64 path; the
 // displacement, the zeta -> b power and every accumulation are FP64 in both.
@@ -111,31 +102,6 @@ __device__ __forceinline__ const ParamR<float> *table_r<float>(const DeviceTable
 template <>
 __device__ __forceinline__ const ParamR<double> *table_r<double>(const DeviceTable &t) { return t.pd; }
 
-// ------------------------------------------------------------- LDS layout -
-
-template <typename real, int SCAP>
-struct Shared {
-    // per centre atom of the batch
-    double xi[kWave], yi[kWave], zi[kWave];
-    double fi[kWave][3];
-    int ti[kWave];
-    int eoff[kWave + 1];
-    int pcnt[kWave];
-    int pstart[kWave + 1];
-    int tstart[kWave + 1];
-    // per packed slot (i, n)
-    double rsq[SCAP];
-    double fs[SCAP][3];      // force on atom n accumulated in this batch
-    real ux[SCAP], uy[SCAP], uz[SCAP];
-    real r[SCAP], rinv[SCAP];
-    real zeta[SCAP];
-    real dzeta[SCAP];        // dV(i,n,zeta)/dzeta
-    int j[SCAP];
-    int e[SCAP];             // entry (j, i) of the slot's reverse pair
-    int tj[SCAP];
-    int al[SCAP];            // centre atom (batch-local)
-};
-
 // f_R = A exp(-lambda1 r), f_A = -B exp(-lambda2 r) and their derivatives.
 // FP64: direct.  FP32: exp(ln A - lambda1 r) with the argument carried as an
 // unevaluated float pair (two-sum and fma error terms), so the rounding of
@@ -188,34 +154,210 @@ __device__ __forceinline__ void cutoff_terms(const ParamR<real> &q, real r, real
     }
 }
 
-// zeta(i,j,k) and its gradients with respect to x_j and x_k.
+// -------------------------------------------------------- packed records -
+
+// One packed neighbour n of a centre atom i (the in-range entries of i's
+// list, Section 3): the unit vector and distance in the working precision,
+// the neighbour index, the entry (n, i) of n's row that receives the force
+// i's terms put on n, and the membership bits of the exact FP64 cutoff tests.
 template <typename real>
-struct Trip {
-    real z;
-    real gj[3], gk[3];
+struct Rec;
+template <>
+struct alignas(16) Rec<float> {
+    int j, rev, mask;
+    float r, rinv, ux, uy, uz;
+};
+template <>
+struct alignas(16) Rec<double> {
+    int j, rev, mask, pad;
+    double r, rinv, ux, uy, uz;
 };
 
-template <typename real, bool GRAD>
-__device__ __forceinline__ void triplet_term(const ParamR<real> &q, real rj, real rjinv,
-                                             const real uj[3], real rk, real rkinv,
-                                             const real uk[3], Trip<real> &o)
+// mask: bits 0-7 type of n; bit 8: r_in < cutoff of entry (t_i, t_n, t_n)
+// (n is a bond partner); bit 9 + t: r_in < cutoff of entry (t_i, t, t_n)
+// (n is a third atom for a partner of type t).
+constexpr int kPairBit = 8;
+constexpr int kThirdBit = 9;
+
+constexpr int kPackB = 16;     // centre atoms per pack wavefront batch
+constexpr int kChunks = 4;     // 64-entry chunks whose loads are issued together
+constexpr int kScap = 64;      // packed slots per compute batch (one per lane)
+
+// ------------------------------------------------------------- pack kernel -
+//
+// Lanes = list entries of kPackB consecutive centre atoms (a contiguous CSR
+// range).  Each lane computes the FP64 minimum-image displacement and r^2 of
+// its entry and keeps it if r^2 is below the (symmetric) packing radius; the
+// kept entries of atom i are written, in list order, to records
+// [i * kRecCap, i * kRecCap + count).  slotpos[e] receives the rank of entry
+// e among the kept entries of its row (-1: not kept, -2: beyond the record
+// capacity).  Because the radius is symmetric and r^2 of (i, n) and (n, i) is
+// bit-identical, i keeps n exactly when n keeps i, so the centre i can find
+// where atom n expects the force i's terms put on it: rank slotpos[(n, i)].
+template <typename real, bool ONE>
+__global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
 {
-    const real one = real(1);
-    real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
-    // cutoff function of r_ik
-    real fc, dfc;
-    cutoff_terms(q, rk, fc, dfc);
-    // angular term, cancellation-free: g = gamma (1 + (c^2/d^2) t^2 / (d^2 + t^2))
-    real t = cs - q.h;
-    real den = q.d2 + t * t;
-    real iden = M<real>::rcp(den);
-    real g = q.gamma * (one + q.c2d2 * t * t * iden);
-    // exp((lambda3 (rij - rik))^m)
-    real ex = one, dex = real(0);
+    __shared__ double xi[kPackB], yi[kPackB], zi[kPackB];
+    __shared__ int ti[kPackB], cnt[kPackB];
+    __shared__ int eoff[kPackB + 1];
+    const int lane = threadIdx.x;
+    Rec<real> *recs = reinterpret_cast<Rec<real> *>(a.recs);
+    const int nbatch = (a.n + kPackB - 1) / kPackB;
+    if (blockIdx.x == 0 && lane == 0) *a.drop_count = 0;
+
+    for (int bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
+        const int a0 = bt * kPackB;
+        const int nb = min(kPackB, a.n - a0);
+        if (lane < nb) {
+            const size_t i = (size_t)(a0 + lane);
+            const double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
+            xi[lane] = x; yi[lane] = y; zi[lane] = z;
+            ti[lane] = ONE ? 0 : a.types[i];
+            cnt[lane] = 0;
+            const double dx = x - a.pos_build[3 * i], dy = y - a.pos_build[3 * i + 1],
+                         dz = z - a.pos_build[3 * i + 2];
+            if (!(dx * dx + dy * dy + dz * dz <= a.stale_sq)) atomicOr(a.flags, kFlagStale);
+        }
+        if (lane < nb) eoff[lane] = a.offsets[a0 + lane];
+        if (lane == 0) eoff[nb] = a.offsets[a0 + nb];
+        __syncthreads();
+        const int e_begin = eoff[0], e_end = eoff[nb];
+        for (int eb = e_begin; eb < e_end; eb += kWave * kChunks) {
+            int jv[kChunks], rv[kChunks], tv[kChunks];
+            double xv[kChunks], yv[kChunks], zv[kChunks];
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                const int e = eb + c * kWave + lane;
+                int2 q = e < e_end ? a.jr[e] : make_int2(-1, 0);
+                jv[c] = q.x;
+                rv[c] = q.y;
+            }
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                xv[c] = yv[c] = zv[c] = 0.0;
+                tv[c] = 0;
+                if (jv[c] >= 0) {
+                    const double *pj = a.pos + 3 * (size_t)jv[c];
+                    xv[c] = pj[0]; yv[c] = pj[1]; zv[c] = pj[2];
+                    if (!ONE) tv[c] = a.types[jv[c]];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                const int e0 = eb + c * kWave;
+                if (e0 >= e_end) break;
+                const int e = e0 + lane;
+                bool acc = false;
+                int al = 0;
+                double dx = 0, dy = 0, dz = 0, rsq = 0;
+                if (e < e_end) {
+                    al = find_seg(eoff, nb, e);
+                    dx = image(xv[c] - xi[al], a.L[0], a.invL[0]);
+                    dy = image(yv[c] - yi[al], a.L[1], a.invL[1]);
+                    dz = image(zv[c] - zi[al], a.L[2], a.invL[2]);
+                    rsq = norm2(dx, dy, dz);
+                    const double psq = ONE ? tab.packsq[0] : tab.packsq[ti[al] * tab.ntypes + tv[c]];
+                    acc = rsq < psq;
+                }
+                const unsigned long long m = __ballot(acc);
+                // rank of this entry among the kept entries of its atom
+                const int first = max(eoff[al] - e0, 0);
+                const unsigned long long below = (lane ? (~0ull >> (64 - lane)) : 0ull);
+                const unsigned long long from = first ? ~(~0ull >> (64 - first)) : ~0ull;
+                const int k = cnt[al] + __popcll(m & below & from);
+                if (e < e_end) a.slotpos[e] = acc ? (k < kRecCap ? k : -2) : -1;
+                if (acc) {
+                    if (k < kRecCap) {
+                        Rec<real> o;
+                        const real r = M<real>::sqrt((real)rsq);
+                        const real ri = M<real>::rcp(r);
+                        o.j = jv[c];
+                        o.rev = rv[c];
+                        int mask = tv[c];
+                        if (ONE) {
+                            mask |= (1 << kPairBit) | (1 << kThirdBit);
+                        } else {
+                            const int nt = tab.ntypes, t_i = ti[al], t_n = tv[c];
+                            if (rsq < tab.px[(t_i * nt + t_n) * nt + t_n].cutsq) mask |= 1 << kPairBit;
+                            for (int t = 0; t < nt; ++t)
+                                if (rsq < tab.px[(t_i * nt + t) * nt + t_n].cutsq) mask |= 1 << (kThirdBit + t);
+                        }
+                        o.mask = mask;
+                        o.r = r;
+                        o.rinv = ri;
+                        o.ux = (real)dx * ri;
+                        o.uy = (real)dy * ri;
+                        o.uz = (real)dz * ri;
+                        recs[(size_t)(a0 + al) * kRecCap + k] = o;
+                    }
+                }
+                __syncthreads();
+                if (acc) atomicMax(&cnt[al], k + 1);
+                __syncthreads();
+            }
+        }
+        if (lane < nb) {
+            const int i = a0 + lane;
+            int c = cnt[lane];
+            if (c > kRecCap) {
+                // more kept neighbours than a record row holds: the atom's
+                // terms are dropped (reported); k_fixup_dropped zeroes the
+                // force slots its neighbours reserved for it
+                atomicOr(a.flags, kFlagOverflow);
+                a.drop_list[atomicAdd(a.drop_count, 1)] = i;
+                double *o = a.own + 3 * (size_t)i;
+                o[0] = o[1] = o[2] = 0.0;
+                c = 0;
+            }
+            a.pcount[i] = c;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------- compute kernel -
+
+template <typename real>
+struct Shared {
+    // per centre atom of the batch
+    int ti[kWave];
+    int pcnt[kWave];
+    int pstart[kWave + 1];
+    // per packed slot (i, n)
+    double fs[kScap][3];         // force on n from i's terms (FP64)
+    real ux[kScap], uy[kScap], uz[kScap], r[kScap], rinv[kScap];
+    real dzeta[kScap];           // dV(i,n,zeta_in)/dzeta
+    int mask[kScap];
+};
+
+template <typename real>
+struct Angular {
+    real g, dg;   // g(theta) and dg/dcos(theta)
+};
+
+// g(theta) = gamma (1 + c^2/d^2 - c^2/(d^2 + (cos - h)^2)) written without
+// cancellation as gamma (1 + (c^2/d^2) t^2 / (d^2 + t^2)), t = cos - h.
+template <typename real>
+__device__ __forceinline__ Angular<real> angular(const ParamR<real> &q, real cs)
+{
+    const real t = cs - q.h;
+    const real iden = M<real>::rcp(q.d2 + t * t);
+    Angular<real> a;
+    a.g = q.gamma * (real(1) + q.c2d2 * t * t * iden);
+    a.dg = q.gamma * q.two_c2 * t * iden * iden;
+    return a;
+}
+
+// exp((lambda3 (rj - rk))^m) and its derivative with respect to rj.
+template <typename real>
+__device__ __forceinline__ void exp_term(const ParamR<real> &q, real rj, real rk, real &ex, real &dex)
+{
+    ex = real(1);
+    dex = real(0);
     if (q.lam3 != real(0)) {
-        real dr = rj - rk;
+        const real dr = rj - rk;
         if (q.m == real(3)) {
-            real dr2 = dr * dr;
+            const real dr2 = dr * dr;
             ex = M<real>::exp(q.lam3m * dr2 * dr);
             dex = real(3) * q.lam3m * dr2 * ex;
         } else {
@@ -223,81 +365,31 @@ __device__ __forceinline__ void triplet_term(const ParamR<real> &q, real rj, rea
             dex = q.lam3 * ex;
         }
     }
-    o.z = fc * g * ex;
-    if (GRAD) {
-        real dg = q.gamma * q.two_c2 * t * iden * iden;
-        real a = fc * ex * dg;          // multiplies d cos / dx
-        real bj = fc * g * dex;         // along u_ij
-        real bk = dfc * g * ex - bj;    // along u_ik
-        real aj = a * rjinv, ak = a * rkinv;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            o.gj[c] = aj * (uk[c] - cs * uj[c]) + bj * uj[c];
-            o.gk[c] = ak * (uj[c] - cs * uk[c]) + bk * uk[c];
-        }
-    }
 }
 
-struct TripIdx {
-    int al, sj, sk;
-};
-
-template <typename real, int SCAP>
-__device__ __forceinline__ TripIdx decode_triplet(const Shared<real, SCAP> &sh, int nat, int t)
-{
-    TripIdx r;
-    r.al = find_seg(sh.tstart, nat, t);
-    int q = t - sh.tstart[r.al];
-    int p1 = sh.pcnt[r.al] - 1;   // >= 1 whenever atom al owns triplets
-    // q / p1 by a float reciprocal: q < 2^12, the quotient is never within
-    // 1/(2 p1) of an integer boundary, far above the float rounding error.
-    int jl = (int)(((float)q + 0.5f) * __builtin_amdgcn_rcpf((float)p1));
-    int kl = q - jl * p1;
-    kl += (kl >= jl);
-    r.sj = sh.pstart[r.al] + jl;
-    r.sk = sh.pstart[r.al] + kl;
-    return r;
-}
-
-template <typename real, bool ONE, int SCAP>
-__device__ __forceinline__ bool triplet_eval(const Shared<real, SCAP> &sh, const TripIdx &ix,
-                                             const DeviceTable &tab, const ParamR<real> *ptab,
-                                             Trip<real> &o, bool grad)
-{
-    int ti = ONE ? 0 : sh.ti[ix.al];
-    int tj = ONE ? 0 : sh.tj[ix.sj];
-    int tk = ONE ? 0 : sh.tj[ix.sk];
-    int nt = ONE ? 1 : tab.ntypes;
-    int e_ij = (ti * nt + tj) * nt + tj;
-    int e_ijk = (ti * nt + tj) * nt + tk;
-    if (!ONE) {
-        // bond (i,j) must be inside its own cutoff, k inside the (i,j,k) cutoff
-        if (!(sh.rsq[ix.sj] < tab.px[e_ij].cutsq) || !(sh.rsq[ix.sk] < tab.px[e_ijk].cutsq)) {
-            o.z = real(0);
-            for (int c = 0; c < 3; ++c) o.gj[c] = o.gk[c] = real(0);
-            return false;
-        }
-    }
-    const ParamR<real> &q = ptab[e_ijk];
-    real uj[3] = {sh.ux[ix.sj], sh.uy[ix.sj], sh.uz[ix.sj]};
-    real uk[3] = {sh.ux[ix.sk], sh.uy[ix.sk], sh.uz[ix.sk]};
-    if (grad)
-        triplet_term<real, true>(q, sh.r[ix.sj], sh.rinv[ix.sj], uj, sh.r[ix.sk], sh.rinv[ix.sk], uk, o);
-    else
-        triplet_term<real, false>(q, sh.r[ix.sj], sh.rinv[ix.sj], uj, sh.r[ix.sk], sh.rinv[ix.sk], uk, o);
-    return true;
-}
-
-// ------------------------------------------------------------------ kernel -
-
-constexpr int kChunks = 4;   // 64-entry chunks whose loads phase A issues together
-
-template <typename real, bool ONE, int SCAP, int TI>
+// One 64-lane wavefront per workgroup walks batches of consecutive centre
+// atoms whose packed neighbours fill at most one slot per lane; a lane owns
+// the pair (i, j) of its slot (the pair-vectorised scheme of Section 3 with
+// pairs of several centre atoms side by side):
+//   1  zeta_ij: loop over the other slots k of centre i (first K loop);
+//   2  f_C, f_R, f_A, b_ij and db/dzeta in FP64 log form, energy, pair force,
+//      dV/dzeta_ij (shared through LDS);
+//   3  second K loop: the lane sums, in FP64, every force term on atom j of
+//      centre i's terms -- its j-role terms -dV/dzeta_ij dzeta(i,j,k)/dx_j and
+//      its k-role terms -dV/dzeta_ik dzeta(i,k,j)/dx_j -- so no two lanes
+//      ever update the same force;
+//   4  virial d_ij (x) F_j; the force on i is minus the sum over its slots.
+// Each slot's force goes to the slot atom j reserved for centre i (plane
+// slotpos[(j, i)] of the per-atom force planes), each centre's own force to
+// `own`; k_gather_forces sums them per atom.
+template <typename real, bool ONE>
 __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable tab)
 {
-    __shared__ Shared<real, SCAP> sh;
+    __shared__ Shared<real> sh;
     const int lane = threadIdx.x;
     const ParamR<real> *ptab = table_r<real>(tab);
+    const Rec<real> *recs = reinterpret_cast<const Rec<real> *>(a.recs);
+    const int nt = ONE ? 1 : tab.ntypes;
 
     double e_acc = 0.0;
     double w_acc[6] = {0, 0, 0, 0, 0, 0};
@@ -311,184 +403,80 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
         const int a_end = min(a0 + B, a.n);
         while (a0 < a_end) {
             const int nb = a_end - a0;
-            // ---- stage centre atoms
+            // ---- batch: the leading atoms whose slots fit one per lane
+            int p = 0, tiv = 0;
             if (lane < nb) {
-                const size_t i = (size_t)(a0 + lane);
-                double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
-                sh.xi[lane] = x; sh.yi[lane] = y; sh.zi[lane] = z;
-                sh.ti[lane] = ONE ? 0 : a.types[i];
-                sh.pcnt[lane] = 0;
-                sh.fi[lane][0] = sh.fi[lane][1] = sh.fi[lane][2] = 0.0;
-                if (a.pos_build) {
-                    double dx = x - a.pos_build[3 * i], dy = y - a.pos_build[3 * i + 1],
-                           dz = z - a.pos_build[3 * i + 2];
-                    if (!(dx * dx + dy * dy + dz * dz <= a.stale_sq)) atomicOr(a.flags, kFlagStale);
-                }
+                p = a.pcount[a0 + lane];
+                tiv = ONE ? 0 : a.types[a0 + lane];
             }
-            if (lane < nb) sh.eoff[lane] = a.offsets[a0 + lane];
-            if (lane == 0) sh.eoff[nb] = a.offsets[a0 + nb];
+            const int ip = wave_incl_scan(p);
+            const int cut = __popcll(__ballot(lane < nb && ip <= kScap));   // >= 1: p <= kRecCap
+            if (lane < cut) {
+                sh.ti[lane] = tiv;
+                sh.pcnt[lane] = p;
+                sh.pstart[lane + 1] = ip;
+            }
+            if (lane == 0) sh.pstart[0] = 0;
+            const int npacked = __shfl(ip, cut - 1, kWave);
             __syncthreads();
 
-            // ---- phase A: skin exclusion and packing.  The index and position
-            // loads of up to kChunks 64-entry chunks are issued together so the
-            // gathers overlap; chunks are then consumed in order.
-            const int e_begin = sh.eoff[0], e_end = sh.eoff[nb];
-            int npacked = 0;
-            int cut = nb;
-            bool stop = false;
-            for (int eb = e_begin; eb < e_end && !stop; eb += kWave * kChunks) {
-                int jv[kChunks], rv[kChunks], tv[kChunks];
-                double xv[kChunks], yv[kChunks], zv[kChunks];
-#pragma unroll
-                for (int c = 0; c < kChunks; ++c) {
-                    const int e = eb + c * kWave + lane;
-                    int2 q = e < e_end ? a.jr[e] : make_int2(-1, 0);
-                    jv[c] = q.x;
-                    rv[c] = q.y;
-                }
-#pragma unroll
-                for (int c = 0; c < kChunks; ++c) {
-                    xv[c] = yv[c] = zv[c] = 0.0;
-                    tv[c] = 0;
-                    if (jv[c] >= 0) {
-                        const double *pj = a.pos + 3 * (size_t)jv[c];
-                        xv[c] = pj[0]; yv[c] = pj[1]; zv[c] = pj[2];
-                        if (!ONE) tv[c] = a.types[jv[c]];
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < kChunks; ++c) {
-                    const int e0 = eb + c * kWave;
-                    if (stop || e0 >= e_end) break;
-                    const int e = e0 + lane;
-                    bool acc = false;
-                    int al = 0;
-                    double dx = 0, dy = 0, dz = 0, rsq = 0;
-                    if (e < e_end) {
-                        al = find_seg(sh.eoff, nb, e);
-                        dx = image(xv[c] - sh.xi[al], a.L[0], a.invL[0]);
-                        dy = image(yv[c] - sh.yi[al], a.L[1], a.invL[1]);
-                        dz = image(zv[c] - sh.zi[al], a.L[2], a.invL[2]);
-                        rsq = norm2(dx, dy, dz);
-                        const double psq = ONE ? tab.packsq[0] : tab.packsq[sh.ti[al] * tab.ntypes + tv[c]];
-                        acc = rsq < psq;
-                    }
-                    unsigned long long m = __ballot(acc);
-                    const int below = lanes_below(m);
-                    const int cnt = __popcll(m);
-                    if (npacked + cnt > SCAP) {
-                        // cut the batch before the first atom whose slots do not fit
-                        unsigned long long over = __ballot(acc && (npacked + below >= SCAP));
-                        int fl = __ffsll((long long)over) - 1;
-                        cut = __shfl(al, fl, kWave);
-                        acc = acc && (al < cut);
-                        stop = true;
-                    }
-                    if (e < e_end && (!stop || al < cut)) a.packed[e] = acc ? 1 : 0;
-                    if (acc) {
-                        const int s = npacked + below;
-                        real r = M<real>::sqrt((real)rsq);
-                        real ri = M<real>::rcp(r);
-                        sh.rsq[s] = rsq;
-                        sh.r[s] = r;
-                        sh.rinv[s] = ri;
-                        sh.ux[s] = (real)dx * ri;
-                        sh.uy[s] = (real)dy * ri;
-                        sh.uz[s] = (real)dz * ri;
-                        sh.zeta[s] = real(0);
-                        sh.j[s] = jv[c];
-                        sh.e[s] = rv[c];
-                        sh.tj[s] = tv[c];
-                        sh.al[s] = al;
-                        atomicAdd(&sh.pcnt[al], 1);
-                    }
-                    if (!stop) npacked += cnt;
-                }
+            // ---- slot lanes: load the packed record of pair (i, j)
+            const int s = lane;
+            const bool has_slot = s < npacked;
+            int al = 0, jl = 0, pc = 0, sb = 0, j = 0, kpos = -1, mj = 0, ti = 0;
+            real rj = 0, rjinv = 0, uj[3] = {0, 0, 0};
+            if (has_slot) {
+                al = find_seg(sh.pstart, cut, s);
+                sb = sh.pstart[al];
+                jl = s - sb;
+                pc = sh.pcnt[al];
+                ti = ONE ? 0 : sh.ti[al];
+                const Rec<real> rc = recs[(size_t)(a0 + al) * kRecCap + jl];
+                j = rc.j;
+                kpos = a.slotpos[rc.rev];
+                mj = rc.mask;
+                rj = rc.r; rjinv = rc.rinv;
+                uj[0] = rc.ux; uj[1] = rc.uy; uj[2] = rc.uz;
+                sh.ux[s] = rc.ux; sh.uy[s] = rc.uy; sh.uz[s] = rc.uz;
+                sh.r[s] = rc.r; sh.rinv[s] = rc.rinv;
+                sh.mask[s] = rc.mask;
             }
             __syncthreads();
-            if (cut == 0) {
-                // a single atom has more packed neighbours than SCAP: its terms
-                // are skipped (reported), none of its entries is marked packed
-                if (lane == 0) atomicOr(a.flags, kFlagOverflow);
-                for (int e = sh.eoff[0] + lane; e < sh.eoff[1]; e += kWave) {
-                    a.packed[e] = 0;
-                    double *f = a.contrib + 3 * (size_t)a.jr[e].y;
-                    f[0] = f[1] = f[2] = 0.0;
-                }
-                if (lane == 0) {
-                    double *o = a.own + 3 * (size_t)a0;
-                    o[0] = o[1] = o[2] = 0.0;
-                }
-                a0 += 1;
-                __syncthreads();
-                continue;
-            }
 
-            // ---- per-atom slot and triplet offsets
-            {
-                int p = lane < cut ? sh.pcnt[lane] : 0;
-                int t = p * (p - 1);
-                int ip = wave_incl_scan(p);
-                int it = wave_incl_scan(t);
-                if (lane < cut) {
-                    sh.pstart[lane + 1] = ip;
-                    sh.tstart[lane + 1] = it;
-                }
-                if (lane == 0) { sh.pstart[0] = 0; sh.tstart[0] = 0; }
-                npacked = __shfl(ip, cut - 1, kWave);
-            }
-            __syncthreads();
-            const int ntrip = sh.tstart[cut];
-            const bool cached = ntrip <= kWave * TI;
-
-            // ---- phase C: first K loop (zeta and its gradients)
-            Trip<real> tc[TI];
-            TripIdx tix[TI];
-#pragma unroll
-            for (int it = 0; it < TI; ++it) {
-                const int t = lane + it * kWave;
-                tc[it].z = real(0);
-                if (t < ntrip) {
-                    tix[it] = decode_triplet(sh, cut, t);
-                    bool ok = triplet_eval<real, ONE, SCAP>(sh, tix[it], tab, ptab, tc[it], cached);
-                    if (ok) {
-                        atomicAdd(&sh.zeta[tix[it].sj], tc[it].z);
+            const int tj = mj & 0xff;
+            const bool j_pair = (mj >> kPairBit) & 1;
+            double fx = 0, fy = 0, fz = 0;     // force on j from centre i's terms
+            if (has_slot) {
+                // ---- 1: zeta_ij over the other slots k of centre i
+                real zr = real(0);
+                if (j_pair) {
+                    for (int kl = 0; kl < pc; ++kl) {
+                        if (kl == jl) continue;
+                        const int sk = sb + kl;
+                        const int mk = sh.mask[sk];
+                        if (!((mk >> (kThirdBit + tj)) & 1)) continue;
+                        const ParamR<real> &q = ptab[ONE ? 0 : (ti * nt + tj) * nt + (mk & 0xff)];
+                        const real rk = sh.r[sk];
+                        const real cs = uj[0] * sh.ux[sk] + uj[1] * sh.uy[sk] + uj[2] * sh.uz[sk];
+                        real fck, dfck, ex, dex;
+                        cutoff_terms(q, rk, fck, dfck);
+                        exp_term(q, rj, rk, ex, dex);
+                        zr += fck * angular(q, cs).g * ex;
                         ++n_trip;
                     }
                 }
-            }
-            if (!cached) {
-                for (int t = lane + TI * kWave; t < ntrip; t += kWave) {
-                    TripIdx ix = decode_triplet(sh, cut, t);
-                    Trip<real> o;
-                    if (triplet_eval<real, ONE, SCAP>(sh, ix, tab, ptab, o, false)) {
-                        atomicAdd(&sh.zeta[ix.sj], o.z);
-                        ++n_trip;
-                    }
-                }
-            }
-            __syncthreads();
-
-            // ---- phase D: pair terms, bond order, dV/dzeta
-            for (int s = lane; s < npacked; s += kWave) {
-                const int al = sh.al[s];
-                const int ti = ONE ? 0 : sh.ti[al];
-                const int tj = ONE ? 0 : sh.tj[s];
-                const int nt = ONE ? 1 : tab.ntypes;
-                const int e_ij = (ti * nt + tj) * nt + tj;
-                const ParamX px = tab.px[e_ij];
-                double fsx = 0, fsy = 0, fsz = 0;
+                // ---- 2: pair terms, bond order, dV/dzeta
                 real dz_out = real(0);
-                if (ONE || sh.rsq[s] < px.cutsq) {
+                if (j_pair) {
                     ++n_pairs;
+                    const int e_ij = ONE ? 0 : (ti * nt + tj) * nt + tj;
                     const ParamR<real> &q = ptab[e_ij];
-                    const real r = sh.r[s];
-                    real fc, dfc;
-                    cutoff_terms(q, r, fc, dfc);
-                    real fr, fa, dfr, dfa;
-                    pair_terms(q, r, fr, dfr, fa, dfa);
+                    const ParamX px = tab.px[e_ij];
+                    real fc, dfc, fr, fa, dfr, dfa;
+                    cutoff_terms(q, rj, fc, dfc);
+                    pair_terms(q, rj, fr, dfr, fa, dfa);
                     // Eq. (2) in FP64 log form
-                    const double zeta = (double)sh.zeta[s];
+                    const double zeta = (double)zr;
                     double b = 1.0, db = 0.0;
                     if (zeta > 0.0) {
                         const double x = ::exp(px.eta * (px.logbeta + ::log(zeta)));
@@ -498,82 +486,80 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                     const real br = (real)b;
                     e_acc += 0.5 * (double)fc * ((double)fr + b * (double)fa);
                     const real dvdr = real(0.5) * (dfc * (fr + br * fa) + fc * (dfr + br * dfa));
-                    // force on j is -dV/dx_j = -dvdr * u
-                    const real fx = -dvdr * sh.ux[s], fy = -dvdr * sh.uy[s], fz = -dvdr * sh.uz[s];
-                    fsx = fx; fsy = fy; fsz = fz;
-                    atomicAdd(&sh.fi[al][0], -(double)fx);
-                    atomicAdd(&sh.fi[al][1], -(double)fy);
-                    atomicAdd(&sh.fi[al][2], -(double)fz);
-                    const real dxr = r * sh.ux[s], dyr = r * sh.uy[s], dzr = r * sh.uz[s];
-                    w_acc[0] += (double)(dxr * fx);
-                    w_acc[1] += (double)(dyr * fy);
-                    w_acc[2] += (double)(dzr * fz);
-                    w_acc[3] += (double)(dxr * fy);
-                    w_acc[4] += (double)(dxr * fz);
-                    w_acc[5] += (double)(dyr * fz);
+                    fx = (double)(-dvdr * uj[0]);
+                    fy = (double)(-dvdr * uj[1]);
+                    fz = (double)(-dvdr * uj[2]);
                     dz_out = (real)(0.5 * (double)fc * (double)fa * db);
                 }
-                sh.fs[s][0] = fsx; sh.fs[s][1] = fsy; sh.fs[s][2] = fsz;
                 sh.dzeta[s] = dz_out;
             }
             __syncthreads();
 
-            // ---- phase E: second K loop (dV/dzeta times the gradients)
-            auto apply = [&](const TripIdx &ix, const Trip<real> &o) {
-                const real dzv = sh.dzeta[ix.sj];
-                if (dzv == real(0)) return;
-                real fj[3], fk[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    fj[c] = -dzv * o.gj[c];
-                    fk[c] = -dzv * o.gk[c];
+            if (has_slot) {
+                // ---- 3: second K loop, every force term of centre i on atom j
+                const real dzj = sh.dzeta[s];
+                for (int kl = 0; kl < pc; ++kl) {
+                    if (kl == jl) continue;
+                    const int sk = sb + kl;
+                    const int mk = sh.mask[sk];
+                    const int tk = mk & 0xff;
+                    // j-role in (i; j, k) and k-role in (i; k, j)
+                    const bool use1 = j_pair && ((mk >> (kThirdBit + tj)) & 1) && dzj != real(0);
+                    const real dzk = sh.dzeta[sk];
+                    const bool use2 = ((mk >> kPairBit) & 1) && ((mj >> (kThirdBit + tk)) & 1) && dzk != real(0);
+                    if (!use1 && !use2) continue;
+                    const real rk = sh.r[sk];
+                    const real uk[3] = {sh.ux[sk], sh.uy[sk], sh.uz[sk]};
+                    const real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
+                    // d cos(theta_ijk) / d x_j
+                    const real dc[3] = {(uk[0] - cs * uj[0]) * rjinv, (uk[1] - cs * uj[1]) * rjinv,
+                                        (uk[2] - cs * uj[2]) * rjinv};
+                    real cdc = real(0), cu = real(0);   // F_j -= cdc * dc + cu * u_j
+                    if (use1) {
+                        const ParamR<real> &q = ptab[ONE ? 0 : (ti * nt + tj) * nt + tk];
+                        real fck, dfck, ex, dex;
+                        cutoff_terms(q, rk, fck, dfck);
+                        exp_term(q, rj, rk, ex, dex);
+                        const Angular<real> an = angular(q, cs);
+                        cdc += dzj * fck * ex * an.dg;
+                        cu += dzj * fck * an.g * dex;
+                    }
+                    if (use2) {
+                        const ParamR<real> &q = ptab[ONE ? 0 : (ti * nt + tk) * nt + tj];
+                        real fcj, dfcj, ex, dex;
+                        cutoff_terms(q, rj, fcj, dfcj);
+                        exp_term(q, rk, rj, ex, dex);
+                        const Angular<real> an = angular(q, cs);
+                        cdc += dzk * fcj * ex * an.dg;
+                        cu += dzk * (dfcj * an.g * ex - fcj * an.g * dex);
+                    }
+                    fx -= (double)(cdc * dc[0] + cu * uj[0]);
+                    fy -= (double)(cdc * dc[1] + cu * uj[1]);
+                    fz -= (double)(cdc * dc[2] + cu * uj[2]);
                 }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    atomicAdd(&sh.fs[ix.sj][c], (double)fj[c]);
-                    atomicAdd(&sh.fs[ix.sk][c], (double)fk[c]);
-                    atomicAdd(&sh.fi[ix.al][c], -(double)(fj[c] + fk[c]));
+                // ---- 4: virial and output
+                const double dxj = (double)(rj * uj[0]), dyj = (double)(rj * uj[1]), dzj_ = (double)(rj * uj[2]);
+                w_acc[0] += dxj * fx;
+                w_acc[1] += dyj * fy;
+                w_acc[2] += dzj_ * fz;
+                w_acc[3] += dxj * fy;
+                w_acc[4] += dxj * fz;
+                w_acc[5] += dyj * fz;
+                if (kpos >= 0) {
+                    double *f = a.planes + 3 * ((size_t)kpos * a.n + (size_t)j);
+                    f[0] = fx; f[1] = fy; f[2] = fz;
                 }
-                const real rj = sh.r[ix.sj], rk = sh.r[ix.sk];
-                const real dj[3] = {rj * sh.ux[ix.sj], rj * sh.uy[ix.sj], rj * sh.uz[ix.sj]};
-                const real dk[3] = {rk * sh.ux[ix.sk], rk * sh.uy[ix.sk], rk * sh.uz[ix.sk]};
-                w_acc[0] += (double)(dj[0] * fj[0] + dk[0] * fk[0]);
-                w_acc[1] += (double)(dj[1] * fj[1] + dk[1] * fk[1]);
-                w_acc[2] += (double)(dj[2] * fj[2] + dk[2] * fk[2]);
-                w_acc[3] += (double)(dj[0] * fj[1] + dk[0] * fk[1]);
-                w_acc[4] += (double)(dj[0] * fj[2] + dk[0] * fk[2]);
-                w_acc[5] += (double)(dj[1] * fj[2] + dk[1] * fk[2]);
-            };
-            if (cached) {
-#pragma unroll
-                for (int it = 0; it < TI; ++it) {
-                    const int t = lane + it * kWave;
-                    if (t < ntrip) apply(tix[it], tc[it]);
-                }
-            } else {
-                for (int t = lane; t < ntrip; t += kWave) {
-                    TripIdx ix = decode_triplet(sh, cut, t);
-                    Trip<real> o;
-                    if (triplet_eval<real, ONE, SCAP>(sh, ix, tab, ptab, o, true)) apply(ix, o);
-                }
+                sh.fs[s][0] = fx; sh.fs[s][1] = fy; sh.fs[s][2] = fz;
             }
             __syncthreads();
-
-            // ---- phase F: write this batch's force terms (no atomics): the
-            // force on packed neighbour j goes to the entry (j, i) of j's own
-            // row, the force on each centre atom to its own slot; the gather
-            // kernel adds up each atom's row.
-            for (int s = lane; s < npacked; s += kWave) {
-                double *f = a.contrib + 3 * (size_t)sh.e[s];
-                f[0] = sh.fs[s][0];
-                f[1] = sh.fs[s][1];
-                f[2] = sh.fs[s][2];
-            }
             if (lane < cut) {
+                double ox = 0, oy = 0, oz = 0;
+                const int s0 = sh.pstart[lane], s1 = sh.pstart[lane + 1];
+                for (int q = s0; q < s1; ++q) {
+                    ox -= sh.fs[q][0]; oy -= sh.fs[q][1]; oz -= sh.fs[q][2];
+                }
                 double *o = a.own + 3 * (size_t)(a0 + lane);
-                o[0] = sh.fi[lane][0];
-                o[1] = sh.fi[lane][1];
-                o[2] = sh.fi[lane][2];
+                o[0] = ox; o[1] = oy; o[2] = oz;
             }
             __syncthreads();
             a0 += cut;
@@ -591,12 +577,35 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
         ntr += __shfl_xor(ntr, off, kWave);
     }
     if (lane == 0) {
-        double *p = a.partials + 8 * (size_t)blockIdx.x;
+        double *pp = a.partials + 8 * (size_t)blockIdx.x;
 #pragma unroll
-        for (int c = 0; c < 7; ++c) p[c] = v[c];
-        p[7] = 0.0;
+        for (int c = 0; c < 7; ++c) pp[c] = v[c];
+        pp[7] = 0.0;
         a.counters[2 * (size_t)blockIdx.x] = np;
         a.counters[2 * (size_t)blockIdx.x + 1] = ntr;
+    }
+}
+
+// Atoms dropped by k_pack (more kept neighbours than a record row holds)
+// never run as centres; zero the force slots their neighbours reserved for
+// them so the gather adds nothing stale.  Workgroups loop until the list is
+// drained.
+__global__ void k_fixup_dropped(const int *__restrict__ offsets, const int2 *__restrict__ jr,
+                                const int *__restrict__ slotpos, const int *__restrict__ drop_list,
+                                const int *__restrict__ drop_count, int n, double *__restrict__ planes)
+{
+    const int nd = *drop_count;
+    for (int q = blockIdx.x; q < nd; q += gridDim.x) {
+        const int m = drop_list[q];
+        for (int e = offsets[m] + (int)threadIdx.x; e < offsets[m + 1]; e += blockDim.x) {
+            if (slotpos[e] == -1) continue;            // m did not keep this neighbour
+            const int2 q2 = jr[e];
+            const int k = slotpos[q2.y];               // rank of m in the neighbour's row
+            if (k >= 0) {
+                double *f = planes + 3 * ((size_t)k * n + (size_t)q2.x);
+                f[0] = f[1] = f[2] = 0.0;
+            }
+        }
     }
 }
 
@@ -631,40 +640,25 @@ __global__ void k_finalize(const double *__restrict__ partials, const long long 
     }
 }
 
-// F_m = (terms of centre m) + sum over the entries (m, i) of m's row that m
-// packed of the force centre i's terms put on m.  The packing radius is
-// symmetric and r^2 of (m, i) and (i, m) is bit-identical, so m packed i
-// exactly when i packed m, and i stored that force at entry (m, i).
-// 16 lanes per row, each row read contiguously; lane partial sums reduced
-// across the 16 lanes.
-__global__ void k_gather_forces(const int *__restrict__ offsets, const unsigned char *__restrict__ packed,
-                                const double *__restrict__ contrib, const double *__restrict__ own,
-                                int n, double *__restrict__ forces)
+// F_m = (terms of centre m) + the force each centre i that keeps m put into
+// plane k of m, k = rank of i among m's kept neighbours (k < pcount[m]).
+// One thread per atom; each plane read is coalesced across the wavefront.
+__global__ void k_gather_forces(const int *__restrict__ pcount, const double *__restrict__ planes,
+                                const double *__restrict__ own, int n, double *__restrict__ forces)
 {
-    const int m = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
-    const int l = threadIdx.x % 16;
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    if (m < n) {
-        const int e1 = offsets[m + 1];
-        for (int e = offsets[m] + l; e < e1; e += 16) {
-            if (packed[e]) {
-                fx += contrib[3 * (size_t)e];
-                fy += contrib[3 * (size_t)e + 1];
-                fz += contrib[3 * (size_t)e + 2];
-            }
-        }
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double fx = own[3 * (size_t)m], fy = own[3 * (size_t)m + 1], fz = own[3 * (size_t)m + 2];
+    const int pc = pcount[m];
+    for (int k = 0; k < pc; ++k) {
+        const double *f = planes + 3 * ((size_t)k * n + (size_t)m);
+        fx += f[0];
+        fy += f[1];
+        fz += f[2];
     }
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
-        fx += __shfl_xor(fx, off, 16);
-        fy += __shfl_xor(fy, off, 16);
-        fz += __shfl_xor(fz, off, 16);
-    }
-    if (m < n && l == 0) {
-        forces[3 * (size_t)m] = own[3 * (size_t)m] + fx;
-        forces[3 * (size_t)m + 1] = own[3 * (size_t)m + 1] + fy;
-        forces[3 * (size_t)m + 2] = own[3 * (size_t)m + 2] + fz;
-    }
+    forces[3 * (size_t)m] = fx;
+    forces[3 * (size_t)m + 1] = fy;
+    forces[3 * (size_t)m + 2] = fz;
 }
 
 __global__ void k_fill_zero(double *p, size_t count)
@@ -674,31 +668,55 @@ __global__ void k_fill_zero(double *p, size_t count)
     for (; i < count; i += stride) p[i] = 0.0;
 }
 
-constexpr int kScap = 64;
-constexpr int kTi = 3;
-
 template <typename real, bool ONE>
-int grid_for(int n, int atoms_per_batch)
+int occupancy_grid(const void *kern, long long work_items)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tersoff<real, ONE, kScap, kTi>,
-                                                     kWave, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    long long groups = ((long long)n + atoms_per_batch - 1) / atoms_per_batch;
     long long g = (long long)per_cu * cus;
-    if (g > groups) g = groups;
+    if (g > work_items) g = work_items;
     return (int)(g < 1 ? 1 : g);
+}
+
+template <typename real, bool ONE>
+void grids_for(int n, int atoms_per_batch, int grids[3])
+{
+    grids[0] = occupancy_grid<real, ONE>((const void *)k_pack<real, ONE>, (n + kPackB - 1) / kPackB);
+    grids[1] = occupancy_grid<real, ONE>((const void *)k_tersoff<real, ONE>,
+                                         ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
+    grids[2] = kBigGrid;
 }
 
 }  // namespace
 
-int compute_grid_size(bool mixed, bool one_type, int n, int atoms_per_batch)
+void compute_grids(bool mixed, bool one_type, int n, int atoms_per_batch, int grids[3])
 {
-    if (mixed) return one_type ? grid_for<float, true>(n, atoms_per_batch) : grid_for<float, false>(n, atoms_per_batch);
-    return one_type ? grid_for<double, true>(n, atoms_per_batch) : grid_for<double, false>(n, atoms_per_batch);
+    if (mixed) {
+        if (one_type) grids_for<float, true>(n, atoms_per_batch, grids);
+        else grids_for<float, false>(n, atoms_per_batch, grids);
+    } else {
+        if (one_type) grids_for<double, true>(n, atoms_per_batch, grids);
+        else grids_for<double, false>(n, atoms_per_batch, grids);
+    }
+}
+
+size_t record_bytes(bool mixed) { return mixed ? sizeof(Rec<float>) : sizeof(Rec<double>); }
+
+hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s)
+{
+    const bool one = t.ntypes == 1;
+    if (mixed) {
+        if (one) hipLaunchKernelGGL((k_pack<float, true>), dim3(grid), dim3(kWave), 0, s, a, t);
+        else hipLaunchKernelGGL((k_pack<float, false>), dim3(grid), dim3(kWave), 0, s, a, t);
+    } else {
+        if (one) hipLaunchKernelGGL((k_pack<double, true>), dim3(grid), dim3(kWave), 0, s, a, t);
+        else hipLaunchKernelGGL((k_pack<double, false>), dim3(grid), dim3(kWave), 0, s, a, t);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mixed, int grid,
@@ -707,12 +725,21 @@ hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mix
     const bool one = t.ntypes == 1;
     if (a.atoms_per_batch < 1 || a.atoms_per_batch > kWave) return hipErrorInvalidValue;
     if (mixed) {
-        if (one) hipLaunchKernelGGL((k_tersoff<float, true, kScap, kTi>), dim3(grid), dim3(kWave), 0, s, a, t);
-        else hipLaunchKernelGGL((k_tersoff<float, false, kScap, kTi>), dim3(grid), dim3(kWave), 0, s, a, t);
+        if (one) hipLaunchKernelGGL((k_tersoff<float, true>), dim3(grid), dim3(kWave), 0, s, a, t);
+        else hipLaunchKernelGGL((k_tersoff<float, false>), dim3(grid), dim3(kWave), 0, s, a, t);
     } else {
-        if (one) hipLaunchKernelGGL((k_tersoff<double, true, kScap, kTi>), dim3(grid), dim3(kWave), 0, s, a, t);
-        else hipLaunchKernelGGL((k_tersoff<double, false, kScap, kTi>), dim3(grid), dim3(kWave), 0, s, a, t);
+        if (one) hipLaunchKernelGGL((k_tersoff<double, true>), dim3(grid), dim3(kWave), 0, s, a, t);
+        else hipLaunchKernelGGL((k_tersoff<double, false>), dim3(grid), dim3(kWave), 0, s, a, t);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fixup_dropped(const int *offsets, const int2 *jr, const int *slotpos,
+                                const int *drop_list, const int *drop_count, int n, double *planes,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fixup_dropped, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jr, slotpos,
+                       drop_list, drop_count, n, planes);
     return hipGetLastError();
 }
 
@@ -723,12 +750,11 @@ hipError_t launch_finalize(const double *partials, const long long *counters, in
     return hipGetLastError();
 }
 
-hipError_t launch_gather_forces(const int *offsets, const unsigned char *packed,
-                                const double *contrib, const double *own, int n, double *forces,
-                                hipStream_t s)
+hipError_t launch_gather_forces(const int *pcount, const double *planes, const double *own, int n,
+                                double *forces, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_forces, dim3((n + 15) / 16), dim3(256), 0, s, offsets, packed,
-                       contrib, own, n, forces);
+    hipLaunchKernelGGL(k_gather_forces, dim3((n + 255) / 256), dim3(256), 0, s, pcount, planes, own,
+                       n, forces);
     return hipGetLastError();
 }
 

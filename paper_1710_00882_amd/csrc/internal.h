@@ -54,34 +54,55 @@ struct DeviceTable {
 // Flags raised by kernels (bitwise OR into a device int).
 enum : int { kFlagOverflow = 1, kFlagStale = 2 };
 
-struct ComputeLaunch {
+constexpr int kRecCap = 32;   // packed-neighbour records per atom (more: E_OVERFLOW)
+constexpr int kBigGrid = 64;  // workgroups of the dropped-atom fixup kernel
+
+struct PackLaunch {
     const double *pos;          // n x 3
     const int *types;           // n
-    const int *offsets;         // n + 1 (CSR, int32)
+    const int *offsets;         // n + 1 (CSR, int32, internal row order)
     const int2 *jr;             // S: (neighbour j, entry of i in row j)
     int n;
     double L[3], invL[3];
+    void *recs;                 // n x kRecCap packed records
+    int *pcount;                // n: records per atom
+    int *slotpos;               // S: rank among the row's kept entries, -1 not kept, -2 beyond cap
+    double *own;                // n x 3 (zeroed for dropped atoms only)
+    int *flags;
+    int *drop_list;             // n: atoms with more kept neighbours than kRecCap
+    int *drop_count;            // reset to 0 here
+    const double *pos_build;    // n x 3 positions of the last build (stale check)
+    double stale_sq;            // (skin / 2)^2
+};
+
+struct ComputeLaunch {
+    const int *types;           // n
+    const void *recs;           // n x kRecCap packed records
+    const int *pcount;          // n
+    const int *slotpos;         // S
+    int n;
     double *own;                // n x 3: force from the terms of each centre atom
-    double *contrib;            // S x 3: at entry (j, i), the force centre i's terms put on j
-    unsigned char *packed;      // S: 1 if centre i packed entry j in this evaluation
+    double *planes;             // kRecCap x n x 3: plane k of atom j = force from its k-th kept neighbour's terms
     double *partials;           // grid x 8
     long long *counters;        // grid x 2 (pairs, triplets)
-    int *flags;
-    const double *pos_build;    // n x 3 positions of the last build (stale check) or null
-    double stale_sq;            // (skin / 2)^2
     int atoms_per_batch;        // nominal atoms per batch (<= kWave)
 };
 
-// Launchers (compute.hip)
+// Launchers (compute.hip).  grids = {pack, compute} workgroup counts plus
+// kBigGrid for the fixup kernel.
+void compute_grids(bool mixed, bool one_type, int n, int atoms_per_batch, int grids[3]);
+size_t record_bytes(bool mixed);
+hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s);
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mixed,
                           int grid, hipStream_t s);
-int compute_grid_size(bool mixed, bool one_type, int n, int atoms_per_batch);
+hipError_t launch_fixup_dropped(const int *offsets, const int2 *jr, const int *slotpos,
+                                const int *drop_list, const int *drop_count, int n, double *planes,
+                                hipStream_t s);
 hipError_t launch_finalize(const double *partials, const long long *counters, int grid,
                            double *out7, long long *counts_out, hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
-hipError_t launch_gather_forces(const int *offsets, const unsigned char *packed,
-                                const double *contrib, const double *own, int n, double *forces,
-                                hipStream_t s);
+hipError_t launch_gather_forces(const int *pcount, const double *planes, const double *own, int n,
+                                double *forces, hipStream_t s);
 
 // Neighbour build (neighbors.hip)
 struct CellGrid {
@@ -97,13 +118,13 @@ hipError_t launch_scatter_cells(const double *pos, int n, const int *cell_of,
 hipError_t launch_search(const double *pos, int n, const CellGrid &g, double rcut,
                          const int *cell_of, const int *cell_start, const int *cell_count,
                          const int *cell_atoms, const double *cell_pos, int cap, int *ell,
-                         int *row_count, hipStream_t s);
-hipError_t launch_sort_rows(const int *ell, int cap, const int *row_count, const int *offsets,
-                            int n, int *idx, hipStream_t s);
-// jr[e] = (j, rev) for entry e = (i, j), rev = the entry of i in row j (the
+                         float *ell_r2, int *row_count, hipStream_t s);
+hipError_t launch_sort_rows(const int *ell, const float *ell_r2, int cap, const int *row_count,
+                            const int *offsets, int n, int *idx, int2 *jr, int *perm, hipStream_t s);
+// jr[e].y for internal entry e = (i, j): the internal entry of (j, i) (the
 // list is symmetric).  Sets *flags |= 4 if some reverse entry is missing.
-hipError_t launch_reverse_map(const int *offsets, const int *idx, int n, int2 *jr, int *flags,
-                              hipStream_t s);
+hipError_t launch_reverse_map(const int *offsets, const int *idx, const int *perm, int n, int2 *jr,
+                              int *flags, hipStream_t s);
 hipError_t launch_check_inputs(const double *pos, const int *types, int n, int ntypes,
                                int *flags, hipStream_t s);
 

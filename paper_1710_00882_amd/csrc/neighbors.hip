@@ -10,7 +10,8 @@
 // exclusive scan of cell counts -> scatter atom ids and positions into cell
 // order -> one thread per atom scans the unique neighbouring cells into a
 // fixed-capacity row buffer -> scan of row counts (CSR offsets) -> each row is
-// rank-sorted by 16 lanes into its CSR slot.
+// rank-sorted by 16 lanes into its CSR slot (public order by j, internal
+// order nearest-first) -> reverse-entry map of the internal order.
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -77,7 +78,7 @@ __global__ void k_search(const double *__restrict__ pos, int n, CellGrid g, doub
                          const int *__restrict__ cell_of, const int *__restrict__ cell_start,
                          const int *__restrict__ cell_count, const int *__restrict__ cell_atoms,
                          const double *__restrict__ cpos, int cap, int *__restrict__ ell,
-                         int *__restrict__ row_count)
+                         float *__restrict__ ell_r2, int *__restrict__ row_count)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -92,6 +93,7 @@ __global__ void k_search(const double *__restrict__ pos, int n, CellGrid g, doub
     int lo2 = g.nc[2] >= 3 ? -1 : 0, hi2 = g.nc[2] >= 3 ? 1 : g.nc[2] - 1;
     int cnt = 0;
     int *row = ell + (size_t)i * cap;
+    float *row_r2 = ell_r2 + (size_t)i * cap;
     for (int o0 = lo0; o0 <= hi0; ++o0) {
         int x = c0 + o0; x += (x < 0) ? g.nc[0] : 0; x -= (x >= g.nc[0]) ? g.nc[0] : 0;
         for (int o1 = lo1; o1 <= hi1; ++o1) {
@@ -108,7 +110,10 @@ __global__ void k_search(const double *__restrict__ pos, int n, CellGrid g, doub
                     double dz = image_component(cpos[3 * (size_t)s + 2], zi, g.L[2]);
                     double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                     if (r2 < rc2) {
-                        if (cnt < cap) row[cnt] = j;
+                        if (cnt < cap) {
+                            row[cnt] = j;
+                            row_r2[cnt] = (float)r2;
+                        }
                         ++cnt;
                     }
                 }
@@ -118,10 +123,14 @@ __global__ void k_search(const double *__restrict__ pos, int n, CellGrid g, doub
     row_count[i] = cnt;
 }
 
-// 16 lanes per row: each lane takes elements lane, lane+16, ... and writes
-// each at its rank within the row (row entries are distinct atom ids).
-__global__ void k_sort_rows(const int *__restrict__ ell, int cap, const int *__restrict__ row_count,
-                            const int *__restrict__ offsets, int n, int *__restrict__ idx)
+// 16 lanes per row: each lane takes elements lane, lane+16, ... and places
+// each by its rank within the row (row entries are distinct atom ids), twice:
+// by j for the public list, and nearest-first (r^2 at build, ties by j) for
+// the internal order the compute kernels walk; perm maps a public position
+// to the internal position of the same entry.
+__global__ void k_sort_rows(const int *__restrict__ ell, const float *__restrict__ ell_r2, int cap,
+                            const int *__restrict__ row_count, const int *__restrict__ offsets, int n,
+                            int *__restrict__ idx, int2 *__restrict__ jr, int *__restrict__ perm)
 {
     int r = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
     int l = threadIdx.x % 16;
@@ -129,25 +138,35 @@ __global__ void k_sort_rows(const int *__restrict__ ell, int cap, const int *__r
     int cnt = row_count[r];
     if (cnt > cap) return;   // never launched in this state (the build retries first)
     const int *row = ell + (size_t)r * cap;
+    const float *row_r2 = ell_r2 + (size_t)r * cap;
     int base = offsets[r];
     for (int e = l; e < cnt; e += 16) {
-        int v = row[e];
-        int rank = 0;
-        for (int m = 0; m < cnt; ++m) rank += row[m] < v;
-        idx[base + rank] = v;
+        const int v = row[e];
+        const float d = row_r2[e];
+        int rank_j = 0, rank_d = 0;
+        for (int m = 0; m < cnt; ++m) {
+            const int w = row[m];
+            const float dm = row_r2[m];
+            rank_j += w < v;
+            rank_d += (dm < d) || (dm == d && w < v);
+        }
+        idx[base + rank_j] = v;
+        jr[base + rank_d] = make_int2(v, -1);
+        perm[base + rank_j] = base + rank_d;
     }
 }
 
-// jr[e] = (j, rev) for e = (i, j), rev = position of i in the sorted row of j.
-// The inclusion predicate is symmetric (negating t negates s and d exactly),
-// so the entry exists; a missing one raises flag 4.
-__global__ void k_reverse_map(const int *__restrict__ offsets, const int *__restrict__ idx, int n,
-                              int2 *__restrict__ jr, int *flags)
+// jr[e].y for internal entry e = (i, j): the internal position of entry
+// (j, i), found by binary search of i in j's public (sorted) row and mapped
+// through perm.  The inclusion predicate is symmetric (negating t negates s
+// and d exactly), so the entry exists; a missing one raises flag 4.
+__global__ void k_reverse_map(const int *__restrict__ offsets, const int *__restrict__ idx,
+                              const int *__restrict__ perm, int n, int2 *__restrict__ jr, int *flags)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     for (int e = offsets[i]; e < offsets[i + 1]; ++e) {
-        const int j = idx[e];
+        const int j = jr[e].x;
         int lo = offsets[j], hi = offsets[j + 1] - 1, at = -1;
         while (lo <= hi) {
             int mid = (lo + hi) >> 1;
@@ -157,9 +176,10 @@ __global__ void k_reverse_map(const int *__restrict__ offsets, const int *__rest
         }
         if (at < 0) {
             atomicOr(flags, 4);
-            at = e;
+            jr[e].y = e;
+        } else {
+            jr[e].y = perm[at];
         }
-        jr[e] = make_int2(j, at);
     }
 }
 
@@ -277,11 +297,11 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int n, int *tmp, int *
     return hipGetLastError();
 }
 
-hipError_t launch_reverse_map(const int *offsets, const int *idx, int n, int2 *jr, int *flags,
-                              hipStream_t s)
+hipError_t launch_reverse_map(const int *offsets, const int *idx, const int *perm, int n, int2 *jr,
+                              int *flags, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reverse_map, dim3(blocks_for(n, 256)), dim3(256), 0, s, offsets, idx, n, jr,
-                       flags);
+    hipLaunchKernelGGL(k_reverse_map, dim3(blocks_for(n, 256)), dim3(256), 0, s, offsets, idx, perm, n,
+                       jr, flags);
     return hipGetLastError();
 }
 
@@ -313,19 +333,19 @@ hipError_t launch_scatter_cells(const double *pos, int n, const int *cell_of,
 hipError_t launch_search(const double *pos, int n, const CellGrid &g, double rcut,
                          const int *cell_of, const int *cell_start, const int *cell_count,
                          const int *cell_atoms, const double *cell_pos, int cap, int *ell,
-                         int *row_count, hipStream_t s)
+                         float *ell_r2, int *row_count, hipStream_t s)
 {
     hipLaunchKernelGGL(k_search, dim3(blocks_for(n, 128)), dim3(128), 0, s, pos, n, g,
                        rcut * rcut, cell_of, cell_start, cell_count, cell_atoms, cell_pos, cap,
-                       ell, row_count);
+                       ell, ell_r2, row_count);
     return hipGetLastError();
 }
 
-hipError_t launch_sort_rows(const int *ell, int cap, const int *row_count, const int *offsets,
-                            int n, int *idx, hipStream_t s)
+hipError_t launch_sort_rows(const int *ell, const float *ell_r2, int cap, const int *row_count,
+                            const int *offsets, int n, int *idx, int2 *jr, int *perm, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_rows, dim3(blocks_for(n, 16)), dim3(256), 0, s, ell, cap,
-                       row_count, offsets, n, idx);
+    hipLaunchKernelGGL(k_sort_rows, dim3(blocks_for(n, 16)), dim3(256), 0, s, ell, ell_r2, cap,
+                       row_count, offsets, n, idx, jr, perm);
     return hipGetLastError();
 }
 

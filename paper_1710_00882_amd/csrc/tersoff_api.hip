@@ -58,13 +58,14 @@ struct tersoff_ctx {
     long long S = 0;
     int ell_cap = 32;
     int atoms_per_batch = 16;
-    int grid[2] = {0, 0};   // [fp64, mixed]
+    int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};   // [fp64, mixed] x {pack, compute, per-atom}
 
     DevBuf<double> pos_build;
-    DevBuf<int> types, offsets, idx;
+    DevBuf<int> types, offsets, idx, perm, pcount, drop_list, slotpos;
     DevBuf<int2> jr;
-    DevBuf<unsigned char> packed;
-    DevBuf<double> own, contrib;
+    DevBuf<float> ell_r2;
+    DevBuf<unsigned char> recs;
+    DevBuf<double> own, planes;
     DevBuf<int> cell_of, rank, cell_count, cell_start, cell_atoms;
     DevBuf<double> cell_pos;
     DevBuf<int> ell, row_count, scan_tmp, misc;   // misc: [0] flags, [1] max row, [2] check flags
@@ -73,7 +74,7 @@ struct tersoff_ctx {
 
     // profiling: event pairs recorded around compute / build launches
     bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_compute, ev_build, ev_gather;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_compute, ev_build, ev_gather, ev_pack;
     std::vector<hipEvent_t> ev_pool;
 
     std::string last_error;
@@ -251,7 +252,8 @@ void tersoff_destroy(tersoff_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     c->pos_build.release(); c->types.release(); c->offsets.release(); c->idx.release();
-    c->jr.release(); c->packed.release(); c->own.release(); c->contrib.release();
+    c->jr.release(); c->slotpos.release(); c->own.release(); c->planes.release();
+    c->perm.release(); c->pcount.release(); c->drop_list.release(); c->ell_r2.release(); c->recs.release();
     c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
     c->cell_atoms.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
     c->scan_tmp.release(); c->misc.release(); c->partials.release(); c->force_scratch.release();
@@ -259,6 +261,7 @@ void tersoff_destroy(tersoff_ctx *c)
     for (auto &pr : c->ev_compute) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto &pr : c->ev_build) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto &pr : c->ev_gather) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (auto &pr : c->ev_pack) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->d_table) (void)hipFree(c->d_table);
     delete c;
@@ -271,20 +274,21 @@ int tersoff_profile(tersoff_ctx *c, int32_t enable)
     return TERSOFF_OK;
 }
 
-int tersoff_profile_read(tersoff_ctx *c, double out[6])
+int tersoff_profile_read(tersoff_ctx *c, double out[8])
 {
     if (!c || !out) return TERSOFF_E_INVALID;
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipDeviceSynchronize());
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> *lists[3] = {&c->ev_compute, &c->ev_build, &c->ev_gather};
-    for (int l = 0; l < 3; ++l) {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> *lists[4] = {&c->ev_compute, &c->ev_build, &c->ev_gather,
+                                                                &c->ev_pack};
+    for (int l = 0; l < 4; ++l) {
         double t = 0.0;
         for (auto &pr : *lists[l]) {
             float ms = 0.f;
             HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
             t += ms;
         }
-        const int slot = l == 2 ? 4 : 2 * l;
+        const int slot = 2 * l;
         out[slot] = t;
         out[slot + 1] = (double)lists[l]->size();
         for (auto &pr : *lists[l]) { c->ev_pool.push_back(pr.first); c->ev_pool.push_back(pr.second); }
@@ -299,9 +303,9 @@ int tersoff_set_batch_atoms(tersoff_ctx *c, int32_t atoms)
     if (atoms < 1 || atoms > kWave) return fail(c, TERSOFF_E_INVALID, "batch atoms must be in [1, 64]");
     c->atoms_per_batch = atoms;
     if (c->built) {
-        c->grid[0] = compute_grid_size(false, c->ntypes == 1, c->n, atoms);
-        c->grid[1] = compute_grid_size(true, c->ntypes == 1, c->n, atoms);
-        int gmax = std::max(c->grid[0], c->grid[1]);
+        compute_grids(false, c->ntypes == 1, c->n, atoms, c->grid[0]);
+        compute_grids(true, c->ntypes == 1, c->n, atoms, c->grid[1]);
+        int gmax = std::max(c->grid[0][1], c->grid[1][1]);
         HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
         HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
     }
@@ -364,6 +368,8 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, c->cell_atoms.ensure(N));
     HIP_TRY(c, c->cell_pos.ensure(3 * (size_t)N));
     HIP_TRY(c, c->row_count.ensure(N));
+    HIP_TRY(c, c->pcount.ensure(N));
+    HIP_TRY(c, c->drop_list.ensure(N));
     HIP_TRY(c, c->offsets.ensure((size_t)N + 1));
     HIP_TRY(c, c->scan_tmp.ensure(std::max(scan_tmp_size((int)ncell), scan_tmp_size(N))));
     HIP_TRY(c, c->pos_build.ensure(3 * (size_t)N));
@@ -377,9 +383,10 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     int host_tot[2] = {0, 0};
     for (int attempt = 0; attempt < 4; ++attempt) {
         HIP_TRY(c, c->ell.ensure((size_t)N * c->ell_cap));
+        HIP_TRY(c, c->ell_r2.ensure((size_t)N * c->ell_cap));
         HIP_TRY(c, launch_search(pos, N, g, rc, c->cell_of.p, c->cell_start.p, c->cell_count.p,
                                  c->cell_atoms.p, c->cell_pos.p, c->ell_cap, c->ell.p,
-                                 c->row_count.p, s));
+                                 c->ell_r2.p, c->row_count.p, s));
         HIP_TRY(c, launch_exclusive_scan(c->row_count.p, c->offsets.p, N, c->scan_tmp.p, c->misc.p + 1, s));
         HIP_TRY(c, hipMemcpyAsync(&host_tot[0], c->offsets.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipMemcpyAsync(&host_tot[1], c->misc.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -391,12 +398,13 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     if (host_tot[0] < 0) return fail(c, TERSOFF_E_INVALID, "list longer than 2^31 entries");
     c->S = host_tot[0];
     HIP_TRY(c, c->idx.ensure((size_t)std::max(c->S, 1LL)));
-    HIP_TRY(c, launch_sort_rows(c->ell.p, c->ell_cap, c->row_count.p, c->offsets.p, N, c->idx.p, s));
     HIP_TRY(c, c->jr.ensure((size_t)std::max(c->S, 1LL)));
-    HIP_TRY(c, c->packed.ensure((size_t)std::max(c->S, 1LL)));
-    HIP_TRY(c, c->contrib.ensure(3 * (size_t)std::max(c->S, 1LL)));
+    HIP_TRY(c, c->perm.ensure((size_t)std::max(c->S, 1LL)));
+    HIP_TRY(c, launch_sort_rows(c->ell.p, c->ell_r2.p, c->ell_cap, c->row_count.p, c->offsets.p, N,
+                                c->idx.p, c->jr.p, c->perm.p, s));
+    HIP_TRY(c, c->slotpos.ensure((size_t)std::max(c->S, 1LL)));
     HIP_TRY(c, c->own.ensure(3 * (size_t)N));
-    HIP_TRY(c, launch_reverse_map(c->offsets.p, c->idx.p, N, c->jr.p, c->misc.p + 2, s));
+    HIP_TRY(c, launch_reverse_map(c->offsets.p, c->idx.p, c->perm.p, N, c->jr.p, c->misc.p + 2, s));
     HIP_TRY(c, hipMemcpyAsync(&chk, c->misc.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(c->pos_build.p, pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->types.p, types, sizeof(int) * (size_t)N, hipMemcpyDeviceToDevice, s));
@@ -411,9 +419,9 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     for (int a = 0; a < 3; ++a) c->box[a] = box[a];
     c->cutoff = cutoff;
     c->skin = skin;
-    c->grid[0] = compute_grid_size(false, c->ntypes == 1, N, c->atoms_per_batch);
-    c->grid[1] = compute_grid_size(true, c->ntypes == 1, N, c->atoms_per_batch);
-    int gmax = std::max(c->grid[0], c->grid[1]);
+    compute_grids(false, c->ntypes == 1, N, c->atoms_per_batch, c->grid[0]);
+    compute_grids(true, c->ntypes == 1, N, c->atoms_per_batch, c->grid[1]);
+    int gmax = std::max(c->grid[0][1], c->grid[1][1]);
     HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
     HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
     HIP_TRY(c, c->counts.ensure(2));
@@ -433,54 +441,68 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t s = as_stream(stream);
     const bool mixed = precision == TERSOFF_MIXED;
+    const int *grid = c->grid[mixed ? 1 : 0];
     double *f = forces;
     if (!f) {
         HIP_TRY(c, c->force_scratch.ensure(3 * (size_t)c->n));
         f = c->force_scratch.p;
     }
-    ComputeLaunch a{};
-    a.pos = pos;
-    a.types = c->types.p;
-    a.offsets = c->offsets.p;
-    a.jr = c->jr.p;
-    a.n = c->n;
+    HIP_TRY(c, c->recs.ensure(record_bytes(mixed) * kRecCap * (size_t)c->n));
+    HIP_TRY(c, c->planes.ensure(3 * (size_t)kRecCap * (size_t)c->n));
+
+    PackLaunch pk{};
+    pk.pos = pos;
+    pk.types = c->types.p;
+    pk.offsets = c->offsets.p;
+    pk.jr = c->jr.p;
+    pk.n = c->n;
     for (int d = 0; d < 3; ++d) {
-        a.L[d] = c->box[d];
-        a.invL[d] = 1.0 / c->box[d];
+        pk.L[d] = c->box[d];
+        pk.invL[d] = 1.0 / c->box[d];
     }
+    pk.recs = c->recs.p;
+    pk.pcount = c->pcount.p;
+    pk.slotpos = c->slotpos.p;
+    pk.own = c->own.p;
+    pk.flags = c->misc.p;
+    pk.drop_list = c->drop_list.p;
+    pk.drop_count = c->misc.p + 3;
+    pk.pos_build = c->pos_build.p;
+    pk.stale_sq = 0.25 * c->skin * c->skin;
+
+    ComputeLaunch a{};
+    a.types = c->types.p;
+    a.recs = c->recs.p;
+    a.pcount = c->pcount.p;
+    a.slotpos = c->slotpos.p;
+    a.n = c->n;
     a.own = c->own.p;
-    a.contrib = c->contrib.p;
-    a.packed = c->packed.p;
+    a.planes = c->planes.p;
     a.partials = c->partials.p;
     a.counters = c->counters.p;
-    a.flags = c->misc.p;
-    a.pos_build = c->pos_build.p;
-    a.stale_sq = 0.25 * c->skin * c->skin;
     a.atoms_per_batch = c->atoms_per_batch;
-    const int grid = c->grid[mixed ? 1 : 0];
+
+    // event pairs (profiling only): pack, main kernel, fixup + gather
+    hipEvent_t ev[6] = {};
+    if (c->profiling)
+        for (int q = 0; q < 6; ++q) HIP_TRY(c, take_event(c, &ev[q]));
+    if (ev[0]) HIP_TRY(c, hipEventRecord(ev[0], s));
+    HIP_TRY(c, launch_pack(pk, c->tab, mixed, grid[0], s));
+    if (ev[1]) HIP_TRY(c, hipEventRecord(ev[1], s));
+    if (ev[2]) HIP_TRY(c, hipEventRecord(ev[2], s));
+    HIP_TRY(c, launch_compute(a, c->tab, mixed, grid[1], s));
+    if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
+    if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
+    HIP_TRY(c, launch_fixup_dropped(c->offsets.p, c->jr.p, c->slotpos.p, c->drop_list.p, c->misc.p + 3,
+                                    c->n, c->planes.p, s));
+    HIP_TRY(c, launch_gather_forces(c->pcount.p, c->planes.p, c->own.p, c->n, f, s));
+    if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
+    HIP_TRY(c, launch_finalize(c->partials.p, c->counters.p, grid[1], energy_virial, c->counts.p, s));
     if (c->profiling) {
-        hipEvent_t e0, e1;
-        HIP_TRY(c, take_event(c, &e0));
-        HIP_TRY(c, take_event(c, &e1));
-        HIP_TRY(c, hipEventRecord(e0, s));
-        HIP_TRY(c, launch_compute(a, c->tab, mixed, grid, s));
-        HIP_TRY(c, hipEventRecord(e1, s));
-        c->ev_compute.emplace_back(e0, e1);
-    } else {
-        HIP_TRY(c, launch_compute(a, c->tab, mixed, grid, s));
+        c->ev_pack.emplace_back(ev[0], ev[1]);
+        c->ev_compute.emplace_back(ev[2], ev[3]);
+        c->ev_gather.emplace_back(ev[4], ev[5]);
     }
-    if (c->profiling) {
-        hipEvent_t e0, e1;
-        HIP_TRY(c, take_event(c, &e0));
-        HIP_TRY(c, take_event(c, &e1));
-        HIP_TRY(c, hipEventRecord(e0, s));
-        HIP_TRY(c, launch_gather_forces(c->offsets.p, c->packed.p, c->contrib.p, c->own.p, c->n, f, s));
-        HIP_TRY(c, hipEventRecord(e1, s));
-        c->ev_gather.emplace_back(e0, e1);
-    } else {
-        HIP_TRY(c, launch_gather_forces(c->offsets.p, c->packed.p, c->contrib.p, c->own.p, c->n, f, s));
-    }
-    HIP_TRY(c, launch_finalize(c->partials.p, c->counters.p, grid, energy_virial, c->counts.p, s));
     return TERSOFF_OK;
 }
 
