@@ -98,9 +98,10 @@ void tersoff_destroy(tersoff_ctx *ctx);
  *   back the list length).  pos and types are copied; the list and the copies
  *   stay resident in the context until the next build.
  * Errors: E_INVALID (n < 1 or > 2^24, cutoff too small, type out of range,
- *   non-finite position), E_BOX (a box length < 2 (cutoff + skin)), E_NOMEM,
- *   E_DEVICE.  Rows longer than the working capacity are handled by a retry
- *   with a larger capacity. */
+ *   non-finite position), E_BOX (a box length < 2 (cutoff + skin)),
+ *   E_OVERFLOW (an atom has more than 256 neighbours within cutoff + skin),
+ *   E_NOMEM, E_DEVICE.  Rows longer than the working capacity are handled by
+ *   a retry with a larger capacity. */
 int tersoff_build_neighbors(tersoff_ctx *ctx, const double *pos, const int32_t *types,
                             int64_t n, const double box[3], double cutoff, double skin,
                             void *stream);

@@ -156,21 +156,24 @@ __device__ __forceinline__ void cutoff_terms(const ParamR<real> &q, real r, real
 
 // -------------------------------------------------------- packed records -
 
-// One packed neighbour n of a centre atom i (the in-range entries of i's
-// list, Section 3): the unit vector and distance in the working precision,
-// the neighbour index, the entry (n, i) of n's row that receives the force
-// i's terms put on n, and the membership bits of the exact FP64 cutoff tests.
+// One packed neighbour n of a centre atom i (an in-range entry of i's list,
+// Section 3): the neighbour index, the entry (n, i) of n's row, the
+// membership bits of the exact FP64 cutoff tests, and the distance and unit
+// vector in the working precision.  The records of a batch of B consecutive
+// centre atoms are stored contiguously, atom by atom, in the batch's region
+// of B * kRecCap records, so both the packing writes and the compute reads
+// are contiguous across lanes.
 template <typename real>
 struct Rec;
 template <>
 struct alignas(16) Rec<float> {
     int j, rev, mask;
-    float r, rinv, ux, uy, uz;
+    float r, ux, uy, uz, pad;
 };
 template <>
 struct alignas(16) Rec<double> {
     int j, rev, mask, pad;
-    double r, rinv, ux, uy, uz;
+    double r, ux, uy, uz;
 };
 
 // mask: bits 0-7 type of n; bit 8: r_in < cutoff of entry (t_i, t_n, t_n)
@@ -179,17 +182,16 @@ struct alignas(16) Rec<double> {
 constexpr int kPairBit = 8;
 constexpr int kThirdBit = 9;
 
-constexpr int kPackB = 16;     // centre atoms per pack wavefront batch
 constexpr int kChunks = 4;     // 64-entry chunks whose loads are issued together
 constexpr int kScap = 64;      // packed slots per compute batch (one per lane)
 
 // ------------------------------------------------------------- pack kernel -
 //
-// Lanes = list entries of kPackB consecutive centre atoms (a contiguous CSR
-// range).  Each lane computes the FP64 minimum-image displacement and r^2 of
+// Lanes = list entries of B consecutive centre atoms (their rows flattened
+// through a prefix count of the row lengths).  Each lane computes the FP64 minimum-image displacement and r^2 of
 // its entry and keeps it if r^2 is below the (symmetric) packing radius; the
-// kept entries of atom i are written, in list order, to records
-// [i * kRecCap, i * kRecCap + count).  slotpos[e] receives the rank of entry
+// kept entries are written, atom by atom and in list order, to the batch's
+// record region.  slotpos[e] receives the rank of entry
 // e among the kept entries of its row (-1: not kept, -2: beyond the record
 // capacity).  Because the radius is symmetric and r^2 of (i, n) and (n, i) is
 // bit-identical, i keeps n exactly when n keeps i, so the centre i can find
@@ -197,17 +199,18 @@ constexpr int kScap = 64;      // packed slots per compute batch (one per lane)
 template <typename real, bool ONE>
 __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
 {
-    __shared__ double xi[kPackB], yi[kPackB], zi[kPackB];
-    __shared__ int ti[kPackB], cnt[kPackB];
-    __shared__ int eoff[kPackB + 1];
+    __shared__ double xi[kWave], yi[kWave], zi[kWave];
+    __shared__ int ti[kWave], cnt[kWave];
+    __shared__ int eoff[kWave + 1];
     const int lane = threadIdx.x;
-    Rec<real> *recs = reinterpret_cast<Rec<real> *>(a.recs);
-    const int nbatch = (a.n + kPackB - 1) / kPackB;
+    Rec<real> *recs = static_cast<Rec<real> *>(a.recs);
+    const int B = a.atoms_per_batch;
+    const int nbatch = (a.n + B - 1) / B;
     if (blockIdx.x == 0 && lane == 0) *a.drop_count = 0;
 
     for (int bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
-        const int a0 = bt * kPackB;
-        const int nb = min(kPackB, a.n - a0);
+        const int a0 = bt * B;
+        const int nb = min(B, a.n - a0);
         if (lane < nb) {
             const size_t i = (size_t)(a0 + lane);
             const double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
@@ -218,19 +221,34 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                          dz = z - a.pos_build[3 * i + 2];
             if (!(dx * dx + dy * dy + dz * dz <= a.stale_sq)) atomicOr(a.flags, kFlagStale);
         }
-        if (lane < nb) eoff[lane] = a.offsets[a0 + lane];
-        if (lane == 0) eoff[nb] = a.offsets[a0 + nb];
+        {
+            // local entry offsets of the batch's rows
+            const int rc = lane < nb ? a.row_count[a0 + lane] : 0;
+            const int inc = wave_incl_scan(rc);
+            if (lane < nb) eoff[lane + 1] = inc;
+            if (lane == 0) eoff[0] = 0;
+        }
         __syncthreads();
         const int e_begin = eoff[0], e_end = eoff[nb];
+        int npacked = 0;   // kept entries of the batch so far (records beyond an atom's cap excluded)
         for (int eb = e_begin; eb < e_end; eb += kWave * kChunks) {
-            int jv[kChunks], rv[kChunks], tv[kChunks];
+            int jv[kChunks], rvv[kChunks], tv[kChunks];
             double xv[kChunks], yv[kChunks], zv[kChunks];
+            int ev[kChunks], alv[kChunks];
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
                 const int e = eb + c * kWave + lane;
-                int2 q = e < e_end ? a.jr[e] : make_int2(-1, 0);
-                jv[c] = q.x;
-                rv[c] = q.y;
+                jv[c] = -1;
+                rvv[c] = 0;
+                alv[c] = 0;
+                ev[c] = 0;
+                if (e < e_end) {
+                    const int al = find_seg(eoff, nb, e);
+                    alv[c] = al;
+                    ev[c] = (a0 + al) * a.cap + (e - eoff[al]);   // row-buffer address of the entry
+                    jv[c] = a.jn[ev[c]];
+                    rvv[c] = a.rv[ev[c]];
+                }
             }
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
@@ -251,7 +269,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 int al = 0;
                 double dx = 0, dy = 0, dz = 0, rsq = 0;
                 if (e < e_end) {
-                    al = find_seg(eoff, nb, e);
+                    al = alv[c];
                     dx = image(xv[c] - xi[al], a.L[0], a.invL[0]);
                     dy = image(yv[c] - yi[al], a.L[1], a.invL[1]);
                     dz = image(zv[c] - zi[al], a.L[2], a.invL[2]);
@@ -265,14 +283,15 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 const unsigned long long below = (lane ? (~0ull >> (64 - lane)) : 0ull);
                 const unsigned long long from = first ? ~(~0ull >> (64 - first)) : ~0ull;
                 const int k = cnt[al] + __popcll(m & below & from);
-                if (e < e_end) a.slotpos[e] = acc ? (k < kRecCap ? k : -2) : -1;
+                const unsigned long long mrec = __ballot(acc && k < kRecCap);
+                if (e < e_end) a.slotpos[ev[c]] = (signed char)(acc ? (k < kRecCap ? k : -2) : -1);
                 if (acc) {
                     if (k < kRecCap) {
-                        Rec<real> o;
                         const real r = M<real>::sqrt((real)rsq);
                         const real ri = M<real>::rcp(r);
+                        Rec<real> o;
                         o.j = jv[c];
-                        o.rev = rv[c];
+                        o.rev = rvv[c];
                         int mask = tv[c];
                         if (ONE) {
                             mask |= (1 << kPairBit) | (1 << kThirdBit);
@@ -284,13 +303,15 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                         }
                         o.mask = mask;
                         o.r = r;
-                        o.rinv = ri;
                         o.ux = (real)dx * ri;
                         o.uy = (real)dy * ri;
                         o.uz = (real)dz * ri;
-                        recs[(size_t)(a0 + al) * kRecCap + k] = o;
+                        if constexpr (sizeof(real) == 4) o.pad = 0.f; else o.pad = 0;
+                        // batch order: slot = kept entries of the batch before this one
+                        recs[(size_t)a0 * kRecCap + npacked + lanes_below(mrec)] = o;
                     }
                 }
+                npacked += __popcll(mrec);
                 __syncthreads();
                 if (acc) atomicMax(&cnt[al], k + 1);
                 __syncthreads();
@@ -300,14 +321,13 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
             const int i = a0 + lane;
             int c = cnt[lane];
             if (c > kRecCap) {
-                // more kept neighbours than a record row holds: the atom's
-                // terms are dropped (reported); k_fixup_dropped zeroes the
-                // force slots its neighbours reserved for it
+                // more kept neighbours than its records hold: the atom is
+                // evaluated with its first kRecCap neighbours only and the
+                // result is reported invalid; k_fixup_dropped zeroes the force
+                // slots its neighbours reserved for it
                 atomicOr(a.flags, kFlagOverflow);
                 a.drop_list[atomicAdd(a.drop_count, 1)] = i;
-                double *o = a.own + 3 * (size_t)i;
-                o[0] = o[1] = o[2] = 0.0;
-                c = 0;
+                c = kRecCap;
             }
             a.pcount[i] = c;
         }
@@ -388,7 +408,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
     __shared__ Shared<real> sh;
     const int lane = threadIdx.x;
     const ParamR<real> *ptab = table_r<real>(tab);
-    const Rec<real> *recs = reinterpret_cast<const Rec<real> *>(a.recs);
+    const Rec<real> *recs = static_cast<const Rec<real> *>(a.recs);
     const int nt = ONE ? 1 : tab.ntypes;
 
     double e_acc = 0.0;
@@ -401,6 +421,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
     for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
         int a0 = grp * B;
         const int a_end = min(a0 + B, a.n);
+        const Rec<real> *region = recs + (size_t)a0 * kRecCap;   // this batch's records, in order
         while (a0 < a_end) {
             const int nb = a_end - a0;
             // ---- batch: the leading atoms whose slots fit one per lane
@@ -431,15 +452,16 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 jl = s - sb;
                 pc = sh.pcnt[al];
                 ti = ONE ? 0 : sh.ti[al];
-                const Rec<real> rc = recs[(size_t)(a0 + al) * kRecCap + jl];
+                const Rec<real> rc = region[s];
                 j = rc.j;
                 kpos = a.slotpos[rc.rev];
                 mj = rc.mask;
-                rj = rc.r; rjinv = rc.rinv;
+                rj = rc.r;
                 uj[0] = rc.ux; uj[1] = rc.uy; uj[2] = rc.uz;
-                sh.ux[s] = rc.ux; sh.uy[s] = rc.uy; sh.uz[s] = rc.uz;
-                sh.r[s] = rc.r; sh.rinv[s] = rc.rinv;
-                sh.mask[s] = rc.mask;
+                rjinv = M<real>::rcp(rj);
+                sh.ux[s] = uj[0]; sh.uy[s] = uj[1]; sh.uz[s] = uj[2];
+                sh.r[s] = rj; sh.rinv[s] = rjinv;
+                sh.mask[s] = mj;
             }
             __syncthreads();
 
@@ -563,6 +585,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             }
             __syncthreads();
             a0 += cut;
+            region += npacked;
         }
     }
 
@@ -590,19 +613,20 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
 // never run as centres; zero the force slots their neighbours reserved for
 // them so the gather adds nothing stale.  Workgroups loop until the list is
 // drained.
-__global__ void k_fixup_dropped(const int *__restrict__ offsets, const int2 *__restrict__ jr,
-                                const int *__restrict__ slotpos, const int *__restrict__ drop_list,
-                                const int *__restrict__ drop_count, int n, double *__restrict__ planes)
+__global__ void k_fixup_dropped(const int *__restrict__ row_count, const int *__restrict__ jn,
+                                const int *__restrict__ rv, int cap, const signed char *__restrict__ slotpos,
+                                const int *__restrict__ drop_list, const int *__restrict__ drop_count,
+                                int n, double *__restrict__ planes)
 {
     const int nd = *drop_count;
     for (int q = blockIdx.x; q < nd; q += gridDim.x) {
         const int m = drop_list[q];
-        for (int e = offsets[m] + (int)threadIdx.x; e < offsets[m + 1]; e += blockDim.x) {
+        const int e0 = m * cap, e1 = m * cap + row_count[m];
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
             if (slotpos[e] == -1) continue;            // m did not keep this neighbour
-            const int2 q2 = jr[e];
-            const int k = slotpos[q2.y];               // rank of m in the neighbour's row
+            const int k = slotpos[rv[e]];              // rank of m in the neighbour's row
             if (k >= 0) {
-                double *f = planes + 3 * ((size_t)k * n + (size_t)q2.x);
+                double *f = planes + 3 * ((size_t)k * n + (size_t)jn[e]);
                 f[0] = f[1] = f[2] = 0.0;
             }
         }
@@ -685,7 +709,8 @@ int occupancy_grid(const void *kern, long long work_items)
 template <typename real, bool ONE>
 void grids_for(int n, int atoms_per_batch, int grids[3])
 {
-    grids[0] = occupancy_grid<real, ONE>((const void *)k_pack<real, ONE>, (n + kPackB - 1) / kPackB);
+    grids[0] = occupancy_grid<real, ONE>((const void *)k_pack<real, ONE>,
+                                         ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
     grids[1] = occupancy_grid<real, ONE>((const void *)k_tersoff<real, ONE>,
                                          ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
     grids[2] = kBigGrid;
@@ -734,11 +759,11 @@ hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mix
     return hipGetLastError();
 }
 
-hipError_t launch_fixup_dropped(const int *offsets, const int2 *jr, const int *slotpos,
-                                const int *drop_list, const int *drop_count, int n, double *planes,
-                                hipStream_t s)
+hipError_t launch_fixup_dropped(const int *row_count, const int *jn, const int *rv, int cap,
+                                const signed char *slotpos, const int *drop_list, const int *drop_count,
+                                int n, double *planes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fixup_dropped, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jr, slotpos,
+    hipLaunchKernelGGL(k_fixup_dropped, dim3(kBigGrid), dim3(kWave), 0, s, row_count, jn, rv, cap, slotpos,
                        drop_list, drop_count, n, planes);
     return hipGetLastError();
 }

@@ -60,26 +60,29 @@ constexpr int kBigGrid = 64;  // workgroups of the dropped-atom fixup kernel
 struct PackLaunch {
     const double *pos;          // n x 3
     const int *types;           // n
-    const int *offsets;         // n + 1 (CSR, int32, internal row order)
-    const int2 *jr;             // S: (neighbour j, entry of i in row j)
+    const int *row_count;       // n: list length of each atom
+    const int *jn;              // n x cap: sorted neighbour rows (row i at i * cap)
+    const int *rv;              // n x cap: entry of (j, i) for entry (i, j)
+    int cap;
     int n;
     double L[3], invL[3];
-    void *recs;                 // n x kRecCap packed records
+    void *recs;                 // packed records: region of B * kRecCap per batch of B atoms
     int *pcount;                // n: records per atom
-    int *slotpos;               // S: rank among the row's kept entries, -1 not kept, -2 beyond cap
+    signed char *slotpos;       // n x cap: rank among the row's kept entries, -1 not kept, -2 beyond kRecCap
     double *own;                // n x 3 (zeroed for dropped atoms only)
     int *flags;
     int *drop_list;             // n: atoms with more kept neighbours than kRecCap
     int *drop_count;            // reset to 0 here
     const double *pos_build;    // n x 3 positions of the last build (stale check)
     double stale_sq;            // (skin / 2)^2
+    int atoms_per_batch;        // B: centre atoms per batch (<= kWave), shared with the compute kernel
 };
 
 struct ComputeLaunch {
     const int *types;           // n
-    const void *recs;           // n x kRecCap packed records
+    const void *recs;           // packed records (batch regions)
     const int *pcount;          // n
-    const int *slotpos;         // S
+    const signed char *slotpos; // n x cap
     int n;
     double *own;                // n x 3: force from the terms of each centre atom
     double *planes;             // kRecCap x n x 3: plane k of atom j = force from its k-th kept neighbour's terms
@@ -95,9 +98,9 @@ size_t record_bytes(bool mixed);
 hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s);
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mixed,
                           int grid, hipStream_t s);
-hipError_t launch_fixup_dropped(const int *offsets, const int2 *jr, const int *slotpos,
-                                const int *drop_list, const int *drop_count, int n, double *planes,
-                                hipStream_t s);
+hipError_t launch_fixup_dropped(const int *row_count, const int *jn, const int *rv, int cap,
+                                const signed char *slotpos, const int *drop_list, const int *drop_count,
+                                int n, double *planes, hipStream_t s);
 hipError_t launch_finalize(const double *partials, const long long *counters, int grid,
                            double *out7, long long *counts_out, hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
@@ -108,25 +111,24 @@ hipError_t launch_gather_forces(const int *pcount, const double *planes, const d
 struct CellGrid {
     int nc[3];
     double L[3];
+    double invL[3];
     double cell_w[3];
+    float Lf[3], invLf[3];   // single-precision copies for the conservative pre-test
+    float Lsum;              // Lf[0] + Lf[1] + Lf[2]
 };
-hipError_t launch_bin_atoms(const double *pos, int n, const CellGrid &g, int *cell_of,
-                            int *rank_in_cell, int *cell_count, hipStream_t s);
+hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,
+                            int *cell_of, int *rank_in_cell, int *cell_count, int *flags, hipStream_t s);
 hipError_t launch_scatter_cells(const double *pos, int n, const int *cell_of,
                                 const int *rank_in_cell, const int *cell_start,
                                 int *cell_atoms, double *cell_pos, hipStream_t s);
-hipError_t launch_search(const double *pos, int n, const CellGrid &g, double rcut,
-                         const int *cell_of, const int *cell_start, const int *cell_count,
-                         const int *cell_atoms, const double *cell_pos, int cap, int *ell,
-                         float *ell_r2, int *row_count, hipStream_t s);
-hipError_t launch_sort_rows(const int *ell, const float *ell_r2, int cap, const int *row_count,
-                            const int *offsets, int n, int *idx, int2 *jr, int *perm, hipStream_t s);
-// jr[e].y for internal entry e = (i, j): the internal entry of (j, i) (the
+hipError_t launch_search(const CellGrid &g, double rcut, const int *cell_start, const int *cell_count,
+                         const int *cell_atoms, const double *cell_pos, int ncell, int cap, int *ell,
+                         int *row_count, hipStream_t s);
+// rv[e] for entry e = (i, j) = i * cap + q: the entry of i in row j (the
 // list is symmetric).  Sets *flags |= 4 if some reverse entry is missing.
-hipError_t launch_reverse_map(const int *offsets, const int *idx, const int *perm, int n, int2 *jr,
-                              int *flags, hipStream_t s);
-hipError_t launch_check_inputs(const double *pos, const int *types, int n, int ntypes,
-                               int *flags, hipStream_t s);
+hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, int n, int *rv, int *flags,
+                              hipStream_t s);
+constexpr int kMaxRow = 256;    // longest neighbour row the build supports
 
 // Exclusive scan of n int32 values; out[n] receives the total.  tmp must hold
 // scan_tmp_size(n) ints.  Also writes the maximum input to *max_out when

@@ -6,13 +6,15 @@
 // with FP contraction disabled, so the lists are bit-identical to any other
 // implementation of that predicate.
 //
-// Steps: input check -> bin atoms to cells (count + rank per cell) ->
+// Steps: bin atoms to cells (count + rank per cell, input checks) ->
 // exclusive scan of cell counts -> scatter atom ids and positions into cell
-// order -> one thread per atom scans the unique neighbouring cells into a
-// fixed-capacity row buffer -> scan of row counts (CSR offsets) -> each row is
-// rank-sorted by 16 lanes into its CSR slot (public order by j, internal
-// order nearest-first) -> reverse-entry map of the internal order.
+// order -> one wavefront per supercell (a few cells along the last axis)
+// tests the atoms of the surrounding cells and writes each of its atoms' rows,
+// sorted, to the row buffer (row i at i * cap, cap >= the longest row) ->
+// scan of row counts (list length, longest row) -> reverse-entry map.
 #include "internal.h"
+
+#include <algorithm>
 
 #pragma clang fp contract(off)
 
@@ -27,25 +29,21 @@ __device__ inline int cell_index(double x, double L, double w, int nc)
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
-__global__ void k_check_inputs(const double *__restrict__ pos, const int *__restrict__ types,
-                               int n, int ntypes, int *flags)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int f = 0;
-    for (int a = 0; a < 3; ++a)
-        if (!isfinite(pos[3 * (size_t)i + a])) f |= 1;
-    int t = types[i];
-    if (t < 0 || t >= ntypes) f |= 2;
-    if (f) atomicOr(flags, f);
-}
-
-__global__ void k_bin(const double *__restrict__ pos, int n, CellGrid g, int *__restrict__ cell_of,
-                      int *__restrict__ rank, int *__restrict__ count)
+// Cell of every atom (positions wrapped into the box for binning only) and
+// its rank within the cell; non-finite positions raise flag 1 and types
+// outside [0, ntypes) flag 2.
+__global__ void k_bin(const double *__restrict__ pos, const int *__restrict__ types, int n, int ntypes,
+                      CellGrid g, int *__restrict__ cell_of, int *__restrict__ rank,
+                      int *__restrict__ count, int *flags)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double *p = pos + 3 * (size_t)i;
+    int f = 0;
+    if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) f |= 1;
+    const int t = types[i];
+    if (t < 0 || t >= ntypes) f |= 2;
+    if (f) atomicOr(flags, f);
     int cx = cell_index(p[0], g.L[0], g.cell_w[0], g.nc[0]);
     int cy = cell_index(p[1], g.L[1], g.cell_w[1], g.nc[1]);
     int cz = cell_index(p[2], g.L[2], g.cell_w[2], g.nc[2]);
@@ -67,119 +65,300 @@ __global__ void k_scatter(const double *__restrict__ pos, int n, const int *__re
     cell_pos[3 * (size_t)slot + 2] = pos[3 * (size_t)i + 2];
 }
 
-__device__ inline double image_component(double xj, double xi, double L)
+// s = rint(t / L) evaluated as rint(t * (1/L)) whenever that is provably the
+// same integer: t * (1/L) is within a few ulps of t / L, so the two round
+// alike unless the quotient lies within ~1e-12 (relative) of a half-integer;
+// only then is the IEEE division taken.
+__device__ inline double image_component(double xj, double xi, double L, double invL)
 {
-    double t = xj - xi;
-    double s = rint(t / L);
+    const double t = xj - xi;
+    const double q = t * invL;
+    const double fq = q - floor(q);
+    double s;
+    if (fabs(fq - 0.5) > 1e-12 * fmax(1.0, fabs(q))) s = rint(q);
+    else s = rint(t / L);
     return fma(-s, L, t);
 }
 
-__global__ void k_search(const double *__restrict__ pos, int n, CellGrid g, double rc2,
-                         const int *__restrict__ cell_of, const int *__restrict__ cell_start,
-                         const int *__restrict__ cell_count, const int *__restrict__ cell_atoms,
-                         const double *__restrict__ cpos, int cap, int *__restrict__ ell,
-                         float *__restrict__ ell_r2, int *__restrict__ row_count)
+// Conservative single-precision pre-test: false only if the pair is surely
+// outside the list radius.  With t = x_j - x_i in FP64 and u = 2^-24, the
+// single-precision minimum image differs from the exact one by at most
+// u (2|t| + L + |d|) per axis (or lands on the other image, which for a pair
+// within range can only happen when both images lie at L/2 ~ rcs), so
+// widening the radius by 2.5e-7 (2 sum|t| + sum L) + 1e-5 never rejects a
+// neighbour; survivors get the exact FP64 test.
+__device__ inline bool may_be_neighbour(double xj, double yj, double zj, double xi, double yi, double zi,
+                                        const CellGrid &g, float rcs)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double xi = pos[3 * (size_t)i], yi = pos[3 * (size_t)i + 1], zi = pos[3 * (size_t)i + 2];
-    int c = cell_of[i];
-    int c2 = c % g.nc[2];
-    int c1 = (c / g.nc[2]) % g.nc[1];
-    int c0 = c / (g.nc[2] * g.nc[1]);
-    // unique neighbouring cells per axis: {-1,0,1} when nc >= 3, {0,1} when 2, {0} when 1
-    int lo0 = g.nc[0] >= 3 ? -1 : 0, hi0 = g.nc[0] >= 3 ? 1 : g.nc[0] - 1;
-    int lo1 = g.nc[1] >= 3 ? -1 : 0, hi1 = g.nc[1] >= 3 ? 1 : g.nc[1] - 1;
-    int lo2 = g.nc[2] >= 3 ? -1 : 0, hi2 = g.nc[2] >= 3 ? 1 : g.nc[2] - 1;
-    int cnt = 0;
-    int *row = ell + (size_t)i * cap;
-    float *row_r2 = ell_r2 + (size_t)i * cap;
-    for (int o0 = lo0; o0 <= hi0; ++o0) {
-        int x = c0 + o0; x += (x < 0) ? g.nc[0] : 0; x -= (x >= g.nc[0]) ? g.nc[0] : 0;
-        for (int o1 = lo1; o1 <= hi1; ++o1) {
-            int y = c1 + o1; y += (y < 0) ? g.nc[1] : 0; y -= (y >= g.nc[1]) ? g.nc[1] : 0;
-            for (int o2 = lo2; o2 <= hi2; ++o2) {
-                int z = c2 + o2; z += (z < 0) ? g.nc[2] : 0; z -= (z >= g.nc[2]) ? g.nc[2] : 0;
-                int cc = (x * g.nc[1] + y) * g.nc[2] + z;
-                int s0 = cell_start[cc], s1 = s0 + cell_count[cc];
-                for (int s = s0; s < s1; ++s) {
-                    int j = cell_atoms[s];
-                    if (j == i) continue;
-                    double dx = image_component(cpos[3 * (size_t)s + 0], xi, g.L[0]);
-                    double dy = image_component(cpos[3 * (size_t)s + 1], yi, g.L[1]);
-                    double dz = image_component(cpos[3 * (size_t)s + 2], zi, g.L[2]);
-                    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                    if (r2 < rc2) {
-                        if (cnt < cap) {
-                            row[cnt] = j;
-                            row_r2[cnt] = (float)r2;
-                        }
-                        ++cnt;
-                    }
+    const float a0 = (float)(xj - xi), a1 = (float)(yj - yi), a2 = (float)(zj - zi);
+    const float d0 = fmaf(-rintf(a0 * g.invLf[0]), g.Lf[0], a0);
+    const float d1 = fmaf(-rintf(a1 * g.invLf[1]), g.Lf[1], a1);
+    const float d2 = fmaf(-rintf(a2 * g.invLf[2]), g.Lf[2], a2);
+    const float r2 = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+    const float delta = 2.5e-7f * (2.f * (fabsf(a0) + fabsf(a1) + fabsf(a2)) + g.Lsum) + 1e-5f;
+    const float lim = rcs + delta;
+    return r2 < lim * lim;
+}
+
+__device__ inline bool in_range(double xj, double yj, double zj, double xi, double yi, double zi,
+                                const CellGrid &g, double rc2)
+{
+    const double dx = image_component(xj, xi, g.L[0], g.invL[0]);
+    const double dy = image_component(yj, yi, g.L[1], g.invL[1]);
+    const double dz = image_component(zj, zi, g.L[2], g.invL[2]);
+    return fma(dz, dz, fma(dy, dy, dx * dx)) < rc2;
+}
+
+// One wavefront per supercell: kSuper consecutive cells along the last axis.
+// The atoms of the unique cells around it (3 x 3 x (kSuper + 2) cells, or
+// fewer on small grids) are staged in LDS.  Fast path: the lanes run over
+// all (atom of the supercell, candidate) pairs, a single-precision pre-test
+// keeps the possible neighbours, the exact FP64 predicate decides them, the
+// accepted pairs are packed in order (ballot + prefix count), and every row
+// is rank-sorted by j and written to the fixed-capacity row buffer.
+// Supercells with too many candidates or pairs take the general path: one
+// atom at a time, candidates in chunks.
+constexpr int kSuper = 4;
+constexpr int kCandCap = 256;
+constexpr int kRowCap = kMaxRow;
+constexpr int kSurvCap = 512;
+constexpr int kCellAtomCap = 64;
+constexpr int kMaxStencil = 3 * 3 * (kSuper + 2);
+
+__global__ __launch_bounds__(64) void k_search_cells(CellGrid g, double rc2, const int *__restrict__ cell_start,
+                                                     const int *__restrict__ cell_count,
+                                                     const int *__restrict__ cell_atoms,
+                                                     const double *__restrict__ cpos, int nsuper, int cap,
+                                                     int *__restrict__ ell, int *__restrict__ row_count)
+{
+    __shared__ int cj[kCandCap];
+    __shared__ double cx[kCandCap], cy[kCandCap], cz[kCandCap];
+    __shared__ int row[kRowCap];
+    __shared__ int surv[kSurvCap];
+    __shared__ int pa[kSurvCap], pj[kSurvCap];
+    __shared__ int rowcnt[kCellAtomCap], rowst[kCellAtomCap];
+    __shared__ int pre[kMaxStencil + 1], st[kMaxStencil];
+    const int lane = threadIdx.x;
+    const int nsz = (g.nc[2] + kSuper - 1) / kSuper;          // supercells per column
+    const int n0 = g.nc[0] >= 3 ? 3 : g.nc[0];
+    const int n1 = g.nc[1] >= 3 ? 3 : g.nc[1];
+    const bool zall = g.nc[2] < kSuper + 2;                    // small grid: every z cell once
+    const int n2 = zall ? g.nc[2] : kSuper + 2;
+    const int nq = n0 * n1 * n2;
+    const float rcs = (float)sqrt(rc2);
+    for (int sc = blockIdx.x; sc < nsuper; sc += gridDim.x) {
+        const int col = sc / nsz;                              // (x, y) column
+        const int z0 = (sc - col * nsz) * kSuper;
+        const int kz = min(kSuper, g.nc[2] - z0);
+        const int cx0 = col / g.nc[1], cy0 = col % g.nc[1];
+        const int c_first = (cx0 * g.nc[1] + cy0) * g.nc[2] + z0;
+        // stencil cells: x, y offsets {-1,0,1} (or all cells when nc < 3), z from z0-1 to z0+kSuper
+        int cntq = 0, stq = 0;
+        if (lane < nq) {
+            const int q0 = lane / (n1 * n2), q1 = (lane / n2) % n1, q2 = lane % n2;
+            int x = cx0 + (n0 == 3 ? q0 - 1 : q0 - cx0);
+            int y = cy0 + (n1 == 3 ? q1 - 1 : q1 - cy0);
+            int z = zall ? q2 : z0 - 1 + q2;
+            x += x < 0 ? g.nc[0] : 0; x -= x >= g.nc[0] ? g.nc[0] : 0;
+            y += y < 0 ? g.nc[1] : 0; y -= y >= g.nc[1] ? g.nc[1] : 0;
+            z += z < 0 ? g.nc[2] : 0; z -= z >= g.nc[2] ? g.nc[2] : 0;
+            const int cc = (x * g.nc[1] + y) * g.nc[2] + z;
+            stq = cell_start[cc];
+            cntq = cell_count[cc];
+        }
+        const int cs = cell_start[c_first];
+        const int A = cell_start[c_first + kz - 1] + cell_count[c_first + kz - 1] - cs;
+        int incl = cntq;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int u = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += u;
+        }
+        if (A == 0) continue;
+        const int T = __shfl(incl, nq - 1, 64);
+        if (lane < nq) {
+            pre[lane] = incl - cntq;
+            st[lane] = stq;
+        }
+        if (lane == 0) pre[nq] = T;
+        __syncthreads();
+        // staged position of the supercell's first atom: stencil cell (centre x, centre y, z0)
+        const int qf = (n0 == 3 ? 1 : cx0) * n1 * n2 + (n1 == 3 ? 1 : cy0) * n2 + (zall ? z0 : 1);
+        auto stage = [&](int t0, int tn) {
+            for (int tt = lane; tt < tn; tt += 64) {
+                const int t = t0 + tt;
+                int lo = 0, hi = nq - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= t) lo = mid; else hi = mid - 1;
+                }
+                const int sidx = st[lo] + (t - pre[lo]);
+                cj[tt] = cell_atoms[sidx];
+                cx[tt] = cpos[3 * (size_t)sidx];
+                cy[tt] = cpos[3 * (size_t)sidx + 1];
+                cz[tt] = cpos[3 * (size_t)sidx + 2];
+            }
+        };
+        const bool one_chunk = T <= kCandCap;
+        if (one_chunk) stage(0, T);
+        __syncthreads();
+
+        bool fast = one_chunk && A <= kCellAtomCap;
+        int nsurv = 0;
+        const unsigned magic = 0xFFFFFFFFu / (unsigned)max(T, 1) + 1u;   // f / T = umulhi(f, magic), f, T < 2^16
+        const int ic0 = pre[qf];
+        if (fast) {
+            // pass 1: single-precision pre-test over all (atom, candidate) pairs
+            const int AT = A * T;
+            for (int base = 0; base < AT; base += 64) {
+                const int f = base + lane;
+                bool keep = false;
+                if (f < AT) {
+                    const int ia = (int)__umulhi((unsigned)f, magic);
+                    const int t = f - ia * T;
+                    const int ti = ic0 + ia;
+                    if (t != ti)
+                        keep = may_be_neighbour(cx[t], cy[t], cz[t], cx[ti], cy[ti], cz[ti], g, rcs);
+                }
+                const unsigned long long m = __ballot(keep);
+                const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                if (keep && nsurv + below < kSurvCap) surv[nsurv + below] = f;
+                nsurv += __popcll(m);
+            }
+            fast = nsurv <= kSurvCap;
+        }
+        if (fast) {
+            __syncthreads();
+            // pass 2: exact predicate on the survivors, accepted pairs kept in order
+            int nacc = 0;
+            for (int base = 0; base < nsurv; base += 64) {
+                const int k = base + lane;
+                bool acc = false;
+                int ia = 0, t = 0;
+                if (k < nsurv) {
+                    const int f = surv[k];
+                    ia = (int)__umulhi((unsigned)f, magic);
+                    t = f - ia * T;
+                    const int ti = ic0 + ia;
+                    acc = in_range(cx[t], cy[t], cz[t], cx[ti], cy[ti], cz[ti], g, rc2);
+                }
+                const unsigned long long m = __ballot(acc);
+                const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                if (acc) {
+                    pa[nacc + below] = ia;
+                    pj[nacc + below] = cj[t];
+                }
+                nacc += __popcll(m);
+            }
+            if (lane < A) rowcnt[lane] = 0;
+            __syncthreads();
+            for (int k = lane; k < nacc; k += 64) atomicAdd(&rowcnt[pa[k]], 1);
+            __syncthreads();
+            {
+                const int v = lane < A ? rowcnt[lane] : 0;
+                int inc = v;
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    int u = __shfl_up(inc, off, 64);
+                    if (lane >= off) inc += u;
+                }
+                if (lane < A) rowst[lane] = inc - v;
+            }
+            __syncthreads();
+            for (int k = lane; k < nacc; k += 64) {
+                const int ia = pa[k], v = pj[k];
+                const int r0 = rowst[ia], rn = rowcnt[ia];
+                if (rn <= cap) {
+                    int rk = 0;
+                    for (int q = 0; q < rn; ++q) rk += pj[r0 + q] < v;
+                    ell[(size_t)cj[ic0 + ia] * cap + rk] = v;
                 }
             }
+            if (lane < A) row_count[cj[ic0 + lane]] = rowcnt[lane];
+            __syncthreads();
+            continue;
+        }
+
+        // general path: one atom at a time, candidates in chunks
+        for (int ia = 0; ia < A; ++ia) {
+            const int si = cs + ia;
+            const int i = cell_atoms[si];
+            const double xi = cpos[3 * (size_t)si], yi = cpos[3 * (size_t)si + 1], zi = cpos[3 * (size_t)si + 2];
+            int cnt = 0;
+            for (int t0 = 0; t0 < T; t0 += kCandCap) {
+                const int tn = min(kCandCap, T - t0);
+                if (!one_chunk) {
+                    __syncthreads();
+                    stage(t0, tn);
+                    __syncthreads();
+                }
+                for (int tb = 0; tb < tn; tb += 64) {
+                    const int tt = tb + lane;
+                    bool acc = false;
+                    int j = 0;
+                    if (tt < tn) {
+                        j = cj[tt];
+                        if (j != i) acc = in_range(cx[tt], cy[tt], cz[tt], xi, yi, zi, g, rc2);
+                    }
+                    const unsigned long long m = __ballot(acc);
+                    const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                    if (acc && cnt + below < kRowCap) row[cnt + below] = j;
+                    cnt += __popcll(m);
+                }
+            }
+            __syncthreads();
+            if (cnt <= cap && cnt <= kRowCap) {
+                int *out = ell + (size_t)i * cap;
+                for (int e = lane; e < cnt; e += 64) {
+                    const int v = row[e];
+                    int rk = 0;
+                    for (int q = 0; q < cnt; ++q) rk += row[q] < v;
+                    out[rk] = v;
+                }
+            }
+            if (lane == 0) row_count[i] = cnt;
+            __syncthreads();
         }
     }
-    row_count[i] = cnt;
 }
 
-// 16 lanes per row: each lane takes elements lane, lane+16, ... and places
-// each by its rank within the row (row entries are distinct atom ids), twice:
-// by j for the public list, and nearest-first (r^2 at build, ties by j) for
-// the internal order the compute kernels walk; perm maps a public position
-// to the internal position of the same entry.
-__global__ void k_sort_rows(const int *__restrict__ ell, const float *__restrict__ ell_r2, int cap,
-                            const int *__restrict__ row_count, const int *__restrict__ offsets, int n,
-                            int *__restrict__ idx, int2 *__restrict__ jr, int *__restrict__ perm)
+// rv[e] for entry e = (i, j) = i * cap + q of the row buffer: the entry of i
+// in the sorted row of j.  One thread per (i, q); row j is read in 16-entry
+// pieces of four 16-byte loads issued together.  The inclusion predicate is
+// symmetric (negating t negates s and d exactly), so the entry exists; a
+// missing one raises flag 4.
+__global__ void k_reverse_map(const int *__restrict__ ell, int cap, const int *__restrict__ row_count, int n,
+                              int *__restrict__ rv, int *flags)
 {
-    int r = blockIdx.x * (blockDim.x / 16) + threadIdx.x / 16;
-    int l = threadIdx.x % 16;
-    if (r >= n) return;
-    int cnt = row_count[r];
-    if (cnt > cap) return;   // never launched in this state (the build retries first)
-    const int *row = ell + (size_t)r * cap;
-    const float *row_r2 = ell_r2 + (size_t)r * cap;
-    int base = offsets[r];
-    for (int e = l; e < cnt; e += 16) {
-        const int v = row[e];
-        const float d = row_r2[e];
-        int rank_j = 0, rank_d = 0;
-        for (int m = 0; m < cnt; ++m) {
-            const int w = row[m];
-            const float dm = row_r2[m];
-            rank_j += w < v;
-            rank_d += (dm < d) || (dm == d && w < v);
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(tid / cap);
+    const int q = (int)(tid - (long long)i * cap);
+    if (i >= n || q >= row_count[i]) return;
+    const int j = ell[(size_t)i * cap + q];
+    const int cj = row_count[j];
+    const int4 *row = reinterpret_cast<const int4 *>(ell + (size_t)j * cap);
+    int at = -1;
+    for (int b = 0; b < cj && at < 0; b += 16) {
+        int4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (b + 4 * u < cap) ? row[(b >> 2) + u] : make_int4(-1, -1, -1, -1);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = b + 4 * u;
+            if (k + 0 < cj && v[u].x == i) at = k + 0;
+            if (k + 1 < cj && v[u].y == i) at = k + 1;
+            if (k + 2 < cj && v[u].z == i) at = k + 2;
+            if (k + 3 < cj && v[u].w == i) at = k + 3;
         }
-        idx[base + rank_j] = v;
-        jr[base + rank_d] = make_int2(v, -1);
-        perm[base + rank_j] = base + rank_d;
     }
-}
-
-// jr[e].y for internal entry e = (i, j): the internal position of entry
-// (j, i), found by binary search of i in j's public (sorted) row and mapped
-// through perm.  The inclusion predicate is symmetric (negating t negates s
-// and d exactly), so the entry exists; a missing one raises flag 4.
-__global__ void k_reverse_map(const int *__restrict__ offsets, const int *__restrict__ idx,
-                              const int *__restrict__ perm, int n, int2 *__restrict__ jr, int *flags)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int e = offsets[i]; e < offsets[i + 1]; ++e) {
-        const int j = jr[e].x;
-        int lo = offsets[j], hi = offsets[j + 1] - 1, at = -1;
-        while (lo <= hi) {
-            int mid = (lo + hi) >> 1;
-            int v = idx[mid];
-            if (v == i) { at = mid; break; }
-            if (v < i) lo = mid + 1; else hi = mid - 1;
-        }
-        if (at < 0) {
-            atomicOr(flags, 4);
-            jr[e].y = e;
-        } else {
-            jr[e].y = perm[at];
-        }
+    if (at < 0) {
+        atomicOr(flags, 4);
+        rv[(size_t)i * cap + q] = (int)((size_t)i * cap + q);
+    } else {
+        rv[(size_t)i * cap + q] = (int)((size_t)j * cap + at);
     }
 }
 
@@ -297,27 +476,20 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int n, int *tmp, int *
     return hipGetLastError();
 }
 
-hipError_t launch_reverse_map(const int *offsets, const int *idx, const int *perm, int n, int2 *jr,
-                              int *flags, hipStream_t s)
+hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, int n, int *rv, int *flags,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reverse_map, dim3(blocks_for(n, 256)), dim3(256), 0, s, offsets, idx, perm, n,
-                       jr, flags);
+    const long long threads = (long long)n * cap;
+    hipLaunchKernelGGL(k_reverse_map, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, ell, cap,
+                       row_count, n, rv, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_check_inputs(const double *pos, const int *types, int n, int ntypes,
-                               int *flags, hipStream_t s)
+hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,
+                            int *cell_of, int *rank_in_cell, int *cell_count, int *flags, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_check_inputs, dim3(blocks_for(n, 256)), dim3(256), 0, s, pos, types, n,
-                       ntypes, flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_bin_atoms(const double *pos, int n, const CellGrid &g, int *cell_of,
-                            int *rank_in_cell, int *cell_count, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, pos, n, g, cell_of,
-                       rank_in_cell, cell_count);
+    hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, pos, types, n, ntypes, g, cell_of,
+                       rank_in_cell, cell_count, flags);
     return hipGetLastError();
 }
 
@@ -330,22 +502,20 @@ hipError_t launch_scatter_cells(const double *pos, int n, const int *cell_of,
     return hipGetLastError();
 }
 
-hipError_t launch_search(const double *pos, int n, const CellGrid &g, double rcut,
-                         const int *cell_of, const int *cell_start, const int *cell_count,
-                         const int *cell_atoms, const double *cell_pos, int cap, int *ell,
-                         float *ell_r2, int *row_count, hipStream_t s)
+hipError_t launch_search(const CellGrid &g, double rcut, const int *cell_start, const int *cell_count,
+                         const int *cell_atoms, const double *cell_pos, int ncell, int cap, int *ell,
+                         int *row_count, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_search, dim3(blocks_for(n, 128)), dim3(128), 0, s, pos, n, g,
-                       rcut * rcut, cell_of, cell_start, cell_count, cell_atoms, cell_pos, cap,
-                       ell, ell_r2, row_count);
-    return hipGetLastError();
-}
-
-hipError_t launch_sort_rows(const int *ell, const float *ell_r2, int cap, const int *row_count,
-                            const int *offsets, int n, int *idx, int2 *jr, int *perm, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_sort_rows, dim3(blocks_for(n, 16)), dim3(256), 0, s, ell, ell_r2, cap,
-                       row_count, offsets, n, idx, jr, perm);
+    (void)ncell;
+    const int nsuper = g.nc[0] * g.nc[1] * ((g.nc[2] + kSuper - 1) / kSuper);
+    int per_cu = 0, dev = 0, cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_search_cells, 64, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int grid = std::max(1, std::min(nsuper, per_cu * cus));
+    hipLaunchKernelGGL(k_search_cells, dim3(grid), dim3(64), 0, s, g, rcut * rcut, cell_start, cell_count,
+                       cell_atoms, cell_pos, nsuper, cap, ell, row_count);
     return hipGetLastError();
 }
 

@@ -61,9 +61,8 @@ struct tersoff_ctx {
     int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};   // [fp64, mixed] x {pack, compute, per-atom}
 
     DevBuf<double> pos_build;
-    DevBuf<int> types, offsets, idx, perm, pcount, drop_list, slotpos;
-    DevBuf<int2> jr;
-    DevBuf<float> ell_r2;
+    DevBuf<int> types, offsets, pcount, drop_list, rv;
+    DevBuf<signed char> slotpos;
     DevBuf<unsigned char> recs;
     DevBuf<double> own, planes;
     DevBuf<int> cell_of, rank, cell_count, cell_start, cell_atoms;
@@ -251,9 +250,9 @@ void tersoff_destroy(tersoff_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    c->pos_build.release(); c->types.release(); c->offsets.release(); c->idx.release();
-    c->jr.release(); c->slotpos.release(); c->own.release(); c->planes.release();
-    c->perm.release(); c->pcount.release(); c->drop_list.release(); c->ell_r2.release(); c->recs.release();
+    c->pos_build.release(); c->types.release(); c->offsets.release();
+    c->rv.release(); c->slotpos.release(); c->own.release(); c->planes.release();
+    c->pcount.release(); c->drop_list.release(); c->recs.release();
     c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
     c->cell_atoms.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
     c->scan_tmp.release(); c->misc.release(); c->partials.release(); c->force_scratch.release();
@@ -343,24 +342,20 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
         HIP_TRY(c, take_event(c, &evb1));
         HIP_TRY(c, hipEventRecord(evb0, s));
     }
-    HIP_TRY(c, c->misc.ensure(4));
-    HIP_TRY(c, hipMemsetAsync(c->misc.p, 0, 4 * sizeof(int), s));
-    HIP_TRY(c, launch_check_inputs(pos, types, N, c->ntypes, c->misc.p + 2, s));
-    int chk = 0;
-    HIP_TRY(c, hipMemcpyAsync(&chk, c->misc.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    if (chk & 1) return fail(c, TERSOFF_E_INVALID, "non-finite position");
-    if (chk & 2) return fail(c, TERSOFF_E_INVALID, "type out of range");
-
     CellGrid g{};
     long long ncell = 1;
     for (int a = 0; a < 3; ++a) {
         g.L[a] = box[a];
+        g.invL[a] = 1.0 / box[a];
+        g.Lf[a] = (float)box[a];
+        g.invLf[a] = (float)(1.0 / box[a]);
         g.nc[a] = std::max(1, (int)std::floor(box[a] / (rc * (1.0 + 1e-10))));
         g.nc[a] = std::min(g.nc[a], 1024);
         g.cell_w[a] = box[a] / g.nc[a];
         ncell *= g.nc[a];
     }
+    g.Lsum = g.Lf[0] + g.Lf[1] + g.Lf[2];
+    HIP_TRY(c, c->misc.ensure(4));
     HIP_TRY(c, c->cell_of.ensure(N));
     HIP_TRY(c, c->rank.ensure(N));
     HIP_TRY(c, c->cell_count.ensure(ncell));
@@ -375,39 +370,42 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, c->pos_build.ensure(3 * (size_t)N));
     HIP_TRY(c, c->types.ensure(N));
 
+    // misc: [0] compute flags, [1] longest row, [2] build flags, [3] dropped count
+    HIP_TRY(c, hipMemsetAsync(c->misc.p, 0, 4 * sizeof(int), s));
     HIP_TRY(c, hipMemsetAsync(c->cell_count.p, 0, sizeof(int) * ncell, s));
-    HIP_TRY(c, launch_bin_atoms(pos, N, g, c->cell_of.p, c->rank.p, c->cell_count.p, s));
+    HIP_TRY(c, launch_bin_atoms(pos, types, N, c->ntypes, g, c->cell_of.p, c->rank.p, c->cell_count.p,
+                                c->misc.p + 2, s));
     HIP_TRY(c, launch_exclusive_scan(c->cell_count.p, c->cell_start.p, (int)ncell, c->scan_tmp.p, nullptr, s));
     HIP_TRY(c, launch_scatter_cells(pos, N, c->cell_of.p, c->rank.p, c->cell_start.p,
                                     c->cell_atoms.p, c->cell_pos.p, s));
-    int host_tot[2] = {0, 0};
-    for (int attempt = 0; attempt < 4; ++attempt) {
+    int host[3] = {0, 0, 0};   // list length, longest row, build flags
+    for (int attempt = 0; attempt < 2; ++attempt) {
         HIP_TRY(c, c->ell.ensure((size_t)N * c->ell_cap));
-        HIP_TRY(c, c->ell_r2.ensure((size_t)N * c->ell_cap));
-        HIP_TRY(c, launch_search(pos, N, g, rc, c->cell_of.p, c->cell_start.p, c->cell_count.p,
-                                 c->cell_atoms.p, c->cell_pos.p, c->ell_cap, c->ell.p,
-                                 c->ell_r2.p, c->row_count.p, s));
+        HIP_TRY(c, launch_search(g, rc, c->cell_start.p, c->cell_count.p, c->cell_atoms.p, c->cell_pos.p,
+                                 (int)ncell, c->ell_cap, c->ell.p, c->row_count.p, s));
         HIP_TRY(c, launch_exclusive_scan(c->row_count.p, c->offsets.p, N, c->scan_tmp.p, c->misc.p + 1, s));
-        HIP_TRY(c, hipMemcpyAsync(&host_tot[0], c->offsets.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipMemcpyAsync(&host_tot[1], c->misc.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(&host[0], c->offsets.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(&host[1], c->misc.p + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
-        if (host_tot[1] <= c->ell_cap) break;
-        c->ell_cap = ((host_tot[1] + 15) / 16) * 16;   // retry with the needed capacity
-        if (attempt == 3) return fail(c, TERSOFF_E_OVERFLOW, "row capacity retry failed");
+        if (host[2] & 1) return fail(c, TERSOFF_E_INVALID, "non-finite position");
+        if (host[2] & 2) return fail(c, TERSOFF_E_INVALID, "type out of range");
+        if (host[1] <= c->ell_cap) break;
+        if (host[1] > kMaxRow) return fail(c, TERSOFF_E_OVERFLOW, "an atom has more than 256 neighbours in range");
+        c->ell_cap = ((host[1] + 15) / 16) * 16;   // retry once with the needed capacity
     }
-    if (host_tot[0] < 0) return fail(c, TERSOFF_E_INVALID, "list longer than 2^31 entries");
-    c->S = host_tot[0];
-    HIP_TRY(c, c->idx.ensure((size_t)std::max(c->S, 1LL)));
-    HIP_TRY(c, c->jr.ensure((size_t)std::max(c->S, 1LL)));
-    HIP_TRY(c, c->perm.ensure((size_t)std::max(c->S, 1LL)));
-    HIP_TRY(c, launch_sort_rows(c->ell.p, c->ell_r2.p, c->ell_cap, c->row_count.p, c->offsets.p, N,
-                                c->idx.p, c->jr.p, c->perm.p, s));
-    HIP_TRY(c, c->slotpos.ensure((size_t)std::max(c->S, 1LL)));
+    if (host[1] > c->ell_cap) return fail(c, TERSOFF_E_OVERFLOW, "row capacity retry failed");
+    if (host[0] < 0) return fail(c, TERSOFF_E_INVALID, "list longer than 2^31 entries");
+    c->S = host[0];
+    if ((long long)N * c->ell_cap >= (1LL << 31)) return fail(c, TERSOFF_E_INVALID, "n x row capacity >= 2^31");
+    const size_t NE = (size_t)N * c->ell_cap;
+    HIP_TRY(c, c->rv.ensure(NE));
+    HIP_TRY(c, c->slotpos.ensure(NE));
     HIP_TRY(c, c->own.ensure(3 * (size_t)N));
-    HIP_TRY(c, launch_reverse_map(c->offsets.p, c->idx.p, c->perm.p, N, c->jr.p, c->misc.p + 2, s));
-    HIP_TRY(c, hipMemcpyAsync(&chk, c->misc.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, launch_reverse_map(c->ell.p, c->ell_cap, c->row_count.p, N, c->rv.p, c->misc.p + 2, s));
     HIP_TRY(c, hipMemcpyAsync(c->pos_build.p, pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->types.p, types, sizeof(int) * (size_t)N, hipMemcpyDeviceToDevice, s));
+    int chk = 0;
+    HIP_TRY(c, hipMemcpyAsync(&chk, c->misc.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
     if (evb1) {
         HIP_TRY(c, hipEventRecord(evb1, s));
         c->ev_build.emplace_back(evb0, evb1);
@@ -447,14 +445,17 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
         HIP_TRY(c, c->force_scratch.ensure(3 * (size_t)c->n));
         f = c->force_scratch.p;
     }
-    HIP_TRY(c, c->recs.ensure(record_bytes(mixed) * kRecCap * (size_t)c->n));
+    const size_t nbat = ((size_t)c->n + c->atoms_per_batch - 1) / c->atoms_per_batch;
+    HIP_TRY(c, c->recs.ensure(record_bytes(mixed) * kRecCap * nbat * c->atoms_per_batch));
     HIP_TRY(c, c->planes.ensure(3 * (size_t)kRecCap * (size_t)c->n));
 
     PackLaunch pk{};
     pk.pos = pos;
     pk.types = c->types.p;
-    pk.offsets = c->offsets.p;
-    pk.jr = c->jr.p;
+    pk.row_count = c->row_count.p;
+    pk.jn = c->ell.p;
+    pk.rv = c->rv.p;
+    pk.cap = c->ell_cap;
     pk.n = c->n;
     for (int d = 0; d < 3; ++d) {
         pk.L[d] = c->box[d];
@@ -469,6 +470,7 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     pk.drop_count = c->misc.p + 3;
     pk.pos_build = c->pos_build.p;
     pk.stale_sq = 0.25 * c->skin * c->skin;
+    pk.atoms_per_batch = c->atoms_per_batch;
 
     ComputeLaunch a{};
     a.types = c->types.p;
@@ -493,8 +495,8 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     HIP_TRY(c, launch_compute(a, c->tab, mixed, grid[1], s));
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
-    HIP_TRY(c, launch_fixup_dropped(c->offsets.p, c->jr.p, c->slotpos.p, c->drop_list.p, c->misc.p + 3,
-                                    c->n, c->planes.p, s));
+    HIP_TRY(c, launch_fixup_dropped(c->row_count.p, c->ell.p, c->rv.p, c->ell_cap, c->slotpos.p,
+                                    c->drop_list.p, c->misc.p + 3, c->n, c->planes.p, s));
     HIP_TRY(c, launch_gather_forces(c->pcount.p, c->planes.p, c->own.p, c->n, f, s));
     if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
     HIP_TRY(c, launch_finalize(c->partials.p, c->counters.p, grid[1], energy_virial, c->counts.p, s));
@@ -528,12 +530,16 @@ int tersoff_get_neighbors(tersoff_ctx *c, int64_t *offsets, int32_t *idx, int64_
     if (!offsets || !total) return fail(c, TERSOFF_E_INVALID, "null pointer");
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipDeviceSynchronize());
-    std::vector<int> off((size_t)c->n + 1);
-    HIP_TRY(c, hipMemcpy(off.data(), c->offsets.p, sizeof(int) * off.size(), hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < off.size(); ++i) offsets[i] = off[i];
+    std::vector<int> cnt((size_t)c->n);
+    HIP_TRY(c, hipMemcpy(cnt.data(), c->row_count.p, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost));
+    offsets[0] = 0;
+    for (size_t i = 0; i < cnt.size(); ++i) offsets[i + 1] = offsets[i] + cnt[i];
     *total = c->S;
     if (cap < c->S || (!idx && c->S > 0)) return fail(c, TERSOFF_E_INVALID, "idx capacity below list length");
-    if (c->S > 0) HIP_TRY(c, hipMemcpy(idx, c->idx.p, sizeof(int) * (size_t)c->S, hipMemcpyDeviceToHost));
+    std::vector<int> rows((size_t)c->n * c->ell_cap);
+    HIP_TRY(c, hipMemcpy(rows.data(), c->ell.p, sizeof(int) * rows.size(), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < cnt.size(); ++i)
+        std::memcpy(idx + offsets[i], rows.data() + i * c->ell_cap, sizeof(int) * (size_t)cnt[i]);
     return TERSOFF_OK;
 }
 
