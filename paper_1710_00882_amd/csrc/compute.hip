@@ -93,6 +93,26 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Workgroups are dealt to the 8 XCDs of the chip round-robin (workgroup b on
+// XCD b mod 8), each XCD with its own L2.  Give every XCD a contiguous range
+// of work items so that neighbouring atoms -- which share position, record
+// and force cache lines -- are handled under the same L2.  Any other
+// placement only costs locality, never correctness.
+struct ItemRange {
+    int begin, end, stride;
+};
+
+__device__ __forceinline__ ItemRange xcd_items(int nitems)
+{
+    const int G = gridDim.x;
+    if (G < 8) return {(int)blockIdx.x, nitems, G};
+    const int x = blockIdx.x & 7, l = blockIdx.x >> 3;
+    const int gx = (G - x + 7) / 8;          // workgroups on this XCD
+    const int per = (nitems + 7) / 8;
+    const int b0 = x * per;
+    return {b0 + l, min(nitems, b0 + per), gx};
+}
+
 // ------------------------------------------------------------ parameters --
 
 template <typename real>
@@ -208,7 +228,8 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
     const int nbatch = (a.n + B - 1) / B;
     if (blockIdx.x == 0 && lane == 0) *a.drop_count = 0;
 
-    for (int bt = blockIdx.x; bt < nbatch; bt += gridDim.x) {
+    const ItemRange items = xcd_items(nbatch);
+    for (int bt = items.begin; bt < items.end; bt += items.stride) {
         const int a0 = bt * B;
         const int nb = min(B, a.n - a0);
         if (lane < nb) {
@@ -418,7 +439,8 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
     const int B = a.atoms_per_batch;
     const int ngroups = (a.n + B - 1) / B;
 
-    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const ItemRange items = xcd_items(ngroups);
+    for (int grp = items.begin; grp < items.end; grp += items.stride) {
         int a0 = grp * B;
         const int a_end = min(a0 + B, a.n);
         const Rec<real> *region = recs + (size_t)a0 * kRecCap;   // this batch's records, in order

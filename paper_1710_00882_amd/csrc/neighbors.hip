@@ -100,6 +100,19 @@ __device__ inline bool may_be_neighbour(double xj, double yj, double zj, double 
     return r2 < lim * lim;
 }
 
+// Pre-test on staged single-precision coordinates that already carry the
+// periodic image of their stencil cell (relative to the supercell origin):
+// for a pair within range that image is the minimum image, so the staged
+// difference equals the exact displacement up to a few float roundings of
+// coordinates within a few cells of the origin (< 1e-5 A); the radius is
+// widened by 1e-4 A.
+__device__ inline bool may_be_neighbour_shifted(float xj, float yj, float zj, float xi, float yi, float zi,
+                                                float lim2)
+{
+    const float d0 = xj - xi, d1 = yj - yi, d2 = zj - zi;
+    return fmaf(d2, d2, fmaf(d1, d1, d0 * d0)) < lim2;
+}
+
 __device__ inline bool in_range(double xj, double yj, double zj, double xi, double yi, double zi,
                                 const CellGrid &g, double rc2)
 {
@@ -133,11 +146,13 @@ __global__ __launch_bounds__(64) void k_search_cells(CellGrid g, double rc2, con
 {
     __shared__ int cj[kCandCap];
     __shared__ double cx[kCandCap], cy[kCandCap], cz[kCandCap];
+    __shared__ float fx[kCandCap], fy[kCandCap], fz[kCandCap];
     __shared__ int row[kRowCap];
     __shared__ int surv[kSurvCap];
     __shared__ int pa[kSurvCap], pj[kSurvCap];
     __shared__ int rowcnt[kCellAtomCap], rowst[kCellAtomCap];
     __shared__ int pre[kMaxStencil + 1], st[kMaxStencil];
+    __shared__ double shx[kMaxStencil], shy[kMaxStencil], shz[kMaxStencil];
     const int lane = threadIdx.x;
     const int nsz = (g.nc[2] + kSuper - 1) / kSuper;          // supercells per column
     const int n0 = g.nc[0] >= 3 ? 3 : g.nc[0];
@@ -146,6 +161,10 @@ __global__ __launch_bounds__(64) void k_search_cells(CellGrid g, double rc2, con
     const int n2 = zall ? g.nc[2] : kSuper + 2;
     const int nq = n0 * n1 * n2;
     const float rcs = (float)sqrt(rc2);
+    // the stencil fixes each candidate's periodic image when every axis has
+    // at least three cells around the supercell
+    const bool shifted = n0 == 3 && n1 == 3 && !zall;
+    const float lim = rcs + 1e-4f, lim2 = lim * lim;
     for (int sc = blockIdx.x; sc < nsuper; sc += gridDim.x) {
         const int col = sc / nsz;                              // (x, y) column
         const int z0 = (sc - col * nsz) * kSuper;
@@ -159,12 +178,14 @@ __global__ __launch_bounds__(64) void k_search_cells(CellGrid g, double rc2, con
             int x = cx0 + (n0 == 3 ? q0 - 1 : q0 - cx0);
             int y = cy0 + (n1 == 3 ? q1 - 1 : q1 - cy0);
             int z = zall ? q2 : z0 - 1 + q2;
-            x += x < 0 ? g.nc[0] : 0; x -= x >= g.nc[0] ? g.nc[0] : 0;
-            y += y < 0 ? g.nc[1] : 0; y -= y >= g.nc[1] ? g.nc[1] : 0;
-            z += z < 0 ? g.nc[2] : 0; z -= z >= g.nc[2] ? g.nc[2] : 0;
+            double sx = 0, sy = 0, sz = 0;   // image shift of this stencil cell
+            if (x < 0) { x += g.nc[0]; sx = -g.L[0]; } else if (x >= g.nc[0]) { x -= g.nc[0]; sx = g.L[0]; }
+            if (y < 0) { y += g.nc[1]; sy = -g.L[1]; } else if (y >= g.nc[1]) { y -= g.nc[1]; sy = g.L[1]; }
+            if (z < 0) { z += g.nc[2]; sz = -g.L[2]; } else if (z >= g.nc[2]) { z -= g.nc[2]; sz = g.L[2]; }
             const int cc = (x * g.nc[1] + y) * g.nc[2] + z;
             stq = cell_start[cc];
             cntq = cell_count[cc];
+            shx[lane] = sx; shy[lane] = sy; shz[lane] = sz;
         }
         const int cs = cell_start[c_first];
         const int A = cell_start[c_first + kz - 1] + cell_count[c_first + kz - 1] - cs;
@@ -182,6 +203,7 @@ __global__ __launch_bounds__(64) void k_search_cells(CellGrid g, double rc2, con
         }
         if (lane == 0) pre[nq] = T;
         __syncthreads();
+        const double ox = cx0 * g.cell_w[0], oy = cy0 * g.cell_w[1], oz = z0 * g.cell_w[2];
         // staged position of the supercell's first atom: stencil cell (centre x, centre y, z0)
         const int qf = (n0 == 3 ? 1 : cx0) * n1 * n2 + (n1 == 3 ? 1 : cy0) * n2 + (zall ? z0 : 1);
         auto stage = [&](int t0, int tn) {
@@ -194,9 +216,14 @@ __global__ __launch_bounds__(64) void k_search_cells(CellGrid g, double rc2, con
                 }
                 const int sidx = st[lo] + (t - pre[lo]);
                 cj[tt] = cell_atoms[sidx];
-                cx[tt] = cpos[3 * (size_t)sidx];
-                cy[tt] = cpos[3 * (size_t)sidx + 1];
-                cz[tt] = cpos[3 * (size_t)sidx + 2];
+                const double x = cpos[3 * (size_t)sidx], y = cpos[3 * (size_t)sidx + 1], z = cpos[3 * (size_t)sidx + 2];
+                cx[tt] = x; cy[tt] = y; cz[tt] = z;
+                if (shifted) {
+                    // wrapped coordinate as in the binning, plus the cell's image shift
+                    fx[tt] = (float)(x - g.L[0] * floor(x / g.L[0]) + shx[lo] - ox);
+                    fy[tt] = (float)(y - g.L[1] * floor(y / g.L[1]) + shy[lo] - oy);
+                    fz[tt] = (float)(z - g.L[2] * floor(z / g.L[2]) + shz[lo] - oz);
+                }
             }
         };
         const bool one_chunk = T <= kCandCap;
@@ -218,7 +245,8 @@ __global__ __launch_bounds__(64) void k_search_cells(CellGrid g, double rc2, con
                     const int t = f - ia * T;
                     const int ti = ic0 + ia;
                     if (t != ti)
-                        keep = may_be_neighbour(cx[t], cy[t], cz[t], cx[ti], cy[ti], cz[ti], g, rcs);
+                        keep = shifted ? may_be_neighbour_shifted(fx[t], fy[t], fz[t], fx[ti], fy[ti], fz[ti], lim2)
+                                       : may_be_neighbour(cx[t], cy[t], cz[t], cx[ti], cy[ti], cz[ti], g, rcs);
                 }
                 const unsigned long long m = __ballot(keep);
                 const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
@@ -326,18 +354,20 @@ __global__ __launch_bounds__(64) void k_search_cells(CellGrid g, double rc2, con
 }
 
 // rv[e] for entry e = (i, j) = i * cap + q of the row buffer: the entry of i
-// in the sorted row of j.  One thread per (i, q); row j is read in 16-entry
-// pieces of four 16-byte loads issued together.  The inclusion predicate is
-// symmetric (negating t negates s and d exactly), so the entry exists; a
-// missing one raises flag 4.
+// in the sorted row of j.  One thread per (i, q) with i < j searches row j
+// (16-entry pieces of four 16-byte loads issued together) and fills both
+// rv[(i, j)] and rv[(j, i)].  The inclusion predicate is symmetric (negating
+// t negates s and d exactly), so the entry exists; a missing one raises
+// flag 4.
 __global__ void k_reverse_map(const int *__restrict__ ell, int cap, const int *__restrict__ row_count, int n,
                               int *__restrict__ rv, int *flags)
 {
-    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = (int)(tid / cap);
-    const int q = (int)(tid - (long long)i * cap);
+    const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;   // n * cap < 2^31
+    const int i = (int)(tid / (unsigned)cap);
+    const int q = (int)(tid - (unsigned)i * (unsigned)cap);
     if (i >= n || q >= row_count[i]) return;
     const int j = ell[(size_t)i * cap + q];
+    if (j < i) return;   // the pair is handled from the other side
     const int cj = row_count[j];
     const int4 *row = reinterpret_cast<const int4 *>(ell + (size_t)j * cap);
     int at = -1;
@@ -354,11 +384,14 @@ __global__ void k_reverse_map(const int *__restrict__ ell, int cap, const int *_
             if (k + 3 < cj && v[u].w == i) at = k + 3;
         }
     }
+    const int e = (int)((size_t)i * cap + q);
     if (at < 0) {
         atomicOr(flags, 4);
-        rv[(size_t)i * cap + q] = (int)((size_t)i * cap + q);
+        rv[e] = e;
     } else {
-        rv[(size_t)i * cap + q] = (int)((size_t)j * cap + at);
+        const int f = (int)((size_t)j * cap + at);
+        rv[e] = f;
+        rv[f] = e;
     }
 }
 

@@ -56,7 +56,8 @@ struct tersoff_ctx {
     double cutoff = 0.0, skin = 0.0;
     bool built = false;
     long long S = 0;
-    int ell_cap = 32;
+    int ell_cap = 32;        // row capacity for the next build (multiple of 8)
+    int list_cap = 0;        // row stride of the resident list
     int atoms_per_batch = 16;
     int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};   // [fp64, mixed] x {pack, compute, per-atom}
 
@@ -391,17 +392,18 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
         if (host[2] & 2) return fail(c, TERSOFF_E_INVALID, "type out of range");
         if (host[1] <= c->ell_cap) break;
         if (host[1] > kMaxRow) return fail(c, TERSOFF_E_OVERFLOW, "an atom has more than 256 neighbours in range");
-        c->ell_cap = ((host[1] + 15) / 16) * 16;   // retry once with the needed capacity
+        c->ell_cap = ((host[1] + 7) / 8) * 8;   // retry once with the needed capacity
     }
     if (host[1] > c->ell_cap) return fail(c, TERSOFF_E_OVERFLOW, "row capacity retry failed");
+    c->list_cap = c->ell_cap;
     if (host[0] < 0) return fail(c, TERSOFF_E_INVALID, "list longer than 2^31 entries");
     c->S = host[0];
-    if ((long long)N * c->ell_cap >= (1LL << 31)) return fail(c, TERSOFF_E_INVALID, "n x row capacity >= 2^31");
-    const size_t NE = (size_t)N * c->ell_cap;
+    if ((long long)N * c->list_cap >= (1LL << 31)) return fail(c, TERSOFF_E_INVALID, "n x row capacity >= 2^31");
+    const size_t NE = (size_t)N * c->list_cap;
     HIP_TRY(c, c->rv.ensure(NE));
     HIP_TRY(c, c->slotpos.ensure(NE));
     HIP_TRY(c, c->own.ensure(3 * (size_t)N));
-    HIP_TRY(c, launch_reverse_map(c->ell.p, c->ell_cap, c->row_count.p, N, c->rv.p, c->misc.p + 2, s));
+    HIP_TRY(c, launch_reverse_map(c->ell.p, c->list_cap, c->row_count.p, N, c->rv.p, c->misc.p + 2, s));
     HIP_TRY(c, hipMemcpyAsync(c->pos_build.p, pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->types.p, types, sizeof(int) * (size_t)N, hipMemcpyDeviceToDevice, s));
     int chk = 0;
@@ -412,6 +414,8 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     }
     HIP_TRY(c, hipStreamSynchronize(s));
     if (chk & 4) return fail(c, TERSOFF_E_DEVICE, "neighbour list is not symmetric");
+    // the next build starts from the capacity this list needed (plus a margin)
+    c->ell_cap = std::max(8, ((host[1] + 2 + 7) / 8) * 8);
 
     c->n = N;
     for (int a = 0; a < 3; ++a) c->box[a] = box[a];
@@ -455,7 +459,7 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     pk.row_count = c->row_count.p;
     pk.jn = c->ell.p;
     pk.rv = c->rv.p;
-    pk.cap = c->ell_cap;
+    pk.cap = c->list_cap;
     pk.n = c->n;
     for (int d = 0; d < 3; ++d) {
         pk.L[d] = c->box[d];
@@ -495,7 +499,7 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     HIP_TRY(c, launch_compute(a, c->tab, mixed, grid[1], s));
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
-    HIP_TRY(c, launch_fixup_dropped(c->row_count.p, c->ell.p, c->rv.p, c->ell_cap, c->slotpos.p,
+    HIP_TRY(c, launch_fixup_dropped(c->row_count.p, c->ell.p, c->rv.p, c->list_cap, c->slotpos.p,
                                     c->drop_list.p, c->misc.p + 3, c->n, c->planes.p, s));
     HIP_TRY(c, launch_gather_forces(c->pcount.p, c->planes.p, c->own.p, c->n, f, s));
     if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
@@ -536,10 +540,10 @@ int tersoff_get_neighbors(tersoff_ctx *c, int64_t *offsets, int32_t *idx, int64_
     for (size_t i = 0; i < cnt.size(); ++i) offsets[i + 1] = offsets[i] + cnt[i];
     *total = c->S;
     if (cap < c->S || (!idx && c->S > 0)) return fail(c, TERSOFF_E_INVALID, "idx capacity below list length");
-    std::vector<int> rows((size_t)c->n * c->ell_cap);
+    std::vector<int> rows((size_t)c->n * c->list_cap);
     HIP_TRY(c, hipMemcpy(rows.data(), c->ell.p, sizeof(int) * rows.size(), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < cnt.size(); ++i)
-        std::memcpy(idx + offsets[i], rows.data() + i * c->ell_cap, sizeof(int) * (size_t)cnt[i]);
+        std::memcpy(idx + offsets[i], rows.data() + i * c->list_cap, sizeof(int) * (size_t)cnt[i]);
     return TERSOFF_OK;
 }
 
