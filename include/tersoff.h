@@ -163,6 +163,84 @@ const char *tersoff_strerror(int status);
 /* Message of the last error raised on this context ("" if none). */
 const char *tersoff_last_error(const tersoff_ctx *ctx);
 
+/* ---- Serving: many small, independent configurations ------------------
+ *
+ * The evaluation of one configuration is Eq. (1)-(3) / Algorithm 1 on its
+ * own periodic box, exactly as tersoff_build_neighbors + tersoff_compute
+ * define it.  A worker thread of the context gathers queued requests into
+ * batches (first come first served, up to the capacities below, one
+ * precision per batch), builds every configuration's neighbour list and
+ * evaluates the whole batch with one replay of a captured HIP graph, while
+ * the next batch is formed from requests that arrived in the meantime.  A
+ * configuration's result does not depend on which other configurations share
+ * its batch.  Buffers are host memory; the device memory of two batches in
+ * flight is allocated once, at start, from the capacities. */
+typedef struct {
+    int64_t max_batch_atoms;    /* atoms per batch, in [1, 2^24]; also the largest request  */
+    int32_t max_batch_systems;  /* configurations per batch (slots), in [1, 2^20]           */
+    int32_t max_neighbors;      /* row capacity of a batch's lists (0: 48; at most 256); a
+                                   configuration with a longer row gets E_OVERFLOW          */
+    double cutoff;              /* 0: the largest R + D of the table                        */
+    double skin;                /* list radius = cutoff + skin                              */
+    int64_t max_queued;         /* waiting requests before submit returns E_AGAIN (0: 65536) */
+} tersoff_serve_config;
+
+typedef struct {
+    const double *pos;      /* host, n x 3 float64; read when the request joins a batch  */
+    const int32_t *types;   /* host, n int32 in [0, ntypes)                              */
+    int64_t n;
+    double box[3];          /* orthorhombic periodic lengths, each >= 2 (cutoff + skin)  */
+    int32_t precision;      /* TERSOFF_FP64 or TERSOFF_MIXED                              */
+    double *forces;         /* host, n x 3, written before the result is ready; or NULL  */
+    uint64_t tag;           /* returned unchanged                                        */
+    int64_t release_ns;     /* tersoff_clock_ns() time before which the request is not
+                               started (0: at once); latency counts from the later of
+                               submission and release                                    */
+} tersoff_request;
+
+typedef struct {
+    int32_t status;         /* OK, or E_OVERFLOW (a row above max_neighbors or an atom
+                               above the per-atom record capacity: values invalid),
+                               or E_DEVICE                                               */
+    int32_t batch_systems;  /* configurations in the batch that evaluated it             */
+    int64_t n;
+    double energy;          /* eV                                                        */
+    double virial[6];       /* xx yy zz xy xz yz, eV                                     */
+    double latency_ms;      /* from submission (or release) to result ready              */
+    uint64_t tag;
+} tersoff_result;
+
+/* Start the serving worker of a context (device memory for two batches is
+ * allocated here).  Errors: E_INVALID (capacities, cutoff below the largest
+ * R + D, skin < 0), E_STATE (already started), E_NOMEM, E_DEVICE. */
+int tersoff_serve_start(tersoff_ctx *ctx, const tersoff_serve_config *cfg);
+
+/* Finish every queued and running request, then stop the worker and free its
+ * memory (tersoff_destroy does this too).  Results not yet collected are
+ * dropped.  Errors: E_STATE (not started). */
+int tersoff_serve_stop(tersoff_ctx *ctx);
+
+/* Queue one configuration.  pos, types and forces must stay valid until its
+ * result has been collected.  Thread-safe.
+ * Errors: E_INVALID (null pointer, n < 1 or above max_batch_atoms, type out
+ *   of range, non-finite position or box, precision, a box with more cells
+ *   than a batch holds), E_BOX (a box length < 2 (cutoff + skin)), E_AGAIN
+ *   (queue full), E_STATE (serving not started or stopping). */
+int tersoff_submit(tersoff_ctx *ctx, const tersoff_request *req, uint64_t *ticket);
+
+/* Collect the result of a ticket, waiting up to timeout_ms (0: do not wait).
+ * Returns OK (result written; the ticket is then retired), E_PENDING (not
+ * ready yet), E_INVALID (unknown or already collected ticket) or E_STATE.
+ * Thread-safe. */
+int tersoff_poll(tersoff_ctx *ctx, uint64_t ticket, double timeout_ms, tersoff_result *res);
+
+/* Serving counters: out[0] batches run, out[1] configurations, out[2] atoms,
+ * out[3] device bytes held, out[4] max_batch_atoms, out[5] max_batch_systems. */
+int tersoff_serve_stats(tersoff_ctx *ctx, double out[6]);
+
+/* Monotonic clock (ns) of tersoff_request.release_ns. */
+int64_t tersoff_clock_ns(void);
+
 #ifdef __cplusplus
 }
 #endif

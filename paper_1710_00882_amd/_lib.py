@@ -27,7 +27,26 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_BOX", -4: "E_OVERFLOW"
 SYMBOLS = ("tersoff_create", "tersoff_destroy", "tersoff_build_neighbors", "tersoff_compute",
            "tersoff_check", "tersoff_get_neighbors", "tersoff_get_counts", "tersoff_num_atoms",
            "tersoff_strerror", "tersoff_last_error", "tersoff_profile", "tersoff_profile_read",
-           "tersoff_set_batch_atoms")
+           "tersoff_set_batch_atoms", "tersoff_serve_start", "tersoff_serve_stop", "tersoff_submit",
+           "tersoff_poll", "tersoff_serve_stats", "tersoff_clock_ns")
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("max_batch_atoms", ctypes.c_int64), ("max_batch_systems", ctypes.c_int32),
+                ("max_neighbors", ctypes.c_int32), ("cutoff", ctypes.c_double), ("skin", ctypes.c_double),
+                ("max_queued", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("types", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("box", ctypes.c_double * 3), ("precision", ctypes.c_int32), ("forces", ctypes.c_void_p),
+                ("tag", ctypes.c_uint64), ("release_ns", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_systems", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("energy", ctypes.c_double), ("virial", ctypes.c_double * 6), ("latency_ms", ctypes.c_double),
+                ("tag", ctypes.c_uint64)]
 
 _lib = None
 
@@ -75,6 +94,18 @@ def load():
     lib.tersoff_strerror.restype = ctypes.c_char_p
     lib.tersoff_last_error.argtypes = [P]
     lib.tersoff_last_error.restype = ctypes.c_char_p
+    lib.tersoff_serve_start.argtypes = [P, ctypes.POINTER(ServeConfig)]
+    lib.tersoff_serve_start.restype = ctypes.c_int
+    lib.tersoff_serve_stop.argtypes = [P]
+    lib.tersoff_serve_stop.restype = ctypes.c_int
+    lib.tersoff_submit.argtypes = [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.tersoff_submit.restype = ctypes.c_int
+    lib.tersoff_poll.argtypes = [P, ctypes.c_uint64, f64, ctypes.POINTER(Result)]
+    lib.tersoff_poll.restype = ctypes.c_int
+    lib.tersoff_serve_stats.argtypes = [P, P]
+    lib.tersoff_serve_stats.restype = ctypes.c_int
+    lib.tersoff_clock_ns.argtypes = []
+    lib.tersoff_clock_ns.restype = i64
     _lib = lib
     return lib
 
@@ -118,6 +149,7 @@ class Tersoff:
         if getattr(self, "_h", None):
             self._lib.tersoff_destroy(self._h)
             self._h = None
+            self._held = {}
 
     def __del__(self):
         try:
@@ -217,3 +249,79 @@ class Tersoff:
         if st != OK:
             self._raise(st, "tersoff_get_counts")
         return tuple(int(v) for v in c)
+
+    # ---- serving -------------------------------------------------------------
+    def serve_start(self, max_batch_atoms, max_batch_systems, max_neighbors=0, cutoff=0.0, skin=1.0,
+                    max_queued=0):
+        cfg = ServeConfig(int(max_batch_atoms), int(max_batch_systems), int(max_neighbors), float(cutoff),
+                          float(skin), int(max_queued))
+        st = self._lib.tersoff_serve_start(self._h, ctypes.byref(cfg))
+        if st != OK:
+            self._raise(st, "tersoff_serve_start")
+        self._held = {}
+
+    def serve_stop(self):
+        st = self._lib.tersoff_serve_stop(self._h)
+        self._held = {}
+        if st != OK:
+            self._raise(st, "tersoff_serve_stop")
+
+    def submit(self, pos, types, box, precision="mixed", forces=None, tag=0, release_ns=0):
+        """Queue one configuration (host numpy arrays, kept alive here until
+        its result is collected).  Returns the ticket; raises TersoffError
+        (status E_AGAIN when the queue is full)."""
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        types = np.ascontiguousarray(types, dtype=np.int32)
+        if pos.ndim != 2 or pos.shape[1] != 3 or types.shape != (pos.shape[0],):
+            raise ValueError("pos must be (n, 3) and types (n,)")
+        if forces is not None:
+            if forces.dtype != np.float64 or forces.shape != pos.shape or not forces.flags.c_contiguous:
+                raise ValueError("forces must be a C-contiguous float64 array shaped like pos")
+        req = Request()
+        req.pos = pos.ctypes.data
+        req.types = types.ctypes.data
+        req.n = pos.shape[0]
+        for a, v in enumerate(np.asarray(box, dtype=np.float64).reshape(3)):
+            req.box[a] = float(v)
+        req.precision = PRECISIONS[precision]
+        req.forces = forces.ctypes.data if forces is not None else None
+        req.tag = int(tag)
+        req.release_ns = int(release_ns)
+        t = ctypes.c_uint64(0)
+        st = self._lib.tersoff_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if st != OK:
+            raise TersoffError(st, "tersoff_submit rejected the request")
+        self._held[t.value] = (pos, types, forces)
+        return t.value
+
+    def poll(self, ticket, timeout_ms=0.0):
+        """Result dict of a ticket, or None while it is pending."""
+        r = Result()
+        st = self._lib.tersoff_poll(self._h, int(ticket), float(timeout_ms), ctypes.byref(r))
+        if st == -8:
+            return None
+        if st != OK:
+            raise TersoffError(st, "tersoff_poll")
+        held = self._held.pop(int(ticket), (None, None, None))
+        return dict(status=int(r.status), energy=float(r.energy), virial=np.array(r.virial[:]),
+                    latency_ms=float(r.latency_ms), tag=int(r.tag), n=int(r.n),
+                    batch_systems=int(r.batch_systems), forces=held[2])
+
+    def wait(self, ticket, timeout_ms=60000.0):
+        res = self.poll(ticket, timeout_ms)
+        if res is None:
+            raise TimeoutError(f"ticket {ticket} not ready after {timeout_ms} ms")
+        return res
+
+    def serve_stats(self):
+        out = np.zeros(6)
+        st = self._lib.tersoff_serve_stats(self._h, out.ctypes.data_as(ctypes.c_void_p))
+        if st != OK:
+            self._raise(st, "tersoff_serve_stats")
+        return dict(batches=int(out[0]), systems=int(out[1]), atoms=int(out[2]), device_bytes=int(out[3]),
+                    max_batch_atoms=int(out[4]), max_batch_systems=int(out[5]))
+
+
+def clock_ns() -> int:
+    """The library's monotonic clock (the time base of release_ns)."""
+    return int(load().tersoff_clock_ns())

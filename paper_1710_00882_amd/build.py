@@ -25,6 +25,7 @@ SOURCES = {
     "tersoff_api.hip": [],
     "compute.hip": [],
     "neighbors.hip": ["-ffp-contract=off"],
+    "serve.hip": [],
 }
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -15,6 +15,7 @@
 // displacement, the zeta -> b power and every accumulation are FP64 in both.
 #include "internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace tsf {
@@ -216,31 +217,44 @@ constexpr int kScap = 64;      // packed slots per compute batch (one per lane)
 // capacity).  Because the radius is symmetric and r^2 of (i, n) and (n, i) is
 // bit-identical, i keeps n exactly when n keeps i, so the centre i can find
 // where atom n expects the force i's terms put on it: rank slotpos[(n, i)].
-template <typename real, bool ONE>
+//
+// BATCHED: the atoms belong to several systems (each row holds atoms of its
+// own system only); every centre atom uses its system's box, and there is no
+// stale check (a batch is built and evaluated together).
+template <typename real, bool ONE, bool BATCHED>
 __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
 {
     __shared__ double xi[kWave], yi[kWave], zi[kWave];
+    __shared__ double bL[BATCHED ? 3 : 1][BATCHED ? kWave : 1], biL[BATCHED ? 3 : 1][BATCHED ? kWave : 1];
     __shared__ int ti[kWave], cnt[kWave];
     __shared__ int eoff[kWave + 1];
     const int lane = threadIdx.x;
     Rec<real> *recs = static_cast<Rec<real> *>(a.recs);
     const int B = a.atoms_per_batch;
-    const int nbatch = (a.n + B - 1) / B;
-    if (blockIdx.x == 0 && lane == 0) *a.drop_count = 0;
+    const int n = BATCHED ? *a.n_dev : a.n;
+    const int nbatch = (n + B - 1) / B;
 
     const ItemRange items = xcd_items(nbatch);
     for (int bt = items.begin; bt < items.end; bt += items.stride) {
         const int a0 = bt * B;
-        const int nb = min(B, a.n - a0);
+        const int nb = min(B, n - a0);
         if (lane < nb) {
             const size_t i = (size_t)(a0 + lane);
             const double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
             xi[lane] = x; yi[lane] = y; zi[lane] = z;
             ti[lane] = ONE ? 0 : a.types[i];
             cnt[lane] = 0;
-            const double dx = x - a.pos_build[3 * i], dy = y - a.pos_build[3 * i + 1],
-                         dz = z - a.pos_build[3 * i + 2];
-            if (!(dx * dx + dy * dy + dz * dz <= a.stale_sq)) atomicOr(a.flags, kFlagStale);
+            if constexpr (BATCHED) {
+                const CellGrid &g = a.sys[a.sys_of[i]].g;
+                for (int d = 0; d < 3; ++d) {
+                    bL[d][lane] = g.L[d];
+                    biL[d][lane] = g.invL[d];
+                }
+            } else {
+                const double dx = x - a.pos_build[3 * i], dy = y - a.pos_build[3 * i + 1],
+                             dz = z - a.pos_build[3 * i + 2];
+                if (!(dx * dx + dy * dy + dz * dz <= a.stale_sq)) atomicOr(a.flags, kFlagStale);
+            }
         }
         {
             // local entry offsets of the batch's rows
@@ -291,9 +305,15 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 double dx = 0, dy = 0, dz = 0, rsq = 0;
                 if (e < e_end) {
                     al = alv[c];
-                    dx = image(xv[c] - xi[al], a.L[0], a.invL[0]);
-                    dy = image(yv[c] - yi[al], a.L[1], a.invL[1]);
-                    dz = image(zv[c] - zi[al], a.L[2], a.invL[2]);
+                    if constexpr (BATCHED) {
+                        dx = image(xv[c] - xi[al], bL[0][al], biL[0][al]);
+                        dy = image(yv[c] - yi[al], bL[1][al], biL[1][al]);
+                        dz = image(zv[c] - zi[al], bL[2][al], biL[2][al]);
+                    } else {
+                        dx = image(xv[c] - xi[al], a.L[0], a.invL[0]);
+                        dy = image(yv[c] - yi[al], a.L[1], a.invL[1]);
+                        dz = image(zv[c] - zi[al], a.L[2], a.invL[2]);
+                    }
                     rsq = norm2(dx, dy, dz);
                     const double psq = ONE ? tab.packsq[0] : tab.packsq[ti[al] * tab.ntypes + tv[c]];
                     acc = rsq < psq;
@@ -423,10 +443,15 @@ __device__ __forceinline__ void exp_term(const ParamR<real> &q, real rj, real rk
 // Each slot's force goes to the slot atom j reserved for centre i (plane
 // slotpos[(j, i)] of the per-atom force planes), each centre's own force to
 // `own`; k_gather_forces sums them per atom.
-template <typename real, bool ONE>
+//
+// BATCHED: the batch holds several systems; each centre atom's energy and
+// virial (the sums over its slots) are stored per atom for the per-system
+// reduction, in place of the per-workgroup partial sums.
+template <typename real, bool ONE, bool BATCHED>
 __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable tab)
 {
     __shared__ Shared<real> sh;
+    __shared__ double sev[BATCHED ? kScap : 1][BATCHED ? 7 : 1];   // per-slot energy and virial
     const int lane = threadIdx.x;
     const ParamR<real> *ptab = table_r<real>(tab);
     const Rec<real> *recs = static_cast<const Rec<real> *>(a.recs);
@@ -437,12 +462,13 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
     long long n_pairs = 0, n_trip = 0;
 
     const int B = a.atoms_per_batch;
-    const int ngroups = (a.n + B - 1) / B;
+    const int n = BATCHED ? *a.n_dev : a.n;
+    const int ngroups = (n + B - 1) / B;
 
     const ItemRange items = xcd_items(ngroups);
     for (int grp = items.begin; grp < items.end; grp += items.stride) {
         int a0 = grp * B;
-        const int a_end = min(a0 + B, a.n);
+        const int a_end = min(a0 + B, n);
         const Rec<real> *region = recs + (size_t)a0 * kRecCap;   // this batch's records, in order
         while (a0 < a_end) {
             const int nb = a_end - a0;
@@ -490,6 +516,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             const int tj = mj & 0xff;
             const bool j_pair = (mj >> kPairBit) & 1;
             double fx = 0, fy = 0, fz = 0;     // force on j from centre i's terms
+            double e_pair = 0.0;   // energy of pair (i, j)
             if (has_slot) {
                 // ---- 1: zeta_ij over the other slots k of centre i
                 real zr = real(0);
@@ -528,7 +555,8 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                         db = -0.5 * b * x / (zeta * (1.0 + x));
                     }
                     const real br = (real)b;
-                    e_acc += 0.5 * (double)fc * ((double)fr + b * (double)fa);
+                    e_pair = 0.5 * (double)fc * ((double)fr + b * (double)fa);
+                    e_acc += e_pair;
                     const real dvdr = real(0.5) * (dfc * (fr + br * fa) + fc * (dfr + br * dfa));
                     fx = (double)(-dvdr * uj[0]);
                     fy = (double)(-dvdr * uj[1]);
@@ -589,11 +617,20 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 w_acc[3] += dxj * fy;
                 w_acc[4] += dxj * fz;
                 w_acc[5] += dyj * fz;
-                if (kpos >= 0) {
-                    double *f = a.planes + 3 * ((size_t)kpos * a.n + (size_t)j);
+                if ((unsigned)kpos < (unsigned)kRecCap) {
+                    double *f = a.planes + 3 * ((size_t)kpos * a.plane_stride + (size_t)j);
                     f[0] = fx; f[1] = fy; f[2] = fz;
                 }
                 sh.fs[s][0] = fx; sh.fs[s][1] = fy; sh.fs[s][2] = fz;
+                if constexpr (BATCHED) {
+                    sev[s][0] = e_pair;
+                    sev[s][1] = dxj * fx;
+                    sev[s][2] = dyj * fy;
+                    sev[s][3] = dzj_ * fz;
+                    sev[s][4] = dxj * fy;
+                    sev[s][5] = dxj * fz;
+                    sev[s][6] = dyj * fz;
+                }
             }
             __syncthreads();
             if (lane < cut) {
@@ -604,6 +641,14 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 }
                 double *o = a.own + 3 * (size_t)(a0 + lane);
                 o[0] = ox; o[1] = oy; o[2] = oz;
+                if constexpr (BATCHED) {
+                    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+                    for (int q = s0; q < s1; ++q)
+                        for (int c = 0; c < 7; ++c) v[c] += sev[q][c];
+                    double *ea = a.eatom + 8 * (size_t)(a0 + lane);
+                    for (int c = 0; c < 7; ++c) ea[c] = v[c];
+                    ea[7] = 0.0;
+                }
             }
             __syncthreads();
             a0 += cut;
@@ -611,6 +656,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
         }
     }
 
+    if constexpr (BATCHED) return;
     // ---- per-workgroup partial sums of energy, virial and counts
     double v[7] = {e_acc, w_acc[0], w_acc[1], w_acc[2], w_acc[3], w_acc[4], w_acc[5]};
 #pragma unroll
@@ -638,7 +684,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
 __global__ void k_fixup_dropped(const int *__restrict__ row_count, const int *__restrict__ jn,
                                 const int *__restrict__ rv, int cap, const signed char *__restrict__ slotpos,
                                 const int *__restrict__ drop_list, const int *__restrict__ drop_count,
-                                int n, double *__restrict__ planes)
+                                int plane_stride, double *__restrict__ planes)
 {
     const int nd = *drop_count;
     for (int q = blockIdx.x; q < nd; q += gridDim.x) {
@@ -647,16 +693,19 @@ __global__ void k_fixup_dropped(const int *__restrict__ row_count, const int *__
         for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
             if (slotpos[e] == -1) continue;            // m did not keep this neighbour
             const int k = slotpos[rv[e]];              // rank of m in the neighbour's row
-            if (k >= 0) {
-                double *f = planes + 3 * ((size_t)k * n + (size_t)jn[e]);
+            if ((unsigned)k < (unsigned)kRecCap) {
+                double *f = planes + 3 * ((size_t)k * plane_stride + (size_t)jn[e]);
                 f[0] = f[1] = f[2] = 0.0;
             }
         }
     }
 }
 
+// Sums the per-workgroup partials; also empties the dropped-atom list for
+// the next evaluation (every kernel reading it has run by now).
 __global__ void k_finalize(const double *__restrict__ partials, const long long *__restrict__ counters,
-                           int grid, double *__restrict__ out, long long *__restrict__ counts)
+                           int grid, double *__restrict__ out, long long *__restrict__ counts,
+                           int *__restrict__ drop_count)
 {
     __shared__ double sh[8][256];
     __shared__ long long shc[2][256];
@@ -683,6 +732,42 @@ __global__ void k_finalize(const double *__restrict__ partials, const long long 
         for (int c = 0; c < 7; ++c) out[c] = sh[c][0];
         counts[0] = shc[0][0];
         counts[1] = shc[1][0];
+        *drop_count = 0;
+    }
+}
+
+// One workgroup per system of a batch: sums of the per-atom energy and
+// virial over the system's atoms (thread t takes local atoms t, t + 256, ...,
+// then a fixed tree), so a system's result does not depend on where in the
+// batch it sits; status bits from the search and the dropped-atom list.
+__global__ void k_reduce_systems(const SysDesc *__restrict__ sys, const BatchDims *__restrict__ dims,
+                                 const double *__restrict__ eatom, const int *__restrict__ drop_list,
+                                 const int *__restrict__ drop_count, const int *__restrict__ sys_status,
+                                 double *__restrict__ out)
+{
+    __shared__ double sh[7][256];
+    const int nsys = dims->n_sys;
+    const int nd = *drop_count;
+    for (int s = blockIdx.x; s < nsys; s += gridDim.x) {
+        const int a0 = sys[s].atom_off, na = sys[s].natoms;
+        double v[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int k = threadIdx.x; k < na; k += blockDim.x)
+            for (int c = 0; c < 7; ++c) v[c] += eatom[8 * (size_t)(a0 + k) + c];
+        for (int c = 0; c < 7; ++c) sh[c][threadIdx.x] = v[c];
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off)
+                for (int c = 0; c < 7; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            int st = sys_status[s];
+            for (int q = 0; q < nd; ++q)
+                if (drop_list[q] >= a0 && drop_list[q] < a0 + na) st |= 2;
+            for (int c = 0; c < 7; ++c) out[8 * (size_t)s + c] = sh[c][0];
+            out[8 * (size_t)s + 7] = (double)st;
+        }
+        __syncthreads();
     }
 }
 
@@ -690,14 +775,15 @@ __global__ void k_finalize(const double *__restrict__ partials, const long long 
 // plane k of m, k = rank of i among m's kept neighbours (k < pcount[m]).
 // One thread per atom; each plane read is coalesced across the wavefront.
 __global__ void k_gather_forces(const int *__restrict__ pcount, const double *__restrict__ planes,
-                                const double *__restrict__ own, int n, double *__restrict__ forces)
+                                const double *__restrict__ own, int n, const int *__restrict__ n_dev,
+                                int plane_stride, double *__restrict__ forces)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
+    if (m >= (n_dev ? *n_dev : n)) return;
     double fx = own[3 * (size_t)m], fy = own[3 * (size_t)m + 1], fz = own[3 * (size_t)m + 2];
     const int pc = pcount[m];
     for (int k = 0; k < pc; ++k) {
-        const double *f = planes + 3 * ((size_t)k * n + (size_t)m);
+        const double *f = planes + 3 * ((size_t)k * plane_stride + (size_t)m);
         fx += f[0];
         fy += f[1];
         fz += f[2];
@@ -707,14 +793,14 @@ __global__ void k_gather_forces(const int *__restrict__ pcount, const double *__
     forces[3 * (size_t)m + 2] = fz;
 }
 
-__global__ void k_fill_zero(double *p, size_t count)
+template <typename T>
+__global__ void k_fill_zero(T *p, size_t count)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < count; i += stride) p[i] = 0.0;
+    for (; i < count; i += stride) p[i] = T(0);
 }
 
-template <typename real, bool ONE>
 int occupancy_grid(const void *kern, long long work_items)
 {
     int per_cu = 0;
@@ -728,80 +814,112 @@ int occupancy_grid(const void *kern, long long work_items)
     return (int)(g < 1 ? 1 : g);
 }
 
-template <typename real, bool ONE>
+template <typename real, bool ONE, bool BATCHED>
 void grids_for(int n, int atoms_per_batch, int grids[3])
 {
-    grids[0] = occupancy_grid<real, ONE>((const void *)k_pack<real, ONE>,
-                                         ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
-    grids[1] = occupancy_grid<real, ONE>((const void *)k_tersoff<real, ONE>,
-                                         ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
+    grids[0] = occupancy_grid((const void *)k_pack<real, ONE, BATCHED>,
+                              ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
+    grids[1] = occupancy_grid((const void *)k_tersoff<real, ONE, BATCHED>,
+                              ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
     grids[2] = kBigGrid;
+}
+
+template <bool BATCHED>
+void grids_dispatch(bool mixed, bool one_type, int n, int atoms_per_batch, int grids[3])
+{
+    if (mixed) {
+        if (one_type) grids_for<float, true, BATCHED>(n, atoms_per_batch, grids);
+        else grids_for<float, false, BATCHED>(n, atoms_per_batch, grids);
+    } else {
+        if (one_type) grids_for<double, true, BATCHED>(n, atoms_per_batch, grids);
+        else grids_for<double, false, BATCHED>(n, atoms_per_batch, grids);
+    }
+}
+
+template <bool BATCHED>
+void pack_dispatch(const PackLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s)
+{
+    const bool one = t.ntypes == 1;
+    if (mixed) {
+        if (one) hipLaunchKernelGGL((k_pack<float, true, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
+        else hipLaunchKernelGGL((k_pack<float, false, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
+    } else {
+        if (one) hipLaunchKernelGGL((k_pack<double, true, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
+        else hipLaunchKernelGGL((k_pack<double, false, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
+    }
+}
+
+template <bool BATCHED>
+void compute_dispatch(const ComputeLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s)
+{
+    const bool one = t.ntypes == 1;
+    if (mixed) {
+        if (one) hipLaunchKernelGGL((k_tersoff<float, true, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
+        else hipLaunchKernelGGL((k_tersoff<float, false, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
+    } else {
+        if (one) hipLaunchKernelGGL((k_tersoff<double, true, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
+        else hipLaunchKernelGGL((k_tersoff<double, false, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
+    }
 }
 
 }  // namespace
 
-void compute_grids(bool mixed, bool one_type, int n, int atoms_per_batch, int grids[3])
+void compute_grids(bool mixed, bool one_type, bool batched, int n, int atoms_per_batch, int grids[3])
 {
-    if (mixed) {
-        if (one_type) grids_for<float, true>(n, atoms_per_batch, grids);
-        else grids_for<float, false>(n, atoms_per_batch, grids);
-    } else {
-        if (one_type) grids_for<double, true>(n, atoms_per_batch, grids);
-        else grids_for<double, false>(n, atoms_per_batch, grids);
-    }
+    if (batched) grids_dispatch<true>(mixed, one_type, n, atoms_per_batch, grids);
+    else grids_dispatch<false>(mixed, one_type, n, atoms_per_batch, grids);
 }
 
 size_t record_bytes(bool mixed) { return mixed ? sizeof(Rec<float>) : sizeof(Rec<double>); }
 
 hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s)
 {
-    const bool one = t.ntypes == 1;
-    if (mixed) {
-        if (one) hipLaunchKernelGGL((k_pack<float, true>), dim3(grid), dim3(kWave), 0, s, a, t);
-        else hipLaunchKernelGGL((k_pack<float, false>), dim3(grid), dim3(kWave), 0, s, a, t);
-    } else {
-        if (one) hipLaunchKernelGGL((k_pack<double, true>), dim3(grid), dim3(kWave), 0, s, a, t);
-        else hipLaunchKernelGGL((k_pack<double, false>), dim3(grid), dim3(kWave), 0, s, a, t);
-    }
+    if (a.n_dev) pack_dispatch<true>(a, t, mixed, grid, s);
+    else pack_dispatch<false>(a, t, mixed, grid, s);
     return hipGetLastError();
 }
 
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mixed, int grid,
                           hipStream_t s)
 {
-    const bool one = t.ntypes == 1;
     if (a.atoms_per_batch < 1 || a.atoms_per_batch > kWave) return hipErrorInvalidValue;
-    if (mixed) {
-        if (one) hipLaunchKernelGGL((k_tersoff<float, true>), dim3(grid), dim3(kWave), 0, s, a, t);
-        else hipLaunchKernelGGL((k_tersoff<float, false>), dim3(grid), dim3(kWave), 0, s, a, t);
-    } else {
-        if (one) hipLaunchKernelGGL((k_tersoff<double, true>), dim3(grid), dim3(kWave), 0, s, a, t);
-        else hipLaunchKernelGGL((k_tersoff<double, false>), dim3(grid), dim3(kWave), 0, s, a, t);
-    }
+    if (a.n_dev) compute_dispatch<true>(a, t, mixed, grid, s);
+    else compute_dispatch<false>(a, t, mixed, grid, s);
     return hipGetLastError();
 }
 
 hipError_t launch_fixup_dropped(const int *row_count, const int *jn, const int *rv, int cap,
                                 const signed char *slotpos, const int *drop_list, const int *drop_count,
-                                int n, double *planes, hipStream_t s)
+                                int plane_stride, double *planes, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fixup_dropped, dim3(kBigGrid), dim3(kWave), 0, s, row_count, jn, rv, cap, slotpos,
-                       drop_list, drop_count, n, planes);
+                       drop_list, drop_count, plane_stride, planes);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const double *partials, const long long *counters, int grid,
-                           double *out7, long long *counts_out, hipStream_t s)
+                           double *out7, long long *counts_out, int *drop_count, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, counters, grid, out7, counts_out);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, counters, grid, out7, counts_out,
+                       drop_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_systems(const SysDesc *sys, const BatchDims *dims, int max_sys, const double *eatom,
+                                 const int *drop_list, const int *drop_count, const int *sys_status,
+                                 double *out, hipStream_t s)
+{
+    const int grid = std::max(1, std::min(max_sys, kBatchGrid));
+    hipLaunchKernelGGL(k_reduce_systems, dim3(grid), dim3(256), 0, s, sys, dims, eatom, drop_list, drop_count,
+                       sys_status, out);
     return hipGetLastError();
 }
 
 hipError_t launch_gather_forces(const int *pcount, const double *planes, const double *own, int n,
-                                double *forces, hipStream_t s)
+                                const int *n_dev, int plane_stride, double *forces, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_forces, dim3((n + 255) / 256), dim3(256), 0, s, pcount, planes, own,
-                       n, forces);
+    hipLaunchKernelGGL(k_gather_forces, dim3(std::max(1, (n + 255) / 256)), dim3(256), 0, s, pcount, planes,
+                       own, n, n_dev, plane_stride, forces);
     return hipGetLastError();
 }
 
@@ -810,7 +928,16 @@ hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s)
     if (count == 0) return hipSuccess;
     size_t blocks = (count + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, p, count);
+    hipLaunchKernelGGL(k_fill_zero<double>, dim3((unsigned)blocks), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero_int(int *p, size_t count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_zero<int>, dim3((unsigned)blocks), dim3(256), 0, s, p, count);
     return hipGetLastError();
 }
 

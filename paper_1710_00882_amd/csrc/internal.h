@@ -51,6 +51,32 @@ struct DeviceTable {
     const double *packsq;       // ntypes^2, symmetric: packing radius^2 of a (ti, tn) entry
 };
 
+// Cell grid of one periodic box (cells at least the list radius wide).
+struct CellGrid {
+    int nc[3];
+    double L[3];
+    double invL[3];
+    double cell_w[3];
+    float Lf[3], invLf[3];   // single-precision copies for the conservative pre-test
+    float Lsum;              // Lf[0] + Lf[1] + Lf[2]
+};
+// One configuration of a batch: its box and cell grid, and where its atoms,
+// cells and supercells start in the batch's concatenated arrays.
+struct SysDesc {
+    CellGrid g;
+    int atom_off, natoms;
+    int cell_off, super_off;
+};
+
+// Sizes of the batch in flight, read by the kernels from device memory so
+// that one captured launch sequence serves batches of any size up to the
+// capacities its grids were sized for.
+struct BatchDims {
+    int n_atoms, n_cells, n_super, n_sys;
+};
+
+constexpr int kBatchGrid = 2048;   // workgroups of the grid-stride kernels of a batch
+
 // Flags raised by kernels (bitwise OR into a device int).
 enum : int { kFlagOverflow = 1, kFlagStale = 2 };
 
@@ -72,10 +98,14 @@ struct PackLaunch {
     double *own;                // n x 3 (zeroed for dropped atoms only)
     int *flags;
     int *drop_list;             // n: atoms with more kept neighbours than kRecCap
-    int *drop_count;            // reset to 0 here
+    int *drop_count;            // 0 on entry (the finalize / batch set-up kernels reset it)
     const double *pos_build;    // n x 3 positions of the last build (stale check)
     double stale_sq;            // (skin / 2)^2
     int atoms_per_batch;        // B: centre atoms per batch (<= kWave), shared with the compute kernel
+    // batches of systems (null for one system): atom count, box of each atom's system
+    const int *n_dev;
+    const SysDesc *sys;
+    const int *sys_of;
 };
 
 struct ComputeLaunch {
@@ -89,36 +119,41 @@ struct ComputeLaunch {
     double *partials;           // grid x 8
     long long *counters;        // grid x 2 (pairs, triplets)
     int atoms_per_batch;        // nominal atoms per batch (<= kWave)
+    int plane_stride;           // atoms per force plane (n, or the batch capacity)
+    // batches of systems (null for one system): atom count; per-atom energy
+    // and virial (8 doubles per atom) in place of the per-workgroup partials
+    const int *n_dev;
+    double *eatom;
 };
 
 // Launchers (compute.hip).  grids = {pack, compute} workgroup counts plus
 // kBigGrid for the fixup kernel.
-void compute_grids(bool mixed, bool one_type, int n, int atoms_per_batch, int grids[3]);
+void compute_grids(bool mixed, bool one_type, bool batched, int n, int atoms_per_batch, int grids[3]);
 size_t record_bytes(bool mixed);
 hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s);
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mixed,
                           int grid, hipStream_t s);
 hipError_t launch_fixup_dropped(const int *row_count, const int *jn, const int *rv, int cap,
                                 const signed char *slotpos, const int *drop_list, const int *drop_count,
-                                int n, double *planes, hipStream_t s);
+                                int plane_stride, double *planes, hipStream_t s);
+// Sums the partials into out7 / counts_out and resets *drop_count to 0.
 hipError_t launch_finalize(const double *partials, const long long *counters, int grid,
-                           double *out7, long long *counts_out, hipStream_t s);
+                           double *out7, long long *counts_out, int *drop_count, hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
 hipError_t launch_gather_forces(const int *pcount, const double *planes, const double *own, int n,
-                                double *forces, hipStream_t s);
+                                const int *n_dev, int plane_stride, double *forces, hipStream_t s);
+// Per-system sums of the per-atom energy / virial of a batch and status bits
+// (1: a neighbour row over capacity, 2: an atom over the record capacity):
+// out[8 s + c] = E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, status.
+hipError_t launch_reduce_systems(const SysDesc *sys, const BatchDims *dims, int max_sys, const double *eatom,
+                                 const int *drop_list, const int *drop_count, const int *sys_status,
+                                 double *out, hipStream_t s);
+hipError_t launch_fill_zero_int(int *p, size_t count, hipStream_t s);
 
 // Neighbour build (neighbors.hip)
-struct CellGrid {
-    int nc[3];
-    double L[3];
-    double invL[3];
-    double cell_w[3];
-    float Lf[3], invLf[3];   // single-precision copies for the conservative pre-test
-    float Lsum;              // Lf[0] + Lf[1] + Lf[2]
-};
 hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,
                             int *cell_of, int *rank_in_cell, int *cell_count, int *flags, hipStream_t s);
-hipError_t launch_scatter_cells(const double *pos, int n, const int *cell_of,
+hipError_t launch_scatter_cells(const double *pos, int n, const int *n_dev, const int *cell_of,
                                 const int *rank_in_cell, const int *cell_start,
                                 int *cell_atoms, double *cell_pos, hipStream_t s);
 hipError_t launch_search(const CellGrid &g, double rcut, const int *cell_start, const int *cell_count,
@@ -126,8 +161,18 @@ hipError_t launch_search(const CellGrid &g, double rcut, const int *cell_start, 
                          int *row_count, hipStream_t s);
 // rv[e] for entry e = (i, j) = i * cap + q: the entry of i in row j (the
 // list is symmetric).  Sets *flags |= 4 if some reverse entry is missing.
-hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, int n, int *rv, int *flags,
-                              hipStream_t s);
+hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, int n, const int *n_dev, int *rv,
+                              int *flags, hipStream_t s);
+// Batched build: binning of every system's atoms into its own cells, and the
+// supercell search over all systems; a row over `cap` is stored empty and
+// raises bit 1 of its system's status.
+hipError_t launch_bin_systems(const double *pos, const int *sys_of, const SysDesc *sys, const BatchDims *dims,
+                              int max_atoms, int *cell_of, int *rank_in_cell, int *cell_count, hipStream_t s);
+hipError_t launch_search_systems(const SysDesc *sys, const BatchDims *dims, int max_super, double rcut,
+                                 const int *cell_start, const int *cell_count, const int *cell_atoms,
+                                 const double *cell_pos, int cap, int *ell, int *row_count, int *sys_status,
+                                 hipStream_t s);
+int supercells(const int nc[3]);   // supercells of a grid (the search's work items)
 constexpr int kMaxRow = 256;    // longest neighbour row the build supports
 
 // Exclusive scan of n int32 values; out[n] receives the total.  tmp must hold

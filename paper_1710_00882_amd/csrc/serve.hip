@@ -1,0 +1,634 @@
+// Serving runtime: many small, independent configurations (each with its own
+// periodic box) evaluated in batches.
+//
+// Requests wait in a FIFO queue.  A worker thread forms a batch from the head
+// of the queue -- as many requests as fit the batch's atom, configuration,
+// cell and supercell capacities (the device-memory budget fixed at start) and
+// share one precision -- concatenates their atoms into pinned staging
+// buffers, and launches it on one of two buffer sets, each with its own
+// stream.  While one batch runs, the next is formed from whatever arrived in
+// the meantime and launched on the other set (continuous batching); results
+// are handed back in launch order.
+//
+// The device work of a batch is one captured HIP graph per buffer set and
+// precision, replayed for every batch: the kernels read the batch's sizes and
+// per-configuration descriptors from device memory, so a replay needs only
+// the host-to-device copies of the inputs and descriptors before it and the
+// copies of the results after it.  Graph contents: clear counters -> bin every
+// configuration's atoms into its own cells -> scan -> scatter -> supercell
+// search over all configurations -> reverse map -> pack -> energy / force /
+// virial kernel (per-atom energy and virial) -> dropped-atom fixup -> force
+// gather -> per-configuration reduction.  A configuration's result does not
+// depend on the other configurations of its batch or on its place in it.
+#include "serve.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+namespace tsf {
+
+namespace {
+
+constexpr int kLanes = 2;          // buffer sets (batches in flight)
+constexpr int kServeBatchAtoms = 16;
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+template <typename T>
+struct Dev {
+    T *p = nullptr;
+    hipError_t alloc(size_t n, size_t &total)
+    {
+        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        hipError_t e = hipMalloc((void **)&p, bytes);
+        if (e == hipSuccess) total += bytes;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    }
+};
+
+template <typename T>
+struct Pinned {
+    T *p = nullptr;
+    hipError_t alloc(size_t n)
+    {
+        return hipHostMalloc((void **)&p, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault);
+    }
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+    }
+};
+
+struct Pending {
+    uint64_t ticket;
+    tersoff_request req;
+    int64_t t_start;   // max(submit time, release time)
+    CellGrid g;
+    int ncell, nsuper;
+};
+
+struct Lane {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};   // [FP64, mixed]
+    Pinned<double> h_pos, h_forces, h_out;
+    Pinned<int> h_types, h_sys_of;
+    Pinned<SysDesc> h_desc;
+    Pinned<BatchDims> h_dims;
+    Dev<double> pos, cell_pos, own, planes, forces, eatom, out;
+    Dev<int> types, sys_of, cell_of, rank, cell_count, cell_start, cell_atoms, scan_tmp;
+    Dev<int> ell, row_count, rv, pcount, drop_list, ctl;   // ctl: [0] flags, [1] dropped count, [2..] status
+    Dev<signed char> slotpos;
+    Dev<unsigned char> recs;
+    Dev<SysDesc> desc;
+    Dev<BatchDims> dims;
+    std::vector<Pending> batch;
+    int natoms = 0;
+    bool mixed = false;
+    bool want_forces = false;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct Server {
+    ServerEnv env{};
+    int max_atoms = 0, max_sys = 0, max_cells = 0, max_super = 0, cap = 0;
+    double rc = 0.0;
+    size_t max_queued = 0;
+    size_t device_bytes = 0;
+    int grids[2][3] = {};
+    Lane lanes[kLanes];
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Pending> queue;
+    std::unordered_map<uint64_t, tersoff_result> results;
+    std::unordered_set<uint64_t> live;   // submitted, result not yet collected
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    double n_batches = 0, n_systems = 0, n_atoms = 0;
+};
+
+namespace {
+
+#define SRV_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return e_;               \
+    } while (0)
+
+// Cell grid of one box: cells at least rc wide (as in the single-system
+// build), at most 1024 per axis.
+CellGrid grid_of(const double box[3], double rc, long long &ncell)
+{
+    CellGrid g{};
+    ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.L[a] = box[a];
+        g.invL[a] = 1.0 / box[a];
+        g.Lf[a] = (float)box[a];
+        g.invLf[a] = (float)(1.0 / box[a]);
+        g.nc[a] = std::max(1, (int)std::floor(box[a] / (rc * (1.0 + 1e-10))));
+        g.nc[a] = std::min(g.nc[a], 1024);
+        g.cell_w[a] = box[a] / g.nc[a];
+        ncell *= g.nc[a];
+    }
+    g.Lsum = g.Lf[0] + g.Lf[1] + g.Lf[2];
+    return g;
+}
+
+hipError_t alloc_lane(Server &S, Lane &L)
+{
+    const size_t A = (size_t)S.max_atoms, NS = (size_t)S.max_sys, NC = (size_t)S.max_cells;
+    const size_t E = A * (size_t)S.cap;
+    size_t &tot = S.device_bytes;
+    SRV_TRY(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
+    SRV_TRY(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+    SRV_TRY(L.h_pos.alloc(3 * A));
+    SRV_TRY(L.h_forces.alloc(3 * A));
+    SRV_TRY(L.h_out.alloc(8 * NS));
+    SRV_TRY(L.h_types.alloc(A));
+    SRV_TRY(L.h_sys_of.alloc(A));
+    SRV_TRY(L.h_desc.alloc(NS));
+    SRV_TRY(L.h_dims.alloc(1));
+    SRV_TRY(L.pos.alloc(3 * A, tot));
+    SRV_TRY(L.cell_pos.alloc(3 * A, tot));
+    SRV_TRY(L.own.alloc(3 * A, tot));
+    SRV_TRY(L.planes.alloc(3 * (size_t)kRecCap * A, tot));
+    SRV_TRY(L.forces.alloc(3 * A, tot));
+    SRV_TRY(L.eatom.alloc(8 * A, tot));
+    SRV_TRY(L.out.alloc(8 * NS, tot));
+    SRV_TRY(L.types.alloc(A, tot));
+    SRV_TRY(L.sys_of.alloc(A, tot));
+    SRV_TRY(L.cell_of.alloc(A, tot));
+    SRV_TRY(L.rank.alloc(A, tot));
+    SRV_TRY(L.cell_count.alloc(NC, tot));
+    SRV_TRY(L.cell_start.alloc(NC + 1, tot));
+    SRV_TRY(L.cell_atoms.alloc(A, tot));
+    SRV_TRY(L.scan_tmp.alloc(scan_tmp_size((int)NC), tot));
+    SRV_TRY(L.ell.alloc(E, tot));
+    SRV_TRY(L.row_count.alloc(A, tot));
+    SRV_TRY(L.rv.alloc(E, tot));
+    SRV_TRY(L.pcount.alloc(A, tot));
+    SRV_TRY(L.drop_list.alloc(A, tot));
+    SRV_TRY(L.ctl.alloc(2 + NS, tot));
+    SRV_TRY(L.slotpos.alloc(E, tot));
+    const size_t nbat = (A + kServeBatchAtoms - 1) / kServeBatchAtoms;
+    SRV_TRY(L.recs.alloc(record_bytes(false) * kRecCap * nbat * kServeBatchAtoms, tot));
+    SRV_TRY(L.desc.alloc(NS, tot));
+    SRV_TRY(L.dims.alloc(1, tot));
+    // A row cleared for exceeding the capacity leaves reverse entries of its
+    // partners unwritten; start them (and the ranks they index) at valid
+    // values so that such a configuration only yields a flagged result.
+    SRV_TRY(hipMemsetAsync(L.rv.p, 0, sizeof(int) * E, L.stream));
+    SRV_TRY(hipMemsetAsync(L.slotpos.p, 0xff, E, L.stream));
+    SRV_TRY(hipMemsetAsync(L.pcount.p, 0, sizeof(int) * A, L.stream));
+    return hipStreamSynchronize(L.stream);
+}
+
+void free_lane(Lane &L)
+{
+    for (auto &x : L.exec)
+        if (x) (void)hipGraphExecDestroy(x), x = nullptr;
+    L.h_pos.release(); L.h_forces.release(); L.h_out.release(); L.h_types.release();
+    L.h_sys_of.release(); L.h_desc.release(); L.h_dims.release();
+    L.pos.release(); L.cell_pos.release(); L.own.release(); L.planes.release(); L.forces.release();
+    L.eatom.release(); L.out.release(); L.types.release(); L.sys_of.release(); L.cell_of.release();
+    L.rank.release(); L.cell_count.release(); L.cell_start.release(); L.cell_atoms.release();
+    L.scan_tmp.release(); L.ell.release(); L.row_count.release(); L.rv.release(); L.pcount.release();
+    L.drop_list.release(); L.ctl.release(); L.slotpos.release(); L.recs.release(); L.desc.release();
+    L.dims.release();
+    if (L.done) (void)hipEventDestroy(L.done), L.done = nullptr;
+    if (L.stream) (void)hipStreamDestroy(L.stream), L.stream = nullptr;
+}
+
+// The device work of one batch, enqueued on the lane's stream (captured once
+// per precision; no allocation, no memset nodes, no host synchronisation).
+hipError_t enqueue_batch(Server &S, Lane &L, bool mixed)
+{
+    hipStream_t s = L.stream;
+    const int *n_dev = &L.dims.p->n_atoms;
+    SRV_TRY(launch_fill_zero_int(L.cell_count.p, (size_t)S.max_cells, s));
+    SRV_TRY(launch_fill_zero_int(L.ctl.p, 2 + (size_t)S.max_sys, s));
+    SRV_TRY(launch_bin_systems(L.pos.p, L.sys_of.p, L.desc.p, L.dims.p, S.max_atoms, L.cell_of.p, L.rank.p,
+                               L.cell_count.p, s));
+    SRV_TRY(launch_exclusive_scan(L.cell_count.p, L.cell_start.p, S.max_cells, L.scan_tmp.p, nullptr, s));
+    SRV_TRY(launch_scatter_cells(L.pos.p, S.max_atoms, n_dev, L.cell_of.p, L.rank.p, L.cell_start.p,
+                                 L.cell_atoms.p, L.cell_pos.p, s));
+    SRV_TRY(launch_search_systems(L.desc.p, L.dims.p, S.max_super, S.rc, L.cell_start.p, L.cell_count.p,
+                                  L.cell_atoms.p, L.cell_pos.p, S.cap, L.ell.p, L.row_count.p, L.ctl.p + 2, s));
+    SRV_TRY(launch_reverse_map(L.ell.p, S.cap, L.row_count.p, S.max_atoms, n_dev, L.rv.p, L.ctl.p, s));
+
+    PackLaunch pk{};
+    pk.pos = L.pos.p;
+    pk.types = L.types.p;
+    pk.row_count = L.row_count.p;
+    pk.jn = L.ell.p;
+    pk.rv = L.rv.p;
+    pk.cap = S.cap;
+    pk.n = S.max_atoms;
+    pk.recs = L.recs.p;
+    pk.pcount = L.pcount.p;
+    pk.slotpos = L.slotpos.p;
+    pk.own = L.own.p;
+    pk.flags = L.ctl.p;
+    pk.drop_list = L.drop_list.p;
+    pk.drop_count = L.ctl.p + 1;
+    pk.pos_build = L.pos.p;
+    pk.stale_sq = 0.0;
+    pk.atoms_per_batch = kServeBatchAtoms;
+    pk.n_dev = n_dev;
+    pk.sys = L.desc.p;
+    pk.sys_of = L.sys_of.p;
+    SRV_TRY(launch_pack(pk, S.env.tab, mixed, S.grids[mixed][0], s));
+
+    ComputeLaunch a{};
+    a.types = L.types.p;
+    a.recs = L.recs.p;
+    a.pcount = L.pcount.p;
+    a.slotpos = L.slotpos.p;
+    a.n = S.max_atoms;
+    a.own = L.own.p;
+    a.planes = L.planes.p;
+    a.atoms_per_batch = kServeBatchAtoms;
+    a.plane_stride = S.max_atoms;
+    a.n_dev = n_dev;
+    a.eatom = L.eatom.p;
+    SRV_TRY(launch_compute(a, S.env.tab, mixed, S.grids[mixed][1], s));
+    SRV_TRY(launch_fixup_dropped(L.row_count.p, L.ell.p, L.rv.p, S.cap, L.slotpos.p, L.drop_list.p, L.ctl.p + 1,
+                                 S.max_atoms, L.planes.p, s));
+    SRV_TRY(launch_gather_forces(L.pcount.p, L.planes.p, L.own.p, S.max_atoms, n_dev, S.max_atoms, L.forces.p, s));
+    SRV_TRY(launch_reduce_systems(L.desc.p, L.dims.p, S.max_sys, L.eatom.p, L.drop_list.p, L.ctl.p + 1,
+                                  L.ctl.p + 2, L.out.p, s));
+    return hipSuccess;
+}
+
+hipError_t capture(Server &S, Lane &L, bool mixed)
+{
+    hipGraph_t g = nullptr;
+    SRV_TRY(hipStreamBeginCapture(L.stream, hipStreamCaptureModeRelaxed));
+    const hipError_t e = enqueue_batch(S, L, mixed);
+    const hipError_t e2 = hipStreamEndCapture(L.stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return e != hipSuccess ? e : e2;
+    }
+    const hipError_t e3 = hipGraphInstantiate(&L.exec[mixed ? 1 : 0], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e3;
+}
+
+// Takes requests from the head of the queue while they are released, share
+// the head's precision and fit the capacities (called with the lock held).
+void form_batch(Server &S, Lane &L)
+{
+    L.batch.clear();
+    const int64_t now = now_ns();
+    int natoms = 0, ncell = 0, nsuper = 0;
+    while (!S.queue.empty() && (int)L.batch.size() < S.max_sys) {
+        const Pending &p = S.queue.front();
+        if (p.t_start > now) break;
+        if (!L.batch.empty() && (p.req.precision == TERSOFF_MIXED) != L.mixed) break;
+        if (natoms + p.req.n > S.max_atoms || ncell + p.ncell > S.max_cells || nsuper + p.nsuper > S.max_super)
+            break;
+        if (L.batch.empty()) L.mixed = p.req.precision == TERSOFF_MIXED;
+        natoms += (int)p.req.n;
+        ncell += p.ncell;
+        nsuper += p.nsuper;
+        L.batch.push_back(p);
+        S.queue.pop_front();
+    }
+}
+
+hipError_t launch_lane(Server &S, Lane &L)
+{
+    int off = 0, coff = 0, soff = 0;
+    L.want_forces = false;
+    const int nsys = (int)L.batch.size();
+    for (int q = 0; q < nsys; ++q) {
+        const Pending &p = L.batch[q];
+        const int n = (int)p.req.n;
+        std::memcpy(L.h_pos.p + 3 * (size_t)off, p.req.pos, sizeof(double) * 3 * (size_t)n);
+        std::memcpy(L.h_types.p + off, p.req.types, sizeof(int) * (size_t)n);
+        std::fill(L.h_sys_of.p + off, L.h_sys_of.p + off + n, q);
+        SysDesc &d = L.h_desc.p[q];
+        d.g = p.g;
+        d.atom_off = off;
+        d.natoms = n;
+        d.cell_off = coff;
+        d.super_off = soff;
+        off += n;
+        coff += p.ncell;
+        soff += p.nsuper;
+        L.want_forces |= p.req.forces != nullptr;
+    }
+    L.natoms = off;
+    *L.h_dims.p = BatchDims{off, coff, soff, nsys};
+    hipStream_t s = L.stream;
+    SRV_TRY(hipMemcpyAsync(L.pos.p, L.h_pos.p, sizeof(double) * 3 * (size_t)off, hipMemcpyHostToDevice, s));
+    SRV_TRY(hipMemcpyAsync(L.types.p, L.h_types.p, sizeof(int) * (size_t)off, hipMemcpyHostToDevice, s));
+    SRV_TRY(hipMemcpyAsync(L.sys_of.p, L.h_sys_of.p, sizeof(int) * (size_t)off, hipMemcpyHostToDevice, s));
+    SRV_TRY(hipMemcpyAsync(L.desc.p, L.h_desc.p, sizeof(SysDesc) * (size_t)nsys, hipMemcpyHostToDevice, s));
+    SRV_TRY(hipMemcpyAsync(L.dims.p, L.h_dims.p, sizeof(BatchDims), hipMemcpyHostToDevice, s));
+    SRV_TRY(hipGraphLaunch(L.exec[L.mixed ? 1 : 0], s));
+    SRV_TRY(hipMemcpyAsync(L.h_out.p, L.out.p, sizeof(double) * 8 * (size_t)nsys, hipMemcpyDeviceToHost, s));
+    if (L.want_forces)
+        SRV_TRY(hipMemcpyAsync(L.h_forces.p, L.forces.p, sizeof(double) * 3 * (size_t)off, hipMemcpyDeviceToHost,
+                               s));
+    return hipEventRecord(L.done, s);
+}
+
+// Results of a finished (or failed) batch to the waiting callers.
+void retire(Server &S, Lane &L, hipError_t status)
+{
+    const int64_t now = now_ns();
+    std::vector<std::pair<uint64_t, tersoff_result>> out;
+    out.reserve(L.batch.size());
+    for (size_t q = 0; q < L.batch.size(); ++q) {
+        const Pending &p = L.batch[q];
+        tersoff_result r{};
+        r.tag = p.req.tag;
+        r.n = p.req.n;
+        r.batch_systems = (int32_t)L.batch.size();
+        if (status != hipSuccess) {
+            r.status = TERSOFF_E_DEVICE;
+        } else {
+            const double *o = L.h_out.p + 8 * q;
+            const int st = (int)o[7];
+            r.status = st ? TERSOFF_E_OVERFLOW : TERSOFF_OK;
+            r.energy = o[0];
+            for (int c = 0; c < 6; ++c) r.virial[c] = o[1 + c];
+            if (p.req.forces)
+                std::memcpy(p.req.forces, L.h_forces.p + 3 * (size_t)L.h_desc.p[q].atom_off,
+                            sizeof(double) * 3 * (size_t)p.req.n);
+        }
+        r.latency_ms = 1e-6 * (double)(now - p.t_start);
+        out.emplace_back(p.ticket, r);
+    }
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        for (auto &pr : out) S.results[pr.first] = pr.second;
+        S.n_batches += 1;
+        S.n_systems += (double)L.batch.size();
+        S.n_atoms += (double)L.natoms;
+    }
+    S.cv_done.notify_all();
+    L.batch.clear();
+    L.busy = false;
+}
+
+void worker_main(Server *Sp)
+{
+    Server &S = *Sp;
+    (void)hipSetDevice(S.env.device);
+    std::deque<int> inflight;   // lanes in launch order
+    for (;;) {
+        while (!inflight.empty()) {
+            Lane &L = S.lanes[inflight.front()];
+            const hipError_t q = hipEventQuery(L.done);
+            if (q == hipErrorNotReady) break;
+            retire(S, L, q);
+            inflight.pop_front();
+        }
+        int free_lane = -1;
+        for (int l = 0; l < kLanes; ++l)
+            if (!S.lanes[l].busy) {
+                free_lane = l;
+                break;
+            }
+        if (free_lane >= 0) {
+            Lane &L = S.lanes[free_lane];
+            {
+                std::unique_lock<std::mutex> lk(S.mu);
+                form_batch(S, L);
+                if (L.batch.empty() && inflight.empty()) {
+                    if (S.stopping && S.queue.empty()) break;
+                    if (S.queue.empty()) {
+                        S.cv_work.wait(lk, [&] { return S.stopping || !S.queue.empty(); });
+                    } else {
+                        const int64_t wait = S.queue.front().t_start - now_ns();
+                        if (wait > 0) S.cv_work.wait_for(lk, std::chrono::nanoseconds(wait));
+                    }
+                    continue;
+                }
+            }
+            if (!L.batch.empty()) {
+                L.busy = true;
+                const hipError_t e = launch_lane(S, L);
+                if (e != hipSuccess) {
+                    (void)hipStreamSynchronize(L.stream);
+                    retire(S, L, e);
+                } else {
+                    inflight.push_back(free_lane);
+                }
+                continue;
+            }
+        }
+        if (inflight.empty()) continue;
+        if (free_lane < 0) {
+            (void)hipEventSynchronize(S.lanes[inflight.front()].done);
+        } else {
+            // a lane is free but nothing is ready: wake on a new request or
+            // after a short interval to retire the running batch
+            std::unique_lock<std::mutex> lk(S.mu);
+            S.cv_work.wait_for(lk, std::chrono::microseconds(20));
+        }
+    }
+}
+
+}  // namespace
+
+int server_create(const ServerEnv &env, const tersoff_serve_config &cfg, Server **out, std::string &err)
+{
+    *out = nullptr;
+    const double cutoff = cfg.cutoff > 0 ? cfg.cutoff : env.max_cut;
+    if (!(cutoff >= env.max_cut) || !(cfg.skin >= 0) || !std::isfinite(cfg.skin)) {
+        err = "cutoff below the largest R + D, or negative skin";
+        return TERSOFF_E_INVALID;
+    }
+    const int cap = cfg.max_neighbors > 0 ? ((cfg.max_neighbors + 7) / 8) * 8 : 48;
+    if (cap > kMaxRow) {
+        err = "max_neighbors above 256";
+        return TERSOFF_E_INVALID;
+    }
+    if (cfg.max_batch_atoms < 1 || cfg.max_batch_atoms > (1 << 24) || cfg.max_batch_systems < 1 ||
+        cfg.max_batch_systems > (1 << 20) || (long long)cfg.max_batch_atoms * cap >= (1LL << 31)) {
+        err = "max_batch_atoms must be in [1, 2^24] with max_batch_atoms x row capacity < 2^31, "
+              "max_batch_systems in [1, 2^20]";
+        return TERSOFF_E_INVALID;
+    }
+    Server *S = new (std::nothrow) Server();
+    if (!S) return TERSOFF_E_NOMEM;
+    S->env = env;
+    S->max_atoms = (int)cfg.max_batch_atoms;
+    S->max_sys = cfg.max_batch_systems;
+    S->max_cells = std::max(S->max_atoms, 4096);
+    S->max_super = S->max_cells;
+    S->cap = cap;
+    S->rc = cutoff + cfg.skin;
+    S->max_queued = cfg.max_queued > 0 ? (size_t)cfg.max_queued : 65536;
+    compute_grids(false, env.ntypes == 1, true, S->max_atoms, kServeBatchAtoms, S->grids[0]);
+    compute_grids(true, env.ntypes == 1, true, S->max_atoms, kServeBatchAtoms, S->grids[1]);
+    hipError_t e = hipSetDevice(env.device);
+    for (int l = 0; l < kLanes && e == hipSuccess; ++l) e = alloc_lane(*S, S->lanes[l]);
+    for (int l = 0; l < kLanes && e == hipSuccess; ++l) {
+        e = capture(*S, S->lanes[l], false);
+        if (e == hipSuccess) e = capture(*S, S->lanes[l], true);
+    }
+    if (e != hipSuccess) {
+        err = std::string("serving set-up: ") + hipGetErrorString(e);
+        for (auto &L : S->lanes) free_lane(L);
+        delete S;
+        return e == hipErrorOutOfMemory ? TERSOFF_E_NOMEM : TERSOFF_E_DEVICE;
+    }
+    try {
+        S->worker = std::thread(worker_main, S);
+    } catch (...) {
+        for (auto &L : S->lanes) free_lane(L);
+        delete S;
+        err = "cannot start the serving thread";
+        return TERSOFF_E_DEVICE;
+    }
+    *out = S;
+    return TERSOFF_OK;
+}
+
+void server_destroy(Server *S)
+{
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stopping = true;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    (void)hipSetDevice(S->env.device);
+    for (auto &L : S->lanes) {
+        if (L.stream) (void)hipStreamSynchronize(L.stream);
+        free_lane(L);
+    }
+    delete S;
+}
+
+int server_submit(Server *S, const tersoff_request &req, uint64_t *ticket, std::string &err)
+{
+    if (!req.pos || !req.types || req.n < 1) {
+        err = "request needs positions, types and n >= 1";
+        return TERSOFF_E_INVALID;
+    }
+    if (req.n > S->max_atoms) {
+        err = "request larger than the batch capacity";
+        return TERSOFF_E_INVALID;
+    }
+    if (req.precision != TERSOFF_FP64 && req.precision != TERSOFF_MIXED) {
+        err = "precision must be TERSOFF_FP64 or TERSOFF_MIXED";
+        return TERSOFF_E_INVALID;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (!(req.box[a] > 0) || !std::isfinite(req.box[a])) {
+            err = "box must be positive";
+            return TERSOFF_E_INVALID;
+        }
+        if (req.box[a] < 2.0 * S->rc) {
+            err = "box length below 2 (cutoff + skin)";
+            return TERSOFF_E_BOX;
+        }
+    }
+    for (int64_t i = 0; i < req.n; ++i) {
+        if (req.types[i] < 0 || req.types[i] >= S->env.ntypes) {
+            err = "type out of range";
+            return TERSOFF_E_INVALID;
+        }
+        if (!std::isfinite(req.pos[3 * i]) || !std::isfinite(req.pos[3 * i + 1]) ||
+            !std::isfinite(req.pos[3 * i + 2])) {
+            err = "non-finite position";
+            return TERSOFF_E_INVALID;
+        }
+    }
+    Pending p{};
+    p.req = req;
+    long long ncell = 0;
+    p.g = grid_of(req.box, S->rc, ncell);
+    if (ncell > S->max_cells) {
+        err = "box has more cells than a batch holds";
+        return TERSOFF_E_INVALID;
+    }
+    p.ncell = (int)ncell;
+    p.nsuper = supercells(p.g.nc);
+    const int64_t now = now_ns();
+    p.t_start = std::max<int64_t>(now, req.release_ns);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stopping) {
+            err = "server is stopping";
+            return TERSOFF_E_STATE;
+        }
+        if (S->queue.size() >= S->max_queued) {
+            err = "queue full";
+            return TERSOFF_E_AGAIN;
+        }
+        p.ticket = S->next_ticket++;
+        S->queue.push_back(p);
+        S->live.insert(p.ticket);
+    }
+    S->cv_work.notify_one();
+    *ticket = p.ticket;
+    return TERSOFF_OK;
+}
+
+int server_poll(Server *S, uint64_t ticket, tersoff_result *res, double timeout_ms, std::string &err)
+{
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (!S->live.count(ticket)) {
+        err = "unknown ticket (never issued, or its result was already collected)";
+        return TERSOFF_E_INVALID;
+    }
+    auto ready = [&] { return S->results.count(ticket) != 0; };
+    if (!ready() && timeout_ms > 0) {
+        const auto until = std::chrono::steady_clock::now() +
+                           std::chrono::nanoseconds((int64_t)(timeout_ms * 1e6));
+        S->cv_done.wait_until(lk, until, ready);
+    }
+    auto it = S->results.find(ticket);
+    if (it == S->results.end()) return TERSOFF_E_PENDING;
+    *res = it->second;
+    S->results.erase(it);
+    S->live.erase(ticket);
+    return TERSOFF_OK;
+}
+
+void server_stats(Server *S, double out[6])
+{
+    std::lock_guard<std::mutex> lk(S->mu);
+    out[0] = S->n_batches;
+    out[1] = S->n_systems;
+    out[2] = S->n_atoms;
+    out[3] = (double)S->device_bytes;
+    out[4] = (double)S->max_atoms;
+    out[5] = (double)S->max_sys;
+}
+
+}  // namespace tsf
+
+extern "C" int64_t tersoff_clock_ns(void) { return tsf::now_ns(); }

@@ -2,6 +2,7 @@
 // include/tersoff.h).  The context owns every device buffer; positions,
 // types and the neighbour list stay resident between calls.
 #include "internal.h"
+#include "serve.h"
 
 #include "tersoff.h"
 
@@ -76,6 +77,8 @@ struct tersoff_ctx {
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_compute, ev_build, ev_gather, ev_pack;
     std::vector<hipEvent_t> ev_pool;
+
+    tsf::Server *server = nullptr;   // serving runtime (tersoff_serve_start .. tersoff_serve_stop)
 
     std::string last_error;
 };
@@ -249,6 +252,8 @@ int tersoff_create(const double *params, int32_t ntypes, tersoff_ctx **out)
 void tersoff_destroy(tersoff_ctx *c)
 {
     if (!c) return;
+    tsf::server_destroy(c->server);
+    c->server = nullptr;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     c->pos_build.release(); c->types.release(); c->offsets.release();
@@ -303,8 +308,8 @@ int tersoff_set_batch_atoms(tersoff_ctx *c, int32_t atoms)
     if (atoms < 1 || atoms > kWave) return fail(c, TERSOFF_E_INVALID, "batch atoms must be in [1, 64]");
     c->atoms_per_batch = atoms;
     if (c->built) {
-        compute_grids(false, c->ntypes == 1, c->n, atoms, c->grid[0]);
-        compute_grids(true, c->ntypes == 1, c->n, atoms, c->grid[1]);
+        compute_grids(false, c->ntypes == 1, false, c->n, atoms, c->grid[0]);
+        compute_grids(true, c->ntypes == 1, false, c->n, atoms, c->grid[1]);
         int gmax = std::max(c->grid[0][1], c->grid[1][1]);
         HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
         HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
@@ -377,7 +382,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, launch_bin_atoms(pos, types, N, c->ntypes, g, c->cell_of.p, c->rank.p, c->cell_count.p,
                                 c->misc.p + 2, s));
     HIP_TRY(c, launch_exclusive_scan(c->cell_count.p, c->cell_start.p, (int)ncell, c->scan_tmp.p, nullptr, s));
-    HIP_TRY(c, launch_scatter_cells(pos, N, c->cell_of.p, c->rank.p, c->cell_start.p,
+    HIP_TRY(c, launch_scatter_cells(pos, N, nullptr, c->cell_of.p, c->rank.p, c->cell_start.p,
                                     c->cell_atoms.p, c->cell_pos.p, s));
     int host[3] = {0, 0, 0};   // list length, longest row, build flags
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -403,7 +408,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, c->rv.ensure(NE));
     HIP_TRY(c, c->slotpos.ensure(NE));
     HIP_TRY(c, c->own.ensure(3 * (size_t)N));
-    HIP_TRY(c, launch_reverse_map(c->ell.p, c->list_cap, c->row_count.p, N, c->rv.p, c->misc.p + 2, s));
+    HIP_TRY(c, launch_reverse_map(c->ell.p, c->list_cap, c->row_count.p, N, nullptr, c->rv.p, c->misc.p + 2, s));
     HIP_TRY(c, hipMemcpyAsync(c->pos_build.p, pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->types.p, types, sizeof(int) * (size_t)N, hipMemcpyDeviceToDevice, s));
     int chk = 0;
@@ -421,8 +426,8 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     for (int a = 0; a < 3; ++a) c->box[a] = box[a];
     c->cutoff = cutoff;
     c->skin = skin;
-    compute_grids(false, c->ntypes == 1, N, c->atoms_per_batch, c->grid[0]);
-    compute_grids(true, c->ntypes == 1, N, c->atoms_per_batch, c->grid[1]);
+    compute_grids(false, c->ntypes == 1, false, N, c->atoms_per_batch, c->grid[0]);
+    compute_grids(true, c->ntypes == 1, false, N, c->atoms_per_batch, c->grid[1]);
     int gmax = std::max(c->grid[0][1], c->grid[1][1]);
     HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
     HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
@@ -487,6 +492,7 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     a.partials = c->partials.p;
     a.counters = c->counters.p;
     a.atoms_per_batch = c->atoms_per_batch;
+    a.plane_stride = c->n;
 
     // event pairs (profiling only): pack, main kernel, fixup + gather
     hipEvent_t ev[6] = {};
@@ -501,9 +507,10 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
     HIP_TRY(c, launch_fixup_dropped(c->row_count.p, c->ell.p, c->rv.p, c->list_cap, c->slotpos.p,
                                     c->drop_list.p, c->misc.p + 3, c->n, c->planes.p, s));
-    HIP_TRY(c, launch_gather_forces(c->pcount.p, c->planes.p, c->own.p, c->n, f, s));
+    HIP_TRY(c, launch_gather_forces(c->pcount.p, c->planes.p, c->own.p, c->n, nullptr, c->n, f, s));
     if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
-    HIP_TRY(c, launch_finalize(c->partials.p, c->counters.p, grid[1], energy_virial, c->counts.p, s));
+    HIP_TRY(c, launch_finalize(c->partials.p, c->counters.p, grid[1], energy_virial, c->counts.p,
+                               c->misc.p + 3, s));
     if (c->profiling) {
         c->ev_pack.emplace_back(ev[0], ev[1]);
         c->ev_compute.emplace_back(ev[2], ev[3]);
@@ -558,6 +565,51 @@ int tersoff_get_counts(tersoff_ctx *c, int64_t counts[3])
     counts[0] = c->S;
     counts[1] = h[0];
     counts[2] = h[1];
+    return TERSOFF_OK;
+}
+
+int tersoff_serve_start(tersoff_ctx *c, const tersoff_serve_config *cfg)
+{
+    if (!c || !cfg) return TERSOFF_E_INVALID;
+    if (c->server) return fail(c, TERSOFF_E_STATE, "serving already started");
+    tsf::ServerEnv env{c->device, c->ntypes, c->max_cut, c->tab};
+    std::string err;
+    const int st = tsf::server_create(env, *cfg, &c->server, err);
+    if (st != TERSOFF_OK) return fail(c, st, err);
+    return TERSOFF_OK;
+}
+
+int tersoff_serve_stop(tersoff_ctx *c)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    if (!c->server) return fail(c, TERSOFF_E_STATE, "serving not started");
+    tsf::server_destroy(c->server);
+    c->server = nullptr;
+    return TERSOFF_OK;
+}
+
+int tersoff_submit(tersoff_ctx *c, const tersoff_request *req, uint64_t *ticket)
+{
+    if (!c || !req || !ticket) return TERSOFF_E_INVALID;
+    if (!c->server) return TERSOFF_E_STATE;
+    std::string err;
+    // messages of the thread-safe calls are not stored in the context
+    return tsf::server_submit(c->server, *req, ticket, err);
+}
+
+int tersoff_poll(tersoff_ctx *c, uint64_t ticket, double timeout_ms, tersoff_result *res)
+{
+    if (!c || !res) return TERSOFF_E_INVALID;
+    if (!c->server) return TERSOFF_E_STATE;
+    std::string err;
+    return tsf::server_poll(c->server, ticket, res, timeout_ms, err);
+}
+
+int tersoff_serve_stats(tersoff_ctx *c, double out[6])
+{
+    if (!c || !out) return TERSOFF_E_INVALID;
+    if (!c->server) return fail(c, TERSOFF_E_STATE, "serving not started");
+    tsf::server_stats(c->server, out);
     return TERSOFF_OK;
 }
 

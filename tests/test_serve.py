@@ -1,0 +1,193 @@
+"""Batched serving (tersoff_serve_start / tersoff_submit / tersoff_poll) on the
+GPU: every configuration's result equals the oracle's (same tolerances as the
+single-system path), is bit-identical whether it runs alone or inside a mixed
+batch, and stays bit-identical over repeated replays of the captured graph
+with other GPU work in between."""
+import numpy as np
+import pytest
+
+from paper_1710_00882_amd import workloads as W
+
+from gpu_helpers import TOL, assert_parity, oracle_eval, say, virial_tol
+
+pytestmark = pytest.mark.gpu
+
+
+def _stream(count, seed, nmax=1500):
+    return W.serve_stream(count=count, seed=seed, nmin=64, nmax=nmax)
+
+
+def _submit_all(model, systems, precision, forces=True, tag0=0):
+    tickets = []
+    outs = []
+    for q, s in enumerate(systems):
+        f = np.zeros_like(s.pos) if forces else None
+        tickets.append(model.submit(s.pos, s.types, s.box, precision, forces=f, tag=tag0 + q))
+        outs.append(f)
+    return [model.wait(t, 60000.0) for t in tickets]
+
+
+@pytest.fixture(scope="module")
+def server():
+    from paper_1710_00882_amd import Tersoff
+    m = Tersoff(W.si_table())
+    m.serve_start(max_batch_atoms=12000, max_batch_systems=24)
+    yield m
+    m.serve_stop()
+    m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_matches_oracle_and_alone(server, precision):
+    table = W.si_table()
+    systems = _stream(16, seed=11)
+    say(f"[serve] {precision}: {len(systems)} configs, sizes {[s.n for s in systems]}")
+    mix = _submit_all(server, systems, precision, tag0=100)
+    assert max(r["batch_systems"] for r in mix) > 1, "no batch held more than one configuration"
+    for q, (s, r) in enumerate(zip(systems, mix)):
+        assert r["status"] == 0 and r["tag"] == 100 + q and r["n"] == s.n
+        Eo, Fo, Vo, _, _ = oracle_eval(s, table)
+        assert_parity(r["energy"], r["forces"], r["virial"], Eo, Fo, Vo, s.n, precision, label=f"serve[{q}]")
+    # the same configurations one at a time: bit-identical results
+    for q in (0, 5, 11):
+        s = systems[q]
+        alone = _submit_all(server, [s], precision, tag0=200)[0]
+        assert alone["batch_systems"] == 1
+        assert alone["energy"] == mix[q]["energy"]
+        assert np.array_equal(alone["virial"], mix[q]["virial"])
+        assert np.array_equal(alone["forces"], mix[q]["forces"])
+
+
+def test_batched_matches_single_system_path(server):
+    from gpu_helpers import gpu_eval
+    table = W.si_table()
+    systems = _stream(6, seed=12)
+    for precision in ("fp64", "mixed"):
+        res = _submit_all(server, systems, precision)
+        for q, (s, r) in enumerate(zip(systems, res)):
+            E, F, V, m = gpu_eval(s, table, precision)
+            m.close()
+            t = TOL[precision]
+            # same per-atom arithmetic; only the energy / virial summation order differs
+            assert abs(r["energy"] - E) / s.n <= 1e-13
+            assert np.abs(r["virial"] - V).max() <= max(1e-13 * np.abs(V).max(), 1e-13 * s.n)
+            ferr = np.linalg.norm(r["forces"] - F) / np.linalg.norm(F)
+            say(f"[serve] single-vs-batched {precision} cfg{q}: force rel {ferr:.2e}")
+            assert ferr <= 0.1 * t["force"]
+
+
+def test_graph_replays_are_identical(server):
+    """Replays of the captured graph, with eager single-system work and
+    synchronisations in between, give bit-identical results."""
+    import torch
+    from gpu_helpers import gpu_eval
+    systems = _stream(10, seed=13)
+    ref = _submit_all(server, systems, "mixed")
+    other = W.si_512()
+    for rep in range(3):
+        gpu_eval(other, W.si_table(), "fp64")[3].close()
+        torch.cuda.synchronize()
+        res = _submit_all(server, systems, "mixed")
+        for a, b in zip(ref, res):
+            assert a["energy"] == b["energy"]
+            assert np.array_equal(a["virial"], b["virial"])
+            assert np.array_equal(a["forces"], b["forces"])
+    st = server.serve_stats()
+    say(f"[serve] stats {st}")
+    assert st["batches"] >= 4 and st["device_bytes"] > 0
+
+
+def test_mixed_precisions_and_no_forces(server):
+    table = W.si_table()
+    systems = _stream(8, seed=14)
+    tickets = []
+    for q, s in enumerate(systems):
+        prec = "mixed" if q % 2 else "fp64"
+        tickets.append((prec, server.submit(s.pos, s.types, s.box, prec, forces=None, tag=q)))
+    for (prec, t), s in zip(tickets, systems):
+        r = server.wait(t)
+        assert r["status"] == 0 and r["forces"] is None
+        Eo, Fo, Vo, _, _ = oracle_eval(s, table)
+        assert abs(r["energy"] - Eo) / s.n <= TOL[prec]["energy"]
+        assert np.abs(r["virial"] - Vo).max() <= virial_tol(Vo, s.n, prec)
+
+
+def test_two_species_serving():
+    from paper_1710_00882_amd import Tersoff
+    table = W.two_species_table()
+    systems = [W.diamond(n, n, m, jitter=0.08, strain=0.03, seed=40 + n + m, ntypes=2)
+               for n, m in ((2, 2), (3, 2), (4, 3), (5, 4))]
+    m = Tersoff(table)
+    try:
+        m.serve_start(max_batch_atoms=4096, max_batch_systems=8)
+        for prec in ("fp64", "mixed"):
+            res = _submit_all(m, systems, prec)
+            for q, (s, r) in enumerate(zip(systems, res)):
+                assert r["status"] == 0
+                Eo, Fo, Vo, _, _ = oracle_eval(s, table)
+                assert_parity(r["energy"], r["forces"], r["virial"], Eo, Fo, Vo, s.n, prec,
+                              label=f"serve2[{q}]")
+    finally:
+        m.close()
+
+
+def test_row_overflow_is_reported_per_configuration():
+    """A row capacity below the rows of the configurations flags exactly
+    those configurations; a smaller box (rows that fit) in the same batch is
+    unaffected."""
+    from paper_1710_00882_amd import Tersoff, TersoffError
+    table = W.si_table()
+    m = Tersoff(table)
+    try:
+        # rows of jittered Si within 4 A hold 12-20 atoms; a sparse lattice
+        # (a = 7 A: first shell near the switching zone, second shell beyond 4 A) holds 4
+        dense = W.diamond(3, 3, 2, jitter=0.08, seed=5)
+        sparse = W.diamond(2, 2, 2, a=7.0, jitter=0.05, seed=6)
+        m.serve_start(max_batch_atoms=2048, max_batch_systems=4, max_neighbors=8)
+        res = _submit_all(m, [dense, sparse], "fp64")
+        assert res[0]["status"] == -4
+        assert res[1]["status"] == 0
+        Eo, Fo, Vo, _, _ = oracle_eval(sparse, table)
+        assert_parity(res[1]["energy"], res[1]["forces"], res[1]["virial"], Eo, Fo, Vo, sparse.n, "fp64",
+                      label="sparse")
+        with pytest.raises(TersoffError):
+            m.serve_start(max_batch_atoms=16, max_batch_systems=1)   # already started
+    finally:
+        m.close()
+
+
+def test_submit_errors(server):
+    from paper_1710_00882_amd import TersoffError
+    s = _stream(1, seed=15)[0]
+    bad = s.types.copy()
+    bad[0] = 3
+    with pytest.raises(TersoffError) as e:
+        server.submit(s.pos, bad, s.box)
+    assert e.value.status == -1
+    with pytest.raises(TersoffError) as e:
+        server.submit(s.pos, s.types, np.array([7.0, 20.0, 20.0]))
+    assert e.value.status == -3
+    big = W.diamond(12, 12, 11)
+    with pytest.raises(TersoffError) as e:
+        server.submit(big.pos, big.types, big.box)       # above max_batch_atoms
+    assert e.value.status == -1
+    p = s.pos.copy()
+    p[1, 2] = np.nan
+    with pytest.raises(TersoffError) as e:
+        server.submit(p, s.types, s.box)
+    assert e.value.status == -1
+    with pytest.raises(TersoffError) as e:
+        server.poll(987654321)
+    assert e.value.status == -1
+
+
+def test_release_time_and_latency(server):
+    from paper_1710_00882_amd._lib import clock_ns
+    s = _stream(1, seed=16)[0]
+    t0 = clock_ns()
+    t = server.submit(s.pos, s.types, s.box, "mixed", release_ns=t0 + 50_000_000)
+    assert server.poll(t, 10.0) is None          # held back until its release time
+    r = server.wait(t)
+    assert r["status"] == 0
+    assert clock_ns() - t0 >= 50_000_000
+    assert 0.0 <= r["latency_ms"] < 5000.0
