@@ -378,17 +378,20 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
 
 // ----------------------------------------------------------- compute kernel -
 
-template <typename real>
+template <typename real, bool ONE>
 struct Shared {
+    static constexpr int kT = ONE ? 1 : kMaxTypes;
     // per centre atom of the batch
     int ti[kWave];
     int pcnt[kWave];
     int pstart[kWave + 1];
     // per packed slot (i, n)
     double fs[kScap][3];         // force on n from i's terms (FP64)
-    real ux[kScap], uy[kScap], uz[kScap], r[kScap], rinv[kScap];
+    real ux[kScap], uy[kScap], uz[kScap], r[kScap];
     real dzeta[kScap];           // dV(i,n,zeta_in)/dzeta
     int mask[kScap];
+    real fc[kT][kScap], dfc[kT][kScap];   // f_C(r_in), f_C'(r_in) of entry (t_i, t, t_n), per partner type t
+    real ep[kScap], em[kScap];            // exp(lambda3 r_in), exp(-lambda3 r_in) (one type, m = 1)
 };
 
 template <typename real>
@@ -450,12 +453,18 @@ __device__ __forceinline__ void exp_term(const ParamR<real> &q, real rj, real rk
 template <typename real, bool ONE, bool BATCHED>
 __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable tab)
 {
-    __shared__ Shared<real> sh;
+    __shared__ Shared<real, ONE> sh;
     __shared__ double sev[BATCHED ? kScap : 1][BATCHED ? 7 : 1];   // per-slot energy and virial
     const int lane = threadIdx.x;
     const ParamR<real> *ptab = table_r<real>(tab);
     const Rec<real> *recs = static_cast<const Rec<real> *>(a.recs);
     const int nt = ONE ? 1 : tab.ntypes;
+    // one species: the single entry, held in registers; the m = 1 factor
+    // exp(lambda3 (r_ij - r_ik)) then separates into per-slot exponentials
+    // (when they stay far from overflow)
+    const ParamR<real> q0 = ptab[0];
+    const bool sep = ONE && q0.m == real(1) && q0.lam3 != real(0) &&
+                     fabs((double)q0.lam3) * (2.0 * (double)q0.R - (double)q0.Rin) < 40.0;
 
     double e_acc = 0.0;
     double w_acc[6] = {0, 0, 0, 0, 0, 0};
@@ -489,7 +498,8 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             const int npacked = __shfl(ip, cut - 1, kWave);
             __syncthreads();
 
-            // ---- slot lanes: load the packed record of pair (i, j)
+            // ---- slot lanes: load the packed record of pair (i, j), and the
+            // switching function of the slot for every partner type
             const int s = lane;
             const bool has_slot = s < npacked;
             int al = 0, jl = 0, pc = 0, sb = 0, j = 0, kpos = -1, mj = 0, ti = 0;
@@ -508,32 +518,53 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 uj[0] = rc.ux; uj[1] = rc.uy; uj[2] = rc.uz;
                 rjinv = M<real>::rcp(rj);
                 sh.ux[s] = uj[0]; sh.uy[s] = uj[1]; sh.uz[s] = uj[2];
-                sh.r[s] = rj; sh.rinv[s] = rjinv;
+                sh.r[s] = rj;
                 sh.mask[s] = mj;
+                for (int t = 0; t < nt; ++t) {
+                    real fc = real(0), dfc = real(0);
+                    if ((mj >> (kThirdBit + t)) & 1)
+                        cutoff_terms(ONE ? q0 : ptab[(ti * nt + t) * nt + (mj & 0xff)], rj, fc, dfc);
+                    sh.fc[t][s] = fc;
+                    sh.dfc[t][s] = dfc;
+                }
+                if (sep) {
+                    sh.ep[s] = M<real>::exp(q0.lam3 * rj);
+                    sh.em[s] = M<real>::exp(-q0.lam3 * rj);
+                }
             }
             __syncthreads();
+
+            // exp((lambda3 (r_a - r_b))^m) and its derivative with respect to r_a
+            auto ex_term = [&](const ParamR<real> &q, int sa, real ra, int sbb, real rbb, real &ex, real &dex) {
+                if (ONE && sep) {
+                    ex = sh.ep[sa] * sh.em[sbb];
+                    dex = q0.lam3 * ex;
+                } else {
+                    exp_term(q, ra, rbb, ex, dex);
+                }
+            };
 
             const int tj = mj & 0xff;
             const bool j_pair = (mj >> kPairBit) & 1;
             double fx = 0, fy = 0, fz = 0;     // force on j from centre i's terms
             double e_pair = 0.0;   // energy of pair (i, j)
             if (has_slot) {
-                // ---- 1: zeta_ij over the other slots k of centre i
+                // ---- 1: zeta_ij over the other slots k of centre i (k = j skipped
+                // by the index map, not by an idle iteration)
                 real zr = real(0);
                 if (j_pair) {
-                    for (int kl = 0; kl < pc; ++kl) {
-                        if (kl == jl) continue;
-                        const int sk = sb + kl;
-                        const int mk = sh.mask[sk];
-                        if (!((mk >> (kThirdBit + tj)) & 1)) continue;
-                        const ParamR<real> &q = ptab[ONE ? 0 : (ti * nt + tj) * nt + (mk & 0xff)];
+                    for (int kk = 0; kk + 1 < pc; ++kk) {
+                        const int sk = sb + kk + (kk >= jl ? 1 : 0);
+                        const int mk = ONE ? 0 : sh.mask[sk];
+                        const ParamR<real> &q = ONE ? q0 : ptab[(ti * nt + tj) * nt + (mk & 0xff)];
                         const real rk = sh.r[sk];
                         const real cs = uj[0] * sh.ux[sk] + uj[1] * sh.uy[sk] + uj[2] * sh.uz[sk];
-                        real fck, dfck, ex, dex;
-                        cutoff_terms(q, rk, fck, dfck);
-                        exp_term(q, rj, rk, ex, dex);
-                        zr += fck * angular(q, cs).g * ex;
-                        ++n_trip;
+                        real ex, dex;
+                        ex_term(q, s, rj, sk, rk, ex, dex);
+                        const real term = sh.fc[ONE ? 0 : tj][sk] * angular(q, cs).g * ex;
+                        const bool member = ONE || ((mk >> (kThirdBit + tj)) & 1);
+                        zr += member ? term : real(0);
+                        n_trip += member ? 1 : 0;
                     }
                 }
                 // ---- 2: pair terms, bond order, dV/dzeta
@@ -541,10 +572,10 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 if (j_pair) {
                     ++n_pairs;
                     const int e_ij = ONE ? 0 : (ti * nt + tj) * nt + tj;
-                    const ParamR<real> &q = ptab[e_ij];
+                    const ParamR<real> &q = ONE ? q0 : ptab[e_ij];
                     const ParamX px = tab.px[e_ij];
-                    real fc, dfc, fr, fa, dfr, dfa;
-                    cutoff_terms(q, rj, fc, dfc);
+                    const real fc = sh.fc[ONE ? 0 : tj][s], dfc = sh.dfc[ONE ? 0 : tj][s];
+                    real fr, fa, dfr, dfa;
                     pair_terms(q, rj, fr, dfr, fa, dfa);
                     // Eq. (2) in FP64 log form
                     const double zeta = (double)zr;
@@ -568,42 +599,53 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             __syncthreads();
 
             if (has_slot) {
-                // ---- 3: second K loop, every force term of centre i on atom j
+                // ---- 3: second K loop, every force term of centre i on atom j:
+                // its j-role terms in (i; j, k) and its k-role terms in (i; k, j)
                 const real dzj = sh.dzeta[s];
-                for (int kl = 0; kl < pc; ++kl) {
-                    if (kl == jl) continue;
-                    const int sk = sb + kl;
-                    const int mk = sh.mask[sk];
-                    const int tk = mk & 0xff;
-                    // j-role in (i; j, k) and k-role in (i; k, j)
-                    const bool use1 = j_pair && ((mk >> (kThirdBit + tj)) & 1) && dzj != real(0);
-                    const real dzk = sh.dzeta[sk];
-                    const bool use2 = ((mk >> kPairBit) & 1) && ((mj >> (kThirdBit + tk)) & 1) && dzk != real(0);
-                    if (!use1 && !use2) continue;
+                const real fcj0 = sh.fc[0][s], dfcj0 = sh.dfc[0][s];
+                for (int kk = 0; kk + 1 < pc; ++kk) {
+                    const int sk = sb + kk + (kk >= jl ? 1 : 0);
                     const real rk = sh.r[sk];
                     const real uk[3] = {sh.ux[sk], sh.uy[sk], sh.uz[sk]};
+                    const real dzk = sh.dzeta[sk];
                     const real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
                     // d cos(theta_ijk) / d x_j
                     const real dc[3] = {(uk[0] - cs * uj[0]) * rjinv, (uk[1] - cs * uj[1]) * rjinv,
                                         (uk[2] - cs * uj[2]) * rjinv};
-                    real cdc = real(0), cu = real(0);   // F_j -= cdc * dc + cu * u_j
-                    if (use1) {
-                        const ParamR<real> &q = ptab[ONE ? 0 : (ti * nt + tj) * nt + tk];
-                        real fck, dfck, ex, dex;
-                        cutoff_terms(q, rk, fck, dfck);
-                        exp_term(q, rj, rk, ex, dex);
-                        const Angular<real> an = angular(q, cs);
-                        cdc += dzj * fck * ex * an.dg;
-                        cu += dzj * fck * an.g * dex;
-                    }
-                    if (use2) {
-                        const ParamR<real> &q = ptab[ONE ? 0 : (ti * nt + tk) * nt + tj];
-                        real fcj, dfcj, ex, dex;
-                        cutoff_terms(q, rj, fcj, dfcj);
-                        exp_term(q, rk, rj, ex, dex);
-                        const Angular<real> an = angular(q, cs);
-                        cdc += dzk * fcj * ex * an.dg;
-                        cu += dzk * (dfcj * an.g * ex - fcj * an.g * dex);
+                    real cdc, cu;   // F_j -= cdc * dc + cu * u_j
+                    if (ONE) {
+                        // one entry: g and g' shared by both roles; dV/dzeta
+                        // is zero for a slot that is no bond partner
+                        const Angular<real> an = angular(q0, cs);
+                        real ex1, dex1, ex2, dex2;
+                        ex_term(q0, s, rj, sk, rk, ex1, dex1);
+                        ex_term(q0, sk, rk, s, rj, ex2, dex2);
+                        const real w1 = dzj * sh.fc[0][sk];
+                        cdc = (w1 * ex1 + dzk * fcj0 * ex2) * an.dg;
+                        cu = an.g * (w1 * dex1 + dzk * (dfcj0 * ex2 - fcj0 * dex2));
+                    } else {
+                        const int mk = sh.mask[sk];
+                        const int tk = mk & 0xff;
+                        cdc = real(0);
+                        cu = real(0);
+                        if (((mk >> (kThirdBit + tj)) & 1) && dzj != real(0)) {
+                            const ParamR<real> &q = ptab[(ti * nt + tj) * nt + tk];
+                            real ex, dex;
+                            ex_term(q, s, rj, sk, rk, ex, dex);
+                            const Angular<real> an = angular(q, cs);
+                            const real w1 = dzj * sh.fc[tj][sk];
+                            cdc += w1 * ex * an.dg;
+                            cu += w1 * an.g * dex;
+                        }
+                        if (((mj >> (kThirdBit + tk)) & 1) && dzk != real(0)) {
+                            const ParamR<real> &q = ptab[(ti * nt + tk) * nt + tj];
+                            real ex, dex;
+                            ex_term(q, sk, rk, s, rj, ex, dex);
+                            const Angular<real> an = angular(q, cs);
+                            const real fcj = sh.fc[tk][s], dfcj = sh.dfc[tk][s];
+                            cdc += dzk * fcj * ex * an.dg;
+                            cu += dzk * an.g * (dfcj * ex - fcj * dex);
+                        }
                     }
                     fx -= (double)(cdc * dc[0] + cu * uj[0]);
                     fy -= (double)(cdc * dc[1] + cu * uj[1]);
