@@ -60,19 +60,19 @@ struct CellGrid {
     float Lf[3], invLf[3];   // single-precision copies for the conservative pre-test
     float Lsum;              // Lf[0] + Lf[1] + Lf[2]
 };
-// One configuration of a batch: its box and cell grid, and where its atoms,
-// cells and supercells start in the batch's concatenated arrays.
+// One configuration of a batch: its box and cell grid, and where its atoms
+// and cells start in the batch's concatenated arrays.
 struct SysDesc {
     CellGrid g;
     int atom_off, natoms;
-    int cell_off, super_off;
+    int cell_off, pad;
 };
 
 // Sizes of the batch in flight, read by the kernels from device memory so
 // that one captured launch sequence serves batches of any size up to the
 // capacities its grids were sized for.
 struct BatchDims {
-    int n_atoms, n_cells, n_super, n_sys;
+    int n_atoms, n_cells, n_sys, pad;
 };
 
 constexpr int kBatchGrid = 2048;   // workgroups of the grid-stride kernels of a batch
@@ -153,26 +153,51 @@ hipError_t launch_fill_zero_int(int *p, size_t count, hipStream_t s);
 // Neighbour build (neighbors.hip)
 hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,
                             int *cell_of, int *rank_in_cell, int *cell_count, int *flags, hipStream_t s);
-hipError_t launch_scatter_cells(const double *pos, int n, const int *n_dev, const int *cell_of,
-                                const int *rank_in_cell, const int *cell_start,
-                                int *cell_atoms, double *cell_pos, hipStream_t s);
-hipError_t launch_search(const CellGrid &g, double rcut, const int *cell_start, const int *cell_count,
-                         const int *cell_atoms, const double *cell_pos, int ncell, int cap, int *ell,
-                         int *row_count, hipStream_t s);
+// Cell-order copies of the atoms (ids, FP64 positions, wrapped FP32
+// positions with the id in the fourth word).  Batches: dims and the
+// per-atom system set, n the capacity the grid is sized for.
+struct ScatterLaunch {
+    const double *pos;
+    int n;
+    const int *cell_of, *rank, *cell_start;
+    int *cell_atoms;
+    double *cell_pos;
+    float4 *cell_posf;
+    CellGrid g;                      // one system
+    const SysDesc *sys;              // batches
+    const int *sys_of;
+    const BatchDims *dims;
+};
+hipError_t launch_scatter_cells(const ScatterLaunch &a, int grid_cap, hipStream_t s);
+
+// Neighbour rows (sorted, stride cap) of every atom; rows longer than cap
+// are not written (row_count holds the true length, or 0 with bit 1 of the
+// system's status in a batch).  long_rows / n_long: scratch for rows too long
+// for the first pass (n_long must be 0 on entry).
+struct SearchLaunch {
+    CellGrid g;
+    const SysDesc *sys;
+    const int *sys_of;
+    const BatchDims *dims;
+    int n;
+    double rc2;
+    float rcs;
+    const int *cell_start, *cell_count, *cell_atoms, *cell_of;
+    const double *cell_pos;
+    const float4 *cell_posf;
+    int cap;
+    int *ell, *row_count;
+    int *long_rows, *n_long;
+    int *sys_status;
+};
+hipError_t launch_search(const SearchLaunch &a, int grid_cap, hipStream_t s);
 // rv[e] for entry e = (i, j) = i * cap + q: the entry of i in row j (the
 // list is symmetric).  Sets *flags |= 4 if some reverse entry is missing.
 hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, int n, const int *n_dev, int *rv,
                               int *flags, hipStream_t s);
-// Batched build: binning of every system's atoms into its own cells, and the
-// supercell search over all systems; a row over `cap` is stored empty and
-// raises bit 1 of its system's status.
+// Batched build: binning of every system's atoms into its own cells.
 hipError_t launch_bin_systems(const double *pos, const int *sys_of, const SysDesc *sys, const BatchDims *dims,
                               int max_atoms, int *cell_of, int *rank_in_cell, int *cell_count, hipStream_t s);
-hipError_t launch_search_systems(const SysDesc *sys, const BatchDims *dims, int max_super, double rcut,
-                                 const int *cell_start, const int *cell_count, const int *cell_atoms,
-                                 const double *cell_pos, int cap, int *ell, int *row_count, int *sys_status,
-                                 hipStream_t s);
-int supercells(const int nc[3]);   // supercells of a grid (the search's work items)
 constexpr int kMaxRow = 256;    // longest neighbour row the build supports
 
 // Exclusive scan of n int32 values; out[n] receives the total.  tmp must hold

@@ -8,13 +8,15 @@
 //
 // Steps: bin atoms to cells (count + rank per cell, input checks) ->
 // exclusive scan of cell counts -> scatter atom ids and positions into cell
-// order -> one wavefront per supercell (a few cells along the last axis)
-// tests the atoms of the surrounding cells and writes each of its atoms' rows,
-// sorted, to the row buffer (row i at i * cap, cap >= the longest row) ->
-// scan of row counts (list length, longest row) -> reverse-entry map.
+// order -> one thread per atom tests the atoms of the 27 surrounding cells and
+// writes its row, sorted, to the row buffer (row i at i * cap, cap >= the
+// longest row; rows too long for the thread's LDS buffer go to a wavefront
+// per row) -> scan of row counts (list length, longest row) -> reverse-entry
+// map.
 #include "internal.h"
 
 #include <algorithm>
+#include <climits>
 
 #pragma clang fp contract(off)
 
@@ -72,20 +74,27 @@ __global__ void k_bin_systems(const double *__restrict__ pos, const int *__restr
     }
 }
 
-// n_dev, when not null, holds the atom count (batches); n is then the
-// capacity the grid was sized for.
-__global__ void k_scatter(const double *__restrict__ pos, int n, const int *__restrict__ n_dev,
-                          const int *__restrict__ cell_of, const int *__restrict__ rank,
-                          const int *__restrict__ cell_start, int *__restrict__ cell_atoms,
-                          double *__restrict__ cell_pos)
+// Atom ids and positions in cell order; also the position wrapped into the
+// box (as in the binning) in single precision, with the atom id in the fourth
+// word, for the search's pre-test.  BATCHED: each atom's box is its system's.
+template <bool BATCHED>
+__global__ void k_scatter(ScatterLaunch a)
 {
-    const int nn = n_dev ? *n_dev : n;
+    const int nn = BATCHED ? a.dims->n_atoms : a.n;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += gridDim.x * blockDim.x) {
-        int slot = cell_start[cell_of[i]] + rank[i];
-        cell_atoms[slot] = i;
-        cell_pos[3 * (size_t)slot + 0] = pos[3 * (size_t)i + 0];
-        cell_pos[3 * (size_t)slot + 1] = pos[3 * (size_t)i + 1];
-        cell_pos[3 * (size_t)slot + 2] = pos[3 * (size_t)i + 2];
+        const int slot = a.cell_start[a.cell_of[i]] + a.rank[i];
+        const double x = a.pos[3 * (size_t)i + 0], y = a.pos[3 * (size_t)i + 1], z = a.pos[3 * (size_t)i + 2];
+        const CellGrid &g = BATCHED ? a.sys[a.sys_of[i]].g : a.g;
+        a.cell_atoms[slot] = i;
+        a.cell_pos[3 * (size_t)slot + 0] = x;
+        a.cell_pos[3 * (size_t)slot + 1] = y;
+        a.cell_pos[3 * (size_t)slot + 2] = z;
+        float4 f;
+        f.x = (float)(x - g.L[0] * floor(x / g.L[0]));
+        f.y = (float)(y - g.L[1] * floor(y / g.L[1]));
+        f.z = (float)(z - g.L[2] * floor(z / g.L[2]));
+        f.w = __int_as_float(i);
+        a.cell_posf[slot] = f;
     }
 }
 
@@ -104,39 +113,6 @@ __device__ inline double image_component(double xj, double xi, double L, double 
     return fma(-s, L, t);
 }
 
-// Conservative single-precision pre-test: false only if the pair is surely
-// outside the list radius.  With t = x_j - x_i in FP64 and u = 2^-24, the
-// single-precision minimum image differs from the exact one by at most
-// u (2|t| + L + |d|) per axis (or lands on the other image, which for a pair
-// within range can only happen when both images lie at L/2 ~ rcs), so
-// widening the radius by 2.5e-7 (2 sum|t| + sum L) + 1e-5 never rejects a
-// neighbour; survivors get the exact FP64 test.
-__device__ inline bool may_be_neighbour(double xj, double yj, double zj, double xi, double yi, double zi,
-                                        const CellGrid &g, float rcs)
-{
-    const float a0 = (float)(xj - xi), a1 = (float)(yj - yi), a2 = (float)(zj - zi);
-    const float d0 = fmaf(-rintf(a0 * g.invLf[0]), g.Lf[0], a0);
-    const float d1 = fmaf(-rintf(a1 * g.invLf[1]), g.Lf[1], a1);
-    const float d2 = fmaf(-rintf(a2 * g.invLf[2]), g.Lf[2], a2);
-    const float r2 = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
-    const float delta = 2.5e-7f * (2.f * (fabsf(a0) + fabsf(a1) + fabsf(a2)) + g.Lsum) + 1e-5f;
-    const float lim = rcs + delta;
-    return r2 < lim * lim;
-}
-
-// Pre-test on staged single-precision coordinates that already carry the
-// periodic image of their stencil cell (relative to the supercell origin):
-// for a pair within range that image is the minimum image, so the staged
-// difference equals the exact displacement up to a few float roundings of
-// coordinates within a few cells of the origin (< 1e-5 A); the radius is
-// widened by 1e-4 A.
-__device__ inline bool may_be_neighbour_shifted(float xj, float yj, float zj, float xi, float yi, float zi,
-                                                float lim2)
-{
-    const float d0 = xj - xi, d1 = yj - yi, d2 = zj - zi;
-    return fmaf(d2, d2, fmaf(d1, d1, d0 * d0)) < lim2;
-}
-
 __device__ inline bool in_range(double xj, double yj, double zj, double xi, double yi, double zi,
                                 const CellGrid &g, double rc2)
 {
@@ -146,290 +122,223 @@ __device__ inline bool in_range(double xj, double yj, double zj, double xi, doub
     return fma(dz, dz, fma(dy, dy, dx * dx)) < rc2;
 }
 
-// One wavefront per supercell: kSuper consecutive cells along the last axis.
-// The atoms of the unique cells around it (3 x 3 x (kSuper + 2) cells, or
-// fewer on small grids) are staged in LDS.  Fast path: the lanes run over
-// all (atom of the supercell, candidate) pairs, a single-precision pre-test
-// keeps the possible neighbours, the exact FP64 predicate decides them, the
-// accepted pairs are packed in order (ballot + prefix count), and every row
-// is rank-sorted by j and written to the fixed-capacity row buffer.
-// Supercells with too many candidates or pairs take the general path: one
-// atom at a time, candidates in chunks.
-constexpr int kSuper = 4;
-constexpr int kCandCap = 256;
-constexpr int kRowCap = kMaxRow;
-constexpr int kSurvCap = 512;
-constexpr int kCellAtomCap = 64;
-constexpr int kMaxStencil = 3 * 3 * (kSuper + 2);
+// One thread per atom, atoms taken in cell order (neighbouring threads share
+// most stencil cells, so candidate data come from cache), in three phases
+// whose bodies do not diverge much across the wavefront:
+//   1  walk the 27 cells around the atom's own (every cell once along an axis
+//      with fewer than three cells) and keep the candidates that pass a
+//      single-precision pre-test on the wrapped coordinates -- with the
+//      stencil cell's periodic image added when every axis has at least three
+//      cells, else by a single-precision minimum image -- in the thread's
+//      column of an LDS buffer;
+//   2  decide the survivors with the exact FP64 predicate, compacting the
+//      accepted neighbour ids in place;
+//   3  sort the row with a 32-element bitonic network in registers.
+// Atoms with more than kLRow survivors are listed for k_search_long.
+//
+// Pre-test bound: the wrapped single-precision coordinates and the rounded box
+// lengths are each within 2^-24 L of their exact values, and the difference
+// plus image shift adds two more roundings of that size, so every component
+// is within 5 * 2^-24 L_a of the exact minimum-image displacement; the radius
+// is widened by 4e-7 (Lx + Ly + Lz) + 1e-5 (> 6.7 * 2^-24 sum L), so no
+// neighbour is ever rejected by the pre-test.
+constexpr int kLRow = 32;          // survivors / row entries held per thread (LDS)
+constexpr int kSearchThreads = 256;
 
-struct SearchLDS {
-    int cj[kCandCap];
-    double cx[kCandCap], cy[kCandCap], cz[kCandCap];
-    float fx[kCandCap], fy[kCandCap], fz[kCandCap];
-    int row[kRowCap];
-    int surv[kSurvCap];
-    int pa[kSurvCap], pj[kSurvCap];
-    int rowcnt[kCellAtomCap], rowst[kCellAtomCap];
-    int pre[kMaxStencil + 1], st[kMaxStencil];
-    double shx[kMaxStencil], shy[kMaxStencil], shz[kMaxStencil];
+struct StencilCell {
+    int cell;          // cell index (with the system's offset)
+    float sx, sy, sz;  // periodic image shift of the cell's atoms
 };
 
-// Rows of the atoms of supercell sc of grid g, whose cells are numbered from
-// cell_off.  A row longer than cap is not written; its row_count is the true
-// length (CLAMP false) or 0 with bit 1 raised in *sys_flags (CLAMP true, for
-// batches whose kernels run without a host check in between).
-template <bool CLAMP>
-__device__ __forceinline__ void search_supercell(SearchLDS &sm, const CellGrid &g, int cell_off, int sc,
-                                                 double rc2, const int *__restrict__ cell_start,
-                                                 const int *__restrict__ cell_count,
-                                                 const int *__restrict__ cell_atoms,
-                                                 const double *__restrict__ cpos, int cap,
-                                                 int *__restrict__ ell, int *__restrict__ row_count,
-                                                 int *sys_flags)
+// Stencil cell q (0 <= q < n0 n1 n2) around local cell (cx, cy, cz).
+__device__ __forceinline__ StencilCell stencil_cell(const CellGrid &g, int coff, int cx, int cy, int cz, int n0,
+                                                    int n1, int n2, int q)
 {
-    const int lane = threadIdx.x;
-    const int nsz = (g.nc[2] + kSuper - 1) / kSuper;          // supercells per column
-    const int n0 = g.nc[0] >= 3 ? 3 : g.nc[0];
-    const int n1 = g.nc[1] >= 3 ? 3 : g.nc[1];
-    const bool zall = g.nc[2] < kSuper + 2;                    // small grid: every z cell once
-    const int n2 = zall ? g.nc[2] : kSuper + 2;
-    const int nq = n0 * n1 * n2;
-    const float rcs = (float)sqrt(rc2);
-    // the stencil fixes each candidate's periodic image when every axis has
-    // at least three cells around the supercell
-    const bool shifted = n0 == 3 && n1 == 3 && !zall;
-    const float lim = rcs + 1e-4f, lim2 = lim * lim;
-    auto store_count = [&](int i, int cnt) {
-        if (CLAMP && cnt > cap) {
-            row_count[i] = 0;
+    const int q0 = q / (n1 * n2), q1 = (q / n2) % n1, q2 = q % n2;
+    int x = n0 == 3 ? cx + q0 - 1 : q0;
+    int y = n1 == 3 ? cy + q1 - 1 : q1;
+    int z = n2 == 3 ? cz + q2 - 1 : q2;
+    StencilCell c;
+    c.sx = c.sy = c.sz = 0.f;
+    if (x < 0) { x += g.nc[0]; c.sx = -g.Lf[0]; } else if (x >= g.nc[0]) { x -= g.nc[0]; c.sx = g.Lf[0]; }
+    if (y < 0) { y += g.nc[1]; c.sy = -g.Lf[1]; } else if (y >= g.nc[1]) { y -= g.nc[1]; c.sy = g.Lf[1]; }
+    if (z < 0) { z += g.nc[2]; c.sz = -g.Lf[2]; } else if (z >= g.nc[2]) { z -= g.nc[2]; c.sz = g.Lf[2]; }
+    c.cell = coff + (x * g.nc[1] + y) * g.nc[2] + z;
+    return c;
+}
+
+// Ascending bitonic sort of 32 values held in registers (constant indices
+// only, so the array never leaves registers).
+__device__ __forceinline__ void bitonic32(int (&v)[kLRow])
+{
+#pragma unroll
+    for (int k = 2; k <= kLRow; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < kLRow; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int lo = min(v[i], v[l]), hi = max(v[i], v[l]);
+                    if ((i & k) == 0) { v[i] = lo; v[l] = hi; }
+                    else { v[i] = hi; v[l] = lo; }
+                }
+            }
+        }
+    }
+}
+
+template <bool BATCHED>
+__global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
+{
+    __shared__ int buf[kLRow][kSearchThreads];
+    const int tl = threadIdx.x;
+    const int n = BATCHED ? a.dims->n_atoms : a.n;
+    for (int t = blockIdx.x * kSearchThreads + tl; t < n; t += gridDim.x * kSearchThreads) {
+        const float4 fi = a.cell_posf[t];
+        const int i = __float_as_int(fi.w);
+        int coff = 0;
+        int *sys_flags = nullptr;
+        CellGrid g;
+        if constexpr (BATCHED) {
+            const int sidx = a.sys_of[i];
+            g = a.sys[sidx].g;
+            coff = a.sys[sidx].cell_off;
+            sys_flags = a.sys_status + sidx;
+        } else {
+            g = a.g;
+        }
+        const int c = a.cell_of[i] - coff;
+        const int cz = c % g.nc[2], cy = (c / g.nc[2]) % g.nc[1], cx = c / (g.nc[1] * g.nc[2]);
+        const int n0 = min(g.nc[0], 3), n1 = min(g.nc[1], 3), n2 = min(g.nc[2], 3);
+        const bool shifted = n0 == 3 && n1 == 3 && n2 == 3;
+        const float lim = a.rcs + 4e-7f * (g.Lf[0] + g.Lf[1] + g.Lf[2]) + 1e-5f;
+        const float lim2 = lim * lim;
+
+        // ---- 1: pre-test, survivors (candidate slots) to LDS
+        int ns = 0;
+        const int nq = n0 * n1 * n2;
+        for (int q = 0; q < nq; ++q) {
+            const StencilCell sc = stencil_cell(g, coff, cx, cy, cz, n0, n1, n2, q);
+            const int u0 = a.cell_start[sc.cell], u1 = u0 + a.cell_count[sc.cell];
+            for (int u = u0; u < u1; ++u) {
+                const float4 fj = a.cell_posf[u];
+                float d0 = fj.x - fi.x, d1 = fj.y - fi.y, d2 = fj.z - fi.z;
+                if (shifted) {
+                    d0 += sc.sx; d1 += sc.sy; d2 += sc.sz;
+                } else {
+                    d0 = fmaf(-rintf(d0 * g.invLf[0]), g.Lf[0], d0);
+                    d1 = fmaf(-rintf(d1 * g.invLf[1]), g.Lf[1], d1);
+                    d2 = fmaf(-rintf(d2 * g.invLf[2]), g.Lf[2], d2);
+                }
+                const bool keep = fmaf(d2, d2, fmaf(d1, d1, d0 * d0)) < lim2 && u != t;
+                if (keep && ns < kLRow) buf[ns][tl] = u;
+                ns += keep ? 1 : 0;
+            }
+        }
+        if (ns > kLRow) {
+            // too many survivors for the LDS buffer: k_search_long writes this row
+            a.long_rows[atomicAdd(a.n_long, 1)] = t;
+            continue;
+        }
+
+        // ---- 2: exact predicate, accepted ids compacted in place
+        const double xi = a.cell_pos[3 * (size_t)t], yi = a.cell_pos[3 * (size_t)t + 1],
+                     zi = a.cell_pos[3 * (size_t)t + 2];
+        int cnt = 0;
+        for (int k = 0; k < ns; ++k) {
+            const int u = buf[k][tl];
+            if (in_range(a.cell_pos[3 * (size_t)u], a.cell_pos[3 * (size_t)u + 1], a.cell_pos[3 * (size_t)u + 2],
+                         xi, yi, zi, g, a.rc2))
+                buf[cnt++][tl] = a.cell_atoms[u];
+        }
+
+        // ---- 3: sort and store
+        if (cnt <= a.cap) {
+            int v[kLRow];
+#pragma unroll
+            for (int k = 0; k < kLRow; ++k) v[k] = k < cnt ? buf[k][tl] : INT_MAX;
+            bitonic32(v);
+            int *out = a.ell + (size_t)i * a.cap;
+#pragma unroll
+            for (int k = 0; k < kLRow; ++k)
+                if (k < cnt) out[k] = v[k];
+        }
+        if (BATCHED && cnt > a.cap) {
+            a.row_count[i] = 0;
             atomicOr(sys_flags, 1);
         } else {
-            row_count[i] = cnt;
+            a.row_count[i] = cnt;
         }
-    };
+    }
+}
 
-    const int col = sc / nsz;                              // (x, y) column
-    const int z0 = (sc - col * nsz) * kSuper;
-    const int kz = min(kSuper, g.nc[2] - z0);
-    const int cx0 = col / g.nc[1], cy0 = col % g.nc[1];
-    const int c_first = cell_off + (cx0 * g.nc[1] + cy0) * g.nc[2] + z0;
-    // stencil cells: x, y offsets {-1,0,1} (or all cells when nc < 3), z from z0-1 to z0+kSuper
-    int cntq = 0, stq = 0;
-    if (lane < nq) {
-        const int q0 = lane / (n1 * n2), q1 = (lane / n2) % n1, q2 = lane % n2;
-        int x = cx0 + (n0 == 3 ? q0 - 1 : q0 - cx0);
-        int y = cy0 + (n1 == 3 ? q1 - 1 : q1 - cy0);
-        int z = zall ? q2 : z0 - 1 + q2;
-        double sx = 0, sy = 0, sz = 0;   // image shift of this stencil cell
-        if (x < 0) { x += g.nc[0]; sx = -g.L[0]; } else if (x >= g.nc[0]) { x -= g.nc[0]; sx = g.L[0]; }
-        if (y < 0) { y += g.nc[1]; sy = -g.L[1]; } else if (y >= g.nc[1]) { y -= g.nc[1]; sy = g.L[1]; }
-        if (z < 0) { z += g.nc[2]; sz = -g.L[2]; } else if (z >= g.nc[2]) { z -= g.nc[2]; sz = g.L[2]; }
-        const int cc = cell_off + (x * g.nc[1] + y) * g.nc[2] + z;
-        stq = cell_start[cc];
-        cntq = cell_count[cc];
-        sm.shx[lane] = sx; sm.shy[lane] = sy; sm.shz[lane] = sz;
-    }
-    const int cs = cell_start[c_first];
-    const int A = cell_start[c_first + kz - 1] + cell_count[c_first + kz - 1] - cs;
-    int incl = cntq;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        int u = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += u;
-    }
-    if (A == 0) return;
-    const int T = __shfl(incl, nq - 1, 64);
-    if (lane < nq) {
-        sm.pre[lane] = incl - cntq;
-        sm.st[lane] = stq;
-    }
-    if (lane == 0) sm.pre[nq] = T;
-    __syncthreads();
-    const double ox = cx0 * g.cell_w[0], oy = cy0 * g.cell_w[1], oz = z0 * g.cell_w[2];
-    // staged position of the supercell's first atom: stencil cell (centre x, centre y, z0)
-    const int qf = (n0 == 3 ? 1 : cx0) * n1 * n2 + (n1 == 3 ? 1 : cy0) * n2 + (zall ? z0 : 1);
-    auto stage = [&](int t0, int tn) {
-        for (int tt = lane; tt < tn; tt += 64) {
-            const int t = t0 + tt;
-            int lo = 0, hi = nq - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (sm.pre[mid] <= t) lo = mid; else hi = mid - 1;
-            }
-            const int sidx = sm.st[lo] + (t - sm.pre[lo]);
-            sm.cj[tt] = cell_atoms[sidx];
-            const double x = cpos[3 * (size_t)sidx], y = cpos[3 * (size_t)sidx + 1], z = cpos[3 * (size_t)sidx + 2];
-            sm.cx[tt] = x; sm.cy[tt] = y; sm.cz[tt] = z;
-            if (shifted) {
-                // wrapped coordinate as in the binning, plus the cell's image shift
-                sm.fx[tt] = (float)(x - g.L[0] * floor(x / g.L[0]) + sm.shx[lo] - ox);
-                sm.fy[tt] = (float)(y - g.L[1] * floor(y / g.L[1]) + sm.shy[lo] - oy);
-                sm.fz[tt] = (float)(z - g.L[2] * floor(z / g.L[2]) + sm.shz[lo] - oz);
-            }
-        }
-    };
-    const bool one_chunk = T <= kCandCap;
-    if (one_chunk) stage(0, T);
-    __syncthreads();
+// Rows listed by k_search_atoms: one wavefront per atom, the stencil's
+// candidates 64 at a time through the exact predicate, compacted in order
+// into LDS and rank-sorted.
+constexpr int kRowCap = kMaxRow;
 
-    bool fast = one_chunk && A <= kCellAtomCap;
-    int nsurv = 0;
-    const unsigned magic = 0xFFFFFFFFu / (unsigned)max(T, 1) + 1u;   // f / T = umulhi(f, magic), f, T < 2^16
-    const int ic0 = sm.pre[qf];
-    if (fast) {
-        // pass 1: single-precision pre-test over all (atom, candidate) pairs
-        const int AT = A * T;
-        for (int base = 0; base < AT; base += 64) {
-            const int f = base + lane;
-            bool keep = false;
-            if (f < AT) {
-                const int ia = (int)__umulhi((unsigned)f, magic);
-                const int t = f - ia * T;
-                const int ti = ic0 + ia;
-                if (t != ti)
-                    keep = shifted ? may_be_neighbour_shifted(sm.fx[t], sm.fy[t], sm.fz[t], sm.fx[ti], sm.fy[ti],
-                                                              sm.fz[ti], lim2)
-                                   : may_be_neighbour(sm.cx[t], sm.cy[t], sm.cz[t], sm.cx[ti], sm.cy[ti],
-                                                      sm.cz[ti], g, rcs);
-            }
-            const unsigned long long m = __ballot(keep);
-            const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-            if (keep && nsurv + below < kSurvCap) sm.surv[nsurv + below] = f;
-            nsurv += __popcll(m);
+template <bool BATCHED>
+__global__ __launch_bounds__(kWave) void k_search_long(SearchLaunch a)
+{
+    __shared__ int row[kRowCap];
+    const int lane = threadIdx.x;
+    const int nl = *a.n_long;
+    for (int w = blockIdx.x; w < nl; w += gridDim.x) {
+        const int t = a.long_rows[w];
+        const int i = a.cell_atoms[t];
+        const double xi = a.cell_pos[3 * (size_t)t], yi = a.cell_pos[3 * (size_t)t + 1],
+                     zi = a.cell_pos[3 * (size_t)t + 2];
+        int coff = 0;
+        int *sys_flags = nullptr;
+        CellGrid g;
+        if constexpr (BATCHED) {
+            const int sidx = a.sys_of[i];
+            g = a.sys[sidx].g;
+            coff = a.sys[sidx].cell_off;
+            sys_flags = a.sys_status + sidx;
+        } else {
+            g = a.g;
         }
-        fast = nsurv <= kSurvCap;
-    }
-    if (fast) {
-        __syncthreads();
-        // pass 2: exact predicate on the survivors, accepted pairs kept in order
-        int nacc = 0;
-        for (int base = 0; base < nsurv; base += 64) {
-            const int k = base + lane;
-            bool acc = false;
-            int ia = 0, t = 0;
-            if (k < nsurv) {
-                const int f = sm.surv[k];
-                ia = (int)__umulhi((unsigned)f, magic);
-                t = f - ia * T;
-                const int ti = ic0 + ia;
-                acc = in_range(sm.cx[t], sm.cy[t], sm.cz[t], sm.cx[ti], sm.cy[ti], sm.cz[ti], g, rc2);
-            }
-            const unsigned long long m = __ballot(acc);
-            const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-            if (acc) {
-                sm.pa[nacc + below] = ia;
-                sm.pj[nacc + below] = sm.cj[t];
-            }
-            nacc += __popcll(m);
-        }
-        if (lane < A) sm.rowcnt[lane] = 0;
-        __syncthreads();
-        for (int k = lane; k < nacc; k += 64) atomicAdd(&sm.rowcnt[sm.pa[k]], 1);
-        __syncthreads();
-        {
-            const int v = lane < A ? sm.rowcnt[lane] : 0;
-            int inc = v;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                int u = __shfl_up(inc, off, 64);
-                if (lane >= off) inc += u;
-            }
-            if (lane < A) sm.rowst[lane] = inc - v;
-        }
-        __syncthreads();
-        for (int k = lane; k < nacc; k += 64) {
-            const int ia = sm.pa[k], v = sm.pj[k];
-            const int r0 = sm.rowst[ia], rn = sm.rowcnt[ia];
-            if (rn <= cap) {
-                int rk = 0;
-                for (int q = 0; q < rn; ++q) rk += sm.pj[r0 + q] < v;
-                ell[(size_t)sm.cj[ic0 + ia] * cap + rk] = v;
-            }
-        }
-        if (lane < A) store_count(sm.cj[ic0 + lane], sm.rowcnt[lane]);
-        __syncthreads();
-        return;
-    }
-
-    // general path: one atom at a time, candidates in chunks
-    for (int ia = 0; ia < A; ++ia) {
-        const int si = cs + ia;
-        const int i = cell_atoms[si];
-        const double xi = cpos[3 * (size_t)si], yi = cpos[3 * (size_t)si + 1], zi = cpos[3 * (size_t)si + 2];
+        const int c = a.cell_of[i] - coff;
+        const int cz = c % g.nc[2], cy = (c / g.nc[2]) % g.nc[1], cx = c / (g.nc[1] * g.nc[2]);
+        const int n0 = min(g.nc[0], 3), n1 = min(g.nc[1], 3), n2 = min(g.nc[2], 3);
         int cnt = 0;
-        for (int t0 = 0; t0 < T; t0 += kCandCap) {
-            const int tn = min(kCandCap, T - t0);
-            if (!one_chunk) {
-                __syncthreads();
-                stage(t0, tn);
-                __syncthreads();
-            }
-            for (int tb = 0; tb < tn; tb += 64) {
-                const int tt = tb + lane;
+        for (int q = 0; q < n0 * n1 * n2; ++q) {
+            const StencilCell sc = stencil_cell(g, coff, cx, cy, cz, n0, n1, n2, q);
+            const int u0 = a.cell_start[sc.cell], u1 = u0 + a.cell_count[sc.cell];
+            for (int ub = u0; ub < u1; ub += kWave) {
+                const int u = ub + lane;
                 bool acc = false;
-                int j = 0;
-                if (tt < tn) {
-                    j = sm.cj[tt];
-                    if (j != i) acc = in_range(sm.cx[tt], sm.cy[tt], sm.cz[tt], xi, yi, zi, g, rc2);
-                }
+                if (u < u1 && u != t)
+                    acc = in_range(a.cell_pos[3 * (size_t)u], a.cell_pos[3 * (size_t)u + 1],
+                                   a.cell_pos[3 * (size_t)u + 2], xi, yi, zi, g, a.rc2);
                 const unsigned long long m = __ballot(acc);
                 const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                if (acc && cnt + below < kRowCap) sm.row[cnt + below] = j;
+                if (acc && cnt + below < kRowCap) row[cnt + below] = a.cell_atoms[u];
                 cnt += __popcll(m);
             }
         }
         __syncthreads();
-        if (cnt <= cap && cnt <= kRowCap) {
-            int *out = ell + (size_t)i * cap;
-            for (int e = lane; e < cnt; e += 64) {
-                const int v = sm.row[e];
+        if (cnt <= a.cap && cnt <= kRowCap) {
+            int *out = a.ell + (size_t)i * a.cap;
+            for (int e = lane; e < cnt; e += kWave) {
+                const int v = row[e];
                 int rk = 0;
-                for (int q = 0; q < cnt; ++q) rk += sm.row[q] < v;
+                for (int q = 0; q < cnt; ++q) rk += row[q] < v;
                 out[rk] = v;
             }
         }
-        if (lane == 0) store_count(i, cnt);
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(64) void k_search_cells(CellGrid g, double rc2, const int *__restrict__ cell_start,
-                                                     const int *__restrict__ cell_count,
-                                                     const int *__restrict__ cell_atoms,
-                                                     const double *__restrict__ cpos, int nsuper, int cap,
-                                                     int *__restrict__ ell, int *__restrict__ row_count)
-{
-    __shared__ SearchLDS sm;
-    for (int sc = blockIdx.x; sc < nsuper; sc += gridDim.x)
-        search_supercell<false>(sm, g, 0, sc, rc2, cell_start, cell_count, cell_atoms, cpos, cap, ell,
-                                row_count, nullptr);
-}
-
-// Batched form: the supercells of every system of the batch, numbered from
-// each system's super_off; the system of a supercell is found by bisection.
-__global__ __launch_bounds__(64) void k_search_systems(const SysDesc *__restrict__ sys,
-                                                       const BatchDims *__restrict__ dims, double rc2,
-                                                       const int *__restrict__ cell_start,
-                                                       const int *__restrict__ cell_count,
-                                                       const int *__restrict__ cell_atoms,
-                                                       const double *__restrict__ cpos, int cap,
-                                                       int *__restrict__ ell, int *__restrict__ row_count,
-                                                       int *__restrict__ sys_status)
-{
-    __shared__ SearchLDS sm;
-    const int nsuper = dims->n_super, nsys = dims->n_sys;
-    for (int sc = blockIdx.x; sc < nsuper; sc += gridDim.x) {
-        int lo = 0, hi = nsys - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sys[mid].super_off <= sc) lo = mid; else hi = mid - 1;
+        if (lane == 0) {
+            if (BATCHED && cnt > a.cap) {
+                a.row_count[i] = 0;
+                atomicOr(sys_flags, 1);
+            } else {
+                a.row_count[i] = cnt;
+            }
         }
-        const CellGrid g = sys[lo].g;
-        search_supercell<true>(sm, g, sys[lo].cell_off, sc - sys[lo].super_off, rc2, cell_start, cell_count,
-                               cell_atoms, cpos, cap, ell, row_count, sys_status + lo);
+        __syncthreads();
     }
 }
 
@@ -577,6 +486,7 @@ __global__ void k_scan_add(int *__restrict__ out, int n, const int *__restrict__
 }
 
 inline int blocks_for(long long n, int t) { return (int)((n + t - 1) / t); }
+constexpr int kBigGridSearch = 256;   // workgroups of the long-row search
 
 }  // namespace
 
@@ -626,52 +536,30 @@ hipError_t launch_bin_systems(const double *pos, const int *sys_of, const SysDes
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_cells(const double *pos, int n, const int *n_dev, const int *cell_of,
-                                const int *rank_in_cell, const int *cell_start,
-                                int *cell_atoms, double *cell_pos, hipStream_t s)
+hipError_t launch_scatter_cells(const ScatterLaunch &a, int grid_cap, hipStream_t s)
 {
-    int grid = blocks_for(n, 256);
-    if (n_dev) grid = std::min(grid, kBatchGrid);
-    hipLaunchKernelGGL(k_scatter, dim3(std::max(1, grid)), dim3(256), 0, s, pos, n, n_dev, cell_of,
-                       rank_in_cell, cell_start, cell_atoms, cell_pos);
+    int grid = blocks_for(a.n, 256);
+    if (a.dims) {
+        grid = std::min(grid, grid_cap);
+        hipLaunchKernelGGL(k_scatter<true>, dim3(std::max(1, grid)), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_scatter<false>, dim3(std::max(1, grid)), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
-namespace {
-int search_grid(const void *kern, int nsuper)
+hipError_t launch_search(const SearchLaunch &a, int grid_cap, hipStream_t s)
 {
-    int per_cu = 0, dev = 0, cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    return std::max(1, std::min(nsuper, per_cu * cus));
-}
-}  // namespace
-
-hipError_t launch_search_systems(const SysDesc *sys, const BatchDims *dims, int max_super, double rcut,
-                                 const int *cell_start, const int *cell_count, const int *cell_atoms,
-                                 const double *cell_pos, int cap, int *ell, int *row_count, int *sys_status,
-                                 hipStream_t s)
-{
-    const int grid = search_grid((const void *)k_search_systems, max_super);
-    hipLaunchKernelGGL(k_search_systems, dim3(grid), dim3(64), 0, s, sys, dims, rcut * rcut, cell_start,
-                       cell_count, cell_atoms, cell_pos, cap, ell, row_count, sys_status);
+    int grid = std::max(1, blocks_for(a.n, kSearchThreads));
+    if (a.dims) {
+        grid = std::min(grid, grid_cap);
+        hipLaunchKernelGGL(k_search_atoms<true>, dim3(grid), dim3(kSearchThreads), 0, s, a);
+        hipLaunchKernelGGL(k_search_long<true>, dim3(kBigGridSearch), dim3(kWave), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_search_atoms<false>, dim3(grid), dim3(kSearchThreads), 0, s, a);
+        hipLaunchKernelGGL(k_search_long<false>, dim3(kBigGridSearch), dim3(kWave), 0, s, a);
+    }
     return hipGetLastError();
 }
-
-hipError_t launch_search(const CellGrid &g, double rcut, const int *cell_start, const int *cell_count,
-                         const int *cell_atoms, const double *cell_pos, int ncell, int cap, int *ell,
-                         int *row_count, hipStream_t s)
-{
-    (void)ncell;
-    const int nsuper = g.nc[0] * g.nc[1] * ((g.nc[2] + kSuper - 1) / kSuper);
-    const int grid = search_grid((const void *)k_search_cells, nsuper);
-    hipLaunchKernelGGL(k_search_cells, dim3(grid), dim3(64), 0, s, g, rcut * rcut, cell_start, cell_count,
-                       cell_atoms, cell_pos, nsuper, cap, ell, row_count);
-    return hipGetLastError();
-}
-
-int supercells(const int nc[3]) { return nc[0] * nc[1] * ((nc[2] + kSuper - 1) / kSuper); }
 
 }  // namespace tsf

@@ -3,7 +3,7 @@
 //
 // Requests wait in a FIFO queue.  A worker thread forms a batch from the head
 // of the queue -- as many requests as fit the batch's atom, configuration,
-// cell and supercell capacities (the device-memory budget fixed at start) and
+// and cell capacities (the device-memory budget fixed at start) and
 // share one precision -- concatenates their atoms into pinned staging
 // buffers, and launches it on one of two buffer sets, each with its own
 // stream.  While one batch runs, the next is formed from whatever arrived in
@@ -15,7 +15,7 @@
 // per-configuration descriptors from device memory, so a replay needs only
 // the host-to-device copies of the inputs and descriptors before it and the
 // copies of the results after it.  Graph contents: clear counters -> bin every
-// configuration's atoms into its own cells -> scan -> scatter -> supercell
+// configuration's atoms into its own cells -> scan -> scatter -> neighbour
 // search over all configurations -> reverse map -> pack -> energy / force /
 // virial kernel (per-atom energy and virial) -> dropped-atom fixup -> force
 // gather -> per-configuration reduction.  A configuration's result does not
@@ -84,7 +84,7 @@ struct Pending {
     tersoff_request req;
     int64_t t_start;   // max(submit time, release time)
     CellGrid g;
-    int ncell, nsuper;
+    int ncell;
 };
 
 struct Lane {
@@ -96,8 +96,11 @@ struct Lane {
     Pinned<SysDesc> h_desc;
     Pinned<BatchDims> h_dims;
     Dev<double> pos, cell_pos, own, planes, forces, eatom, out;
+    Dev<float4> cell_posf;
+    Dev<int> long_rows;
     Dev<int> types, sys_of, cell_of, rank, cell_count, cell_start, cell_atoms, scan_tmp;
-    Dev<int> ell, row_count, rv, pcount, drop_list, ctl;   // ctl: [0] flags, [1] dropped count, [2..] status
+    Dev<int> ell, row_count, rv, pcount, drop_list;
+    Dev<int> ctl;   // [0] flags, [1] dropped count, [2] long rows, [3 ..] per-system status
     Dev<signed char> slotpos;
     Dev<unsigned char> recs;
     Dev<SysDesc> desc;
@@ -113,7 +116,7 @@ struct Lane {
 
 struct Server {
     ServerEnv env{};
-    int max_atoms = 0, max_sys = 0, max_cells = 0, max_super = 0, cap = 0;
+    int max_atoms = 0, max_sys = 0, max_cells = 0, cap = 0;
     double rc = 0.0;
     size_t max_queued = 0;
     size_t device_bytes = 0;
@@ -174,6 +177,8 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.h_dims.alloc(1));
     SRV_TRY(L.pos.alloc(3 * A, tot));
     SRV_TRY(L.cell_pos.alloc(3 * A, tot));
+    SRV_TRY(L.cell_posf.alloc(A, tot));
+    SRV_TRY(L.long_rows.alloc(A, tot));
     SRV_TRY(L.own.alloc(3 * A, tot));
     SRV_TRY(L.planes.alloc(3 * (size_t)kRecCap * A, tot));
     SRV_TRY(L.forces.alloc(3 * A, tot));
@@ -192,7 +197,7 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.rv.alloc(E, tot));
     SRV_TRY(L.pcount.alloc(A, tot));
     SRV_TRY(L.drop_list.alloc(A, tot));
-    SRV_TRY(L.ctl.alloc(2 + NS, tot));
+    SRV_TRY(L.ctl.alloc(3 + NS, tot));
     SRV_TRY(L.slotpos.alloc(E, tot));
     const size_t nbat = (A + kServeBatchAtoms - 1) / kServeBatchAtoms;
     SRV_TRY(L.recs.alloc(record_bytes(false) * kRecCap * nbat * kServeBatchAtoms, tot));
@@ -214,6 +219,7 @@ void free_lane(Lane &L)
     L.h_pos.release(); L.h_forces.release(); L.h_out.release(); L.h_types.release();
     L.h_sys_of.release(); L.h_desc.release(); L.h_dims.release();
     L.pos.release(); L.cell_pos.release(); L.own.release(); L.planes.release(); L.forces.release();
+    L.cell_posf.release(); L.long_rows.release();
     L.eatom.release(); L.out.release(); L.types.release(); L.sys_of.release(); L.cell_of.release();
     L.rank.release(); L.cell_count.release(); L.cell_start.release(); L.cell_atoms.release();
     L.scan_tmp.release(); L.ell.release(); L.row_count.release(); L.rv.release(); L.pcount.release();
@@ -230,14 +236,43 @@ hipError_t enqueue_batch(Server &S, Lane &L, bool mixed)
     hipStream_t s = L.stream;
     const int *n_dev = &L.dims.p->n_atoms;
     SRV_TRY(launch_fill_zero_int(L.cell_count.p, (size_t)S.max_cells, s));
-    SRV_TRY(launch_fill_zero_int(L.ctl.p, 2 + (size_t)S.max_sys, s));
+    SRV_TRY(launch_fill_zero_int(L.ctl.p, 3 + (size_t)S.max_sys, s));
     SRV_TRY(launch_bin_systems(L.pos.p, L.sys_of.p, L.desc.p, L.dims.p, S.max_atoms, L.cell_of.p, L.rank.p,
                                L.cell_count.p, s));
     SRV_TRY(launch_exclusive_scan(L.cell_count.p, L.cell_start.p, S.max_cells, L.scan_tmp.p, nullptr, s));
-    SRV_TRY(launch_scatter_cells(L.pos.p, S.max_atoms, n_dev, L.cell_of.p, L.rank.p, L.cell_start.p,
-                                 L.cell_atoms.p, L.cell_pos.p, s));
-    SRV_TRY(launch_search_systems(L.desc.p, L.dims.p, S.max_super, S.rc, L.cell_start.p, L.cell_count.p,
-                                  L.cell_atoms.p, L.cell_pos.p, S.cap, L.ell.p, L.row_count.p, L.ctl.p + 2, s));
+    ScatterLaunch sca{};
+    sca.pos = L.pos.p;
+    sca.n = S.max_atoms;
+    sca.cell_of = L.cell_of.p;
+    sca.rank = L.rank.p;
+    sca.cell_start = L.cell_start.p;
+    sca.cell_atoms = L.cell_atoms.p;
+    sca.cell_pos = L.cell_pos.p;
+    sca.cell_posf = L.cell_posf.p;
+    sca.sys = L.desc.p;
+    sca.sys_of = L.sys_of.p;
+    sca.dims = L.dims.p;
+    SRV_TRY(launch_scatter_cells(sca, kBatchGrid, s));
+    SearchLaunch sl{};
+    sl.sys = L.desc.p;
+    sl.sys_of = L.sys_of.p;
+    sl.dims = L.dims.p;
+    sl.n = S.max_atoms;
+    sl.rc2 = S.rc * S.rc;
+    sl.rcs = (float)S.rc;
+    sl.cell_start = L.cell_start.p;
+    sl.cell_count = L.cell_count.p;
+    sl.cell_atoms = L.cell_atoms.p;
+    sl.cell_of = L.cell_of.p;
+    sl.cell_pos = L.cell_pos.p;
+    sl.cell_posf = L.cell_posf.p;
+    sl.cap = S.cap;
+    sl.ell = L.ell.p;
+    sl.row_count = L.row_count.p;
+    sl.long_rows = L.long_rows.p;
+    sl.n_long = L.ctl.p + 2;
+    sl.sys_status = L.ctl.p + 3;
+    SRV_TRY(launch_search(sl, kBatchGrid, s));
     SRV_TRY(launch_reverse_map(L.ell.p, S.cap, L.row_count.p, S.max_atoms, n_dev, L.rv.p, L.ctl.p, s));
 
     PackLaunch pk{};
@@ -280,7 +315,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, bool mixed)
                                  S.max_atoms, L.planes.p, s));
     SRV_TRY(launch_gather_forces(L.pcount.p, L.planes.p, L.own.p, S.max_atoms, n_dev, S.max_atoms, L.forces.p, s));
     SRV_TRY(launch_reduce_systems(L.desc.p, L.dims.p, S.max_sys, L.eatom.p, L.drop_list.p, L.ctl.p + 1,
-                                  L.ctl.p + 2, L.out.p, s));
+                                  L.ctl.p + 3, L.out.p, s));
     return hipSuccess;
 }
 
@@ -300,22 +335,21 @@ hipError_t capture(Server &S, Lane &L, bool mixed)
 }
 
 // Takes requests from the head of the queue while they are released, share
-// the head's precision and fit the capacities (called with the lock held).
+// the head's precision and fit the atom, slot and cell capacities (called with
+// the lock held).
 void form_batch(Server &S, Lane &L)
 {
     L.batch.clear();
     const int64_t now = now_ns();
-    int natoms = 0, ncell = 0, nsuper = 0;
+    int natoms = 0, ncell = 0;
     while (!S.queue.empty() && (int)L.batch.size() < S.max_sys) {
         const Pending &p = S.queue.front();
         if (p.t_start > now) break;
         if (!L.batch.empty() && (p.req.precision == TERSOFF_MIXED) != L.mixed) break;
-        if (natoms + p.req.n > S.max_atoms || ncell + p.ncell > S.max_cells || nsuper + p.nsuper > S.max_super)
-            break;
+        if (natoms + p.req.n > S.max_atoms || ncell + p.ncell > S.max_cells) break;
         if (L.batch.empty()) L.mixed = p.req.precision == TERSOFF_MIXED;
         natoms += (int)p.req.n;
         ncell += p.ncell;
-        nsuper += p.nsuper;
         L.batch.push_back(p);
         S.queue.pop_front();
     }
@@ -323,7 +357,7 @@ void form_batch(Server &S, Lane &L)
 
 hipError_t launch_lane(Server &S, Lane &L)
 {
-    int off = 0, coff = 0, soff = 0;
+    int off = 0, coff = 0;
     L.want_forces = false;
     const int nsys = (int)L.batch.size();
     for (int q = 0; q < nsys; ++q) {
@@ -337,14 +371,13 @@ hipError_t launch_lane(Server &S, Lane &L)
         d.atom_off = off;
         d.natoms = n;
         d.cell_off = coff;
-        d.super_off = soff;
+        d.pad = 0;
         off += n;
         coff += p.ncell;
-        soff += p.nsuper;
         L.want_forces |= p.req.forces != nullptr;
     }
     L.natoms = off;
-    *L.h_dims.p = BatchDims{off, coff, soff, nsys};
+    *L.h_dims.p = BatchDims{off, coff, nsys, 0};
     hipStream_t s = L.stream;
     SRV_TRY(hipMemcpyAsync(L.pos.p, L.h_pos.p, sizeof(double) * 3 * (size_t)off, hipMemcpyHostToDevice, s));
     SRV_TRY(hipMemcpyAsync(L.types.p, L.h_types.p, sizeof(int) * (size_t)off, hipMemcpyHostToDevice, s));
@@ -484,7 +517,6 @@ int server_create(const ServerEnv &env, const tersoff_serve_config &cfg, Server 
     S->max_atoms = (int)cfg.max_batch_atoms;
     S->max_sys = cfg.max_batch_systems;
     S->max_cells = std::max(S->max_atoms, 4096);
-    S->max_super = S->max_cells;
     S->cap = cap;
     S->rc = cutoff + cfg.skin;
     S->max_queued = cfg.max_queued > 0 ? (size_t)cfg.max_queued : 65536;
@@ -575,7 +607,6 @@ int server_submit(Server *S, const tersoff_request &req, uint64_t *ticket, std::
         return TERSOFF_E_INVALID;
     }
     p.ncell = (int)ncell;
-    p.nsuper = supercells(p.g.nc);
     const int64_t now = now_ns();
     p.t_start = std::max<int64_t>(now, req.release_ns);
     {

@@ -69,6 +69,8 @@ struct tersoff_ctx {
     DevBuf<double> own, planes;
     DevBuf<int> cell_of, rank, cell_count, cell_start, cell_atoms;
     DevBuf<double> cell_pos;
+    DevBuf<float4> cell_posf;
+    DevBuf<int> long_rows;
     DevBuf<int> ell, row_count, scan_tmp, misc;   // misc: [0] flags, [1] max row, [2] check flags
     DevBuf<double> partials, force_scratch;
     DevBuf<long long> counters, counts;
@@ -261,6 +263,7 @@ void tersoff_destroy(tersoff_ctx *c)
     c->pcount.release(); c->drop_list.release(); c->recs.release();
     c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
     c->cell_atoms.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
+    c->cell_posf.release(); c->long_rows.release();
     c->scan_tmp.release(); c->misc.release(); c->partials.release(); c->force_scratch.release();
     c->counters.release(); c->counts.release();
     for (auto &pr : c->ev_compute) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
@@ -361,13 +364,15 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
         ncell *= g.nc[a];
     }
     g.Lsum = g.Lf[0] + g.Lf[1] + g.Lf[2];
-    HIP_TRY(c, c->misc.ensure(4));
+    HIP_TRY(c, c->misc.ensure(8));
     HIP_TRY(c, c->cell_of.ensure(N));
     HIP_TRY(c, c->rank.ensure(N));
     HIP_TRY(c, c->cell_count.ensure(ncell));
     HIP_TRY(c, c->cell_start.ensure(ncell + 1));
     HIP_TRY(c, c->cell_atoms.ensure(N));
     HIP_TRY(c, c->cell_pos.ensure(3 * (size_t)N));
+    HIP_TRY(c, c->cell_posf.ensure((size_t)N));
+    HIP_TRY(c, c->long_rows.ensure((size_t)N));
     HIP_TRY(c, c->row_count.ensure(N));
     HIP_TRY(c, c->pcount.ensure(N));
     HIP_TRY(c, c->drop_list.ensure(N));
@@ -376,19 +381,45 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, c->pos_build.ensure(3 * (size_t)N));
     HIP_TRY(c, c->types.ensure(N));
 
-    // misc: [0] compute flags, [1] longest row, [2] build flags, [3] dropped count
-    HIP_TRY(c, hipMemsetAsync(c->misc.p, 0, 4 * sizeof(int), s));
+    // misc: [0] compute flags, [1] longest row, [2] build flags, [3] dropped
+    // count, [4] rows left to the long-row search
+    HIP_TRY(c, hipMemsetAsync(c->misc.p, 0, 8 * sizeof(int), s));
     HIP_TRY(c, hipMemsetAsync(c->cell_count.p, 0, sizeof(int) * ncell, s));
     HIP_TRY(c, launch_bin_atoms(pos, types, N, c->ntypes, g, c->cell_of.p, c->rank.p, c->cell_count.p,
                                 c->misc.p + 2, s));
     HIP_TRY(c, launch_exclusive_scan(c->cell_count.p, c->cell_start.p, (int)ncell, c->scan_tmp.p, nullptr, s));
-    HIP_TRY(c, launch_scatter_cells(pos, N, nullptr, c->cell_of.p, c->rank.p, c->cell_start.p,
-                                    c->cell_atoms.p, c->cell_pos.p, s));
+    ScatterLaunch sca{};
+    sca.pos = pos;
+    sca.n = N;
+    sca.cell_of = c->cell_of.p;
+    sca.rank = c->rank.p;
+    sca.cell_start = c->cell_start.p;
+    sca.cell_atoms = c->cell_atoms.p;
+    sca.cell_pos = c->cell_pos.p;
+    sca.cell_posf = c->cell_posf.p;
+    sca.g = g;
+    HIP_TRY(c, launch_scatter_cells(sca, 0, s));
+    SearchLaunch sl{};
+    sl.g = g;
+    sl.n = N;
+    sl.rc2 = rc * rc;
+    sl.rcs = (float)rc;
+    sl.cell_start = c->cell_start.p;
+    sl.cell_count = c->cell_count.p;
+    sl.cell_atoms = c->cell_atoms.p;
+    sl.cell_of = c->cell_of.p;
+    sl.cell_pos = c->cell_pos.p;
+    sl.cell_posf = c->cell_posf.p;
+    sl.row_count = c->row_count.p;
+    sl.long_rows = c->long_rows.p;
+    sl.n_long = c->misc.p + 4;
     int host[3] = {0, 0, 0};   // list length, longest row, build flags
     for (int attempt = 0; attempt < 2; ++attempt) {
         HIP_TRY(c, c->ell.ensure((size_t)N * c->ell_cap));
-        HIP_TRY(c, launch_search(g, rc, c->cell_start.p, c->cell_count.p, c->cell_atoms.p, c->cell_pos.p,
-                                 (int)ncell, c->ell_cap, c->ell.p, c->row_count.p, s));
+        HIP_TRY(c, hipMemsetAsync(c->misc.p + 4, 0, sizeof(int), s));
+        sl.cap = c->ell_cap;
+        sl.ell = c->ell.p;
+        HIP_TRY(c, launch_search(sl, 0, s));
         HIP_TRY(c, launch_exclusive_scan(c->row_count.p, c->offsets.p, N, c->scan_tmp.p, c->misc.p + 1, s));
         HIP_TRY(c, hipMemcpyAsync(&host[0], c->offsets.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipMemcpyAsync(&host[1], c->misc.p + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
