@@ -77,6 +77,26 @@ struct BatchDims {
 
 constexpr int kBatchGrid = 2048;   // workgroups of the grid-stride kernels of a batch
 
+// Workgroups are dealt to the 8 XCDs of the chip round-robin (workgroup b on
+// XCD b mod 8), each XCD with its own L2.  Give every XCD a contiguous range
+// of work items so that neighbouring atoms -- which share position, record
+// and force cache lines -- are handled under the same L2.  Any other
+// placement only costs locality, never correctness.
+struct ItemRange {
+    int begin, end, stride;
+};
+
+__device__ __forceinline__ ItemRange xcd_items(int nitems)
+{
+    const int G = gridDim.x;
+    if (G < 8) return {(int)blockIdx.x, nitems, G};
+    const int x = blockIdx.x & 7, l = blockIdx.x >> 3;
+    const int gx = (G - x + 7) / 8;          // workgroups on this XCD
+    const int per = (nitems + 7) / 8;
+    const int b0 = x * per;
+    return {b0 + l, min(nitems, b0 + per), gx};
+}
+
 // Flags raised by kernels (bitwise OR into a device int).
 enum : int { kFlagOverflow = 1, kFlagStale = 2 };
 

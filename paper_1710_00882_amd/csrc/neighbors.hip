@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #pragma clang fp contract(off)
 
@@ -38,20 +39,23 @@ __global__ void k_bin(const double *__restrict__ pos, const int *__restrict__ ty
                       CellGrid g, int *__restrict__ cell_of, int *__restrict__ rank,
                       int *__restrict__ count, int *flags)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double *p = pos + 3 * (size_t)i;
-    int f = 0;
-    if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) f |= 1;
-    const int t = types[i];
-    if (t < 0 || t >= ntypes) f |= 2;
-    if (f) atomicOr(flags, f);
-    int cx = cell_index(p[0], g.L[0], g.cell_w[0], g.nc[0]);
-    int cy = cell_index(p[1], g.L[1], g.cell_w[1], g.nc[1]);
-    int cz = cell_index(p[2], g.L[2], g.cell_w[2], g.nc[2]);
-    int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
-    cell_of[i] = c;
-    rank[i] = atomicAdd(&count[c], 1);
+    const ItemRange r = xcd_items((n + blockDim.x - 1) / blockDim.x);
+    for (int it = r.begin; it < r.end; it += r.stride) {
+        const int i = it * blockDim.x + threadIdx.x;
+        if (i >= n) continue;
+        const double *p = pos + 3 * (size_t)i;
+        int f = 0;
+        if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) f |= 1;
+        const int t = types[i];
+        if (t < 0 || t >= ntypes) f |= 2;
+        if (f) atomicOr(flags, f);
+        int cx = cell_index(p[0], g.L[0], g.cell_w[0], g.nc[0]);
+        int cy = cell_index(p[1], g.L[1], g.cell_w[1], g.nc[1]);
+        int cz = cell_index(p[2], g.L[2], g.cell_w[2], g.nc[2]);
+        int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
+        cell_of[i] = c;
+        rank[i] = atomicAdd(&count[c], 1);
+    }
 }
 
 // Cell of every atom of a batch of systems (no input checks: a batch holds
@@ -61,7 +65,10 @@ __global__ void k_bin_systems(const double *__restrict__ pos, const int *__restr
                               int *__restrict__ cell_of, int *__restrict__ rank, int *__restrict__ count)
 {
     const int n = dims->n_atoms;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const ItemRange r = xcd_items((n + blockDim.x - 1) / blockDim.x);
+    for (int it = r.begin; it < r.end; it += r.stride) {
+        const int i = it * blockDim.x + threadIdx.x;
+        if (i >= n) continue;
         const double *p = pos + 3 * (size_t)i;
         const SysDesc &d = sys[sys_of[i]];
         const CellGrid &g = d.g;
@@ -81,7 +88,10 @@ template <bool BATCHED>
 __global__ void k_scatter(ScatterLaunch a)
 {
     const int nn = BATCHED ? a.dims->n_atoms : a.n;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += gridDim.x * blockDim.x) {
+    const ItemRange r = xcd_items((nn + blockDim.x - 1) / blockDim.x);
+    for (int it = r.begin; it < r.end; it += r.stride) {
+        const int i = it * blockDim.x + threadIdx.x;
+        if (i >= nn) continue;
         const int slot = a.cell_start[a.cell_of[i]] + a.rank[i];
         const double x = a.pos[3 * (size_t)i + 0], y = a.pos[3 * (size_t)i + 1], z = a.pos[3 * (size_t)i + 2];
         const CellGrid &g = BATCHED ? a.sys[a.sys_of[i]].g : a.g;
@@ -134,7 +144,7 @@ __device__ inline bool in_range(double xj, double yj, double zj, double xi, doub
 //   2  decide the survivors with the exact FP64 predicate, compacting the
 //      accepted neighbour ids in place;
 //   3  sort the row with a 32-element bitonic network in registers.
-// Atoms with more than kLRow survivors are listed for k_search_long.
+// Atoms with more than kLRow - 1 survivors are listed for k_search_long.
 //
 // Pre-test bound: the wrapped single-precision coordinates and the rounded box
 // lengths are each within 2^-24 L of their exact values, and the difference
@@ -142,7 +152,7 @@ __device__ inline bool in_range(double xj, double yj, double zj, double xi, doub
 // is within 5 * 2^-24 L_a of the exact minimum-image displacement; the radius
 // is widened by 4e-7 (Lx + Ly + Lz) + 1e-5 (> 6.7 * 2^-24 sum L), so no
 // neighbour is ever rejected by the pre-test.
-constexpr int kLRow = 32;          // survivors / row entries held per thread (LDS)
+constexpr int kLRow = 32;          // LDS slots per thread: up to kLRow - 1 survivors, one scratch slot
 constexpr int kSearchThreads = 256;
 
 struct StencilCell {
@@ -194,7 +204,10 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
     __shared__ int buf[kLRow][kSearchThreads];
     const int tl = threadIdx.x;
     const int n = BATCHED ? a.dims->n_atoms : a.n;
-    for (int t = blockIdx.x * kSearchThreads + tl; t < n; t += gridDim.x * kSearchThreads) {
+    const ItemRange items = xcd_items((n + kSearchThreads - 1) / kSearchThreads);
+    for (int it = items.begin; it < items.end; it += items.stride) {
+        const int t = it * kSearchThreads + tl;
+        if (t >= n) continue;
         const float4 fi = a.cell_posf[t];
         const int i = __float_as_int(fi.w);
         int coff = 0;
@@ -215,28 +228,70 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
         const float lim = a.rcs + 4e-7f * (g.Lf[0] + g.Lf[1] + g.Lf[2]) + 1e-5f;
         const float lim2 = lim * lim;
 
-        // ---- 1: pre-test, survivors (candidate slots) to LDS
+        // ---- 1: pre-test, survivors (candidate slots) to LDS.  The cells
+        // (x, y, z-1 .. z+1) of a column are consecutive in cell order, so
+        // their atoms form one contiguous range unless the column wraps.
         int ns = 0;
-        const int nq = n0 * n1 * n2;
-        for (int q = 0; q < nq; ++q) {
-            const StencilCell sc = stencil_cell(g, coff, cx, cy, cz, n0, n1, n2, q);
-            const int u0 = a.cell_start[sc.cell], u1 = u0 + a.cell_count[sc.cell];
-            for (int u = u0; u < u1; ++u) {
-                const float4 fj = a.cell_posf[u];
-                float d0 = fj.x - fi.x, d1 = fj.y - fi.y, d2 = fj.z - fi.z;
-                if (shifted) {
-                    d0 += sc.sx; d1 += sc.sy; d2 += sc.sz;
-                } else {
-                    d0 = fmaf(-rintf(d0 * g.invLf[0]), g.Lf[0], d0);
-                    d1 = fmaf(-rintf(d1 * g.invLf[1]), g.Lf[1], d1);
-                    d2 = fmaf(-rintf(d2 * g.invLf[2]), g.Lf[2], d2);
+        // SH: add the stencil image shift (every axis has at least three
+        // cells) or take the single-precision minimum image
+        auto scan = [&](auto sh_tag, int u0, int u1, float sx, float sy, float sz) {
+            constexpr bool SH = decltype(sh_tag)::value;
+            for (int ub = u0; ub < u1; ub += 4) {
+                float4 fj[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) fj[r] = a.cell_posf[min(ub + r, u1 - 1)];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int u = ub + r;
+                    float d0 = fj[r].x - fi.x, d1 = fj[r].y - fi.y, d2 = fj[r].z - fi.z;
+                    if constexpr (SH) {
+                        d0 += sx; d1 += sy; d2 += sz;
+                    } else {
+                        d0 = fmaf(-rintf(d0 * g.invLf[0]), g.Lf[0], d0);
+                        d1 = fmaf(-rintf(d1 * g.invLf[1]), g.Lf[1], d1);
+                        d2 = fmaf(-rintf(d2 * g.invLf[2]), g.Lf[2], d2);
+                    }
+                    const bool keep = u < u1 && u != t && fmaf(d2, d2, fmaf(d1, d1, d0 * d0)) < lim2;
+                    // unconditional store: a rejected candidate is overwritten
+                    // by the next survivor; slot kLRow - 1 takes the overflow
+                    buf[min(ns, kLRow - 1)][tl] = u;
+                    ns += keep ? 1 : 0;
                 }
-                const bool keep = fmaf(d2, d2, fmaf(d1, d1, d0 * d0)) < lim2 && u != t;
-                if (keep && ns < kLRow) buf[ns][tl] = u;
-                ns += keep ? 1 : 0;
             }
-        }
-        if (ns > kLRow) {
+        };
+        auto walk = [&](auto sh_tag) {
+            for (int q0 = 0; q0 < n0; ++q0) {
+                int x = n0 == 3 ? cx + q0 - 1 : q0;
+                float sx = 0.f;
+                if (x < 0) { x += g.nc[0]; sx = -g.Lf[0]; } else if (x >= g.nc[0]) { x -= g.nc[0]; sx = g.Lf[0]; }
+                for (int q1 = 0; q1 < n1; ++q1) {
+                    int y = n1 == 3 ? cy + q1 - 1 : q1;
+                    float sy = 0.f;
+                    if (y < 0) { y += g.nc[1]; sy = -g.Lf[1]; } else if (y >= g.nc[1]) { y -= g.nc[1]; sy = g.Lf[1]; }
+                    const int col = coff + (x * g.nc[1] + y) * g.nc[2];
+                    if (n2 == 3) {
+                        const int zlo = max(cz - 1, 0), zhi = min(cz + 1, g.nc[2] - 1);
+                        scan(sh_tag, a.cell_start[col + zlo], a.cell_start[col + zhi] + a.cell_count[col + zhi], sx,
+                             sy, 0.f);
+                        if (cz == 0) {
+                            const int cw = col + g.nc[2] - 1;
+                            scan(sh_tag, a.cell_start[cw], a.cell_start[cw] + a.cell_count[cw], sx, sy, -g.Lf[2]);
+                        }
+                        if (cz == g.nc[2] - 1)
+                            scan(sh_tag, a.cell_start[col], a.cell_start[col] + a.cell_count[col], sx, sy, g.Lf[2]);
+                    } else {
+                        // every cell of the column once (minimum image decides)
+                        scan(sh_tag, a.cell_start[col],
+                             a.cell_start[col + g.nc[2] - 1] + a.cell_count[col + g.nc[2] - 1], sx, sy, 0.f);
+                    }
+                }
+            }
+        };
+        // the minimum-image form is valid on every grid; the shift form is
+        // taken when it holds for every thread of the wavefront
+        if (__all(shifted ? 1 : 0)) walk(std::integral_constant<bool, true>{});
+        else walk(std::integral_constant<bool, false>{});
+        if (ns > kLRow - 1) {
             // too many survivors for the LDS buffer: k_search_long writes this row
             a.long_rows[atomicAdd(a.n_long, 1)] = t;
             continue;
@@ -389,8 +444,11 @@ __global__ void k_reverse_map(const int *__restrict__ ell, int cap, const int *_
                               const int *__restrict__ n_dev, int *__restrict__ rv, int *flags)
 {
     const unsigned total = (unsigned)(n_dev ? *n_dev : n) * (unsigned)cap;   // n * cap < 2^31
-    for (unsigned tid = blockIdx.x * blockDim.x + threadIdx.x; tid < total; tid += gridDim.x * blockDim.x)
-        reverse_entry(ell, cap, row_count, tid, rv, flags);
+    const ItemRange r = xcd_items((int)((total + blockDim.x - 1) / blockDim.x));
+    for (int it = r.begin; it < r.end; it += r.stride) {
+        const unsigned tid = (unsigned)it * blockDim.x + threadIdx.x;
+        if (tid < total) reverse_entry(ell, cap, row_count, tid, rv, flags);
+    }
 }
 
 // ---- exclusive scan (three passes) -----------------------------------------
