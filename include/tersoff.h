@@ -183,6 +183,9 @@ typedef struct {
     double cutoff;              /* 0: the largest R + D of the table                        */
     double skin;                /* list radius = cutoff + skin                              */
     int64_t max_queued;         /* waiting requests before submit returns E_AGAIN (0: 65536) */
+    int32_t host_threads;       /* host threads copying requests in and results out,
+                                   the worker included (0: 4)                               */
+    int32_t reserved;           /* 0                                                        */
 } tersoff_serve_config;
 
 typedef struct {

@@ -34,7 +34,7 @@ SYMBOLS = ("tersoff_create", "tersoff_destroy", "tersoff_build_neighbors", "ters
 class ServeConfig(ctypes.Structure):
     _fields_ = [("max_batch_atoms", ctypes.c_int64), ("max_batch_systems", ctypes.c_int32),
                 ("max_neighbors", ctypes.c_int32), ("cutoff", ctypes.c_double), ("skin", ctypes.c_double),
-                ("max_queued", ctypes.c_int64)]
+                ("max_queued", ctypes.c_int64), ("host_threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Request(ctypes.Structure):
@@ -252,9 +252,9 @@ class Tersoff:
 
     # ---- serving -------------------------------------------------------------
     def serve_start(self, max_batch_atoms, max_batch_systems, max_neighbors=0, cutoff=0.0, skin=1.0,
-                    max_queued=0):
+                    max_queued=0, host_threads=0):
         cfg = ServeConfig(int(max_batch_atoms), int(max_batch_systems), int(max_neighbors), float(cutoff),
-                          float(skin), int(max_queued))
+                          float(skin), int(max_queued), int(host_threads), 0)
         st = self._lib.tersoff_serve_start(self._h, ctypes.byref(cfg))
         if st != OK:
             self._raise(st, "tersoff_serve_start")

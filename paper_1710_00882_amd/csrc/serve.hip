@@ -23,11 +23,14 @@
 #include "serve.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -79,6 +82,72 @@ struct Pinned {
     }
 };
 
+// Host threads that share the per-request copies of a batch (staging the
+// inputs into pinned memory, handing forces back) with the worker thread.
+class CopyPool {
+public:
+    explicit CopyPool(int helpers)
+    {
+        for (int h = 0; h < helpers; ++h) th_.emplace_back([this] { loop(); });
+    }
+    ~CopyPool()
+    {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    // f(k) for every k in [0, parts), spread over the helpers and the caller.
+    void run(int parts, const std::function<void(int)> &f)
+    {
+        if (th_.empty() || parts < 2) {
+            for (int k = 0; k < parts; ++k) f(k);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            job_ = &f;
+            parts_ = parts;
+            next_.store(0);
+            pending_ = (int)th_.size();
+            ++gen_;
+        }
+        cv_.notify_all();
+        for (int k; (k = next_.fetch_add(1)) < parts;) f(k);
+        std::unique_lock<std::mutex> lk(m_);
+        done_.wait(lk, [&] { return pending_ == 0; });
+        job_ = nullptr;
+    }
+
+private:
+    void loop()
+    {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> lk(m_);
+        for (;;) {
+            cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+            if (stop_) return;
+            seen = gen_;
+            const std::function<void(int)> *f = job_;
+            const int parts = parts_;
+            lk.unlock();
+            for (int k; (k = next_.fetch_add(1)) < parts;) (*f)(k);
+            lk.lock();
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex m_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int)> *job_ = nullptr;
+    int parts_ = 0, pending_ = 0;
+    std::atomic<int> next_{0};
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
 struct Pending {
     uint64_t ticket;
     tersoff_request req;
@@ -122,6 +191,7 @@ struct Server {
     size_t device_bytes = 0;
     int grids[2][3] = {};
     Lane lanes[kLanes];
+    std::unique_ptr<CopyPool> pool;
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -363,9 +433,6 @@ hipError_t launch_lane(Server &S, Lane &L)
     for (int q = 0; q < nsys; ++q) {
         const Pending &p = L.batch[q];
         const int n = (int)p.req.n;
-        std::memcpy(L.h_pos.p + 3 * (size_t)off, p.req.pos, sizeof(double) * 3 * (size_t)n);
-        std::memcpy(L.h_types.p + off, p.req.types, sizeof(int) * (size_t)n);
-        std::fill(L.h_sys_of.p + off, L.h_sys_of.p + off + n, q);
         SysDesc &d = L.h_desc.p[q];
         d.g = p.g;
         d.atom_off = off;
@@ -376,6 +443,13 @@ hipError_t launch_lane(Server &S, Lane &L)
         coff += p.ncell;
         L.want_forces |= p.req.forces != nullptr;
     }
+    S.pool->run(nsys, [&](int q) {
+        const Pending &p = L.batch[q];
+        const size_t n = (size_t)p.req.n, o = (size_t)L.h_desc.p[q].atom_off;
+        std::memcpy(L.h_pos.p + 3 * o, p.req.pos, sizeof(double) * 3 * n);
+        std::memcpy(L.h_types.p + o, p.req.types, sizeof(int) * n);
+        std::fill(L.h_sys_of.p + o, L.h_sys_of.p + o + n, q);
+    });
     L.natoms = off;
     *L.h_dims.p = BatchDims{off, coff, nsys, 0};
     hipStream_t s = L.stream;
@@ -395,19 +469,18 @@ hipError_t launch_lane(Server &S, Lane &L)
 // Results of a finished (or failed) batch to the waiting callers.
 void retire(Server &S, Lane &L, hipError_t status)
 {
-    const int64_t now = now_ns();
-    std::vector<std::pair<uint64_t, tersoff_result>> out;
-    out.reserve(L.batch.size());
-    for (size_t q = 0; q < L.batch.size(); ++q) {
+    const size_t nsys = L.batch.size();
+    std::vector<std::pair<uint64_t, tersoff_result>> out(nsys);
+    S.pool->run((int)nsys, [&](int q) {
         const Pending &p = L.batch[q];
         tersoff_result r{};
         r.tag = p.req.tag;
         r.n = p.req.n;
-        r.batch_systems = (int32_t)L.batch.size();
+        r.batch_systems = (int32_t)nsys;
         if (status != hipSuccess) {
             r.status = TERSOFF_E_DEVICE;
         } else {
-            const double *o = L.h_out.p + 8 * q;
+            const double *o = L.h_out.p + 8 * (size_t)q;
             const int st = (int)o[7];
             r.status = st ? TERSOFF_E_OVERFLOW : TERSOFF_OK;
             r.energy = o[0];
@@ -416,9 +489,11 @@ void retire(Server &S, Lane &L, hipError_t status)
                 std::memcpy(p.req.forces, L.h_forces.p + 3 * (size_t)L.h_desc.p[q].atom_off,
                             sizeof(double) * 3 * (size_t)p.req.n);
         }
-        r.latency_ms = 1e-6 * (double)(now - p.t_start);
-        out.emplace_back(p.ticket, r);
-    }
+        out[q] = {p.ticket, r};
+    });
+    // ready now: every force array of the batch has been written
+    const int64_t now = now_ns();
+    for (size_t q = 0; q < nsys; ++q) out[q].second.latency_ms = 1e-6 * (double)(now - L.batch[q].t_start);
     {
         std::lock_guard<std::mutex> lk(S.mu);
         for (auto &pr : out) S.results[pr.first] = pr.second;
@@ -511,6 +586,10 @@ int server_create(const ServerEnv &env, const tersoff_serve_config &cfg, Server 
               "max_batch_systems in [1, 2^20]";
         return TERSOFF_E_INVALID;
     }
+    if (cfg.host_threads < 0 || cfg.host_threads > 64) {
+        err = "host_threads must be in [0, 64]";
+        return TERSOFF_E_INVALID;
+    }
     Server *S = new (std::nothrow) Server();
     if (!S) return TERSOFF_E_NOMEM;
     S->env = env;
@@ -535,6 +614,7 @@ int server_create(const ServerEnv &env, const tersoff_serve_config &cfg, Server 
         return e == hipErrorOutOfMemory ? TERSOFF_E_NOMEM : TERSOFF_E_DEVICE;
     }
     try {
+        S->pool.reset(new CopyPool(cfg.host_threads > 0 ? cfg.host_threads - 1 : 3));
         S->worker = std::thread(worker_main, S);
     } catch (...) {
         for (auto &L : S->lanes) free_lane(L);
