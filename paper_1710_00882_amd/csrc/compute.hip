@@ -236,6 +236,8 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 if (!(dx * dx + dy * dy + dz * dz <= a.stale_sq)) atomicOr(a.flags, kFlagStale);
             }
         }
+        // the batch's rows are one contiguous segment of the compact list
+        const int ebase = a.offsets[a0];
         {
             // local entry offsets of the batch's rows
             const int rc = lane < nb ? a.row_count[a0 + lane] : 0;
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 if (e < e_end) {
                     const int al = find_seg(eoff, nb, e);
                     alv[c] = al;
-                    ev[c] = (a0 + al) * a.cap + (e - eoff[al]);   // row-buffer address of the entry
+                    ev[c] = ebase + e;   // list index of the entry
                     jv[c] = a.jn[ev[c]];
                     rvv[c] = a.rv[ev[c]];
                 }
@@ -703,15 +705,15 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
 // never run as centres; zero the force slots their neighbours reserved for
 // them so the gather adds nothing stale.  Workgroups loop until the list is
 // drained.
-__global__ void k_fixup_dropped(const int *__restrict__ row_count, const int *__restrict__ jn,
-                                const int *__restrict__ rv, int cap, const signed char *__restrict__ slotpos,
+__global__ void k_fixup_dropped(const int *__restrict__ offsets, const int *__restrict__ jn,
+                                const int *__restrict__ rv, const signed char *__restrict__ slotpos,
                                 const int *__restrict__ drop_list, const int *__restrict__ drop_count,
                                 int plane_stride, double *__restrict__ planes)
 {
     const int nd = *drop_count;
     for (int q = blockIdx.x; q < nd; q += gridDim.x) {
         const int m = drop_list[q];
-        const int e0 = m * cap, e1 = m * cap + row_count[m];
+        const int e0 = offsets[m], e1 = offsets[m + 1];
         for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
             if (slotpos[e] == -1) continue;            // m did not keep this neighbour
             const int k = slotpos[rv[e]];              // rank of m in the neighbour's row
@@ -910,11 +912,11 @@ hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mix
     return hipGetLastError();
 }
 
-hipError_t launch_fixup_dropped(const int *row_count, const int *jn, const int *rv, int cap,
+hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *rv,
                                 const signed char *slotpos, const int *drop_list, const int *drop_count,
                                 int plane_stride, double *planes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fixup_dropped, dim3(kBigGrid), dim3(kWave), 0, s, row_count, jn, rv, cap, slotpos,
+    hipLaunchKernelGGL(k_fixup_dropped, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jn, rv, slotpos,
                        drop_list, drop_count, plane_stride, planes);
     return hipGetLastError();
 }

@@ -107,14 +107,14 @@ struct PackLaunch {
     const double *pos;          // n x 3
     const int *types;           // n
     const int *row_count;       // n: list length of each atom
-    const int *jn;              // n x cap: sorted neighbour rows (row i at i * cap)
-    const int *rv;              // n x cap: entry of (j, i) for entry (i, j)
-    int cap;
+    const int *offsets;         // n + 1: first list entry of each atom (compact list)
+    const int *jn;              // list entries: sorted neighbour rows, row i at offsets[i]
+    const int *rv;              // list entries: index of (j, i) for entry (i, j)
     int n;
     double L[3], invL[3];
     void *recs;                 // packed records: region of B * kRecCap per batch of B atoms
     int *pcount;                // n: records per atom
-    signed char *slotpos;       // n x cap: rank among the row's kept entries, -1 not kept, -2 beyond kRecCap
+    signed char *slotpos;       // list entries: rank among the row's kept entries, -1 not kept, -2 beyond kRecCap
     double *own;                // n x 3 (zeroed for dropped atoms only)
     int *flags;
     int *drop_list;             // n: atoms with more kept neighbours than kRecCap
@@ -132,7 +132,7 @@ struct ComputeLaunch {
     const int *types;           // n
     const void *recs;           // packed records (batch regions)
     const int *pcount;          // n
-    const signed char *slotpos; // n x cap
+    const signed char *slotpos; // list entries
     int n;
     double *own;                // n x 3: force from the terms of each centre atom
     double *planes;             // kRecCap x n x 3: plane k of atom j = force from its k-th kept neighbour's terms
@@ -153,7 +153,7 @@ size_t record_bytes(bool mixed);
 hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s);
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mixed,
                           int grid, hipStream_t s);
-hipError_t launch_fixup_dropped(const int *row_count, const int *jn, const int *rv, int cap,
+hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *rv,
                                 const signed char *slotpos, const int *drop_list, const int *drop_count,
                                 int plane_stride, double *planes, hipStream_t s);
 // Sums the partials into out7 / counts_out and resets *drop_count to 0.
@@ -211,10 +211,11 @@ struct SearchLaunch {
     int *sys_status;
 };
 hipError_t launch_search(const SearchLaunch &a, int grid_cap, hipStream_t s);
-// rv[e] for entry e = (i, j) = i * cap + q: the entry of i in row j (the
-// list is symmetric).  Sets *flags |= 4 if some reverse entry is missing.
-hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, int n, const int *n_dev, int *rv,
-                              int *flags, hipStream_t s);
+// Compact list from the row buffer (row i at i * cap): jn[offsets[i] + q] =
+// ell[i * cap + q], and rv[e] for entry e = (i, j): the index of entry (j, i)
+// (the list is symmetric).  Sets *flags |= 4 if some reverse entry is missing.
+hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, const int *offsets, int n,
+                              const int *n_dev, int *jn, int *rv, int *flags, hipStream_t s);
 // Batched build: binning of every system's atoms into its own cells.
 hipError_t launch_bin_systems(const double *pos, const int *sys_of, const SysDesc *sys, const BatchDims *dims,
                               int max_atoms, int *cell_of, int *rank_in_cell, int *cell_count, hipStream_t s);

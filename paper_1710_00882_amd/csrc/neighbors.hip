@@ -397,20 +397,24 @@ __global__ __launch_bounds__(kWave) void k_search_long(SearchLaunch a)
     }
 }
 
-// rv[e] for entry e = (i, j) = i * cap + q of the row buffer: the entry of i
-// in the sorted row of j.  One thread per (i, q) with i < j searches row j
-// (16-entry pieces of four 16-byte loads issued together) and fills both
-// rv[(i, j)] and rv[(j, i)].  The inclusion predicate is symmetric (negating
-// t negates s and d exactly), so the entry exists; a missing one raises
-// flag 4.
+// Compact list and reverse entries.  For entry (i, q) of the row buffer
+// (row i at i * cap, neighbour j) the compact index is e = offsets[i] + q:
+// jn[e] = j, and the thread with i < j searches row j (16-entry pieces of
+// four 16-byte loads issued together) for i at position p and fills
+// rv[e] = offsets[j] + p and rv[offsets[j] + p] = e.  The inclusion
+// predicate is symmetric (negating t negates s and d exactly), so the entry
+// exists; a missing one raises flag 4.
 __device__ __forceinline__ void reverse_entry(const int *__restrict__ ell, int cap,
-                                              const int *__restrict__ row_count, unsigned tid,
-                                              int *__restrict__ rv, int *flags)
+                                              const int *__restrict__ row_count,
+                                              const int *__restrict__ offsets, unsigned tid,
+                                              int *__restrict__ jn, int *__restrict__ rv, int *flags)
 {
     const int i = (int)(tid / (unsigned)cap);
     const int q = (int)(tid - (unsigned)i * (unsigned)cap);
     if (q >= row_count[i]) return;
     const int j = ell[(size_t)i * cap + q];
+    const int e = offsets[i] + q;
+    jn[e] = j;
     if (j < i) return;   // the pair is handled from the other side
     const int cj = row_count[j];
     const int4 *row = reinterpret_cast<const int4 *>(ell + (size_t)j * cap);
@@ -428,26 +432,27 @@ __device__ __forceinline__ void reverse_entry(const int *__restrict__ ell, int c
             if (k + 3 < cj && v[u].w == i) at = k + 3;
         }
     }
-    const int e = (int)((size_t)i * cap + q);
     if (at < 0) {
         atomicOr(flags, 4);
         rv[e] = e;
     } else {
-        const int f = (int)((size_t)j * cap + at);
+        const int f = offsets[j] + at;
         rv[e] = f;
         rv[f] = e;
     }
 }
 
-// One thread per (i, q), q < cap; n_dev as in k_scatter.
-__global__ void k_reverse_map(const int *__restrict__ ell, int cap, const int *__restrict__ row_count, int n,
-                              const int *__restrict__ n_dev, int *__restrict__ rv, int *flags)
+// One thread per (i, q), q < cap; n_dev, when not null, holds the atom count
+// (batches) and n is the capacity the grid was sized for.
+__global__ void k_reverse_map(const int *__restrict__ ell, int cap, const int *__restrict__ row_count,
+                              const int *__restrict__ offsets, int n, const int *__restrict__ n_dev,
+                              int *__restrict__ jn, int *__restrict__ rv, int *flags)
 {
     const unsigned total = (unsigned)(n_dev ? *n_dev : n) * (unsigned)cap;   // n * cap < 2^31
     const ItemRange r = xcd_items((int)((total + blockDim.x - 1) / blockDim.x));
     for (int it = r.begin; it < r.end; it += r.stride) {
         const unsigned tid = (unsigned)it * blockDim.x + threadIdx.x;
-        if (tid < total) reverse_entry(ell, cap, row_count, tid, rv, flags);
+        if (tid < total) reverse_entry(ell, cap, row_count, offsets, tid, jn, rv, flags);
     }
 }
 
@@ -566,14 +571,14 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int n, int *tmp, int *
     return hipGetLastError();
 }
 
-hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, int n, const int *n_dev, int *rv,
-                              int *flags, hipStream_t s)
+hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, const int *offsets, int n,
+                              const int *n_dev, int *jn, int *rv, int *flags, hipStream_t s)
 {
     const long long threads = (long long)n * cap;
     long long blocks = (threads + 255) / 256;
     if (n_dev && blocks > kBatchGrid) blocks = kBatchGrid;
     hipLaunchKernelGGL(k_reverse_map, dim3((unsigned)std::max(1LL, blocks)), dim3(256), 0, s, ell, cap,
-                       row_count, n, n_dev, rv, flags);
+                       row_count, offsets, n, n_dev, jn, rv, flags);
     return hipGetLastError();
 }
 

@@ -168,7 +168,7 @@ struct Lane {
     Dev<float4> cell_posf;
     Dev<int> long_rows;
     Dev<int> types, sys_of, cell_of, rank, cell_count, cell_start, cell_atoms, scan_tmp;
-    Dev<int> ell, row_count, rv, pcount, drop_list;
+    Dev<int> ell, row_count, offsets, jn, rv, pcount, drop_list;   // jn, rv, slotpos: compact list
     Dev<int> ctl;   // [0] flags, [1] dropped count, [2] long rows, [3 ..] per-system status
     Dev<signed char> slotpos;
     Dev<unsigned char> recs;
@@ -261,9 +261,11 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.cell_count.alloc(NC, tot));
     SRV_TRY(L.cell_start.alloc(NC + 1, tot));
     SRV_TRY(L.cell_atoms.alloc(A, tot));
-    SRV_TRY(L.scan_tmp.alloc(scan_tmp_size((int)NC), tot));
+    SRV_TRY(L.scan_tmp.alloc(std::max(scan_tmp_size((int)NC), scan_tmp_size((int)A)), tot));
     SRV_TRY(L.ell.alloc(E, tot));
     SRV_TRY(L.row_count.alloc(A, tot));
+    SRV_TRY(L.offsets.alloc(A + 1, tot));
+    SRV_TRY(L.jn.alloc(E, tot));
     SRV_TRY(L.rv.alloc(E, tot));
     SRV_TRY(L.pcount.alloc(A, tot));
     SRV_TRY(L.drop_list.alloc(A, tot));
@@ -293,6 +295,7 @@ void free_lane(Lane &L)
     L.eatom.release(); L.out.release(); L.types.release(); L.sys_of.release(); L.cell_of.release();
     L.rank.release(); L.cell_count.release(); L.cell_start.release(); L.cell_atoms.release();
     L.scan_tmp.release(); L.ell.release(); L.row_count.release(); L.rv.release(); L.pcount.release();
+    L.offsets.release(); L.jn.release();
     L.drop_list.release(); L.ctl.release(); L.slotpos.release(); L.recs.release(); L.desc.release();
     L.dims.release();
     if (L.done) (void)hipEventDestroy(L.done), L.done = nullptr;
@@ -343,15 +346,18 @@ hipError_t enqueue_batch(Server &S, Lane &L, bool mixed)
     sl.n_long = L.ctl.p + 2;
     sl.sys_status = L.ctl.p + 3;
     SRV_TRY(launch_search(sl, kBatchGrid, s));
-    SRV_TRY(launch_reverse_map(L.ell.p, S.cap, L.row_count.p, S.max_atoms, n_dev, L.rv.p, L.ctl.p, s));
+    // compact list (counts past the batch's atoms do not enter the offsets of its atoms)
+    SRV_TRY(launch_exclusive_scan(L.row_count.p, L.offsets.p, S.max_atoms, L.scan_tmp.p, nullptr, s));
+    SRV_TRY(launch_reverse_map(L.ell.p, S.cap, L.row_count.p, L.offsets.p, S.max_atoms, n_dev, L.jn.p, L.rv.p,
+                               L.ctl.p, s));
 
     PackLaunch pk{};
     pk.pos = L.pos.p;
     pk.types = L.types.p;
     pk.row_count = L.row_count.p;
-    pk.jn = L.ell.p;
+    pk.offsets = L.offsets.p;
+    pk.jn = L.jn.p;
     pk.rv = L.rv.p;
-    pk.cap = S.cap;
     pk.n = S.max_atoms;
     pk.recs = L.recs.p;
     pk.pcount = L.pcount.p;
@@ -381,7 +387,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, bool mixed)
     a.n_dev = n_dev;
     a.eatom = L.eatom.p;
     SRV_TRY(launch_compute(a, S.env.tab, mixed, S.grids[mixed][1], s));
-    SRV_TRY(launch_fixup_dropped(L.row_count.p, L.ell.p, L.rv.p, S.cap, L.slotpos.p, L.drop_list.p, L.ctl.p + 1,
+    SRV_TRY(launch_fixup_dropped(L.offsets.p, L.jn.p, L.rv.p, L.slotpos.p, L.drop_list.p, L.ctl.p + 1,
                                  S.max_atoms, L.planes.p, s));
     SRV_TRY(launch_gather_forces(L.pcount.p, L.planes.p, L.own.p, S.max_atoms, n_dev, S.max_atoms, L.forces.p, s));
     SRV_TRY(launch_reduce_systems(L.desc.p, L.dims.p, S.max_sys, L.eatom.p, L.drop_list.p, L.ctl.p + 1,

@@ -63,7 +63,7 @@ struct tersoff_ctx {
     int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};   // [fp64, mixed] x {pack, compute, per-atom}
 
     DevBuf<double> pos_build;
-    DevBuf<int> types, offsets, pcount, drop_list, rv;
+    DevBuf<int> types, offsets, pcount, drop_list, rv, jn;   // jn, rv, slotpos: compact list (S entries)
     DevBuf<signed char> slotpos;
     DevBuf<unsigned char> recs;
     DevBuf<double> own, planes;
@@ -258,7 +258,7 @@ void tersoff_destroy(tersoff_ctx *c)
     c->server = nullptr;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    c->pos_build.release(); c->types.release(); c->offsets.release();
+    c->pos_build.release(); c->types.release(); c->offsets.release(); c->jn.release();
     c->rv.release(); c->slotpos.release(); c->own.release(); c->planes.release();
     c->pcount.release(); c->drop_list.release(); c->recs.release();
     c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
@@ -435,11 +435,13 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     if (host[0] < 0) return fail(c, TERSOFF_E_INVALID, "list longer than 2^31 entries");
     c->S = host[0];
     if ((long long)N * c->list_cap >= (1LL << 31)) return fail(c, TERSOFF_E_INVALID, "n x row capacity >= 2^31");
-    const size_t NE = (size_t)N * c->list_cap;
+    const size_t NE = std::max<size_t>((size_t)c->S, 1);
+    HIP_TRY(c, c->jn.ensure(NE));
     HIP_TRY(c, c->rv.ensure(NE));
     HIP_TRY(c, c->slotpos.ensure(NE));
     HIP_TRY(c, c->own.ensure(3 * (size_t)N));
-    HIP_TRY(c, launch_reverse_map(c->ell.p, c->list_cap, c->row_count.p, N, nullptr, c->rv.p, c->misc.p + 2, s));
+    HIP_TRY(c, launch_reverse_map(c->ell.p, c->list_cap, c->row_count.p, c->offsets.p, N, nullptr, c->jn.p,
+                                  c->rv.p, c->misc.p + 2, s));
     HIP_TRY(c, hipMemcpyAsync(c->pos_build.p, pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->types.p, types, sizeof(int) * (size_t)N, hipMemcpyDeviceToDevice, s));
     int chk = 0;
@@ -493,9 +495,9 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     pk.pos = pos;
     pk.types = c->types.p;
     pk.row_count = c->row_count.p;
-    pk.jn = c->ell.p;
+    pk.offsets = c->offsets.p;
+    pk.jn = c->jn.p;
     pk.rv = c->rv.p;
-    pk.cap = c->list_cap;
     pk.n = c->n;
     for (int d = 0; d < 3; ++d) {
         pk.L[d] = c->box[d];
@@ -536,7 +538,7 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     HIP_TRY(c, launch_compute(a, c->tab, mixed, grid[1], s));
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
-    HIP_TRY(c, launch_fixup_dropped(c->row_count.p, c->ell.p, c->rv.p, c->list_cap, c->slotpos.p,
+    HIP_TRY(c, launch_fixup_dropped(c->offsets.p, c->jn.p, c->rv.p, c->slotpos.p,
                                     c->drop_list.p, c->misc.p + 3, c->n, c->planes.p, s));
     HIP_TRY(c, launch_gather_forces(c->pcount.p, c->planes.p, c->own.p, c->n, nullptr, c->n, f, s));
     if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
@@ -572,16 +574,12 @@ int tersoff_get_neighbors(tersoff_ctx *c, int64_t *offsets, int32_t *idx, int64_
     if (!offsets || !total) return fail(c, TERSOFF_E_INVALID, "null pointer");
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipDeviceSynchronize());
-    std::vector<int> cnt((size_t)c->n);
-    HIP_TRY(c, hipMemcpy(cnt.data(), c->row_count.p, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost));
-    offsets[0] = 0;
-    for (size_t i = 0; i < cnt.size(); ++i) offsets[i + 1] = offsets[i] + cnt[i];
+    std::vector<int> off((size_t)c->n + 1);
+    HIP_TRY(c, hipMemcpy(off.data(), c->offsets.p, sizeof(int) * off.size(), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < off.size(); ++i) offsets[i] = off[i];
     *total = c->S;
     if (cap < c->S || (!idx && c->S > 0)) return fail(c, TERSOFF_E_INVALID, "idx capacity below list length");
-    std::vector<int> rows((size_t)c->n * c->list_cap);
-    HIP_TRY(c, hipMemcpy(rows.data(), c->ell.p, sizeof(int) * rows.size(), hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < cnt.size(); ++i)
-        std::memcpy(idx + offsets[i], rows.data() + i * c->list_cap, sizeof(int) * (size_t)cnt[i]);
+    if (c->S > 0) HIP_TRY(c, hipMemcpy(idx, c->jn.p, sizeof(int) * (size_t)c->S, hipMemcpyDeviceToHost));
     return TERSOFF_OK;
 }
 
