@@ -149,9 +149,14 @@ __device__ inline bool in_range(double xj, double yj, double zj, double xi, doub
 // Pre-test bound: the wrapped single-precision coordinates and the rounded box
 // lengths are each within 2^-24 L of their exact values, and the difference
 // plus image shift adds two more roundings of that size, so every component
-// is within 5 * 2^-24 L_a of the exact minimum-image displacement; the radius
-// is widened by 4e-7 (Lx + Ly + Lz) + 1e-5 (> 6.7 * 2^-24 sum L), so no
-// neighbour is ever rejected by the pre-test.
+// is within 5 * 2^-24 L_a of the exact minimum-image displacement, and the
+// single-precision distance within delta = 4e-7 (Lx + Ly + Lz) + 1e-5 of the
+// exact one (the 1e-5 covers the rounding of r^2 and of the radius).  So no
+// neighbour is rejected by the test r < rc + delta, and, in the shift form, a
+// candidate with r < rc - delta is inside for the exact predicate too; only
+// the survivors in between take the FP64 test.  (The minimum-image form can
+// pick the other image for a pair at almost exactly half a box, so there
+// every survivor takes the FP64 test.)
 constexpr int kLRow = 32;          // LDS slots per thread: up to kLRow - 1 survivors, one scratch slot
 constexpr int kSearchThreads = 256;
 
@@ -225,8 +230,10 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
         const int cz = c % g.nc[2], cy = (c / g.nc[2]) % g.nc[1], cx = c / (g.nc[1] * g.nc[2]);
         const int n0 = min(g.nc[0], 3), n1 = min(g.nc[1], 3), n2 = min(g.nc[2], 3);
         const bool shifted = n0 == 3 && n1 == 3 && n2 == 3;
-        const float lim = a.rcs + 4e-7f * (g.Lf[0] + g.Lf[1] + g.Lf[2]) + 1e-5f;
-        const float lim2 = lim * lim;
+        const float delta = 4e-7f * (g.Lf[0] + g.Lf[1] + g.Lf[2]) + 1e-5f;
+        const float lim = a.rcs + delta, lim2 = lim * lim;
+        // below this radius the exact predicate is certain to accept (shift form only)
+        const float sure = fmaxf(a.rcs - delta, 0.f), sure2 = sure * sure;
 
         // ---- 1: pre-test, survivors (candidate slots) to LDS.  The cells
         // (x, y, z-1 .. z+1) of a column are consecutive in cell order, so
@@ -251,10 +258,14 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
                         d1 = fmaf(-rintf(d1 * g.invLf[1]), g.Lf[1], d1);
                         d2 = fmaf(-rintf(d2 * g.invLf[2]), g.Lf[2], d2);
                     }
-                    const bool keep = u < u1 && u != t && fmaf(d2, d2, fmaf(d1, d1, d0 * d0)) < lim2;
-                    // unconditional store: a rejected candidate is overwritten
-                    // by the next survivor; slot kLRow - 1 takes the overflow
-                    buf[min(ns, kLRow - 1)][tl] = u;
+                    const float r2 = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+                    const bool keep = u < u1 && u != t && r2 < lim2;
+                    // survivors surely inside are stored as -(id + 1), the
+                    // others as their cell-order slot for the exact test;
+                    // the store is unconditional: a rejected candidate is
+                    // overwritten by the next survivor, slot kLRow - 1 takes
+                    // the overflow
+                    buf[min(ns, kLRow - 1)][tl] = (SH && r2 < sure2) ? -1 - __float_as_int(fj[r].w) : u;
                     ns += keep ? 1 : 0;
                 }
             }
@@ -297,15 +308,19 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
             continue;
         }
 
-        // ---- 2: exact predicate, accepted ids compacted in place
+        // ---- 2: exact predicate for the survivors near the list radius,
+        // accepted ids compacted in place
         const double xi = a.cell_pos[3 * (size_t)t], yi = a.cell_pos[3 * (size_t)t + 1],
                      zi = a.cell_pos[3 * (size_t)t + 2];
         int cnt = 0;
         for (int k = 0; k < ns; ++k) {
             const int u = buf[k][tl];
-            if (in_range(a.cell_pos[3 * (size_t)u], a.cell_pos[3 * (size_t)u + 1], a.cell_pos[3 * (size_t)u + 2],
-                         xi, yi, zi, g, a.rc2))
+            if (u < 0) {
+                buf[cnt++][tl] = -1 - u;
+            } else if (in_range(a.cell_pos[3 * (size_t)u], a.cell_pos[3 * (size_t)u + 1],
+                                a.cell_pos[3 * (size_t)u + 2], xi, yi, zi, g, a.rc2)) {
                 buf[cnt++][tl] = a.cell_atoms[u];
+            }
         }
 
         // ---- 3: sort and store
