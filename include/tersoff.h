@@ -54,7 +54,13 @@ enum {
 };
 #define TERSOFF_MAX_TYPES 4
 
-typedef enum { TERSOFF_FP64 = 0, TERSOFF_MIXED = 1 } tersoff_precision;
+/* TERSOFF_FP64: all FP64.  TERSOFF_MIXED: FP32 pair and triplet functions;
+ * FP64 displacement, zeta -> b_ij power in log form, and every accumulation
+ * of energy, force and virial.  TERSOFF_SINGLE: as mixed, but the zeta -> b_ij
+ * power and each pair's sum of force terms in FP32 too (FP64 only for the
+ * displacement and the sums across pairs and atoms); the paper's "single"
+ * point (Section 5). */
+typedef enum { TERSOFF_FP64 = 0, TERSOFF_MIXED = 1, TERSOFF_SINGLE = 2 } tersoff_precision;
 
 typedef enum {
     TERSOFF_OK = 0,
@@ -109,9 +115,7 @@ int tersoff_build_neighbors(tersoff_ctx *ctx, const double *pos, const int32_t *
 /* Energy, forces and virial (Eq. 1-3, Algorithm 1) from the resident list.
  * pos: device, n x 3 float64 for the same n atoms as the last build (they may
  *   have moved; the minimum-image displacement is recomputed in FP64).
- * precision: TERSOFF_FP64 (all FP64) or TERSOFF_MIXED (FP32 pair and triplet
- *   functions; FP64 displacement, zeta -> b_ij power in log form, and energy /
- *   force / virial accumulation).
+ * precision: TERSOFF_FP64, TERSOFF_MIXED or TERSOFF_SINGLE (tersoff_precision).
  * energy_virial: device, 7 float64 written: E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz.
  * forces: device, n x 3 float64, overwritten; may be NULL.
  * Stream-ordered on `stream`; does not synchronise.  A capacity overflow or a
@@ -193,7 +197,7 @@ typedef struct {
     const int32_t *types;   /* host, n int32 in [0, ntypes)                              */
     int64_t n;
     double box[3];          /* orthorhombic periodic lengths, each >= 2 (cutoff + skin)  */
-    int32_t precision;      /* TERSOFF_FP64 or TERSOFF_MIXED                              */
+    int32_t precision;      /* a tersoff_precision                                       */
     double *forces;         /* host, n x 3, written before the result is ready; or NULL  */
     uint64_t tag;           /* returned unchanged                                        */
     int64_t release_ns;     /* tersoff_clock_ns() time before which the request is not

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libtersoff.so")
 
 FP64 = 0
 MIXED = 1
-PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+SINGLE = 2
+PRECISIONS = {"fp64": FP64, "mixed": MIXED, "single": SINGLE}
 
 OK = 0
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_BOX", -4: "E_OVERFLOW", -5: "E_STALE",

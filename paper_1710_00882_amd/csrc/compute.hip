@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace tsf {
 
@@ -432,9 +433,15 @@ __device__ __forceinline__ void exp_term(const ParamR<real> &q, real rj, real rk
 // BATCHED: the batch holds several systems; each centre atom's energy and
 // virial (the sums over its slots) are stored per atom for the per-system
 // reduction, in place of the per-workgroup partial sums.
-template <typename real, bool ONE, bool BATCHED>
+//
+// SINGLE (with real = float): the all-FP32 variant -- the zeta -> b power and
+// each lane's sum of the force terms on j in FP32 as well; FP64 remains only
+// in the displacement (packing) and in the sums across lanes and atoms.
+template <typename real, bool ONE, bool BATCHED, bool SINGLE>
 __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable tab)
 {
+    static_assert(!SINGLE || sizeof(real) == 4, "the single-precision variant computes in float");
+    using facc = typename std::conditional<SINGLE, float, double>::type;   // per-lane force sum
     __shared__ Shared<real, ONE> sh;
     __shared__ double sev[BATCHED ? kScap : 1][BATCHED ? 7 : 1];   // per-slot energy and virial
     const int lane = threadIdx.x;
@@ -528,7 +535,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
 
             const int tj = mj & 0xff;
             const bool j_pair = (mj >> kPairBit) & 1;
-            double fx = 0, fy = 0, fz = 0;     // force on j from centre i's terms
+            facc fx = 0, fy = 0, fz = 0;       // force on j from centre i's terms
             double e_pair = 0.0;   // energy of pair (i, j)
             if (has_slot) {
                 // ---- 1: zeta_ij over the other slots k of centre i (k = j skipped
@@ -559,22 +566,44 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                     const real fc = sh.fc[ONE ? 0 : tj][s], dfc = sh.dfc[ONE ? 0 : tj][s];
                     real fr, fa, dfr, dfa;
                     pair_terms(q, rj, fr, dfr, fa, dfa);
-                    // Eq. (2) in FP64 log form
-                    const double zeta = (double)zr;
-                    double b = 1.0, db = 0.0;
-                    if (zeta > 0.0) {
-                        const double x = ::exp(px.eta * (px.logbeta + ::log(zeta)));
-                        b = ::exp(-::log1p(x) * px.inv2eta);
-                        db = -0.5 * b * x / (zeta * (1.0 + x));
+                    // Eq. (2) in log form: FP64, or FP32 in the single variant
+                    real br;
+                    if constexpr (SINGLE) {
+                        // b - 1 is carried instead of b (b is within ~1e-4 of 1,
+                        // and its FP32 rounding would bias the energy through
+                        // the large f_A at short range)
+                        float bm1 = 0.f, db = 0.f;
+                        if (zr > 0.f) {
+                            const float x = expf((float)px.eta * ((float)px.logbeta + logf(zr)));
+                            bm1 = expm1f(-log1pf(x) * (float)px.inv2eta);
+                            db = -0.5f * (1.f + bm1) * x / (zr * (1.f + x));
+                        }
+                        br = 1.f + bm1;
+                        e_pair = (double)(0.5f * fc * ((fr + fa) + bm1 * fa));
+                        dz_out = 0.5f * fc * fa * db;
+                        const real dvdr1 = real(0.5) * (dfc * ((fr + fa) + bm1 * fa) + fc * ((dfr + dfa) + bm1 * dfa));
+                        fx = -dvdr1 * uj[0];
+                        fy = -dvdr1 * uj[1];
+                        fz = -dvdr1 * uj[2];
+                    } else {
+                        const double zeta = (double)zr;
+                        double b = 1.0, db = 0.0;
+                        if (zeta > 0.0) {
+                            const double x = ::exp(px.eta * (px.logbeta + ::log(zeta)));
+                            b = ::exp(-::log1p(x) * px.inv2eta);
+                            db = -0.5 * b * x / (zeta * (1.0 + x));
+                        }
+                        br = (real)b;
+                        e_pair = 0.5 * (double)fc * ((double)fr + b * (double)fa);
+                        dz_out = (real)(0.5 * (double)fc * (double)fa * db);
                     }
-                    const real br = (real)b;
-                    e_pair = 0.5 * (double)fc * ((double)fr + b * (double)fa);
                     e_acc += e_pair;
-                    const real dvdr = real(0.5) * (dfc * (fr + br * fa) + fc * (dfr + br * dfa));
-                    fx = (double)(-dvdr * uj[0]);
-                    fy = (double)(-dvdr * uj[1]);
-                    fz = (double)(-dvdr * uj[2]);
-                    dz_out = (real)(0.5 * (double)fc * (double)fa * db);
+                    if constexpr (!SINGLE) {
+                        const real dvdr = real(0.5) * (dfc * (fr + br * fa) + fc * (dfr + br * dfa));
+                        fx = (facc)(-dvdr * uj[0]);
+                        fy = (facc)(-dvdr * uj[1]);
+                        fz = (facc)(-dvdr * uj[2]);
+                    }
                 }
                 sh.dzeta[s] = dz_out;
             }
@@ -629,31 +658,32 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                             cu += dzk * an.g * (dfcj * ex - fcj * dex);
                         }
                     }
-                    fx -= (double)(cdc * dc[0] + cu * uj[0]);
-                    fy -= (double)(cdc * dc[1] + cu * uj[1]);
-                    fz -= (double)(cdc * dc[2] + cu * uj[2]);
+                    fx -= (facc)(cdc * dc[0] + cu * uj[0]);
+                    fy -= (facc)(cdc * dc[1] + cu * uj[1]);
+                    fz -= (facc)(cdc * dc[2] + cu * uj[2]);
                 }
-                // ---- 4: virial and output
+                // ---- 4: virial and output (FP64 from here on)
+                const double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
                 const double dxj = (double)(rj * uj[0]), dyj = (double)(rj * uj[1]), dzj_ = (double)(rj * uj[2]);
-                w_acc[0] += dxj * fx;
-                w_acc[1] += dyj * fy;
-                w_acc[2] += dzj_ * fz;
-                w_acc[3] += dxj * fy;
-                w_acc[4] += dxj * fz;
-                w_acc[5] += dyj * fz;
+                w_acc[0] += dxj * Fx;
+                w_acc[1] += dyj * Fy;
+                w_acc[2] += dzj_ * Fz;
+                w_acc[3] += dxj * Fy;
+                w_acc[4] += dxj * Fz;
+                w_acc[5] += dyj * Fz;
                 if ((unsigned)kpos < (unsigned)kRecCap) {
                     double *f = a.planes + 3 * ((size_t)kpos * a.plane_stride + (size_t)j);
-                    f[0] = fx; f[1] = fy; f[2] = fz;
+                    f[0] = Fx; f[1] = Fy; f[2] = Fz;
                 }
-                sh.fs[s][0] = fx; sh.fs[s][1] = fy; sh.fs[s][2] = fz;
+                sh.fs[s][0] = Fx; sh.fs[s][1] = Fy; sh.fs[s][2] = Fz;
                 if constexpr (BATCHED) {
                     sev[s][0] = e_pair;
-                    sev[s][1] = dxj * fx;
-                    sev[s][2] = dyj * fy;
-                    sev[s][3] = dzj_ * fz;
-                    sev[s][4] = dxj * fy;
-                    sev[s][5] = dxj * fz;
-                    sev[s][6] = dyj * fz;
+                    sev[s][1] = dxj * Fx;
+                    sev[s][2] = dyj * Fy;
+                    sev[s][3] = dzj_ * Fz;
+                    sev[s][4] = dxj * Fy;
+                    sev[s][5] = dxj * Fz;
+                    sev[s][6] = dyj * Fz;
                 }
             }
             __syncthreads();
@@ -838,33 +868,36 @@ int occupancy_grid(const void *kern, long long work_items)
     return (int)(g < 1 ? 1 : g);
 }
 
-template <typename real, bool ONE, bool BATCHED>
+template <typename real, bool ONE, bool BATCHED, bool SINGLE>
 void grids_for(int n, int atoms_per_batch, int grids[3])
 {
     grids[0] = occupancy_grid((const void *)k_pack<real, ONE, BATCHED>,
                               ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
-    grids[1] = occupancy_grid((const void *)k_tersoff<real, ONE, BATCHED>,
+    grids[1] = occupancy_grid((const void *)k_tersoff<real, ONE, BATCHED, SINGLE>,
                               ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
     grids[2] = kBigGrid;
 }
 
 template <bool BATCHED>
-void grids_dispatch(bool mixed, bool one_type, int n, int atoms_per_batch, int grids[3])
+void grids_dispatch(int prec, bool one_type, int n, int atoms_per_batch, int grids[3])
 {
-    if (mixed) {
-        if (one_type) grids_for<float, true, BATCHED>(n, atoms_per_batch, grids);
-        else grids_for<float, false, BATCHED>(n, atoms_per_batch, grids);
+    if (prec == kPrecSingle) {
+        if (one_type) grids_for<float, true, BATCHED, true>(n, atoms_per_batch, grids);
+        else grids_for<float, false, BATCHED, true>(n, atoms_per_batch, grids);
+    } else if (prec == kPrecMixed) {
+        if (one_type) grids_for<float, true, BATCHED, false>(n, atoms_per_batch, grids);
+        else grids_for<float, false, BATCHED, false>(n, atoms_per_batch, grids);
     } else {
-        if (one_type) grids_for<double, true, BATCHED>(n, atoms_per_batch, grids);
-        else grids_for<double, false, BATCHED>(n, atoms_per_batch, grids);
+        if (one_type) grids_for<double, true, BATCHED, false>(n, atoms_per_batch, grids);
+        else grids_for<double, false, BATCHED, false>(n, atoms_per_batch, grids);
     }
 }
 
 template <bool BATCHED>
-void pack_dispatch(const PackLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s)
+void pack_dispatch(const PackLaunch &a, const DeviceTable &t, int prec, int grid, hipStream_t s)
 {
     const bool one = t.ntypes == 1;
-    if (mixed) {
+    if (prec != kPrecFP64) {
         if (one) hipLaunchKernelGGL((k_pack<float, true, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
         else hipLaunchKernelGGL((k_pack<float, false, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
     } else {
@@ -874,41 +907,45 @@ void pack_dispatch(const PackLaunch &a, const DeviceTable &t, bool mixed, int gr
 }
 
 template <bool BATCHED>
-void compute_dispatch(const ComputeLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s)
+void compute_dispatch(const ComputeLaunch &a, const DeviceTable &t, int prec, int grid, hipStream_t s)
 {
     const bool one = t.ntypes == 1;
-    if (mixed) {
-        if (one) hipLaunchKernelGGL((k_tersoff<float, true, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
-        else hipLaunchKernelGGL((k_tersoff<float, false, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
+    const dim3 G(grid), W(kWave);
+    if (prec == kPrecSingle) {
+        if (one) hipLaunchKernelGGL((k_tersoff<float, true, BATCHED, true>), G, W, 0, s, a, t);
+        else hipLaunchKernelGGL((k_tersoff<float, false, BATCHED, true>), G, W, 0, s, a, t);
+    } else if (prec == kPrecMixed) {
+        if (one) hipLaunchKernelGGL((k_tersoff<float, true, BATCHED, false>), G, W, 0, s, a, t);
+        else hipLaunchKernelGGL((k_tersoff<float, false, BATCHED, false>), G, W, 0, s, a, t);
     } else {
-        if (one) hipLaunchKernelGGL((k_tersoff<double, true, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
-        else hipLaunchKernelGGL((k_tersoff<double, false, BATCHED>), dim3(grid), dim3(kWave), 0, s, a, t);
+        if (one) hipLaunchKernelGGL((k_tersoff<double, true, BATCHED, false>), G, W, 0, s, a, t);
+        else hipLaunchKernelGGL((k_tersoff<double, false, BATCHED, false>), G, W, 0, s, a, t);
     }
 }
 
 }  // namespace
 
-void compute_grids(bool mixed, bool one_type, bool batched, int n, int atoms_per_batch, int grids[3])
+void compute_grids(int prec, bool one_type, bool batched, int n, int atoms_per_batch, int grids[3])
 {
-    if (batched) grids_dispatch<true>(mixed, one_type, n, atoms_per_batch, grids);
-    else grids_dispatch<false>(mixed, one_type, n, atoms_per_batch, grids);
+    if (batched) grids_dispatch<true>(prec, one_type, n, atoms_per_batch, grids);
+    else grids_dispatch<false>(prec, one_type, n, atoms_per_batch, grids);
 }
 
-size_t record_bytes(bool mixed) { return mixed ? sizeof(Rec<float>) : sizeof(Rec<double>); }
+size_t record_bytes(int prec) { return prec != kPrecFP64 ? sizeof(Rec<float>) : sizeof(Rec<double>); }
 
-hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s)
+hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, int prec, int grid, hipStream_t s)
 {
-    if (a.n_dev) pack_dispatch<true>(a, t, mixed, grid, s);
-    else pack_dispatch<false>(a, t, mixed, grid, s);
+    if (a.n_dev) pack_dispatch<true>(a, t, prec, grid, s);
+    else pack_dispatch<false>(a, t, prec, grid, s);
     return hipGetLastError();
 }
 
-hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mixed, int grid,
+hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec, int grid,
                           hipStream_t s)
 {
     if (a.atoms_per_batch < 1 || a.atoms_per_batch > kWave) return hipErrorInvalidValue;
-    if (a.n_dev) compute_dispatch<true>(a, t, mixed, grid, s);
-    else compute_dispatch<false>(a, t, mixed, grid, s);
+    if (a.n_dev) compute_dispatch<true>(a, t, prec, grid, s);
+    else compute_dispatch<false>(a, t, prec, grid, s);
     return hipGetLastError();
 }
 

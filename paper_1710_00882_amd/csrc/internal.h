@@ -148,10 +148,13 @@ struct ComputeLaunch {
 
 // Launchers (compute.hip).  grids = {pack, compute} workgroup counts plus
 // kBigGrid for the fixup kernel.
-void compute_grids(bool mixed, bool one_type, bool batched, int n, int atoms_per_batch, int grids[3]);
-size_t record_bytes(bool mixed);
-hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, bool mixed, int grid, hipStream_t s);
-hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, bool mixed,
+// Precisions (the values of tersoff_precision).
+enum : int { kPrecFP64 = 0, kPrecMixed = 1, kPrecSingle = 2, kNumPrec = 3 };
+
+void compute_grids(int prec, bool one_type, bool batched, int n, int atoms_per_batch, int grids[3]);
+size_t record_bytes(int prec);
+hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, int prec, int grid, hipStream_t s);
+hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec,
                           int grid, hipStream_t s);
 hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *rv,
                                 const signed char *slotpos, const int *drop_list, const int *drop_count,

@@ -159,7 +159,7 @@ struct Pending {
 struct Lane {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    hipGraphExec_t exec[2] = {nullptr, nullptr};   // [FP64, mixed]
+    hipGraphExec_t exec[kNumPrec] = {};   // one per precision
     Pinned<double> h_pos, h_forces, h_out;
     Pinned<int> h_types, h_sys_of;
     Pinned<SysDesc> h_desc;
@@ -176,7 +176,7 @@ struct Lane {
     Dev<BatchDims> dims;
     std::vector<Pending> batch;
     int natoms = 0;
-    bool mixed = false;
+    int prec = 0;
     bool want_forces = false;
     bool busy = false;
 };
@@ -189,7 +189,7 @@ struct Server {
     double rc = 0.0;
     size_t max_queued = 0;
     size_t device_bytes = 0;
-    int grids[2][3] = {};
+    int grids[kNumPrec][3] = {};
     Lane lanes[kLanes];
     std::unique_ptr<CopyPool> pool;
     std::thread worker;
@@ -272,7 +272,7 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.ctl.alloc(3 + NS, tot));
     SRV_TRY(L.slotpos.alloc(E, tot));
     const size_t nbat = (A + kServeBatchAtoms - 1) / kServeBatchAtoms;
-    SRV_TRY(L.recs.alloc(record_bytes(false) * kRecCap * nbat * kServeBatchAtoms, tot));
+    SRV_TRY(L.recs.alloc(record_bytes(kPrecFP64) * kRecCap * nbat * kServeBatchAtoms, tot));
     SRV_TRY(L.desc.alloc(NS, tot));
     SRV_TRY(L.dims.alloc(1, tot));
     // A row cleared for exceeding the capacity leaves reverse entries of its
@@ -304,7 +304,7 @@ void free_lane(Lane &L)
 
 // The device work of one batch, enqueued on the lane's stream (captured once
 // per precision; no allocation, no memset nodes, no host synchronisation).
-hipError_t enqueue_batch(Server &S, Lane &L, bool mixed)
+hipError_t enqueue_batch(Server &S, Lane &L, int prec)
 {
     hipStream_t s = L.stream;
     const int *n_dev = &L.dims.p->n_atoms;
@@ -372,7 +372,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, bool mixed)
     pk.n_dev = n_dev;
     pk.sys = L.desc.p;
     pk.sys_of = L.sys_of.p;
-    SRV_TRY(launch_pack(pk, S.env.tab, mixed, S.grids[mixed][0], s));
+    SRV_TRY(launch_pack(pk, S.env.tab, prec, S.grids[prec][0], s));
 
     ComputeLaunch a{};
     a.types = L.types.p;
@@ -386,7 +386,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, bool mixed)
     a.plane_stride = S.max_atoms;
     a.n_dev = n_dev;
     a.eatom = L.eatom.p;
-    SRV_TRY(launch_compute(a, S.env.tab, mixed, S.grids[mixed][1], s));
+    SRV_TRY(launch_compute(a, S.env.tab, prec, S.grids[prec][1], s));
     SRV_TRY(launch_fixup_dropped(L.offsets.p, L.jn.p, L.rv.p, L.slotpos.p, L.drop_list.p, L.ctl.p + 1,
                                  S.max_atoms, L.planes.p, s));
     SRV_TRY(launch_gather_forces(L.pcount.p, L.planes.p, L.own.p, S.max_atoms, n_dev, S.max_atoms, L.forces.p, s));
@@ -395,17 +395,17 @@ hipError_t enqueue_batch(Server &S, Lane &L, bool mixed)
     return hipSuccess;
 }
 
-hipError_t capture(Server &S, Lane &L, bool mixed)
+hipError_t capture(Server &S, Lane &L, int prec)
 {
     hipGraph_t g = nullptr;
     SRV_TRY(hipStreamBeginCapture(L.stream, hipStreamCaptureModeRelaxed));
-    const hipError_t e = enqueue_batch(S, L, mixed);
+    const hipError_t e = enqueue_batch(S, L, prec);
     const hipError_t e2 = hipStreamEndCapture(L.stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return e != hipSuccess ? e : e2;
     }
-    const hipError_t e3 = hipGraphInstantiate(&L.exec[mixed ? 1 : 0], g, nullptr, nullptr, 0);
+    const hipError_t e3 = hipGraphInstantiate(&L.exec[prec], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     return e3;
 }
@@ -421,9 +421,9 @@ void form_batch(Server &S, Lane &L)
     while (!S.queue.empty() && (int)L.batch.size() < S.max_sys) {
         const Pending &p = S.queue.front();
         if (p.t_start > now) break;
-        if (!L.batch.empty() && (p.req.precision == TERSOFF_MIXED) != L.mixed) break;
+        if (!L.batch.empty() && p.req.precision != L.prec) break;
         if (natoms + p.req.n > S.max_atoms || ncell + p.ncell > S.max_cells) break;
-        if (L.batch.empty()) L.mixed = p.req.precision == TERSOFF_MIXED;
+        if (L.batch.empty()) L.prec = p.req.precision;
         natoms += (int)p.req.n;
         ncell += p.ncell;
         L.batch.push_back(p);
@@ -464,7 +464,7 @@ hipError_t launch_lane(Server &S, Lane &L)
     SRV_TRY(hipMemcpyAsync(L.sys_of.p, L.h_sys_of.p, sizeof(int) * (size_t)off, hipMemcpyHostToDevice, s));
     SRV_TRY(hipMemcpyAsync(L.desc.p, L.h_desc.p, sizeof(SysDesc) * (size_t)nsys, hipMemcpyHostToDevice, s));
     SRV_TRY(hipMemcpyAsync(L.dims.p, L.h_dims.p, sizeof(BatchDims), hipMemcpyHostToDevice, s));
-    SRV_TRY(hipGraphLaunch(L.exec[L.mixed ? 1 : 0], s));
+    SRV_TRY(hipGraphLaunch(L.exec[L.prec], s));
     SRV_TRY(hipMemcpyAsync(L.h_out.p, L.out.p, sizeof(double) * 8 * (size_t)nsys, hipMemcpyDeviceToHost, s));
     if (L.want_forces)
         SRV_TRY(hipMemcpyAsync(L.h_forces.p, L.forces.p, sizeof(double) * 3 * (size_t)off, hipMemcpyDeviceToHost,
@@ -605,14 +605,12 @@ int server_create(const ServerEnv &env, const tersoff_serve_config &cfg, Server 
     S->cap = cap;
     S->rc = cutoff + cfg.skin;
     S->max_queued = cfg.max_queued > 0 ? (size_t)cfg.max_queued : 65536;
-    compute_grids(false, env.ntypes == 1, true, S->max_atoms, kServeBatchAtoms, S->grids[0]);
-    compute_grids(true, env.ntypes == 1, true, S->max_atoms, kServeBatchAtoms, S->grids[1]);
+    for (int pr = 0; pr < kNumPrec; ++pr)
+        compute_grids(pr, env.ntypes == 1, true, S->max_atoms, kServeBatchAtoms, S->grids[pr]);
     hipError_t e = hipSetDevice(env.device);
     for (int l = 0; l < kLanes && e == hipSuccess; ++l) e = alloc_lane(*S, S->lanes[l]);
-    for (int l = 0; l < kLanes && e == hipSuccess; ++l) {
-        e = capture(*S, S->lanes[l], false);
-        if (e == hipSuccess) e = capture(*S, S->lanes[l], true);
-    }
+    for (int l = 0; l < kLanes && e == hipSuccess; ++l)
+        for (int pr = 0; pr < kNumPrec && e == hipSuccess; ++pr) e = capture(*S, S->lanes[l], pr);
     if (e != hipSuccess) {
         err = std::string("serving set-up: ") + hipGetErrorString(e);
         for (auto &L : S->lanes) free_lane(L);
@@ -659,8 +657,8 @@ int server_submit(Server *S, const tersoff_request &req, uint64_t *ticket, std::
         err = "request larger than the batch capacity";
         return TERSOFF_E_INVALID;
     }
-    if (req.precision != TERSOFF_FP64 && req.precision != TERSOFF_MIXED) {
-        err = "precision must be TERSOFF_FP64 or TERSOFF_MIXED";
+    if (req.precision != TERSOFF_FP64 && req.precision != TERSOFF_MIXED && req.precision != TERSOFF_SINGLE) {
+        err = "precision must be TERSOFF_FP64, TERSOFF_MIXED or TERSOFF_SINGLE";
         return TERSOFF_E_INVALID;
     }
     for (int a = 0; a < 3; ++a) {

@@ -60,7 +60,7 @@ struct tersoff_ctx {
     int ell_cap = 32;        // row capacity for the next build (multiple of 8)
     int list_cap = 0;        // row stride of the resident list
     int atoms_per_batch = 16;
-    int grid[2][3] = {{0, 0, 0}, {0, 0, 0}};   // [fp64, mixed] x {pack, compute, per-atom}
+    int grid[kNumPrec][3] = {};   // [precision] x {pack, compute, fixup}
 
     DevBuf<double> pos_build;
     DevBuf<int> types, offsets, pcount, drop_list, rv, jn;   // jn, rv, slotpos: compact list (S entries)
@@ -311,9 +311,11 @@ int tersoff_set_batch_atoms(tersoff_ctx *c, int32_t atoms)
     if (atoms < 1 || atoms > kWave) return fail(c, TERSOFF_E_INVALID, "batch atoms must be in [1, 64]");
     c->atoms_per_batch = atoms;
     if (c->built) {
-        compute_grids(false, c->ntypes == 1, false, c->n, atoms, c->grid[0]);
-        compute_grids(true, c->ntypes == 1, false, c->n, atoms, c->grid[1]);
-        int gmax = std::max(c->grid[0][1], c->grid[1][1]);
+        int gmax = 0;
+        for (int pr = 0; pr < kNumPrec; ++pr) {
+            compute_grids(pr, c->ntypes == 1, false, c->n, atoms, c->grid[pr]);
+            gmax = std::max(gmax, c->grid[pr][1]);
+        }
         HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
         HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
     }
@@ -459,9 +461,11 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     for (int a = 0; a < 3; ++a) c->box[a] = box[a];
     c->cutoff = cutoff;
     c->skin = skin;
-    compute_grids(false, c->ntypes == 1, false, N, c->atoms_per_batch, c->grid[0]);
-    compute_grids(true, c->ntypes == 1, false, N, c->atoms_per_batch, c->grid[1]);
-    int gmax = std::max(c->grid[0][1], c->grid[1][1]);
+    int gmax = 0;
+    for (int pr = 0; pr < kNumPrec; ++pr) {
+        compute_grids(pr, c->ntypes == 1, false, N, c->atoms_per_batch, c->grid[pr]);
+        gmax = std::max(gmax, c->grid[pr][1]);
+    }
     HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
     HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
     HIP_TRY(c, c->counts.ensure(2));
@@ -476,19 +480,19 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     if (!c) return TERSOFF_E_INVALID;
     if (!c->built) return fail(c, TERSOFF_E_STATE, "compute before build_neighbors");
     if (!pos || !energy_virial) return fail(c, TERSOFF_E_INVALID, "null pointer");
-    if (precision != TERSOFF_FP64 && precision != TERSOFF_MIXED)
-        return fail(c, TERSOFF_E_INVALID, "precision must be TERSOFF_FP64 or TERSOFF_MIXED");
+    if (precision != TERSOFF_FP64 && precision != TERSOFF_MIXED && precision != TERSOFF_SINGLE)
+        return fail(c, TERSOFF_E_INVALID, "precision must be TERSOFF_FP64, TERSOFF_MIXED or TERSOFF_SINGLE");
     HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t s = as_stream(stream);
-    const bool mixed = precision == TERSOFF_MIXED;
-    const int *grid = c->grid[mixed ? 1 : 0];
+    const int prec = precision;
+    const int *grid = c->grid[prec];
     double *f = forces;
     if (!f) {
         HIP_TRY(c, c->force_scratch.ensure(3 * (size_t)c->n));
         f = c->force_scratch.p;
     }
     const size_t nbat = ((size_t)c->n + c->atoms_per_batch - 1) / c->atoms_per_batch;
-    HIP_TRY(c, c->recs.ensure(record_bytes(mixed) * kRecCap * nbat * c->atoms_per_batch));
+    HIP_TRY(c, c->recs.ensure(record_bytes(prec) * kRecCap * nbat * c->atoms_per_batch));
     HIP_TRY(c, c->planes.ensure(3 * (size_t)kRecCap * (size_t)c->n));
 
     PackLaunch pk{};
@@ -532,10 +536,10 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     if (c->profiling)
         for (int q = 0; q < 6; ++q) HIP_TRY(c, take_event(c, &ev[q]));
     if (ev[0]) HIP_TRY(c, hipEventRecord(ev[0], s));
-    HIP_TRY(c, launch_pack(pk, c->tab, mixed, grid[0], s));
+    HIP_TRY(c, launch_pack(pk, c->tab, prec, grid[0], s));
     if (ev[1]) HIP_TRY(c, hipEventRecord(ev[1], s));
     if (ev[2]) HIP_TRY(c, hipEventRecord(ev[2], s));
-    HIP_TRY(c, launch_compute(a, c->tab, mixed, grid[1], s));
+    HIP_TRY(c, launch_compute(a, c->tab, prec, grid[1], s));
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
     HIP_TRY(c, launch_fixup_dropped(c->offsets.p, c->jn.p, c->rv.p, c->slotpos.p,

@@ -46,7 +46,7 @@ def test_neighbors_bit_exact(case):
     assert np.array_equal(idx, oidx)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "single"])
 @pytest.mark.parametrize("case", list(CASES))
 def test_compute_parity(case, precision):
     sysf, tabf = CASES[case]
@@ -120,7 +120,7 @@ def test_recompute_path_many_triplets():
     # dense disordered packing: batches exceed the cached-triplet capacity
     s = W.disordered(2000, density=0.09, dmin=1.7, seed=13)
     table = W.two_species_table()
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "single"):
         E, F, V, m = gpu_eval(s, table, prec)
         m.check()
         Eo, Fo, Vo, off, idx = oracle_eval(s, table)

@@ -102,7 +102,7 @@ def test_mixed_precisions_and_no_forces(server):
     systems = _stream(8, seed=14)
     tickets = []
     for q, s in enumerate(systems):
-        prec = "mixed" if q % 2 else "fp64"
+        prec = ("fp64", "mixed", "single")[q % 3]
         tickets.append((prec, server.submit(s.pos, s.types, s.box, prec, forces=None, tag=q)))
     for (prec, t), s in zip(tickets, systems):
         r = server.wait(t)
