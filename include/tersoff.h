@@ -248,6 +248,47 @@ int tersoff_serve_stats(tersoff_ctx *ctx, double out[6]);
 /* Monotonic clock (ns) of tersoff_request.release_ns. */
 int64_t tersoff_clock_ns(void);
 
+/* ---- Parameter files and a molecular-dynamics driver -------------------- */
+
+/* Parse a parameter file in the LAMMPS "tersoff" format (the public format:
+ * after '#' comments, a stream of 17-word entries -- elements i j k, then
+ * m, gamma, lambda3, c, d, cos(theta0), n, beta, lambda2, B, R, D, lambda1,
+ * A -- in any line layout; R and D as in Eq. (1), cutoff R + D).
+ * elements: host, nelem names; type t is elements[t].  Entries naming other
+ * elements are skipped.
+ * params_out: host, nelem^3 * TERSOFF_NPARAM doubles in the layout of
+ *   tersoff_create.
+ * Errors: E_INVALID (null pointer, nelem outside [1, TERSOFF_MAX_TYPES], a
+ *   word count that is not a multiple of 17, a malformed number, a triplet
+ *   given twice or missing).  Host only; needs no device. */
+int tersoff_parse_params(const char *text, const char *const *elements, int32_t nelem, double *params_out);
+
+typedef struct {
+    double dt;              /* time step, ps                                       */
+    int32_t nsteps;         /* velocity-Verlet steps (>= 0)                        */
+    int32_t precision;      /* a tersoff_precision                                 */
+    const double *mass;     /* host, ntypes masses, amu                            */
+    double cutoff;          /* 0: the largest R + D of the table                   */
+    double skin;            /* > 0, A                                              */
+} tersoff_md_config;
+
+/* Constant-energy molecular dynamics around the evaluation: nsteps steps of
+ * velocity Verlet in metal units (eV, A, ps, amu; acceleration
+ * F / m * 9648.53321 A/ps^2 per eV/(A amu)).  The neighbour list is built at
+ * the start and rebuilt before any step at which an atom has moved more than
+ * skin/2 since the last build (the condition under which Section 2's skin
+ * keeps the list complete).
+ * pos, vel, forces: device, n x 3 float64, advanced in place; forces holds
+ *   the forces of the final positions.  types: device, n int32.
+ * out: host, 4 doubles: potential energy and kinetic energy (eV) of the final
+ *   state, neighbour builds (the first included), temperature (K, 3N degrees
+ *   of freedom).
+ * The stream is synchronised once per step (the displacement check).
+ * Errors: E_INVALID (arguments, masses <= 0, dt <= 0, skin <= 0), and those
+ *   of tersoff_build_neighbors / tersoff_compute / tersoff_check. */
+int tersoff_md_run(tersoff_ctx *ctx, double *pos, double *vel, double *forces, const int32_t *types, int64_t n,
+                   const double box[3], const tersoff_md_config *cfg, double out[4], void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,6 @@ ABI of include/tersoff.h); ``Tersoff`` is its thin ctypes binding.  Importing
 this package does not load the library; the first ``Tersoff(...)`` does, and
 raises if it has not been built.
 """
-from ._lib import FP64, MIXED, Tersoff, TersoffError, clock_ns, load  # noqa: F401
+from ._lib import FP64, MIXED, SINGLE, Tersoff, TersoffError, clock_ns, load, parse_params  # noqa: F401
 
-__all__ = ["Tersoff", "TersoffError", "load", "FP64", "MIXED"]
+__all__ = ["Tersoff", "TersoffError", "load", "parse_params", "clock_ns", "FP64", "MIXED", "SINGLE"]

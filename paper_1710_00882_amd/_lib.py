@@ -29,7 +29,8 @@ SYMBOLS = ("tersoff_create", "tersoff_destroy", "tersoff_build_neighbors", "ters
            "tersoff_check", "tersoff_get_neighbors", "tersoff_get_counts", "tersoff_num_atoms",
            "tersoff_strerror", "tersoff_last_error", "tersoff_profile", "tersoff_profile_read",
            "tersoff_set_batch_atoms", "tersoff_serve_start", "tersoff_serve_stop", "tersoff_submit",
-           "tersoff_poll", "tersoff_serve_stats", "tersoff_clock_ns")
+           "tersoff_poll", "tersoff_serve_stats", "tersoff_clock_ns", "tersoff_parse_params",
+           "tersoff_md_run")
 
 
 class ServeConfig(ctypes.Structure):
@@ -42,6 +43,11 @@ class Request(ctypes.Structure):
     _fields_ = [("pos", ctypes.c_void_p), ("types", ctypes.c_void_p), ("n", ctypes.c_int64),
                 ("box", ctypes.c_double * 3), ("precision", ctypes.c_int32), ("forces", ctypes.c_void_p),
                 ("tag", ctypes.c_uint64), ("release_ns", ctypes.c_int64)]
+
+
+class MDConfig(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("nsteps", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("mass", ctypes.c_void_p), ("cutoff", ctypes.c_double), ("skin", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
@@ -107,6 +113,10 @@ def load():
     lib.tersoff_serve_stats.restype = ctypes.c_int
     lib.tersoff_clock_ns.argtypes = []
     lib.tersoff_clock_ns.restype = i64
+    lib.tersoff_parse_params.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_char_p), i32, P]
+    lib.tersoff_parse_params.restype = ctypes.c_int
+    lib.tersoff_md_run.argtypes = [P, P, P, P, P, i64, P, ctypes.POINTER(MDConfig), P, P]
+    lib.tersoff_md_run.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -251,6 +261,30 @@ class Tersoff:
             self._raise(st, "tersoff_get_counts")
         return tuple(int(v) for v in c)
 
+    def md_run(self, pos, vel, types, box, masses, dt, nsteps, precision="fp64", cutoff=0.0, skin=1.0, forces=None):
+        """Velocity-Verlet NVE on device arrays (advanced in place).  Returns a
+        dict: epot, ekin (eV), builds, temperature (K), and the forces tensor."""
+        import torch
+        _check_dev(pos, torch.float64, (3,), "pos")
+        _check_dev(vel, torch.float64, (3,), "vel")
+        _check_dev(types, torch.int32, None, "types")
+        if forces is None:
+            forces = torch.empty_like(pos)
+        _check_dev(forces, torch.float64, (3,), "forces")
+        m = np.ascontiguousarray(np.asarray(masses, dtype=np.float64).reshape(-1))
+        if m.size != self.ntypes:
+            raise ValueError("one mass per type")
+        b = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(3))
+        cfg = MDConfig(float(dt), int(nsteps), PRECISIONS[precision], m.ctypes.data, float(cutoff), float(skin))
+        out = np.zeros(4)
+        st = self._lib.tersoff_md_run(self._h, pos.data_ptr(), vel.data_ptr(), forces.data_ptr(), types.data_ptr(),
+                                      pos.shape[0], b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(cfg),
+                                      out.ctypes.data_as(ctypes.c_void_p), _stream_ptr(torch, pos.device))
+        if st != OK:
+            self._raise(st, "tersoff_md_run")
+        return dict(epot=float(out[0]), ekin=float(out[1]), builds=int(out[2]), temperature=float(out[3]),
+                    forces=forces)
+
     # ---- serving -------------------------------------------------------------
     def serve_start(self, max_batch_atoms, max_batch_systems, max_neighbors=0, cutoff=0.0, skin=1.0,
                     max_queued=0, host_threads=0):
@@ -326,3 +360,17 @@ class Tersoff:
 def clock_ns() -> int:
     """The library's monotonic clock (the time base of release_ns)."""
     return int(load().tersoff_clock_ns())
+
+
+def parse_params(text: str, elements) -> np.ndarray:
+    """Parameter table (ntypes^3 x 14) from a LAMMPS-format Tersoff parameter
+    file's text; type t is elements[t]."""
+    lib = load()
+    names = [e.encode() for e in elements]
+    arr = (ctypes.c_char_p * len(names))(*names)
+    nt = len(names)
+    out = np.zeros(nt ** 3 * 14)
+    st = lib.tersoff_parse_params(text.encode(), arr, nt, out.ctypes.data_as(ctypes.c_void_p))
+    if st != OK:
+        raise TersoffError(st, "tersoff_parse_params rejected the file")
+    return out.reshape(nt ** 3, 14)

@@ -26,6 +26,8 @@ SOURCES = {
     "compute.hip": [],
     "neighbors.hip": ["-ffp-contract=off"],
     "serve.hip": [],
+    "md.hip": [],
+    "params.cpp": [],
 }
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -38,7 +40,7 @@ COMMON = [
 
 
 def _compile(src: str, extra: list[str]) -> str:
-    obj = os.path.join(BUILD_DIR, src.replace(".hip", ".o"))
+    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
     cmd = [HIPCC, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -231,4 +231,14 @@ size_t scan_tmp_size(int n);
 hipError_t launch_exclusive_scan(const int *in, int *out, int n, int *tmp, int *max_out,
                                  hipStream_t s);
 
+// Molecular-dynamics driver kernels (md.hip).
+hipError_t launch_md_kick(double *vel, const double *f, const int *types, const double *inv_mass, double c, int n,
+                          hipStream_t s);
+hipError_t launch_md_drift(double *pos, const double *vel, double dt, int n, hipStream_t s);
+hipError_t launch_md_displaced(const double *pos, const double *pos_build, double lim2, int n, int *flag,
+                               hipStream_t s);
+int md_kinetic_blocks();
+hipError_t launch_md_kinetic(const double *vel, const int *types, const double *mass, int n, double *partials,
+                             hipStream_t s);
+
 }  // namespace tsf

@@ -82,6 +82,10 @@ struct tersoff_ctx {
 
     tsf::Server *server = nullptr;   // serving runtime (tersoff_serve_start .. tersoff_serve_stop)
 
+    // molecular-dynamics driver: per-type masses, displacement flag, energies
+    DevBuf<double> md_mass, md_inv_mass, md_ev, md_partials;
+    DevBuf<int> md_flag;
+
     std::string last_error;
 };
 
@@ -266,6 +270,8 @@ void tersoff_destroy(tersoff_ctx *c)
     c->cell_posf.release(); c->long_rows.release();
     c->scan_tmp.release(); c->misc.release(); c->partials.release(); c->force_scratch.release();
     c->counters.release(); c->counts.release();
+    c->md_mass.release(); c->md_inv_mass.release(); c->md_ev.release(); c->md_partials.release();
+    c->md_flag.release();
     for (auto &pr : c->ev_compute) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto &pr : c->ev_build) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto &pr : c->ev_gather) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
@@ -643,6 +649,78 @@ int tersoff_serve_stats(tersoff_ctx *c, double out[6])
     if (!c || !out) return TERSOFF_E_INVALID;
     if (!c->server) return fail(c, TERSOFF_E_STATE, "serving not started");
     tsf::server_stats(c->server, out);
+    return TERSOFF_OK;
+}
+
+int tersoff_md_run(tersoff_ctx *c, double *pos, double *vel, double *forces, const int32_t *types, int64_t n,
+                   const double box[3], const tersoff_md_config *cfg, double out[4], void *stream)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    if (!pos || !vel || !forces || !types || !box || !cfg || !out || !cfg->mass)
+        return fail(c, TERSOFF_E_INVALID, "null pointer");
+    if (!(cfg->dt > 0) || !std::isfinite(cfg->dt) || cfg->nsteps < 0 || !(cfg->skin > 0) || !std::isfinite(cfg->skin))
+        return fail(c, TERSOFF_E_INVALID, "dt and skin must be positive, nsteps >= 0");
+    if (cfg->precision < TERSOFF_FP64 || cfg->precision > TERSOFF_SINGLE)
+        return fail(c, TERSOFF_E_INVALID, "unknown precision");
+    std::vector<double> mass(cfg->mass, cfg->mass + c->ntypes), inv(c->ntypes);
+    for (int t = 0; t < c->ntypes; ++t) {
+        if (!(mass[t] > 0) || !std::isfinite(mass[t])) return fail(c, TERSOFF_E_INVALID, "masses must be positive");
+        inv[t] = 1.0 / mass[t];
+    }
+    const double cutoff = cfg->cutoff > 0 ? cfg->cutoff : c->max_cut;
+    // acceleration of 1 eV / (A amu) in A / ps^2: (1.602176634e-19 J / 1e-10 m)
+    // / 1.66053906660e-27 kg, expressed in 1e14 m/s^2
+    const double conv = 1.602176634e-19 / 1e-10 / 1.66053906660e-27 / 1e14;
+    const int N = (int)n;
+    HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(c, c->md_mass.ensure(c->ntypes));
+    HIP_TRY(c, c->md_inv_mass.ensure(c->ntypes));
+    HIP_TRY(c, c->md_ev.ensure(7));
+    HIP_TRY(c, c->md_flag.ensure(1));
+    HIP_TRY(c, c->md_partials.ensure(md_kinetic_blocks()));
+    HIP_TRY(c, hipMemcpyAsync(c->md_mass.p, mass.data(), sizeof(double) * mass.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->md_inv_mass.p, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, s));
+
+    int st = tersoff_build_neighbors(c, pos, types, n, box, cutoff, cfg->skin, stream);
+    if (st != TERSOFF_OK) return st;
+    int builds = 1;
+    st = tersoff_compute(c, pos, cfg->precision, c->md_ev.p, forces, stream);
+    if (st != TERSOFF_OK) return st;
+    const double half = 0.5 * cfg->dt * conv;
+    const double lim2 = 0.25 * cfg->skin * cfg->skin;
+    for (int step = 0; step < cfg->nsteps; ++step) {
+        HIP_TRY(c, launch_md_kick(vel, forces, types, c->md_inv_mass.p, half, N, s));
+        HIP_TRY(c, launch_md_drift(pos, vel, cfg->dt, N, s));
+        HIP_TRY(c, hipMemsetAsync(c->md_flag.p, 0, sizeof(int), s));
+        HIP_TRY(c, launch_md_displaced(pos, c->pos_build.p, lim2, N, c->md_flag.p, s));
+        int moved = 0;
+        HIP_TRY(c, hipMemcpyAsync(&moved, c->md_flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        if (moved) {
+            st = tersoff_build_neighbors(c, pos, types, n, box, cutoff, cfg->skin, stream);
+            if (st != TERSOFF_OK) return st;
+            ++builds;
+        }
+        st = tersoff_compute(c, pos, cfg->precision, c->md_ev.p, forces, stream);
+        if (st != TERSOFF_OK) return st;
+        HIP_TRY(c, launch_md_kick(vel, forces, types, c->md_inv_mass.p, half, N, s));
+    }
+    HIP_TRY(c, launch_md_kinetic(vel, types, c->md_mass.p, N, c->md_partials.p, s));
+    std::vector<double> part(md_kinetic_blocks());
+    double ev[7];
+    HIP_TRY(c, hipMemcpyAsync(part.data(), c->md_partials.p, sizeof(double) * part.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(ev, c->md_ev.p, sizeof(ev), hipMemcpyDeviceToHost, s));
+    st = tersoff_check(c, stream);   // synchronises; overflow / stale flags of the run
+    if (st != TERSOFF_OK) return st;
+    double mv2 = 0.0;
+    for (double v : part) mv2 += v;
+    const double ekin = 0.5 * mv2 / conv;
+    const double kB = 8.617333262e-5;   // eV / K
+    out[0] = ev[0];
+    out[1] = ekin;
+    out[2] = builds;
+    out[3] = 2.0 * ekin / (3.0 * (double)n * kB);
     return TERSOFF_OK;
 }
 
