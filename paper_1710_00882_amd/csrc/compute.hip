@@ -4,7 +4,7 @@
 //   k_pack      skin exclusion and packing (Sections 2 and 3): every list
 //               entry gets its FP64 minimum-image displacement and r^2; the
 //               entries inside the interaction range become compact per-atom
-//               records (unit vector, r, 1/r, membership bits).
+//               records (displacement, membership bits).
 //   k_tersoff   zeta, b_ij, energy, forces and virial from the records, one
 //               wavefront per batch of centre atoms, one lane per pair (i, j).
 //   k_gather_forces
@@ -60,6 +60,11 @@ __device__ __forceinline__ double norm2(double dx, double dy, double dz)
 #pragma clang fp contract(off)
     return fma(dz, dz, fma(dy, dy, dx * dx));
 }
+
+// r^2 of a packed displacement in the working precision (the FP64 form is
+// the packing kernel's, so r is the same there)
+__device__ __forceinline__ double norm2r(double dx, double dy, double dz) { return norm2(dx, dy, dz); }
+__device__ __forceinline__ float norm2r(float dx, float dy, float dz) { return fmaf(dz, dz, fmaf(dy, dy, dx * dx)); }
 
 // Largest a in [0, nseg) with starts[a] <= v (starts ascending, starts[0] <= v).
 __device__ __forceinline__ int find_seg(const int *starts, int nseg, int v)
@@ -160,22 +165,23 @@ __device__ __forceinline__ void cutoff_terms(const ParamR<real> &q, real r, real
 
 // One packed neighbour n of a centre atom i (an in-range entry of i's list,
 // Section 3): the neighbour index, the entry (n, i) of n's row, the
-// membership bits of the exact FP64 cutoff tests, and the distance and unit
-// vector in the working precision.  The records of a batch of B consecutive
+// membership bits of the exact FP64 cutoff tests, and the minimum-image
+// displacement in the working precision (distance and unit vector are
+// formed from it by the compute kernel).  The records of a batch of B consecutive
 // centre atoms are stored contiguously, atom by atom, in the batch's region
 // of B * kRecCap records, so both the packing writes and the compute reads
 // are contiguous across lanes.
 template <typename real>
 struct Rec;
 template <>
-struct alignas(16) Rec<float> {
+struct alignas(8) Rec<float> {
     int j, rev, mask;
-    float r, ux, uy, uz, pad;
+    float dx, dy, dz;
 };
 template <>
-struct alignas(16) Rec<double> {
+struct alignas(8) Rec<double> {
     int j, rev, mask, pad;
-    double r, ux, uy, uz;
+    double dx, dy, dz;
 };
 
 // mask: bits 0-7 type of n; bit 8: r_in < cutoff of entry (t_i, t_n, t_n)
@@ -311,8 +317,6 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 if (e < e_end) a.slotpos[ev[c]] = (signed char)(acc ? (k < kRecCap ? k : -2) : -1);
                 if (acc) {
                     if (k < kRecCap) {
-                        const real r = M<real>::sqrt((real)rsq);
-                        const real ri = M<real>::rcp(r);
                         Rec<real> o;
                         o.j = jv[c];
                         o.rev = rvv[c];
@@ -326,11 +330,10 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                                 if (rsq < tab.px[(t_i * nt + t) * nt + t_n].cutsq) mask |= 1 << (kThirdBit + t);
                         }
                         o.mask = mask;
-                        o.r = r;
-                        o.ux = (real)dx * ri;
-                        o.uy = (real)dy * ri;
-                        o.uz = (real)dz * ri;
-                        if constexpr (sizeof(real) == 4) o.pad = 0.f; else o.pad = 0;
+                        o.dx = (real)dx;
+                        o.dy = (real)dy;
+                        o.dz = (real)dz;
+                        if constexpr (sizeof(real) == 8) o.pad = 0;
                         // batch order: slot = kept entries of the batch before this one
                         recs[(size_t)a0 * kRecCap + npacked + lanes_below(mrec)] = o;
                     }
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             const int s = lane;
             const bool has_slot = s < npacked;
             int al = 0, jl = 0, pc = 0, sb = 0, j = 0, kpos = -1, mj = 0, ti = 0;
-            real rj = 0, rjinv = 0, uj[3] = {0, 0, 0};
+            real rj = 0, rjinv = 0, uj[3] = {0, 0, 0}, dj[3] = {0, 0, 0};
             if (has_slot) {
                 al = find_seg(sh.pstart, cut, s);
                 sb = sh.pstart[al];
@@ -503,9 +506,10 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 j = rc.j;
                 kpos = a.slotpos[rc.rev];
                 mj = rc.mask;
-                rj = rc.r;
-                uj[0] = rc.ux; uj[1] = rc.uy; uj[2] = rc.uz;
+                dj[0] = rc.dx; dj[1] = rc.dy; dj[2] = rc.dz;
+                rj = M<real>::sqrt(norm2r(dj[0], dj[1], dj[2]));
                 rjinv = M<real>::rcp(rj);
+                uj[0] = dj[0] * rjinv; uj[1] = dj[1] * rjinv; uj[2] = dj[2] * rjinv;
                 sh.ux[s] = uj[0]; sh.uy[s] = uj[1]; sh.uz[s] = uj[2];
                 sh.r[s] = rj;
                 sh.mask[s] = mj;
@@ -664,7 +668,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 }
                 // ---- 4: virial and output (FP64 from here on)
                 const double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
-                const double dxj = (double)(rj * uj[0]), dyj = (double)(rj * uj[1]), dzj_ = (double)(rj * uj[2]);
+                const double dxj = (double)dj[0], dyj = (double)dj[1], dzj_ = (double)dj[2];
                 w_acc[0] += dxj * Fx;
                 w_acc[1] += dyj * Fy;
                 w_acc[2] += dzj_ * Fz;
