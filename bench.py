@@ -34,7 +34,7 @@ REBUILD_EVERY = 5
 
 # MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 # Unpacked FP32 and FP64 issue at this rate; packed FP32 (twice the rate,
-# 157.3 TFLOP/s) is not generated by this build.
+# 157.3 TFLOP/s) is not generated: the HIP sources are compiled without it.
 PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12      # 78.64
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
@@ -324,7 +324,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(multi-GPU runs are not part of this build)", file=sys.stderr)
+              "(this benchmark runs on a single GPU)", file=sys.stderr)
         sys.exit(2)
 
     from paper_1710_00882_amd import workloads as W
