@@ -154,7 +154,7 @@ int tersoff_profile(tersoff_ctx *ctx, int32_t enable);
 int tersoff_profile_read(tersoff_ctx *ctx, double out[8]);
 
 /* Nominal centre atoms per wavefront batch of the compute kernel, in
- * [1, 64] (default 16).  Performance tuning only; results do not depend on
+ * [1, 64] (default 32).  Performance tuning only; results do not depend on
  * it beyond floating-point summation order.  E_INVALID outside the range. */
 int tersoff_set_batch_atoms(tersoff_ctx *ctx, int32_t atoms);
 

@@ -759,11 +759,10 @@ __global__ void k_fixup_dropped(const int *__restrict__ offsets, const int *__re
     }
 }
 
-// Sums the per-workgroup partials; also empties the dropped-atom list for
-// the next evaluation (every kernel reading it has run by now).
-__global__ void k_finalize(const double *__restrict__ partials, const long long *__restrict__ counters,
-                           int grid, double *__restrict__ out, long long *__restrict__ counts,
-                           int *__restrict__ drop_count)
+// Sums the per-workgroup partials of the compute kernel (one workgroup of
+// 256 threads, fixed summation order).
+__device__ void finalize_sums(const double *__restrict__ partials, const long long *__restrict__ counters,
+                              int grid, double *__restrict__ out, long long *__restrict__ counts)
 {
     __shared__ double sh[8][256];
     __shared__ long long shc[2][256];
@@ -790,7 +789,34 @@ __global__ void k_finalize(const double *__restrict__ partials, const long long 
         for (int c = 0; c < 7; ++c) out[c] = sh[c][0];
         counts[0] = shc[0][0];
         counts[1] = shc[1][0];
-        *drop_count = 0;
+    }
+}
+
+// After the compute kernel, in one launch: the last workgroup sums the
+// partials, the others run the dropped-atom fixup.
+__global__ void k_fixup_finalize(const int *__restrict__ offsets, const int *__restrict__ jn,
+                                 const int *__restrict__ rv, const signed char *__restrict__ slotpos,
+                                 const int *__restrict__ drop_list, const int *__restrict__ drop_count,
+                                 int plane_stride, double *__restrict__ planes, const double *__restrict__ partials,
+                                 const long long *__restrict__ counters, int grid, double *__restrict__ out,
+                                 long long *__restrict__ counts)
+{
+    if (blockIdx.x == gridDim.x - 1) {
+        finalize_sums(partials, counters, grid, out, counts);
+        return;
+    }
+    const int nd = *drop_count;
+    for (int q = blockIdx.x; q < nd; q += gridDim.x - 1) {
+        const int m = drop_list[q];
+        const int e0 = offsets[m], e1 = offsets[m + 1];
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
+            if (slotpos[e] == -1) continue;
+            const int k = slotpos[rv[e]];
+            if ((unsigned)k < (unsigned)kRecCap) {
+                double *f = planes + 3 * ((size_t)k * plane_stride + (size_t)jn[e]);
+                f[0] = f[1] = f[2] = 0.0;
+            }
+        }
     }
 }
 
@@ -832,10 +858,13 @@ __global__ void k_reduce_systems(const SysDesc *__restrict__ sys, const BatchDim
 // F_m = (terms of centre m) + the force each centre i that keeps m put into
 // plane k of m, k = rank of i among m's kept neighbours (k < pcount[m]).
 // One thread per atom; each plane read is coalesced across the wavefront.
+// Also empties the dropped-atom list for the next evaluation when
+// drop_count is given (every kernel reading it has run by now).
 __global__ void k_gather_forces(const int *__restrict__ pcount, const double *__restrict__ planes,
                                 const double *__restrict__ own, int n, const int *__restrict__ n_dev,
-                                int plane_stride, double *__restrict__ forces)
+                                int plane_stride, double *__restrict__ forces, int *drop_count)
 {
+    if (drop_count && blockIdx.x == 0 && threadIdx.x == 0) *drop_count = 0;
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= (n_dev ? *n_dev : n)) return;
     double fx = own[3 * (size_t)m], fy = own[3 * (size_t)m + 1], fz = own[3 * (size_t)m + 2];
@@ -962,11 +991,13 @@ hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *rv
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double *partials, const long long *counters, int grid,
-                           double *out7, long long *counts_out, int *drop_count, hipStream_t s)
+hipError_t launch_fixup_finalize(const int *offsets, const int *jn, const int *rv, const signed char *slotpos,
+                                 const int *drop_list, const int *drop_count, int plane_stride, double *planes,
+                                 const double *partials, const long long *counters, int grid, double *out7,
+                                 long long *counts_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, counters, grid, out7, counts_out,
-                       drop_count);
+    hipLaunchKernelGGL(k_fixup_finalize, dim3(kBigGrid + 1), dim3(256), 0, s, offsets, jn, rv, slotpos, drop_list,
+                       drop_count, plane_stride, planes, partials, counters, grid, out7, counts_out);
     return hipGetLastError();
 }
 
@@ -981,10 +1012,10 @@ hipError_t launch_reduce_systems(const SysDesc *sys, const BatchDims *dims, int 
 }
 
 hipError_t launch_gather_forces(const int *pcount, const double *planes, const double *own, int n,
-                                const int *n_dev, int plane_stride, double *forces, hipStream_t s)
+                                const int *n_dev, int plane_stride, double *forces, int *drop_count, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gather_forces, dim3(std::max(1, (n + 255) / 256)), dim3(256), 0, s, pcount, planes,
-                       own, n, n_dev, plane_stride, forces);
+                       own, n, n_dev, plane_stride, forces, drop_count);
     return hipGetLastError();
 }
 

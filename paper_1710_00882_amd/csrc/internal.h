@@ -118,7 +118,7 @@ struct PackLaunch {
     double *own;                // n x 3 (zeroed for dropped atoms only)
     int *flags;
     int *drop_list;             // n: atoms with more kept neighbours than kRecCap
-    int *drop_count;            // 0 on entry (the finalize / batch set-up kernels reset it)
+    int *drop_count;            // 0 on entry (the gather / batch set-up kernels reset it)
     const double *pos_build;    // n x 3 positions of the last build (stale check)
     double stale_sq;            // (skin / 2)^2
     int atoms_per_batch;        // B: centre atoms per batch (<= kWave), shared with the compute kernel
@@ -159,12 +159,18 @@ hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec
 hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *rv,
                                 const signed char *slotpos, const int *drop_list, const int *drop_count,
                                 int plane_stride, double *planes, hipStream_t s);
-// Sums the partials into out7 / counts_out and resets *drop_count to 0.
-hipError_t launch_finalize(const double *partials, const long long *counters, int grid,
-                           double *out7, long long *counts_out, int *drop_count, hipStream_t s);
+// Dropped-atom fixup and the sum of the compute kernel's partials into out7 /
+// counts_out, in one launch.
+hipError_t launch_fixup_finalize(const int *offsets, const int *jn, const int *rv, const signed char *slotpos,
+                                 const int *drop_list, const int *drop_count, int plane_stride, double *planes,
+                                 const double *partials, const long long *counters, int grid, double *out7,
+                                 long long *counts_out, hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
+// drop_count, when not null, is reset to 0 (the dropped-atom list is empty
+// for the next evaluation).
 hipError_t launch_gather_forces(const int *pcount, const double *planes, const double *own, int n,
-                                const int *n_dev, int plane_stride, double *forces, hipStream_t s);
+                                const int *n_dev, int plane_stride, double *forces, int *drop_count,
+                                hipStream_t s);
 // Per-system sums of the per-atom energy / virial of a batch and status bits
 // (1: a neighbour row over capacity, 2: an atom over the record capacity):
 // out[8 s + c] = E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, status.

@@ -59,7 +59,7 @@ struct tersoff_ctx {
     long long S = 0;
     int ell_cap = 32;        // row capacity for the next build (multiple of 8)
     int list_cap = 0;        // row stride of the resident list
-    int atoms_per_batch = 16;
+    int atoms_per_batch = 32;
     int grid[kNumPrec][3] = {};   // [precision] x {pack, compute, fixup}
 
     DevBuf<double> pos_build;
@@ -548,12 +548,11 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     HIP_TRY(c, launch_compute(a, c->tab, prec, grid[1], s));
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
-    HIP_TRY(c, launch_fixup_dropped(c->offsets.p, c->jn.p, c->rv.p, c->slotpos.p,
-                                    c->drop_list.p, c->misc.p + 3, c->n, c->planes.p, s));
-    HIP_TRY(c, launch_gather_forces(c->pcount.p, c->planes.p, c->own.p, c->n, nullptr, c->n, f, s));
+    HIP_TRY(c, launch_fixup_finalize(c->offsets.p, c->jn.p, c->rv.p, c->slotpos.p, c->drop_list.p, c->misc.p + 3,
+                                     c->n, c->planes.p, c->partials.p, c->counters.p, grid[1], energy_virial,
+                                     c->counts.p, s));
+    HIP_TRY(c, launch_gather_forces(c->pcount.p, c->planes.p, c->own.p, c->n, nullptr, c->n, f, c->misc.p + 3, s));
     if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
-    HIP_TRY(c, launch_finalize(c->partials.p, c->counters.p, grid[1], energy_virial, c->counts.p,
-                               c->misc.p + 3, s));
     if (c->profiling) {
         c->ev_pack.emplace_back(ev[0], ev[1]);
         c->ev_compute.emplace_back(ev[2], ev[3]);
