@@ -13,6 +13,8 @@
 //
 // `real` is float for the mixed path and double for the all-FP64 path; the
 // displacement, the zeta -> b power and every accumulation are FP64 in both.
+// Each pair's force term on its neighbour is stored in the working precision
+// (float planes for the mixed path) and summed per atom in FP64.
 #include "internal.h"
 
 #include <algorithm>
@@ -676,8 +678,8 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 w_acc[4] += dxj * Fz;
                 w_acc[5] += dyj * Fz;
                 if ((unsigned)kpos < (unsigned)kRecCap) {
-                    double *f = a.planes + 3 * ((size_t)kpos * a.plane_stride + (size_t)j);
-                    f[0] = Fx; f[1] = Fy; f[2] = Fz;
+                    real *f = static_cast<real *>(a.planes) + 3 * ((size_t)kpos * a.plane_stride + (size_t)j);
+                    f[0] = (real)Fx; f[1] = (real)Fy; f[2] = (real)Fz;
                 }
                 sh.fs[s][0] = Fx; sh.fs[s][1] = Fy; sh.fs[s][2] = Fz;
                 if constexpr (BATCHED) {
@@ -739,10 +741,11 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
 // never run as centres; zero the force slots their neighbours reserved for
 // them so the gather adds nothing stale.  Workgroups loop until the list is
 // drained.
+template <typename T>
 __global__ void k_fixup_dropped(const int *__restrict__ offsets, const int *__restrict__ jn,
                                 const int *__restrict__ rv, const signed char *__restrict__ slotpos,
                                 const int *__restrict__ drop_list, const int *__restrict__ drop_count,
-                                int plane_stride, double *__restrict__ planes)
+                                int plane_stride, T *__restrict__ planes)
 {
     const int nd = *drop_count;
     for (int q = blockIdx.x; q < nd; q += gridDim.x) {
@@ -752,8 +755,8 @@ __global__ void k_fixup_dropped(const int *__restrict__ offsets, const int *__re
             if (slotpos[e] == -1) continue;            // m did not keep this neighbour
             const int k = slotpos[rv[e]];              // rank of m in the neighbour's row
             if ((unsigned)k < (unsigned)kRecCap) {
-                double *f = planes + 3 * ((size_t)k * plane_stride + (size_t)jn[e]);
-                f[0] = f[1] = f[2] = 0.0;
+                T *f = planes + 3 * ((size_t)k * plane_stride + (size_t)jn[e]);
+                f[0] = f[1] = f[2] = T(0);
             }
         }
     }
@@ -794,10 +797,11 @@ __device__ void finalize_sums(const double *__restrict__ partials, const long lo
 
 // After the compute kernel, in one launch: the last workgroup sums the
 // partials, the others run the dropped-atom fixup.
+template <typename T>
 __global__ void k_fixup_finalize(const int *__restrict__ offsets, const int *__restrict__ jn,
                                  const int *__restrict__ rv, const signed char *__restrict__ slotpos,
                                  const int *__restrict__ drop_list, const int *__restrict__ drop_count,
-                                 int plane_stride, double *__restrict__ planes, const double *__restrict__ partials,
+                                 int plane_stride, T *__restrict__ planes, const double *__restrict__ partials,
                                  const long long *__restrict__ counters, int grid, double *__restrict__ out,
                                  long long *__restrict__ counts)
 {
@@ -813,8 +817,8 @@ __global__ void k_fixup_finalize(const int *__restrict__ offsets, const int *__r
             if (slotpos[e] == -1) continue;
             const int k = slotpos[rv[e]];
             if ((unsigned)k < (unsigned)kRecCap) {
-                double *f = planes + 3 * ((size_t)k * plane_stride + (size_t)jn[e]);
-                f[0] = f[1] = f[2] = 0.0;
+                T *f = planes + 3 * ((size_t)k * plane_stride + (size_t)jn[e]);
+                f[0] = f[1] = f[2] = T(0);
             }
         }
     }
@@ -860,7 +864,8 @@ __global__ void k_reduce_systems(const SysDesc *__restrict__ sys, const BatchDim
 // One thread per atom; each plane read is coalesced across the wavefront.
 // Also empties the dropped-atom list for the next evaluation when
 // drop_count is given (every kernel reading it has run by now).
-__global__ void k_gather_forces(const int *__restrict__ pcount, const double *__restrict__ planes,
+template <typename T>
+__global__ void k_gather_forces(const int *__restrict__ pcount, const T *__restrict__ planes,
                                 const double *__restrict__ own, int n, const int *__restrict__ n_dev,
                                 int plane_stride, double *__restrict__ forces, int *drop_count)
 {
@@ -870,10 +875,10 @@ __global__ void k_gather_forces(const int *__restrict__ pcount, const double *__
     double fx = own[3 * (size_t)m], fy = own[3 * (size_t)m + 1], fz = own[3 * (size_t)m + 2];
     const int pc = pcount[m];
     for (int k = 0; k < pc; ++k) {
-        const double *f = planes + 3 * ((size_t)k * plane_stride + (size_t)m);
-        fx += f[0];
-        fy += f[1];
-        fz += f[2];
+        const T *f = planes + 3 * ((size_t)k * plane_stride + (size_t)m);
+        fx += (double)f[0];
+        fy += (double)f[1];
+        fz += (double)f[2];
     }
     forces[3 * (size_t)m] = fx;
     forces[3 * (size_t)m + 1] = fy;
@@ -984,20 +989,30 @@ hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec
 
 hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *rv,
                                 const signed char *slotpos, const int *drop_list, const int *drop_count,
-                                int plane_stride, double *planes, hipStream_t s)
+                                int plane_stride, int prec, void *planes, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fixup_dropped, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jn, rv, slotpos,
-                       drop_list, drop_count, plane_stride, planes);
+    if (prec != kPrecFP64)
+        hipLaunchKernelGGL(k_fixup_dropped<float>, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jn, rv, slotpos,
+                           drop_list, drop_count, plane_stride, static_cast<float *>(planes));
+    else
+        hipLaunchKernelGGL(k_fixup_dropped<double>, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jn, rv, slotpos,
+                           drop_list, drop_count, plane_stride, static_cast<double *>(planes));
     return hipGetLastError();
 }
 
 hipError_t launch_fixup_finalize(const int *offsets, const int *jn, const int *rv, const signed char *slotpos,
-                                 const int *drop_list, const int *drop_count, int plane_stride, double *planes,
-                                 const double *partials, const long long *counters, int grid, double *out7,
-                                 long long *counts_out, hipStream_t s)
+                                 const int *drop_list, const int *drop_count, int plane_stride, int prec,
+                                 void *planes, const double *partials, const long long *counters, int grid,
+                                 double *out7, long long *counts_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fixup_finalize, dim3(kBigGrid + 1), dim3(256), 0, s, offsets, jn, rv, slotpos, drop_list,
-                       drop_count, plane_stride, planes, partials, counters, grid, out7, counts_out);
+    if (prec != kPrecFP64)
+        hipLaunchKernelGGL(k_fixup_finalize<float>, dim3(kBigGrid + 1), dim3(256), 0, s, offsets, jn, rv, slotpos,
+                           drop_list, drop_count, plane_stride, static_cast<float *>(planes), partials, counters,
+                           grid, out7, counts_out);
+    else
+        hipLaunchKernelGGL(k_fixup_finalize<double>, dim3(kBigGrid + 1), dim3(256), 0, s, offsets, jn, rv, slotpos,
+                           drop_list, drop_count, plane_stride, static_cast<double *>(planes), partials, counters,
+                           grid, out7, counts_out);
     return hipGetLastError();
 }
 
@@ -1011,11 +1026,16 @@ hipError_t launch_reduce_systems(const SysDesc *sys, const BatchDims *dims, int 
     return hipGetLastError();
 }
 
-hipError_t launch_gather_forces(const int *pcount, const double *planes, const double *own, int n,
+hipError_t launch_gather_forces(const int *pcount, int prec, const void *planes, const double *own, int n,
                                 const int *n_dev, int plane_stride, double *forces, int *drop_count, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_forces, dim3(std::max(1, (n + 255) / 256)), dim3(256), 0, s, pcount, planes,
-                       own, n, n_dev, plane_stride, forces, drop_count);
+    const dim3 G(std::max(1, (n + 255) / 256)), W(256);
+    if (prec != kPrecFP64)
+        hipLaunchKernelGGL(k_gather_forces<float>, G, W, 0, s, pcount, static_cast<const float *>(planes), own, n,
+                           n_dev, plane_stride, forces, drop_count);
+    else
+        hipLaunchKernelGGL(k_gather_forces<double>, G, W, 0, s, pcount, static_cast<const double *>(planes), own,
+                           n, n_dev, plane_stride, forces, drop_count);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ struct ParamR {
 // zeta -> b power in log form).
 struct ParamX {
     double cutsq;     // (R + D)^2
-    double logbeta;   // log(beta) (unused when beta == 0)
+    double logbeta;   // log(beta) (-inf when beta == 0)
     double eta;
     double inv2eta;   // 1 / (2 eta)
 };
@@ -135,7 +135,8 @@ struct ComputeLaunch {
     const signed char *slotpos; // list entries
     int n;
     double *own;                // n x 3: force from the terms of each centre atom
-    double *planes;             // kRecCap x n x 3: plane k of atom j = force from its k-th kept neighbour's terms
+    void *planes;               // kRecCap x n x 3: plane k of atom j = force from its k-th kept neighbour's
+                                // terms (float for the mixed and single paths, double for FP64)
     double *partials;           // grid x 8
     long long *counters;        // grid x 2 (pairs, triplets)
     int atoms_per_batch;        // nominal atoms per batch (<= kWave)
@@ -156,19 +157,20 @@ size_t record_bytes(int prec);
 hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, int prec, int grid, hipStream_t s);
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec,
                           int grid, hipStream_t s);
+// Force planes hold float for the mixed and single paths, double for FP64.
 hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *rv,
                                 const signed char *slotpos, const int *drop_list, const int *drop_count,
-                                int plane_stride, double *planes, hipStream_t s);
+                                int plane_stride, int prec, void *planes, hipStream_t s);
 // Dropped-atom fixup and the sum of the compute kernel's partials into out7 /
 // counts_out, in one launch.
 hipError_t launch_fixup_finalize(const int *offsets, const int *jn, const int *rv, const signed char *slotpos,
-                                 const int *drop_list, const int *drop_count, int plane_stride, double *planes,
-                                 const double *partials, const long long *counters, int grid, double *out7,
+                                 const int *drop_list, const int *drop_count, int plane_stride, int prec,
+                                 void *planes, const double *partials, const long long *counters, int grid, double *out7,
                                  long long *counts_out, hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
 // drop_count, when not null, is reset to 0 (the dropped-atom list is empty
 // for the next evaluation).
-hipError_t launch_gather_forces(const int *pcount, const double *planes, const double *own, int n,
+hipError_t launch_gather_forces(const int *pcount, int prec, const void *planes, const double *own, int n,
                                 const int *n_dev, int plane_stride, double *forces, int *drop_count,
                                 hipStream_t s);
 // Per-system sums of the per-atom energy / virial of a batch and status bits

@@ -388,8 +388,8 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     a.eatom = L.eatom.p;
     SRV_TRY(launch_compute(a, S.env.tab, prec, S.grids[prec][1], s));
     SRV_TRY(launch_fixup_dropped(L.offsets.p, L.jn.p, L.rv.p, L.slotpos.p, L.drop_list.p, L.ctl.p + 1,
-                                 S.max_atoms, L.planes.p, s));
-    SRV_TRY(launch_gather_forces(L.pcount.p, L.planes.p, L.own.p, S.max_atoms, n_dev, S.max_atoms, L.forces.p,
+                                 S.max_atoms, prec, L.planes.p, s));
+    SRV_TRY(launch_gather_forces(L.pcount.p, prec, L.planes.p, L.own.p, S.max_atoms, n_dev, S.max_atoms, L.forces.p,
                                  nullptr, s));
     SRV_TRY(launch_reduce_systems(L.desc.p, L.dims.p, S.max_sys, L.eatom.p, L.drop_list.p, L.ctl.p + 1,
                                   L.ctl.p + 3, L.out.p, s));
