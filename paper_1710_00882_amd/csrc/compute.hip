@@ -166,8 +166,7 @@ __device__ __forceinline__ void cutoff_terms(const ParamR<real> &q, real r, real
 // -------------------------------------------------------- packed records -
 
 // One packed neighbour n of a centre atom i (an in-range entry of i's list,
-// Section 3): the neighbour index, the entry (n, i) of n's row, the
-// membership bits of the exact FP64 cutoff tests, and the minimum-image
+// Section 3): the neighbour index, the membership bits of the exact FP64 cutoff tests, and the minimum-image
 // displacement in the working precision (distance and unit vector are
 // formed from it by the compute kernel).  The records of a batch of B consecutive
 // centre atoms are stored contiguously, atom by atom, in the batch's region
@@ -177,12 +176,12 @@ template <typename real>
 struct Rec;
 template <>
 struct alignas(8) Rec<float> {
-    int j, rev, mask;
+    int j, spare, mask;
     float dx, dy, dz;
 };
 template <>
 struct alignas(8) Rec<double> {
-    int j, rev, mask, pad;
+    int j, spare, mask, pad;
     double dx, dy, dz;
 };
 
@@ -193,7 +192,57 @@ constexpr int kPairBit = 8;
 constexpr int kThirdBit = 9;
 
 constexpr int kChunks = 4;     // 64-entry chunks whose loads are issued together
+static_assert(kKeptFast == 8, "the first block of a kept list is two 16-byte words");
+
+// Position of atom `who` in the kept-neighbour list of atom m (-1: absent);
+// `ended` tells whether the list ends (end marker) before kRecCap entries.
+__device__ __forceinline__ int kept_position(const int *__restrict__ kept, const int *__restrict__ kept_more,
+                                             int m, int who, bool &ended)
+{
+    const int4 *kb = reinterpret_cast<const int4 *>(kept + (size_t)m * kKeptFast);
+    int len = kKeptFast, pos = -1;
+    {
+        const int4 v0 = kb[0];
+        const int v[4] = {v0.x, v0.y, v0.z, v0.w};
+#pragma unroll
+        for (int q = 3; q >= 0; --q)
+            if (v[q] < 0) len = q;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < len && v[q] == who) pos = q;
+    }
+    if (pos < 0 && len == kKeptFast) {
+        const int4 v1 = kb[1];
+        const int v[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+        for (int q = 3; q >= 0; --q)
+            if (v[q] < 0) len = 4 + q;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (4 + q < len && v[q] == who) pos = 4 + q;
+    }
+    ended = len < kKeptFast;
+    if (pos < 0 && !ended) {
+        const int *km = kept_more + (size_t)m * kRecCap;
+        for (int q = kKeptFast; q < kRecCap; ++q) {
+            const int x = km[q];
+            if (x < 0) {
+                ended = true;
+                break;
+            }
+            if (x == who) {
+                pos = q;
+                break;
+            }
+        }
+    }
+    return pos;
+}
 constexpr int kScap = 64;      // packed slots per compute batch (one per lane)
+// Resident packing wavefronts per CU: more than this only adds contention for
+// the CU's vector-memory path (the kernel is bound by its neighbour-position
+// gathers, not by latency).
+constexpr int kPackWavesPerCU = 24;
 
 // ------------------------------------------------------------- pack kernel -
 //
@@ -201,11 +250,11 @@ constexpr int kScap = 64;      // packed slots per compute batch (one per lane)
 // through a prefix count of the row lengths).  Each lane computes the FP64 minimum-image displacement and r^2 of
 // its entry and keeps it if r^2 is below the (symmetric) packing radius; the
 // kept entries are written, atom by atom and in list order, to the batch's
-// record region.  slotpos[e] receives the rank of entry
-// e among the kept entries of its row (-1: not kept, -2: beyond the record
-// capacity).  Because the radius is symmetric and r^2 of (i, n) and (n, i) is
-// bit-identical, i keeps n exactly when n keeps i, so the centre i can find
-// where atom n expects the force i's terms put on it: rank slotpos[(n, i)].
+// record region, and each atom's kept neighbours, in the same order, to its
+// kept-neighbour list.  Because the radius is symmetric and r^2 of (i, n) and
+// (n, i) is bit-identical, i keeps n exactly when n keeps i, so the centre i
+// finds where atom n expects the force of i's terms -- force plane k, k the
+// position of i in n's kept list -- by looking i up in that list.
 //
 // BATCHED: the atoms belong to several systems (each row holds atoms of its
 // own system only); every centre atom uses its system's box, and there is no
@@ -217,6 +266,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
     __shared__ double bL[BATCHED ? 3 : 1][BATCHED ? kWave : 1], biL[BATCHED ? 3 : 1][BATCHED ? kWave : 1];
     __shared__ int ti[kWave], cnt[kWave];
     __shared__ int eoff[kWave + 1];
+    __shared__ int kst[kKeptFast][kWave];   // first kept neighbours of the batch's atoms
     const int lane = threadIdx.x;
     Rec<real> *recs = static_cast<Rec<real> *>(a.recs);
     const int B = a.atoms_per_batch;
@@ -258,14 +308,13 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
         const int e_begin = eoff[0], e_end = eoff[nb];
         int npacked = 0;   // kept entries of the batch so far (records beyond an atom's cap excluded)
         for (int eb = e_begin; eb < e_end; eb += kWave * kChunks) {
-            int jv[kChunks], rvv[kChunks], tv[kChunks];
+            int jv[kChunks], tv[kChunks];
             double xv[kChunks], yv[kChunks], zv[kChunks];
             int ev[kChunks], alv[kChunks];
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
                 const int e = eb + c * kWave + lane;
                 jv[c] = -1;
-                rvv[c] = 0;
                 alv[c] = 0;
                 ev[c] = 0;
                 if (e < e_end) {
@@ -273,7 +322,6 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                     alv[c] = al;
                     ev[c] = ebase + e;   // list index of the entry
                     jv[c] = a.jn[ev[c]];
-                    rvv[c] = a.rv[ev[c]];
                 }
             }
 #pragma unroll
@@ -316,12 +364,13 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 const unsigned long long from = first ? ~(~0ull >> (64 - first)) : ~0ull;
                 const int k = cnt[al] + __popcll(m & below & from);
                 const unsigned long long mrec = __ballot(acc && k < kRecCap);
-                if (e < e_end) a.slotpos[ev[c]] = (signed char)(acc ? (k < kRecCap ? k : -2) : -1);
                 if (acc) {
                     if (k < kRecCap) {
+                        if (k < kKeptFast) kst[k][al] = jv[c];
+                        else a.kept_more[(size_t)(a0 + al) * kRecCap + k] = jv[c];
                         Rec<real> o;
                         o.j = jv[c];
-                        o.rev = rvv[c];
+                        o.spare = 0;
                         int mask = tv[c];
                         if (ONE) {
                             mask |= (1 << kPairBit) | (1 << kThirdBit);
@@ -349,6 +398,14 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
         if (lane < nb) {
             const int i = a0 + lane;
             int c = cnt[lane];
+            // the kept list: its first block, and the end marker
+            int4 *kb = reinterpret_cast<int4 *>(a.kept + (size_t)i * kKeptFast);
+            int kv[kKeptFast];
+#pragma unroll
+            for (int q = 0; q < kKeptFast; ++q) kv[q] = q < c ? kst[q][lane] : -1;
+            kb[0] = make_int4(kv[0], kv[1], kv[2], kv[3]);
+            kb[1] = make_int4(kv[4], kv[5], kv[6], kv[7]);
+            if (c >= kKeptFast && c < kRecCap) a.kept_more[(size_t)i * kRecCap + c] = -1;
             if (c > kRecCap) {
                 // more kept neighbours than its records hold: the atom is
                 // evaluated with its first kRecCap neighbours only and the
@@ -431,9 +488,9 @@ __device__ __forceinline__ void exp_term(const ParamR<real> &q, real rj, real rk
 //      its k-role terms -dV/dzeta_ik dzeta(i,k,j)/dx_j -- so no two lanes
 //      ever update the same force;
 //   4  virial d_ij (x) F_j; the force on i is minus the sum over its slots.
-// Each slot's force goes to the slot atom j reserved for centre i (plane
-// slotpos[(j, i)] of the per-atom force planes), each centre's own force to
-// `own`; k_gather_forces sums them per atom.
+// Each slot's force goes to the slot atom j reserved for centre i (plane k
+// of the per-atom force planes, k the position of i in j's kept list), each
+// centre's own force to `own`; k_gather_forces sums them per atom.
 //
 // BATCHED: the batch holds several systems; each centre atom's energy and
 // virial (the sums over its slots) are stored per atom for the per-system
@@ -463,6 +520,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
     double e_acc = 0.0;
     double w_acc[6] = {0, 0, 0, 0, 0, 0};
     long long n_pairs = 0, n_trip = 0;
+    bool asym = false;   // a kept neighbour whose (complete) kept list lacks the centre
 
     const int B = a.atoms_per_batch;
     const int n = BATCHED ? *a.n_dev : a.n;
@@ -506,7 +564,9 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 ti = ONE ? 0 : sh.ti[al];
                 const Rec<real> rc = region[s];
                 j = rc.j;
-                kpos = a.slotpos[rc.rev];
+                bool ended;
+                kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, ended);
+                asym |= kpos < 0 && ended;
                 mj = rc.mask;
                 dj[0] = rc.dx; dj[1] = rc.dy; dj[2] = rc.dz;
                 rj = M<real>::sqrt(norm2r(dj[0], dj[1], dj[2]));
@@ -727,23 +787,25 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
         np += __shfl_xor(np, off, kWave);
         ntr += __shfl_xor(ntr, off, kWave);
     }
+    const bool any_asym = __ballot(asym) != 0ull;
     if (lane == 0) {
         double *pp = a.partials + 8 * (size_t)blockIdx.x;
+        pp[7] = any_asym ? 1.0 : 0.0;
 #pragma unroll
         for (int c = 0; c < 7; ++c) pp[c] = v[c];
-        pp[7] = 0.0;
         a.counters[2 * (size_t)blockIdx.x] = np;
         a.counters[2 * (size_t)blockIdx.x + 1] = ntr;
     }
 }
 
-// Atoms dropped by k_pack (more kept neighbours than a record row holds)
-// never run as centres; zero the force slots their neighbours reserved for
-// them so the gather adds nothing stale.  Workgroups loop until the list is
+// Atoms dropped by k_pack (more kept neighbours than a record row holds) are
+// evaluated with a truncated neighbour set and reported invalid; zero the
+// force slots their neighbours reserved for them so the gather adds nothing
+// from them.  Workgroups loop until the list is
 // drained.
 template <typename T>
 __global__ void k_fixup_dropped(const int *__restrict__ offsets, const int *__restrict__ jn,
-                                const int *__restrict__ rv, const signed char *__restrict__ slotpos,
+                                const int *__restrict__ kept, const int *__restrict__ kept_more,
                                 const int *__restrict__ drop_list, const int *__restrict__ drop_count,
                                 int plane_stride, T *__restrict__ planes)
 {
@@ -752,10 +814,11 @@ __global__ void k_fixup_dropped(const int *__restrict__ offsets, const int *__re
         const int m = drop_list[q];
         const int e0 = offsets[m], e1 = offsets[m + 1];
         for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
-            if (slotpos[e] == -1) continue;            // m did not keep this neighbour
-            const int k = slotpos[rv[e]];              // rank of m in the neighbour's row
-            if ((unsigned)k < (unsigned)kRecCap) {
-                T *f = planes + 3 * ((size_t)k * plane_stride + (size_t)jn[e]);
+            const int nb = jn[e];
+            bool ended;
+            const int k = kept_position(kept, kept_more, nb, m, ended);   // plane nb reserved for m
+            if (k >= 0) {
+                T *f = planes + 3 * ((size_t)k * plane_stride + (size_t)nb);
                 f[0] = f[1] = f[2] = T(0);
             }
         }
@@ -763,19 +826,23 @@ __global__ void k_fixup_dropped(const int *__restrict__ offsets, const int *__re
 }
 
 // Sums the per-workgroup partials of the compute kernel (one workgroup of
-// 256 threads, fixed summation order).
+// 256 threads, fixed summation order) and raises kFlagAsym if a workgroup
+// reported it.
 __device__ void finalize_sums(const double *__restrict__ partials, const long long *__restrict__ counters,
-                              int grid, double *__restrict__ out, long long *__restrict__ counts)
+                              int grid, double *__restrict__ out, long long *__restrict__ counts, int *flags)
 {
     __shared__ double sh[8][256];
     __shared__ long long shc[2][256];
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     long long c0 = 0, c1 = 0;
+    bool asym = false;
     for (int b = threadIdx.x; b < grid; b += blockDim.x) {
         for (int c = 0; c < 7; ++c) v[c] += partials[8 * (size_t)b + c];
+        asym |= partials[8 * (size_t)b + 7] != 0.0;
         c0 += counters[2 * (size_t)b];
         c1 += counters[2 * (size_t)b + 1];
     }
+    if (asym) atomicOr(flags, kFlagAsym);
     for (int c = 0; c < 7; ++c) sh[c][threadIdx.x] = v[c];
     shc[0][threadIdx.x] = c0;
     shc[1][threadIdx.x] = c1;
@@ -799,14 +866,14 @@ __device__ void finalize_sums(const double *__restrict__ partials, const long lo
 // partials, the others run the dropped-atom fixup.
 template <typename T>
 __global__ void k_fixup_finalize(const int *__restrict__ offsets, const int *__restrict__ jn,
-                                 const int *__restrict__ rv, const signed char *__restrict__ slotpos,
+                                 const int *__restrict__ kept, const int *__restrict__ kept_more,
                                  const int *__restrict__ drop_list, const int *__restrict__ drop_count,
                                  int plane_stride, T *__restrict__ planes, const double *__restrict__ partials,
                                  const long long *__restrict__ counters, int grid, double *__restrict__ out,
-                                 long long *__restrict__ counts)
+                                 long long *__restrict__ counts, int *flags)
 {
     if (blockIdx.x == gridDim.x - 1) {
-        finalize_sums(partials, counters, grid, out, counts);
+        finalize_sums(partials, counters, grid, out, counts, flags);
         return;
     }
     const int nd = *drop_count;
@@ -814,10 +881,11 @@ __global__ void k_fixup_finalize(const int *__restrict__ offsets, const int *__r
         const int m = drop_list[q];
         const int e0 = offsets[m], e1 = offsets[m + 1];
         for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
-            if (slotpos[e] == -1) continue;
-            const int k = slotpos[rv[e]];
-            if ((unsigned)k < (unsigned)kRecCap) {
-                T *f = planes + 3 * ((size_t)k * plane_stride + (size_t)jn[e]);
+            const int nb = jn[e];
+            bool ended;
+            const int k = kept_position(kept, kept_more, nb, m, ended);   // plane nb reserved for m
+            if (k >= 0) {
+                T *f = planes + 3 * ((size_t)k * plane_stride + (size_t)nb);
                 f[0] = f[1] = f[2] = T(0);
             }
         }
@@ -893,11 +961,14 @@ __global__ void k_fill_zero(T *p, size_t count)
     for (; i < count; i += stride) p[i] = T(0);
 }
 
-int occupancy_grid(const void *kern, long long work_items)
+// Workgroups of a persistent grid: the resident limit per CU (at most
+// max_per_cu) times the CU count, at most one per work item.
+int occupancy_grid(const void *kern, long long work_items, int max_per_cu = 1 << 20)
 {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
+    per_cu = std::min(per_cu, max_per_cu);
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -910,7 +981,7 @@ template <typename real, bool ONE, bool BATCHED, bool SINGLE>
 void grids_for(int n, int atoms_per_batch, int grids[3])
 {
     grids[0] = occupancy_grid((const void *)k_pack<real, ONE, BATCHED>,
-                              ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
+                              ((long long)n + atoms_per_batch - 1) / atoms_per_batch, kPackWavesPerCU);
     grids[1] = occupancy_grid((const void *)k_tersoff<real, ONE, BATCHED, SINGLE>,
                               ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
     grids[2] = kBigGrid;
@@ -987,32 +1058,32 @@ hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec
     return hipGetLastError();
 }
 
-hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *rv,
-                                const signed char *slotpos, const int *drop_list, const int *drop_count,
-                                int plane_stride, int prec, void *planes, hipStream_t s)
+hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *kept, const int *kept_more,
+                                const int *drop_list, const int *drop_count, int plane_stride, int prec,
+                                void *planes, hipStream_t s)
 {
     if (prec != kPrecFP64)
-        hipLaunchKernelGGL(k_fixup_dropped<float>, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jn, rv, slotpos,
+        hipLaunchKernelGGL(k_fixup_dropped<float>, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jn, kept, kept_more,
                            drop_list, drop_count, plane_stride, static_cast<float *>(planes));
     else
-        hipLaunchKernelGGL(k_fixup_dropped<double>, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jn, rv, slotpos,
+        hipLaunchKernelGGL(k_fixup_dropped<double>, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jn, kept, kept_more,
                            drop_list, drop_count, plane_stride, static_cast<double *>(planes));
     return hipGetLastError();
 }
 
-hipError_t launch_fixup_finalize(const int *offsets, const int *jn, const int *rv, const signed char *slotpos,
+hipError_t launch_fixup_finalize(const int *offsets, const int *jn, const int *kept, const int *kept_more,
                                  const int *drop_list, const int *drop_count, int plane_stride, int prec,
                                  void *planes, const double *partials, const long long *counters, int grid,
-                                 double *out7, long long *counts_out, hipStream_t s)
+                                 double *out7, long long *counts_out, int *flags, hipStream_t s)
 {
     if (prec != kPrecFP64)
-        hipLaunchKernelGGL(k_fixup_finalize<float>, dim3(kBigGrid + 1), dim3(256), 0, s, offsets, jn, rv, slotpos,
+        hipLaunchKernelGGL(k_fixup_finalize<float>, dim3(kBigGrid + 1), dim3(256), 0, s, offsets, jn, kept, kept_more,
                            drop_list, drop_count, plane_stride, static_cast<float *>(planes), partials, counters,
-                           grid, out7, counts_out);
+                           grid, out7, counts_out, flags);
     else
-        hipLaunchKernelGGL(k_fixup_finalize<double>, dim3(kBigGrid + 1), dim3(256), 0, s, offsets, jn, rv, slotpos,
+        hipLaunchKernelGGL(k_fixup_finalize<double>, dim3(kBigGrid + 1), dim3(256), 0, s, offsets, jn, kept, kept_more,
                            drop_list, drop_count, plane_stride, static_cast<double *>(planes), partials, counters,
-                           grid, out7, counts_out);
+                           grid, out7, counts_out, flags);
     return hipGetLastError();
 }
 

@@ -97,10 +97,17 @@ __device__ __forceinline__ ItemRange xcd_items(int nitems)
     return {b0 + l, min(nitems, b0 + per), gx};
 }
 
-// Flags raised by kernels (bitwise OR into a device int).
-enum : int { kFlagOverflow = 1, kFlagStale = 2 };
+// Flags raised by kernels (bitwise OR into a device int).  kFlagAsym: a
+// centre kept a neighbour whose kept list (shorter than kRecCap) lacks it.
+enum : int { kFlagOverflow = 1, kFlagStale = 2, kFlagAsym = 4 };
 
 constexpr int kRecCap = 32;   // packed-neighbour records per atom (more: E_OVERFLOW)
+// Kept-neighbour lists of N atoms in one buffer of (kKeptFast + kRecCap) N
+// ints: the first kKeptFast entries of atom m at kept[m * kKeptFast] (one
+// 32-byte block, -1 after the last entry), entries kKeptFast .. kRecCap - 1
+// at kept_more[m * kRecCap + q], kept_more = kept + kKeptFast N (-1 after the
+// last when the list is shorter than kRecCap).
+constexpr int kKeptFast = 8;
 constexpr int kBigGrid = 64;  // workgroups of the dropped-atom fixup kernel
 
 struct PackLaunch {
@@ -109,12 +116,12 @@ struct PackLaunch {
     const int *row_count;       // n: list length of each atom
     const int *offsets;         // n + 1: first list entry of each atom (compact list)
     const int *jn;              // list entries: sorted neighbour rows, row i at offsets[i]
-    const int *rv;              // list entries: index of (j, i) for entry (i, j)
     int n;
     double L[3], invL[3];
     void *recs;                 // packed records: region of B * kRecCap per batch of B atoms
     int *pcount;                // n: records per atom
-    signed char *slotpos;       // list entries: rank among the row's kept entries, -1 not kept, -2 beyond kRecCap
+    int *kept;                  // n x kKeptFast: kept-neighbour lists (first entries)
+    int *kept_more;             // n x kRecCap: kept-neighbour lists (entries kKeptFast ..)
     double *own;                // n x 3 (zeroed for dropped atoms only)
     int *flags;
     int *drop_list;             // n: atoms with more kept neighbours than kRecCap
@@ -132,12 +139,12 @@ struct ComputeLaunch {
     const int *types;           // n
     const void *recs;           // packed records (batch regions)
     const int *pcount;          // n
-    const signed char *slotpos; // list entries
+    const int *kept;            // kept-neighbour lists of plane_stride atoms (kept_more follows)
     int n;
     double *own;                // n x 3: force from the terms of each centre atom
     void *planes;               // kRecCap x n x 3: plane k of atom j = force from its k-th kept neighbour's
                                 // terms (float for the mixed and single paths, double for FP64)
-    double *partials;           // grid x 8
+    double *partials;           // grid x 8 (E, virial, kFlagAsym as a double)
     long long *counters;        // grid x 2 (pairs, triplets)
     int atoms_per_batch;        // nominal atoms per batch (<= kWave)
     int plane_stride;           // atoms per force plane (n, or the batch capacity)
@@ -158,15 +165,15 @@ hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, int prec, int 
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec,
                           int grid, hipStream_t s);
 // Force planes hold float for the mixed and single paths, double for FP64.
-hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *rv,
-                                const signed char *slotpos, const int *drop_list, const int *drop_count,
-                                int plane_stride, int prec, void *planes, hipStream_t s);
+hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *kept, const int *kept_more,
+                                const int *drop_list, const int *drop_count, int plane_stride, int prec,
+                                void *planes, hipStream_t s);
 // Dropped-atom fixup and the sum of the compute kernel's partials into out7 /
-// counts_out, in one launch.
-hipError_t launch_fixup_finalize(const int *offsets, const int *jn, const int *rv, const signed char *slotpos,
+// counts_out, in one launch; *flags |= kFlagAsym when a partial carries it.
+hipError_t launch_fixup_finalize(const int *offsets, const int *jn, const int *kept, const int *kept_more,
                                  const int *drop_list, const int *drop_count, int plane_stride, int prec,
-                                 void *planes, const double *partials, const long long *counters, int grid, double *out7,
-                                 long long *counts_out, hipStream_t s);
+                                 void *planes, const double *partials, const long long *counters, int grid,
+                                 double *out7, long long *counts_out, int *flags, hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
 // drop_count, when not null, is reset to 0 (the dropped-atom list is empty
 // for the next evaluation).
@@ -223,10 +230,9 @@ struct SearchLaunch {
 };
 hipError_t launch_search(const SearchLaunch &a, int grid_cap, hipStream_t s);
 // Compact list from the row buffer (row i at i * cap): jn[offsets[i] + q] =
-// ell[i * cap + q], and rv[e] for entry e = (i, j): the index of entry (j, i)
-// (the list is symmetric).  Sets *flags |= 4 if some reverse entry is missing.
-hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, const int *offsets, int n,
-                              const int *n_dev, int *jn, int *rv, int *flags, hipStream_t s);
+// ell[i * cap + q] for q < row_count[i].
+hipError_t launch_compact_list(const int *ell, int cap, const int *row_count, const int *offsets, int n,
+                               const int *n_dev, int *jn, hipStream_t s);
 // Batched build: binning of every system's atoms into its own cells.
 hipError_t launch_bin_systems(const double *pos, const int *sys_of, const SysDesc *sys, const BatchDims *dims,
                               int max_atoms, int *cell_of, int *rank_in_cell, int *cell_count, hipStream_t s);

@@ -11,8 +11,8 @@
 // order -> one thread per atom tests the atoms of the 27 surrounding cells and
 // writes its row, sorted, to the row buffer (row i at i * cap, cap >= the
 // longest row; rows too long for the thread's LDS buffer go to a wavefront
-// per row) -> scan of row counts (list length, longest row) -> reverse-entry
-// map.
+// per row) -> scan of row counts (list length, longest row) -> compaction of
+// the rows into the list.
 #include "internal.h"
 
 #include <algorithm>
@@ -412,62 +412,22 @@ __global__ __launch_bounds__(kWave) void k_search_long(SearchLaunch a)
     }
 }
 
-// Compact list and reverse entries.  For entry (i, q) of the row buffer
-// (row i at i * cap, neighbour j) the compact index is e = offsets[i] + q:
-// jn[e] = j, and the thread with i < j searches row j (16-entry pieces of
-// four 16-byte loads issued together) for i at position p and fills
-// rv[e] = offsets[j] + p and rv[offsets[j] + p] = e.  The inclusion
-// predicate is symmetric (negating t negates s and d exactly), so the entry
-// exists; a missing one raises flag 4.
-__device__ __forceinline__ void reverse_entry(const int *__restrict__ ell, int cap,
-                                              const int *__restrict__ row_count,
-                                              const int *__restrict__ offsets, unsigned tid,
-                                              int *__restrict__ jn, int *__restrict__ rv, int *flags)
-{
-    const int i = (int)(tid / (unsigned)cap);
-    const int q = (int)(tid - (unsigned)i * (unsigned)cap);
-    if (q >= row_count[i]) return;
-    const int j = ell[(size_t)i * cap + q];
-    const int e = offsets[i] + q;
-    jn[e] = j;
-    if (j < i) return;   // the pair is handled from the other side
-    const int cj = row_count[j];
-    const int4 *row = reinterpret_cast<const int4 *>(ell + (size_t)j * cap);
-    int at = -1;
-    for (int b = 0; b < cj && at < 0; b += 16) {
-        int4 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = (b + 4 * u < cap) ? row[(b >> 2) + u] : make_int4(-1, -1, -1, -1);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = b + 4 * u;
-            if (k + 0 < cj && v[u].x == i) at = k + 0;
-            if (k + 1 < cj && v[u].y == i) at = k + 1;
-            if (k + 2 < cj && v[u].z == i) at = k + 2;
-            if (k + 3 < cj && v[u].w == i) at = k + 3;
-        }
-    }
-    if (at < 0) {
-        atomicOr(flags, 4);
-        rv[e] = e;
-    } else {
-        const int f = offsets[j] + at;
-        rv[e] = f;
-        rv[f] = e;
-    }
-}
-
-// One thread per (i, q), q < cap; n_dev, when not null, holds the atom count
-// (batches) and n is the capacity the grid was sized for.
-__global__ void k_reverse_map(const int *__restrict__ ell, int cap, const int *__restrict__ row_count,
-                              const int *__restrict__ offsets, int n, const int *__restrict__ n_dev,
-                              int *__restrict__ jn, int *__restrict__ rv, int *flags)
+// Compact list: one thread per (i, q), q < cap; the entry (i, q) of the row
+// buffer (row i at i * cap) moves to jn[offsets[i] + q].  n_dev, when not
+// null, holds the atom count (batches) and n is the capacity the grid was
+// sized for.
+__global__ void k_compact_list(const int *__restrict__ ell, int cap, const int *__restrict__ row_count,
+                               const int *__restrict__ offsets, int n, const int *__restrict__ n_dev,
+                               int *__restrict__ jn)
 {
     const unsigned total = (unsigned)(n_dev ? *n_dev : n) * (unsigned)cap;   // n * cap < 2^31
     const ItemRange r = xcd_items((int)((total + blockDim.x - 1) / blockDim.x));
     for (int it = r.begin; it < r.end; it += r.stride) {
         const unsigned tid = (unsigned)it * blockDim.x + threadIdx.x;
-        if (tid < total) reverse_entry(ell, cap, row_count, offsets, tid, jn, rv, flags);
+        if (tid >= total) continue;
+        const int i = (int)(tid / (unsigned)cap);
+        const int q = (int)(tid - (unsigned)i * (unsigned)cap);
+        if (q < row_count[i]) jn[offsets[i] + q] = ell[tid];
     }
 }
 
@@ -586,14 +546,14 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int n, int *tmp, int *
     return hipGetLastError();
 }
 
-hipError_t launch_reverse_map(const int *ell, int cap, const int *row_count, const int *offsets, int n,
-                              const int *n_dev, int *jn, int *rv, int *flags, hipStream_t s)
+hipError_t launch_compact_list(const int *ell, int cap, const int *row_count, const int *offsets, int n,
+                               const int *n_dev, int *jn, hipStream_t s)
 {
     const long long threads = (long long)n * cap;
     long long blocks = (threads + 255) / 256;
     if (n_dev && blocks > kBatchGrid) blocks = kBatchGrid;
-    hipLaunchKernelGGL(k_reverse_map, dim3((unsigned)std::max(1LL, blocks)), dim3(256), 0, s, ell, cap,
-                       row_count, offsets, n, n_dev, jn, rv, flags);
+    hipLaunchKernelGGL(k_compact_list, dim3((unsigned)std::max(1LL, blocks)), dim3(256), 0, s, ell, cap,
+                       row_count, offsets, n, n_dev, jn);
     return hipGetLastError();
 }
 

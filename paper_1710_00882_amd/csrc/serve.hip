@@ -16,7 +16,7 @@
 // the host-to-device copies of the inputs and descriptors before it and the
 // copies of the results after it.  Graph contents: clear counters -> bin every
 // configuration's atoms into its own cells -> scan -> scatter -> neighbour
-// search over all configurations -> reverse map -> pack -> energy / force /
+// search over all configurations -> list compaction -> pack -> energy / force /
 // virial kernel (per-atom energy and virial) -> dropped-atom fixup -> force
 // gather -> per-configuration reduction.  A configuration's result does not
 // depend on the other configurations of its batch or on its place in it.
@@ -168,9 +168,9 @@ struct Lane {
     Dev<float4> cell_posf;
     Dev<int> long_rows;
     Dev<int> types, sys_of, cell_of, rank, cell_count, cell_start, cell_atoms, scan_tmp;
-    Dev<int> ell, row_count, offsets, jn, rv, pcount, drop_list;   // jn, rv, slotpos: compact list
+    Dev<int> ell, row_count, offsets, jn, pcount, drop_list;   // jn: compact list
+    Dev<int> kept;   // kept-neighbour lists: A x kKeptFast, then A x kRecCap
     Dev<int> ctl;   // [0] flags, [1] dropped count, [2] long rows, [3 ..] per-system status
-    Dev<signed char> slotpos;
     Dev<unsigned char> recs;
     Dev<SysDesc> desc;
     Dev<BatchDims> dims;
@@ -266,20 +266,16 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.row_count.alloc(A, tot));
     SRV_TRY(L.offsets.alloc(A + 1, tot));
     SRV_TRY(L.jn.alloc(E, tot));
-    SRV_TRY(L.rv.alloc(E, tot));
+    SRV_TRY(L.kept.alloc((size_t)(kKeptFast + kRecCap) * A, tot));
     SRV_TRY(L.pcount.alloc(A, tot));
     SRV_TRY(L.drop_list.alloc(A, tot));
     SRV_TRY(L.ctl.alloc(3 + NS, tot));
-    SRV_TRY(L.slotpos.alloc(E, tot));
     const size_t nbat = (A + kServeBatchAtoms - 1) / kServeBatchAtoms;
     SRV_TRY(L.recs.alloc(record_bytes(kPrecFP64) * kRecCap * nbat * kServeBatchAtoms, tot));
     SRV_TRY(L.desc.alloc(NS, tot));
     SRV_TRY(L.dims.alloc(1, tot));
-    // A row cleared for exceeding the capacity leaves reverse entries of its
-    // partners unwritten; start them (and the ranks they index) at valid
-    // values so that such a configuration only yields a flagged result.
-    SRV_TRY(hipMemsetAsync(L.rv.p, 0, sizeof(int) * E, L.stream));
-    SRV_TRY(hipMemsetAsync(L.slotpos.p, 0xff, E, L.stream));
+    // every kept list starts empty (-1)
+    SRV_TRY(hipMemsetAsync(L.kept.p, 0xff, sizeof(int) * (kKeptFast + kRecCap) * A, L.stream));
     SRV_TRY(hipMemsetAsync(L.pcount.p, 0, sizeof(int) * A, L.stream));
     return hipStreamSynchronize(L.stream);
 }
@@ -294,9 +290,10 @@ void free_lane(Lane &L)
     L.cell_posf.release(); L.long_rows.release();
     L.eatom.release(); L.out.release(); L.types.release(); L.sys_of.release(); L.cell_of.release();
     L.rank.release(); L.cell_count.release(); L.cell_start.release(); L.cell_atoms.release();
-    L.scan_tmp.release(); L.ell.release(); L.row_count.release(); L.rv.release(); L.pcount.release();
+    L.scan_tmp.release(); L.ell.release(); L.row_count.release(); L.kept.release();
+    L.pcount.release();
     L.offsets.release(); L.jn.release();
-    L.drop_list.release(); L.ctl.release(); L.slotpos.release(); L.recs.release(); L.desc.release();
+    L.drop_list.release(); L.ctl.release(); L.recs.release(); L.desc.release();
     L.dims.release();
     if (L.done) (void)hipEventDestroy(L.done), L.done = nullptr;
     if (L.stream) (void)hipStreamDestroy(L.stream), L.stream = nullptr;
@@ -348,8 +345,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     SRV_TRY(launch_search(sl, kBatchGrid, s));
     // compact list (counts past the batch's atoms do not enter the offsets of its atoms)
     SRV_TRY(launch_exclusive_scan(L.row_count.p, L.offsets.p, S.max_atoms, L.scan_tmp.p, nullptr, s));
-    SRV_TRY(launch_reverse_map(L.ell.p, S.cap, L.row_count.p, L.offsets.p, S.max_atoms, n_dev, L.jn.p, L.rv.p,
-                               L.ctl.p, s));
+    SRV_TRY(launch_compact_list(L.ell.p, S.cap, L.row_count.p, L.offsets.p, S.max_atoms, n_dev, L.jn.p, s));
 
     PackLaunch pk{};
     pk.pos = L.pos.p;
@@ -357,11 +353,11 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     pk.row_count = L.row_count.p;
     pk.offsets = L.offsets.p;
     pk.jn = L.jn.p;
-    pk.rv = L.rv.p;
     pk.n = S.max_atoms;
     pk.recs = L.recs.p;
     pk.pcount = L.pcount.p;
-    pk.slotpos = L.slotpos.p;
+    pk.kept = L.kept.p;
+    pk.kept_more = L.kept.p + (size_t)kKeptFast * S.max_atoms;
     pk.own = L.own.p;
     pk.flags = L.ctl.p;
     pk.drop_list = L.drop_list.p;
@@ -378,7 +374,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     a.types = L.types.p;
     a.recs = L.recs.p;
     a.pcount = L.pcount.p;
-    a.slotpos = L.slotpos.p;
+    a.kept = L.kept.p;
     a.n = S.max_atoms;
     a.own = L.own.p;
     a.planes = L.planes.p;
@@ -387,7 +383,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     a.n_dev = n_dev;
     a.eatom = L.eatom.p;
     SRV_TRY(launch_compute(a, S.env.tab, prec, S.grids[prec][1], s));
-    SRV_TRY(launch_fixup_dropped(L.offsets.p, L.jn.p, L.rv.p, L.slotpos.p, L.drop_list.p, L.ctl.p + 1,
+    SRV_TRY(launch_fixup_dropped(L.offsets.p, L.jn.p, L.kept.p, pk.kept_more, L.drop_list.p, L.ctl.p + 1,
                                  S.max_atoms, prec, L.planes.p, s));
     SRV_TRY(launch_gather_forces(L.pcount.p, prec, L.planes.p, L.own.p, S.max_atoms, n_dev, S.max_atoms, L.forces.p,
                                  nullptr, s));

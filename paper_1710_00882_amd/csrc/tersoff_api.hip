@@ -63,8 +63,8 @@ struct tersoff_ctx {
     int grid[kNumPrec][3] = {};   // [precision] x {pack, compute, fixup}
 
     DevBuf<double> pos_build;
-    DevBuf<int> types, offsets, pcount, drop_list, rv, jn;   // jn, rv, slotpos: compact list (S entries)
-    DevBuf<signed char> slotpos;
+    DevBuf<int> types, offsets, pcount, drop_list, jn;   // jn: compact list (S entries)
+    DevBuf<int> kept;   // kept-neighbour lists: n x kKeptFast, then n x kRecCap
     DevBuf<unsigned char> recs;
     DevBuf<double> own, planes;
     DevBuf<int> cell_of, rank, cell_count, cell_start, cell_atoms;
@@ -263,7 +263,7 @@ void tersoff_destroy(tersoff_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     c->pos_build.release(); c->types.release(); c->offsets.release(); c->jn.release();
-    c->rv.release(); c->slotpos.release(); c->own.release(); c->planes.release();
+    c->kept.release(); c->own.release(); c->planes.release();
     c->pcount.release(); c->drop_list.release(); c->recs.release();
     c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
     c->cell_atoms.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
@@ -383,6 +383,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, c->long_rows.ensure((size_t)N));
     HIP_TRY(c, c->row_count.ensure(N));
     HIP_TRY(c, c->pcount.ensure(N));
+    HIP_TRY(c, c->kept.ensure((size_t)(kKeptFast + kRecCap) * N));
     HIP_TRY(c, c->drop_list.ensure(N));
     HIP_TRY(c, c->offsets.ensure((size_t)N + 1));
     HIP_TRY(c, c->scan_tmp.ensure(std::max(scan_tmp_size((int)ncell), scan_tmp_size(N))));
@@ -445,21 +446,15 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     if ((long long)N * c->list_cap >= (1LL << 31)) return fail(c, TERSOFF_E_INVALID, "n x row capacity >= 2^31");
     const size_t NE = std::max<size_t>((size_t)c->S, 1);
     HIP_TRY(c, c->jn.ensure(NE));
-    HIP_TRY(c, c->rv.ensure(NE));
-    HIP_TRY(c, c->slotpos.ensure(NE));
     HIP_TRY(c, c->own.ensure(3 * (size_t)N));
-    HIP_TRY(c, launch_reverse_map(c->ell.p, c->list_cap, c->row_count.p, c->offsets.p, N, nullptr, c->jn.p,
-                                  c->rv.p, c->misc.p + 2, s));
+    HIP_TRY(c, launch_compact_list(c->ell.p, c->list_cap, c->row_count.p, c->offsets.p, N, nullptr, c->jn.p, s));
     HIP_TRY(c, hipMemcpyAsync(c->pos_build.p, pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s));
     HIP_TRY(c, hipMemcpyAsync(c->types.p, types, sizeof(int) * (size_t)N, hipMemcpyDeviceToDevice, s));
-    int chk = 0;
-    HIP_TRY(c, hipMemcpyAsync(&chk, c->misc.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
     if (evb1) {
         HIP_TRY(c, hipEventRecord(evb1, s));
         c->ev_build.emplace_back(evb0, evb1);
     }
     HIP_TRY(c, hipStreamSynchronize(s));
-    if (chk & 4) return fail(c, TERSOFF_E_DEVICE, "neighbour list is not symmetric");
     // the next build starts from the capacity this list needed (plus a margin)
     c->ell_cap = std::max(8, ((host[1] + 2 + 7) / 8) * 8);
 
@@ -507,7 +502,6 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     pk.row_count = c->row_count.p;
     pk.offsets = c->offsets.p;
     pk.jn = c->jn.p;
-    pk.rv = c->rv.p;
     pk.n = c->n;
     for (int d = 0; d < 3; ++d) {
         pk.L[d] = c->box[d];
@@ -515,7 +509,8 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     }
     pk.recs = c->recs.p;
     pk.pcount = c->pcount.p;
-    pk.slotpos = c->slotpos.p;
+    pk.kept = c->kept.p;
+    pk.kept_more = c->kept.p + (size_t)kKeptFast * c->n;
     pk.own = c->own.p;
     pk.flags = c->misc.p;
     pk.drop_list = c->drop_list.p;
@@ -528,7 +523,7 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     a.types = c->types.p;
     a.recs = c->recs.p;
     a.pcount = c->pcount.p;
-    a.slotpos = c->slotpos.p;
+    a.kept = c->kept.p;
     a.n = c->n;
     a.own = c->own.p;
     a.planes = c->planes.p;
@@ -548,9 +543,9 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     HIP_TRY(c, launch_compute(a, c->tab, prec, grid[1], s));
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
-    HIP_TRY(c, launch_fixup_finalize(c->offsets.p, c->jn.p, c->rv.p, c->slotpos.p, c->drop_list.p, c->misc.p + 3,
+    HIP_TRY(c, launch_fixup_finalize(c->offsets.p, c->jn.p, c->kept.p, pk.kept_more, c->drop_list.p, c->misc.p + 3,
                                      c->n, prec, c->planes.p, c->partials.p, c->counters.p, grid[1], energy_virial,
-                                     c->counts.p, s));
+                                     c->counts.p, c->misc.p, s));
     HIP_TRY(c, launch_gather_forces(c->pcount.p, prec, c->planes.p, c->own.p, c->n, nullptr, c->n, f, c->misc.p + 3, s));
     if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
     if (c->profiling) {
@@ -573,6 +568,7 @@ int tersoff_check(tersoff_ctx *c, void *stream)
     HIP_TRY(c, hipStreamSynchronize(s));
     if (flags & kFlagOverflow) return fail(c, TERSOFF_E_OVERFLOW, "an atom exceeded the per-batch neighbour capacity");
     if (flags & kFlagStale) return fail(c, TERSOFF_E_STALE, "an atom moved more than skin/2 since the last build");
+    if (flags & kFlagAsym) return fail(c, TERSOFF_E_DEVICE, "kept-neighbour sets are not symmetric");
     return TERSOFF_OK;
 }
 
