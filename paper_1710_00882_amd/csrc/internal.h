@@ -190,7 +190,8 @@ hipError_t launch_fill_zero_int(int *p, size_t count, hipStream_t s);
 
 // Neighbour build (neighbors.hip)
 hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,
-                            int *cell_of, int *rank_in_cell, int *cell_count, int *flags, hipStream_t s);
+                            int *cell_of, int *rank_in_cell, int *cell_count, int *flags, int *types_out,
+                            hipStream_t s);
 // Cell-order copies of the atoms (ids, FP64 positions, wrapped FP32
 // positions with the id in the fourth word).  Batches: dims and the
 // per-atom system set, n the capacity the grid is sized for.
@@ -201,6 +202,7 @@ struct ScatterLaunch {
     int *cell_atoms;
     double *cell_pos;
     float4 *cell_posf;
+    double *pos_copy;                // when not null: a copy of pos (atom order)
     CellGrid g;                      // one system
     const SysDesc *sys;              // batches
     const int *sys_of;
@@ -230,9 +232,10 @@ struct SearchLaunch {
 };
 hipError_t launch_search(const SearchLaunch &a, int grid_cap, hipStream_t s);
 // Compact list from the row buffer (row i at i * cap): jn[offsets[i] + q] =
-// ell[i * cap + q] for q < row_count[i].
+// ell[i * cap + q] for q < row_count[i], entries at or past jn_cap skipped;
+// *total_out = offsets[n] when total_out is not null.
 hipError_t launch_compact_list(const int *ell, int cap, const int *row_count, const int *offsets, int n,
-                               const int *n_dev, int *jn, hipStream_t s);
+                               const int *n_dev, int *jn, int jn_cap, int *total_out, hipStream_t s);
 // Batched build: binning of every system's atoms into its own cells.
 hipError_t launch_bin_systems(const double *pos, const int *sys_of, const SysDesc *sys, const BatchDims *dims,
                               int max_atoms, int *cell_of, int *rank_in_cell, int *cell_count, hipStream_t s);

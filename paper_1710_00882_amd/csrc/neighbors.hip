@@ -34,10 +34,10 @@ __device__ inline int cell_index(double x, double L, double w, int nc)
 
 // Cell of every atom (positions wrapped into the box for binning only) and
 // its rank within the cell; non-finite positions raise flag 1 and types
-// outside [0, ntypes) flag 2.
+// outside [0, ntypes) flag 2.  The types are copied to types_out.
 __global__ void k_bin(const double *__restrict__ pos, const int *__restrict__ types, int n, int ntypes,
                       CellGrid g, int *__restrict__ cell_of, int *__restrict__ rank,
-                      int *__restrict__ count, int *flags)
+                      int *__restrict__ count, int *flags, int *__restrict__ types_out)
 {
     const ItemRange r = xcd_items((n + blockDim.x - 1) / blockDim.x);
     for (int it = r.begin; it < r.end; it += r.stride) {
@@ -47,6 +47,7 @@ __global__ void k_bin(const double *__restrict__ pos, const int *__restrict__ ty
         int f = 0;
         if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) f |= 1;
         const int t = types[i];
+        types_out[i] = t;
         if (t < 0 || t >= ntypes) f |= 2;
         if (f) atomicOr(flags, f);
         int cx = cell_index(p[0], g.L[0], g.cell_w[0], g.nc[0]);
@@ -96,6 +97,11 @@ __global__ void k_scatter(ScatterLaunch a)
         const double x = a.pos[3 * (size_t)i + 0], y = a.pos[3 * (size_t)i + 1], z = a.pos[3 * (size_t)i + 2];
         const CellGrid &g = BATCHED ? a.sys[a.sys_of[i]].g : a.g;
         a.cell_atoms[slot] = i;
+        if (a.pos_copy) {
+            a.pos_copy[3 * (size_t)i + 0] = x;
+            a.pos_copy[3 * (size_t)i + 1] = y;
+            a.pos_copy[3 * (size_t)i + 2] = z;
+        }
         a.cell_pos[3 * (size_t)slot + 0] = x;
         a.cell_pos[3 * (size_t)slot + 1] = y;
         a.cell_pos[3 * (size_t)slot + 2] = z;
@@ -413,13 +419,16 @@ __global__ __launch_bounds__(kWave) void k_search_long(SearchLaunch a)
 }
 
 // Compact list: one thread per (i, q), q < cap; the entry (i, q) of the row
-// buffer (row i at i * cap) moves to jn[offsets[i] + q].  n_dev, when not
-// null, holds the atom count (batches) and n is the capacity the grid was
-// sized for.
+// buffer (row i at i * cap) moves to jn[offsets[i] + q] when that index is
+// below jn_cap (a row longer than cap was not written and is redone by the
+// caller).  n_dev, when not null, holds the atom count (batches) and n is the
+// capacity the grid was sized for.  total_out, when not null, receives the
+// list length offsets[n].
 __global__ void k_compact_list(const int *__restrict__ ell, int cap, const int *__restrict__ row_count,
                                const int *__restrict__ offsets, int n, const int *__restrict__ n_dev,
-                               int *__restrict__ jn)
+                               int *__restrict__ jn, int jn_cap, int *total_out)
 {
+    if (total_out && blockIdx.x == 0 && threadIdx.x == 0) *total_out = offsets[n];
     const unsigned total = (unsigned)(n_dev ? *n_dev : n) * (unsigned)cap;   // n * cap < 2^31
     const ItemRange r = xcd_items((int)((total + blockDim.x - 1) / blockDim.x));
     for (int it = r.begin; it < r.end; it += r.stride) {
@@ -427,7 +436,10 @@ __global__ void k_compact_list(const int *__restrict__ ell, int cap, const int *
         if (tid >= total) continue;
         const int i = (int)(tid / (unsigned)cap);
         const int q = (int)(tid - (unsigned)i * (unsigned)cap);
-        if (q < row_count[i]) jn[offsets[i] + q] = ell[tid];
+        if (q < row_count[i]) {
+            const int e = offsets[i] + q;
+            if (e < jn_cap) jn[e] = ell[tid];
+        }
     }
 }
 
@@ -547,21 +559,22 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int n, int *tmp, int *
 }
 
 hipError_t launch_compact_list(const int *ell, int cap, const int *row_count, const int *offsets, int n,
-                               const int *n_dev, int *jn, hipStream_t s)
+                               const int *n_dev, int *jn, int jn_cap, int *total_out, hipStream_t s)
 {
     const long long threads = (long long)n * cap;
     long long blocks = (threads + 255) / 256;
     if (n_dev && blocks > kBatchGrid) blocks = kBatchGrid;
     hipLaunchKernelGGL(k_compact_list, dim3((unsigned)std::max(1LL, blocks)), dim3(256), 0, s, ell, cap,
-                       row_count, offsets, n, n_dev, jn);
+                       row_count, offsets, n, n_dev, jn, jn_cap, total_out);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,
-                            int *cell_of, int *rank_in_cell, int *cell_count, int *flags, hipStream_t s)
+                            int *cell_of, int *rank_in_cell, int *cell_count, int *flags, int *types_out,
+                            hipStream_t s)
 {
     hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, pos, types, n, ntypes, g, cell_of,
-                       rank_in_cell, cell_count, flags);
+                       rank_in_cell, cell_count, flags, types_out);
     return hipGetLastError();
 }
 

@@ -345,7 +345,8 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     SRV_TRY(launch_search(sl, kBatchGrid, s));
     // compact list (counts past the batch's atoms do not enter the offsets of its atoms)
     SRV_TRY(launch_exclusive_scan(L.row_count.p, L.offsets.p, S.max_atoms, L.scan_tmp.p, nullptr, s));
-    SRV_TRY(launch_compact_list(L.ell.p, S.cap, L.row_count.p, L.offsets.p, S.max_atoms, n_dev, L.jn.p, s));
+    SRV_TRY(launch_compact_list(L.ell.p, S.cap, L.row_count.p, L.offsets.p, S.max_atoms, n_dev, L.jn.p,
+                                S.max_atoms * S.cap, nullptr, s));
 
     PackLaunch pk{};
     pk.pos = L.pos.p;

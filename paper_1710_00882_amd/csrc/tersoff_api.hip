@@ -391,11 +391,14 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, c->types.ensure(N));
 
     // misc: [0] compute flags, [1] longest row, [2] build flags, [3] dropped
-    // count, [4] rows left to the long-row search
+    // count, [4] rows left to the long-row search, [5] list length.  One
+    // host synchronisation at the end: the rows are compacted with the
+    // capacity of this attempt, and a row longer than that capacity (known
+    // only from the scan) repeats the attempt with the needed one.
     HIP_TRY(c, hipMemsetAsync(c->misc.p, 0, 8 * sizeof(int), s));
     HIP_TRY(c, hipMemsetAsync(c->cell_count.p, 0, sizeof(int) * ncell, s));
     HIP_TRY(c, launch_bin_atoms(pos, types, N, c->ntypes, g, c->cell_of.p, c->rank.p, c->cell_count.p,
-                                c->misc.p + 2, s));
+                                c->misc.p + 2, c->types.p, s));
     HIP_TRY(c, launch_exclusive_scan(c->cell_count.p, c->cell_start.p, (int)ncell, c->scan_tmp.p, nullptr, s));
     ScatterLaunch sca{};
     sca.pos = pos;
@@ -406,6 +409,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     sca.cell_atoms = c->cell_atoms.p;
     sca.cell_pos = c->cell_pos.p;
     sca.cell_posf = c->cell_posf.p;
+    sca.pos_copy = c->pos_build.p;
     sca.g = g;
     HIP_TRY(c, launch_scatter_cells(sca, 0, s));
     SearchLaunch sl{};
@@ -422,39 +426,34 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     sl.row_count = c->row_count.p;
     sl.long_rows = c->long_rows.p;
     sl.n_long = c->misc.p + 4;
-    int host[3] = {0, 0, 0};   // list length, longest row, build flags
+    HIP_TRY(c, c->own.ensure(3 * (size_t)N));
+    int host[8] = {};
     for (int attempt = 0; attempt < 2; ++attempt) {
-        HIP_TRY(c, c->ell.ensure((size_t)N * c->ell_cap));
-        HIP_TRY(c, hipMemsetAsync(c->misc.p + 4, 0, sizeof(int), s));
+        if ((long long)N * c->ell_cap >= (1LL << 31)) return fail(c, TERSOFF_E_INVALID, "n x row capacity >= 2^31");
+        const size_t cap_entries = (size_t)N * c->ell_cap;
+        HIP_TRY(c, c->ell.ensure(cap_entries));
+        HIP_TRY(c, c->jn.ensure(cap_entries));
+        if (attempt > 0) HIP_TRY(c, hipMemsetAsync(c->misc.p + 4, 0, sizeof(int), s));
         sl.cap = c->ell_cap;
         sl.ell = c->ell.p;
         HIP_TRY(c, launch_search(sl, 0, s));
         HIP_TRY(c, launch_exclusive_scan(c->row_count.p, c->offsets.p, N, c->scan_tmp.p, c->misc.p + 1, s));
-        HIP_TRY(c, hipMemcpyAsync(&host[0], c->offsets.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipMemcpyAsync(&host[1], c->misc.p + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, launch_compact_list(c->ell.p, c->ell_cap, c->row_count.p, c->offsets.p, N, nullptr, c->jn.p,
+                                       (int)cap_entries, c->misc.p + 5, s));
+        HIP_TRY(c, hipMemcpyAsync(host, c->misc.p, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+        if (evb1) HIP_TRY(c, hipEventRecord(evb1, s));
         HIP_TRY(c, hipStreamSynchronize(s));
         if (host[2] & 1) return fail(c, TERSOFF_E_INVALID, "non-finite position");
         if (host[2] & 2) return fail(c, TERSOFF_E_INVALID, "type out of range");
         if (host[1] <= c->ell_cap) break;
         if (host[1] > kMaxRow) return fail(c, TERSOFF_E_OVERFLOW, "an atom has more than 256 neighbours in range");
-        c->ell_cap = ((host[1] + 7) / 8) * 8;   // retry once with the needed capacity
+        c->ell_cap = ((host[1] + 7) / 8) * 8;   // repeat once with the needed capacity
     }
+    if (evb1) c->ev_build.emplace_back(evb0, evb1);
     if (host[1] > c->ell_cap) return fail(c, TERSOFF_E_OVERFLOW, "row capacity retry failed");
     c->list_cap = c->ell_cap;
-    if (host[0] < 0) return fail(c, TERSOFF_E_INVALID, "list longer than 2^31 entries");
-    c->S = host[0];
-    if ((long long)N * c->list_cap >= (1LL << 31)) return fail(c, TERSOFF_E_INVALID, "n x row capacity >= 2^31");
-    const size_t NE = std::max<size_t>((size_t)c->S, 1);
-    HIP_TRY(c, c->jn.ensure(NE));
-    HIP_TRY(c, c->own.ensure(3 * (size_t)N));
-    HIP_TRY(c, launch_compact_list(c->ell.p, c->list_cap, c->row_count.p, c->offsets.p, N, nullptr, c->jn.p, s));
-    HIP_TRY(c, hipMemcpyAsync(c->pos_build.p, pos, sizeof(double) * 3 * (size_t)N, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(c, hipMemcpyAsync(c->types.p, types, sizeof(int) * (size_t)N, hipMemcpyDeviceToDevice, s));
-    if (evb1) {
-        HIP_TRY(c, hipEventRecord(evb1, s));
-        c->ev_build.emplace_back(evb0, evb1);
-    }
-    HIP_TRY(c, hipStreamSynchronize(s));
+    if (host[5] < 0) return fail(c, TERSOFF_E_INVALID, "list longer than 2^31 entries");
+    c->S = host[5];
     // the next build starts from the capacity this list needed (plus a margin)
     c->ell_cap = std::max(8, ((host[1] + 2 + 7) / 8) * 8);
 
