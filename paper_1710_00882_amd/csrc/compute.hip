@@ -166,30 +166,37 @@ __device__ __forceinline__ void cutoff_terms(const ParamR<real> &q, real r, real
 // -------------------------------------------------------- packed records -
 
 // One packed neighbour n of a centre atom i (an in-range entry of i's list,
-// Section 3): the neighbour index, the membership bits of the exact FP64 cutoff tests, and the minimum-image
-// displacement in the working precision (distance and unit vector are
-// formed from it by the compute kernel).  The records of a batch of B consecutive
-// centre atoms are stored contiguously, atom by atom, in the batch's region
-// of B * kRecCap records, so both the packing writes and the compute reads
-// are contiguous across lanes.
+// Section 3): one word with the neighbour index, its type and the
+// membership bits of the exact FP64 cutoff tests, and the minimum-image
+// displacement in the working precision (distance and unit vector are formed
+// from it by the compute kernel) -- 16 bytes (one vector load) for the
+// single-precision displacement, 32 for FP64.  The records of a batch of B
+// consecutive centre atoms are stored contiguously, atom by atom, in the
+// batch's region of B * kRecCap records, so both the packing writes and the
+// compute reads are contiguous across lanes.
 template <typename real>
 struct Rec;
 template <>
-struct alignas(8) Rec<float> {
-    int j, spare, mask;
+struct alignas(16) Rec<float> {
+    int jm;
     float dx, dy, dz;
 };
 template <>
-struct alignas(8) Rec<double> {
-    int j, spare, mask, pad;
+struct alignas(16) Rec<double> {
+    int jm, pad;
     double dx, dy, dz;
 };
 
-// mask: bits 0-7 type of n; bit 8: r_in < cutoff of entry (t_i, t_n, t_n)
-// (n is a bond partner); bit 9 + t: r_in < cutoff of entry (t_i, t, t_n)
-// (n is a third atom for a partner of type t).
-constexpr int kPairBit = 8;
-constexpr int kThirdBit = 9;
+// jm: bits 0-23 index of n (at most 2^24 atoms); bits 24-25 type of n;
+// bit 26: r_in < cutoff of entry (t_i, t_n, t_n) (n is a bond partner);
+// bit 27 + t: r_in < cutoff of entry (t_i, t, t_n) (n is a third atom for a
+// partner of type t).
+constexpr int kIdMask = (1 << 24) - 1;
+constexpr int kTypeShift = 24;
+constexpr int kPairBit = 26;
+constexpr int kThirdBit = 27;
+static_assert(kMaxTypes <= 4, "two type bits and four third-atom bits per record");
+__device__ __forceinline__ int rec_type(int jm) { return (jm >> kTypeShift) & 3; }
 
 constexpr int kChunks = 4;     // 64-entry chunks whose loads are issued together
 static_assert(kKeptFast == 8, "the first block of a kept list is two 16-byte words");
@@ -369,9 +376,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                         if (k < kKeptFast) kst[k][al] = jv[c];
                         else a.kept_more[(size_t)(a0 + al) * kRecCap + k] = jv[c];
                         Rec<real> o;
-                        o.j = jv[c];
-                        o.spare = 0;
-                        int mask = tv[c];
+                        int mask = jv[c] | (tv[c] << kTypeShift);
                         if (ONE) {
                             mask |= (1 << kPairBit) | (1 << kThirdBit);
                         } else {
@@ -380,7 +385,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                             for (int t = 0; t < nt; ++t)
                                 if (rsq < tab.px[(t_i * nt + t) * nt + t_n].cutsq) mask |= 1 << (kThirdBit + t);
                         }
-                        o.mask = mask;
+                        o.jm = mask;
                         o.dx = (real)dx;
                         o.dy = (real)dy;
                         o.dz = (real)dz;
@@ -563,11 +568,11 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 pc = sh.pcnt[al];
                 ti = ONE ? 0 : sh.ti[al];
                 const Rec<real> rc = region[s];
-                j = rc.j;
+                j = rc.jm & kIdMask;
                 bool ended;
                 kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, ended);
                 asym |= kpos < 0 && ended;
-                mj = rc.mask;
+                mj = rc.jm;
                 dj[0] = rc.dx; dj[1] = rc.dy; dj[2] = rc.dz;
                 rj = M<real>::sqrt(norm2r(dj[0], dj[1], dj[2]));
                 rjinv = M<real>::rcp(rj);
@@ -578,7 +583,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 for (int t = 0; t < nt; ++t) {
                     real fc = real(0), dfc = real(0);
                     if ((mj >> (kThirdBit + t)) & 1)
-                        cutoff_terms(ONE ? q0 : ptab[(ti * nt + t) * nt + (mj & 0xff)], rj, fc, dfc);
+                        cutoff_terms(ONE ? q0 : ptab[(ti * nt + t) * nt + rec_type(mj)], rj, fc, dfc);
                     sh.fc[t][s] = fc;
                     sh.dfc[t][s] = dfc;
                 }
@@ -599,7 +604,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 }
             };
 
-            const int tj = mj & 0xff;
+            const int tj = rec_type(mj);
             const bool j_pair = (mj >> kPairBit) & 1;
             facc fx = 0, fy = 0, fz = 0;       // force on j from centre i's terms
             double e_pair = 0.0;   // energy of pair (i, j)
@@ -611,7 +616,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                     for (int kk = 0; kk + 1 < pc; ++kk) {
                         const int sk = sb + kk + (kk >= jl ? 1 : 0);
                         const int mk = ONE ? 0 : sh.mask[sk];
-                        const ParamR<real> &q = ONE ? q0 : ptab[(ti * nt + tj) * nt + (mk & 0xff)];
+                        const ParamR<real> &q = ONE ? q0 : ptab[(ti * nt + tj) * nt + rec_type(mk)];
                         const real rk = sh.r[sk];
                         const real cs = uj[0] * sh.ux[sk] + uj[1] * sh.uy[sk] + uj[2] * sh.uz[sk];
                         real ex, dex;
@@ -702,7 +707,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                         cu = an.g * (w1 * dex1 + dzk * (dfcj0 * ex2 - fcj0 * dex2));
                     } else {
                         const int mk = sh.mask[sk];
-                        const int tk = mk & 0xff;
+                        const int tk = rec_type(mk);
                         cdc = real(0);
                         cu = real(0);
                         if (((mk >> (kThirdBit + tj)) & 1) && dzj != real(0)) {
