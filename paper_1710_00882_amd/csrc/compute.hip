@@ -302,8 +302,6 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 if (!(dx * dx + dy * dy + dz * dz <= a.stale_sq)) atomicOr(a.flags, kFlagStale);
             }
         }
-        // the batch's rows are one contiguous segment of the compact list
-        const int ebase = a.offsets[a0];
         {
             // local entry offsets of the batch's rows
             const int rc = lane < nb ? a.row_count[a0 + lane] : 0;
@@ -327,8 +325,8 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 if (e < e_end) {
                     const int al = find_seg(eoff, nb, e);
                     alv[c] = al;
-                    ev[c] = ebase + e;   // list index of the entry
-                    jv[c] = a.jn[ev[c]];
+                    ev[c] = (a0 + al) * a.cap + (e - eoff[al]);   // row-buffer index of the entry
+                    jv[c] = a.ell[ev[c]];
                 }
             }
 #pragma unroll
@@ -809,7 +807,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
 // from them.  Workgroups loop until the list is
 // drained.
 template <typename T>
-__global__ void k_fixup_dropped(const int *__restrict__ offsets, const int *__restrict__ jn,
+__global__ void k_fixup_dropped(const int *__restrict__ ell, int cap, const int *__restrict__ row_count,
                                 const int *__restrict__ kept, const int *__restrict__ kept_more,
                                 const int *__restrict__ drop_list, const int *__restrict__ drop_count,
                                 int plane_stride, T *__restrict__ planes)
@@ -817,9 +815,9 @@ __global__ void k_fixup_dropped(const int *__restrict__ offsets, const int *__re
     const int nd = *drop_count;
     for (int q = blockIdx.x; q < nd; q += gridDim.x) {
         const int m = drop_list[q];
-        const int e0 = offsets[m], e1 = offsets[m + 1];
-        for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
-            const int nb = jn[e];
+        const int rc = row_count[m];
+        for (int q = (int)threadIdx.x; q < rc; q += blockDim.x) {
+            const int nb = ell[(size_t)m * cap + q];
             bool ended;
             const int k = kept_position(kept, kept_more, nb, m, ended);   // plane nb reserved for m
             if (k >= 0) {
@@ -870,7 +868,7 @@ __device__ void finalize_sums(const double *__restrict__ partials, const long lo
 // After the compute kernel, in one launch: the last workgroup sums the
 // partials, the others run the dropped-atom fixup.
 template <typename T>
-__global__ void k_fixup_finalize(const int *__restrict__ offsets, const int *__restrict__ jn,
+__global__ void k_fixup_finalize(const int *__restrict__ ell, int cap, const int *__restrict__ row_count,
                                  const int *__restrict__ kept, const int *__restrict__ kept_more,
                                  const int *__restrict__ drop_list, const int *__restrict__ drop_count,
                                  int plane_stride, T *__restrict__ planes, const double *__restrict__ partials,
@@ -884,9 +882,9 @@ __global__ void k_fixup_finalize(const int *__restrict__ offsets, const int *__r
     const int nd = *drop_count;
     for (int q = blockIdx.x; q < nd; q += gridDim.x - 1) {
         const int m = drop_list[q];
-        const int e0 = offsets[m], e1 = offsets[m + 1];
-        for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
-            const int nb = jn[e];
+        const int rc = row_count[m];
+        for (int q = (int)threadIdx.x; q < rc; q += blockDim.x) {
+            const int nb = ell[(size_t)m * cap + q];
             bool ended;
             const int k = kept_position(kept, kept_more, nb, m, ended);   // plane nb reserved for m
             if (k >= 0) {
@@ -1063,32 +1061,34 @@ hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec
     return hipGetLastError();
 }
 
-hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *kept, const int *kept_more,
-                                const int *drop_list, const int *drop_count, int plane_stride, int prec,
-                                void *planes, hipStream_t s)
+hipError_t launch_fixup_dropped(const int *ell, int cap, const int *row_count, const int *kept,
+                                const int *kept_more, const int *drop_list, const int *drop_count,
+                                int plane_stride, int prec, void *planes, hipStream_t s)
 {
     if (prec != kPrecFP64)
-        hipLaunchKernelGGL(k_fixup_dropped<float>, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jn, kept, kept_more,
-                           drop_list, drop_count, plane_stride, static_cast<float *>(planes));
+        hipLaunchKernelGGL(k_fixup_dropped<float>, dim3(kBigGrid), dim3(kWave), 0, s, ell, cap, row_count, kept,
+                           kept_more, drop_list, drop_count, plane_stride, static_cast<float *>(planes));
     else
-        hipLaunchKernelGGL(k_fixup_dropped<double>, dim3(kBigGrid), dim3(kWave), 0, s, offsets, jn, kept, kept_more,
-                           drop_list, drop_count, plane_stride, static_cast<double *>(planes));
+        hipLaunchKernelGGL(k_fixup_dropped<double>, dim3(kBigGrid), dim3(kWave), 0, s, ell, cap, row_count, kept,
+                           kept_more, drop_list, drop_count, plane_stride, static_cast<double *>(planes));
     return hipGetLastError();
 }
 
-hipError_t launch_fixup_finalize(const int *offsets, const int *jn, const int *kept, const int *kept_more,
-                                 const int *drop_list, const int *drop_count, int plane_stride, int prec,
-                                 void *planes, const double *partials, const long long *counters, int grid,
-                                 double *out7, long long *counts_out, int *flags, hipStream_t s)
+hipError_t launch_fixup_finalize(const int *ell, int cap, const int *row_count, const int *kept,
+                                 const int *kept_more, const int *drop_list, const int *drop_count,
+                                 int plane_stride, int prec, void *planes, const double *partials,
+                                 const long long *counters, int grid, double *out7, long long *counts_out,
+                                 int *flags, hipStream_t s)
 {
+    const dim3 G(kBigGrid + 1), W(256);
     if (prec != kPrecFP64)
-        hipLaunchKernelGGL(k_fixup_finalize<float>, dim3(kBigGrid + 1), dim3(256), 0, s, offsets, jn, kept, kept_more,
-                           drop_list, drop_count, plane_stride, static_cast<float *>(planes), partials, counters,
-                           grid, out7, counts_out, flags);
+        hipLaunchKernelGGL(k_fixup_finalize<float>, G, W, 0, s, ell, cap, row_count, kept, kept_more, drop_list,
+                           drop_count, plane_stride, static_cast<float *>(planes), partials, counters, grid, out7,
+                           counts_out, flags);
     else
-        hipLaunchKernelGGL(k_fixup_finalize<double>, dim3(kBigGrid + 1), dim3(256), 0, s, offsets, jn, kept, kept_more,
-                           drop_list, drop_count, plane_stride, static_cast<double *>(planes), partials, counters,
-                           grid, out7, counts_out, flags);
+        hipLaunchKernelGGL(k_fixup_finalize<double>, G, W, 0, s, ell, cap, row_count, kept, kept_more, drop_list,
+                           drop_count, plane_stride, static_cast<double *>(planes), partials, counters, grid, out7,
+                           counts_out, flags);
     return hipGetLastError();
 }
 

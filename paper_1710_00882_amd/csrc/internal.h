@@ -114,8 +114,8 @@ struct PackLaunch {
     const double *pos;          // n x 3
     const int *types;           // n
     const int *row_count;       // n: list length of each atom
-    const int *offsets;         // n + 1: first list entry of each atom (compact list)
-    const int *jn;              // list entries: sorted neighbour rows, row i at offsets[i]
+    const int *ell;             // neighbour rows (sorted), row i at i * cap, row_count[i] entries
+    int cap;                    // row stride
     int n;
     double L[3], invL[3];
     void *recs;                 // packed records: region of B * kRecCap per batch of B atoms
@@ -165,15 +165,16 @@ hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, int prec, int 
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec,
                           int grid, hipStream_t s);
 // Force planes hold float for the mixed and single paths, double for FP64.
-hipError_t launch_fixup_dropped(const int *offsets, const int *jn, const int *kept, const int *kept_more,
-                                const int *drop_list, const int *drop_count, int plane_stride, int prec,
-                                void *planes, hipStream_t s);
+hipError_t launch_fixup_dropped(const int *ell, int cap, const int *row_count, const int *kept,
+                                const int *kept_more, const int *drop_list, const int *drop_count,
+                                int plane_stride, int prec, void *planes, hipStream_t s);
 // Dropped-atom fixup and the sum of the compute kernel's partials into out7 /
 // counts_out, in one launch; *flags |= kFlagAsym when a partial carries it.
-hipError_t launch_fixup_finalize(const int *offsets, const int *jn, const int *kept, const int *kept_more,
-                                 const int *drop_list, const int *drop_count, int plane_stride, int prec,
-                                 void *planes, const double *partials, const long long *counters, int grid,
-                                 double *out7, long long *counts_out, int *flags, hipStream_t s);
+hipError_t launch_fixup_finalize(const int *ell, int cap, const int *row_count, const int *kept,
+                                 const int *kept_more, const int *drop_list, const int *drop_count,
+                                 int plane_stride, int prec, void *planes, const double *partials,
+                                 const long long *counters, int grid, double *out7, long long *counts_out,
+                                 int *flags, hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
 // drop_count, when not null, is reset to 0 (the dropped-atom list is empty
 // for the next evaluation).

@@ -16,7 +16,7 @@
 // the host-to-device copies of the inputs and descriptors before it and the
 // copies of the results after it.  Graph contents: clear counters -> bin every
 // configuration's atoms into its own cells -> scan -> scatter -> neighbour
-// search over all configurations -> list compaction -> pack -> energy / force /
+// search over all configurations (rows at a fixed stride) -> pack -> energy / force /
 // virial kernel (per-atom energy and virial) -> dropped-atom fixup -> force
 // gather -> per-configuration reduction.  A configuration's result does not
 // depend on the other configurations of its batch or on its place in it.
@@ -168,7 +168,7 @@ struct Lane {
     Dev<float4> cell_posf;
     Dev<int> long_rows;
     Dev<int> types, sys_of, cell_of, rank, cell_count, cell_start, cell_atoms, scan_tmp;
-    Dev<int> ell, row_count, offsets, jn, pcount, drop_list;   // jn: compact list
+    Dev<int> ell, row_count, pcount, drop_list;   // ell: neighbour rows, row i at i * cap
     Dev<int> kept;   // kept-neighbour lists: A x kKeptFast, then A x kRecCap
     Dev<int> ctl;   // [0] flags, [1] dropped count, [2] long rows, [3 ..] per-system status
     Dev<unsigned char> recs;
@@ -264,8 +264,6 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.scan_tmp.alloc(std::max(scan_tmp_size((int)NC), scan_tmp_size((int)A)), tot));
     SRV_TRY(L.ell.alloc(E, tot));
     SRV_TRY(L.row_count.alloc(A, tot));
-    SRV_TRY(L.offsets.alloc(A + 1, tot));
-    SRV_TRY(L.jn.alloc(E, tot));
     SRV_TRY(L.kept.alloc((size_t)(kKeptFast + kRecCap) * A, tot));
     SRV_TRY(L.pcount.alloc(A, tot));
     SRV_TRY(L.drop_list.alloc(A, tot));
@@ -292,7 +290,6 @@ void free_lane(Lane &L)
     L.rank.release(); L.cell_count.release(); L.cell_start.release(); L.cell_atoms.release();
     L.scan_tmp.release(); L.ell.release(); L.row_count.release(); L.kept.release();
     L.pcount.release();
-    L.offsets.release(); L.jn.release();
     L.drop_list.release(); L.ctl.release(); L.recs.release(); L.desc.release();
     L.dims.release();
     if (L.done) (void)hipEventDestroy(L.done), L.done = nullptr;
@@ -343,17 +340,13 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     sl.n_long = L.ctl.p + 2;
     sl.sys_status = L.ctl.p + 3;
     SRV_TRY(launch_search(sl, kBatchGrid, s));
-    // compact list (counts past the batch's atoms do not enter the offsets of its atoms)
-    SRV_TRY(launch_exclusive_scan(L.row_count.p, L.offsets.p, S.max_atoms, L.scan_tmp.p, nullptr, s));
-    SRV_TRY(launch_compact_list(L.ell.p, S.cap, L.row_count.p, L.offsets.p, S.max_atoms, n_dev, L.jn.p,
-                                S.max_atoms * S.cap, nullptr, s));
 
     PackLaunch pk{};
     pk.pos = L.pos.p;
     pk.types = L.types.p;
     pk.row_count = L.row_count.p;
-    pk.offsets = L.offsets.p;
-    pk.jn = L.jn.p;
+    pk.ell = L.ell.p;
+    pk.cap = S.cap;
     pk.n = S.max_atoms;
     pk.recs = L.recs.p;
     pk.pcount = L.pcount.p;
@@ -384,8 +377,8 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     a.n_dev = n_dev;
     a.eatom = L.eatom.p;
     SRV_TRY(launch_compute(a, S.env.tab, prec, S.grids[prec][1], s));
-    SRV_TRY(launch_fixup_dropped(L.offsets.p, L.jn.p, L.kept.p, pk.kept_more, L.drop_list.p, L.ctl.p + 1,
-                                 S.max_atoms, prec, L.planes.p, s));
+    SRV_TRY(launch_fixup_dropped(L.ell.p, S.cap, L.row_count.p, L.kept.p, pk.kept_more, L.drop_list.p,
+                                 L.ctl.p + 1, S.max_atoms, prec, L.planes.p, s));
     SRV_TRY(launch_gather_forces(L.pcount.p, prec, L.planes.p, L.own.p, S.max_atoms, n_dev, S.max_atoms, L.forces.p,
                                  nullptr, s));
     SRV_TRY(launch_reduce_systems(L.desc.p, L.dims.p, S.max_sys, L.eatom.p, L.drop_list.p, L.ctl.p + 1,

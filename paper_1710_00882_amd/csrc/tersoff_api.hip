@@ -391,10 +391,11 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, c->types.ensure(N));
 
     // misc: [0] compute flags, [1] longest row, [2] build flags, [3] dropped
-    // count, [4] rows left to the long-row search, [5] list length.  One
-    // host synchronisation at the end: the rows are compacted with the
-    // capacity of this attempt, and a row longer than that capacity (known
-    // only from the scan) repeats the attempt with the needed one.
+    // count, [4] rows left to the long-row search.  One host
+    // synchronisation at the end: a row longer than the capacity of the
+    // attempt (known only from the scan) repeats it with the needed one.
+    // The evaluation reads the row buffer itself (row i at i * cap); the
+    // compact list is formed only when asked for (tersoff_get_neighbors).
     HIP_TRY(c, hipMemsetAsync(c->misc.p, 0, 8 * sizeof(int), s));
     HIP_TRY(c, hipMemsetAsync(c->cell_count.p, 0, sizeof(int) * ncell, s));
     HIP_TRY(c, launch_bin_atoms(pos, types, N, c->ntypes, g, c->cell_of.p, c->rank.p, c->cell_count.p,
@@ -432,15 +433,13 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
         if ((long long)N * c->ell_cap >= (1LL << 31)) return fail(c, TERSOFF_E_INVALID, "n x row capacity >= 2^31");
         const size_t cap_entries = (size_t)N * c->ell_cap;
         HIP_TRY(c, c->ell.ensure(cap_entries));
-        HIP_TRY(c, c->jn.ensure(cap_entries));
         if (attempt > 0) HIP_TRY(c, hipMemsetAsync(c->misc.p + 4, 0, sizeof(int), s));
         sl.cap = c->ell_cap;
         sl.ell = c->ell.p;
         HIP_TRY(c, launch_search(sl, 0, s));
         HIP_TRY(c, launch_exclusive_scan(c->row_count.p, c->offsets.p, N, c->scan_tmp.p, c->misc.p + 1, s));
-        HIP_TRY(c, launch_compact_list(c->ell.p, c->ell_cap, c->row_count.p, c->offsets.p, N, nullptr, c->jn.p,
-                                       (int)cap_entries, c->misc.p + 5, s));
         HIP_TRY(c, hipMemcpyAsync(host, c->misc.p, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(&host[5], c->offsets.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
         if (evb1) HIP_TRY(c, hipEventRecord(evb1, s));
         HIP_TRY(c, hipStreamSynchronize(s));
         if (host[2] & 1) return fail(c, TERSOFF_E_INVALID, "non-finite position");
@@ -499,8 +498,8 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     pk.pos = pos;
     pk.types = c->types.p;
     pk.row_count = c->row_count.p;
-    pk.offsets = c->offsets.p;
-    pk.jn = c->jn.p;
+    pk.ell = c->ell.p;
+    pk.cap = c->list_cap;
     pk.n = c->n;
     for (int d = 0; d < 3; ++d) {
         pk.L[d] = c->box[d];
@@ -542,7 +541,7 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     HIP_TRY(c, launch_compute(a, c->tab, prec, grid[1], s));
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
-    HIP_TRY(c, launch_fixup_finalize(c->offsets.p, c->jn.p, c->kept.p, pk.kept_more, c->drop_list.p, c->misc.p + 3,
+    HIP_TRY(c, launch_fixup_finalize(c->ell.p, c->list_cap, c->row_count.p, c->kept.p, pk.kept_more, c->drop_list.p, c->misc.p + 3,
                                      c->n, prec, c->planes.p, c->partials.p, c->counters.p, grid[1], energy_virial,
                                      c->counts.p, c->misc.p, s));
     HIP_TRY(c, launch_gather_forces(c->pcount.p, prec, c->planes.p, c->own.p, c->n, nullptr, c->n, f, c->misc.p + 3, s));
@@ -583,7 +582,12 @@ int tersoff_get_neighbors(tersoff_ctx *c, int64_t *offsets, int32_t *idx, int64_
     for (size_t i = 0; i < off.size(); ++i) offsets[i] = off[i];
     *total = c->S;
     if (cap < c->S || (!idx && c->S > 0)) return fail(c, TERSOFF_E_INVALID, "idx capacity below list length");
-    if (c->S > 0) HIP_TRY(c, hipMemcpy(idx, c->jn.p, sizeof(int) * (size_t)c->S, hipMemcpyDeviceToHost));
+    if (c->S > 0) {
+        HIP_TRY(c, c->jn.ensure((size_t)c->S));
+        HIP_TRY(c, launch_compact_list(c->ell.p, c->list_cap, c->row_count.p, c->offsets.p, c->n, nullptr, c->jn.p,
+                                       c->S, nullptr, nullptr));
+        HIP_TRY(c, hipMemcpy(idx, c->jn.p, sizeof(int) * (size_t)c->S, hipMemcpyDeviceToHost));
+    }
     return TERSOFF_OK;
 }
 
