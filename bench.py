@@ -47,12 +47,13 @@ FLOPS_PER_PAIR = 61       # r, u, f_C, f_R, f_A, b_ij (log form), energy, pair f
 FLOPS_PER_TRIPLET = 100   # cos, g, g', zeta term, both gradients, dV/dzeta * gradients
 
 # Algorithmic (compulsory) HBM bytes of the packing kernel: per list entry
-# the neighbour index, the reverse entry and the rank byte written (4 + 4 + 1);
-# per atom its position, type, row length and record count (24 + 4 + 4 + 4),
-# each read or written once; per kept record 24 B (mixed, single) or 40 B (FP64).
-PACK_BYTES_PER_ENTRY = 9
-PACK_BYTES_PER_ATOM = 36
-RECORD_BYTES = {"mixed": 24, "single": 24, "fp64": 40}
+# the neighbour index (4); per atom its position and its position at the last
+# build (24 + 24), row length and record count (4 + 4) and the first block of
+# its kept-neighbour list (32), each read or written once; per kept record
+# 16 B (mixed, single) or 32 B (FP64).
+PACK_BYTES_PER_ENTRY = 4
+PACK_BYTES_PER_ATOM = 88
+RECORD_BYTES = {"mixed": 16, "single": 16, "fp64": 32}
 
 # HBM traffic of the mixed compute kernel on the 2,048,000-atom workload from
 # two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch),
@@ -60,10 +61,10 @@ RECORD_BYTES = {"mixed": 24, "single": 24, "fp64": 40}
 # reads 0.5 of the bytes a copy moves, WRITE_SIZE 1.0).  Valid only for the
 # compute source it was measured on (its SHA-256 prefix).
 TRAFFIC_PROFILE = {
-    "source": "4f570b75551f9668",
-    "fetch_kib": 145627.4, "fetch_factor": 2.0,
-    "write_kib": 302388.5, "write_factor": 1.0,
-    "bytes_per_launch": 145627.4 * 1024 * 2.0 + 302388.5 * 1024 * 1.0,
+    "source": "3efc92ea96a12bf6",
+    "fetch_kib": 123771.1, "fetch_factor": 2.0,
+    "write_kib": 223983.1, "write_factor": 1.0,
+    "bytes_per_launch": 123771.1 * 1024 * 2.0 + 223983.1 * 1024 * 1.0,
 }
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1710_00882_amd", "csrc", "compute.hip")
 

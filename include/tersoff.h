@@ -126,8 +126,10 @@ int tersoff_compute(tersoff_ctx *ctx, const double *pos, int32_t precision,
 
 /* Synchronise `stream` and report the device-side status of every compute
  * since the previous check: OK, E_OVERFLOW (an atom exceeded the per-batch
- * neighbour capacity; its terms were skipped) or E_STALE (an atom moved more
- * than skin/2 from its position at the last build).  Clears the flags. */
+ * neighbour capacity; its terms were skipped), E_STALE (an atom moved more
+ * than skin/2 from its position at the last build) or E_DEVICE (a centre
+ * kept a neighbour that did not keep it back -- an internal invariant, not
+ * an input condition).  Clears the flags. */
 int tersoff_check(tersoff_ctx *ctx, void *stream);
 
 /* Copy the resident neighbour list to host memory (synchronises).
