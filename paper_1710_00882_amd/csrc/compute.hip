@@ -12,7 +12,8 @@
 //               keeps m, stored in the force plane m reserved for i).
 //
 // `real` is float for the mixed path and double for the all-FP64 path; the
-// displacement, the zeta -> b power and every accumulation are FP64 in both.
+// displacement, the zeta -> b power (in the mixed path through the short
+// FP64 log and exp of bond_order_f64) and every accumulation are FP64 in both.
 // Each pair's force term on its neighbour is stored in the working precision
 // (float planes for the mixed path) and summed per atom in FP64.
 #include "internal.h"
@@ -61,6 +62,90 @@ __device__ __forceinline__ double norm2(double dx, double dy, double dz)
 {
 #pragma clang fp contract(off)
     return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
+// ---- FP64 logarithm and exponential of the zeta -> b power (Eq. 2) ----
+//
+// ln 2 split into a head with 21 significant bits (so k * head is exact for
+// |k| < 2^11) and the rest.
+constexpr double kLn2Hi = 0x1.62e42p-1;
+constexpr double kLn2Lo = 0x1.fdf473de6af28p-22;
+constexpr double kLog2e = 1.4426950408889634;
+
+// 1/d in FP64: the hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double recip_f64(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return fma(fma(-d, r, 1.0), r, r);
+}
+
+// Natural logarithm of y > 0 (+inf and NaN pass through): y = 2^e m with m in
+// [1/sqrt 2, sqrt 2), ln m = 2 atanh(s), s = (m - 1) / (m + 1), |s| < 0.172,
+// summed as 2 s sum_{k <= 8} s^(2k) / (2k + 1) (the first omitted term is
+// below 1e-15 relative), plus e ln 2 in two parts.
+__device__ __forceinline__ double ln_f64(double y)
+{
+    if (!(y < INFINITY)) return y;
+    double m = __builtin_amdgcn_frexp_mant(y);   // [1/2, 1)
+    int e = __builtin_amdgcn_frexp_exp(y);
+    if (m < 0.7071067811865476) {
+        m += m;
+        e -= 1;
+    }
+    const double f = m - 1.0;                    // exact
+    const double s = f * recip_f64(2.0 + f);
+    const double s2 = s * s;
+    double p = 1.0 / 17.0;
+    p = fma(p, s2, 1.0 / 15.0);
+    p = fma(p, s2, 1.0 / 13.0);
+    p = fma(p, s2, 1.0 / 11.0);
+    p = fma(p, s2, 1.0 / 9.0);
+    p = fma(p, s2, 1.0 / 7.0);
+    p = fma(p, s2, 1.0 / 5.0);
+    p = fma(p, s2, 1.0 / 3.0);
+    const double t = s + s;
+    const double lnm = fma(t, s2 * p, t);
+    const double de = (double)e;
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, lnm));
+}
+
+// e^t: t = k ln 2 + r with k = rint(t / ln 2), |r| <= ln 2 / 2, e^r from its
+// Taylor series through r^12 (truncation below 2e-16 relative), scaled by
+// 2^k.  t is clamped to [-760, 760], beyond which the result is 0 or +inf.
+__device__ __forceinline__ double exp_f64(double t)
+{
+    t = fmin(fmax(t, -760.0), 760.0);
+    const double kf = rint(t * kLog2e);
+    double r = fma(-kf, kLn2Hi, t);
+    r = fma(-kf, kLn2Lo, r);
+    double p = 1.0 / 479001600.0;               // 1/12!
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(p, (int)kf);
+}
+
+// b(zeta) and db/dzeta of Eq. (2) in log form, zeta > 0 (mixed path; about a
+// third of the instructions of the library functions, relative error of b a
+// few 1e-16):
+// x = exp(eta (ln beta + ln zeta)), b = exp(-ln(1 + x) / (2 eta)),
+// db/dzeta = -(1/2) b x / (zeta (1 + x)).
+__device__ __forceinline__ void bond_order_f64(const ParamX &px, double zeta, double &b, double &db)
+{
+    const double x = exp_f64(px.eta * (px.logbeta + ln_f64(zeta)));
+    const double y = 1.0 + x;
+    b = exp_f64(-ln_f64(y) * px.inv2eta);
+    db = -0.5 * b * x * recip_f64(zeta * y);
 }
 
 // r^2 of a packed displacement in the working precision (the FP64 form is
@@ -658,9 +743,14 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                         const double zeta = (double)zr;
                         double b = 1.0, db = 0.0;
                         if (zeta > 0.0) {
-                            const double x = ::exp(px.eta * (px.logbeta + ::log(zeta)));
-                            b = ::exp(-::log1p(x) * px.inv2eta);
-                            db = -0.5 * b * x / (zeta * (1.0 + x));
+                            if constexpr (sizeof(real) == 4) {
+                                bond_order_f64(px, zeta, b, db);
+                            } else {
+                                // the all-FP64 path keeps the library's exp / log / log1p
+                                const double x = ::exp(px.eta * (px.logbeta + ::log(zeta)));
+                                b = ::exp(-::log1p(x) * px.inv2eta);
+                                db = -0.5 * b * x / (zeta * (1.0 + x));
+                            }
                         }
                         br = (real)b;
                         e_pair = 0.5 * (double)fc * ((double)fr + b * (double)fa);
@@ -767,8 +857,10 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 if constexpr (BATCHED) {
                     double v[7] = {0, 0, 0, 0, 0, 0, 0};
                     for (int q = s0; q < s1; ++q)
+                        #pragma unroll
                         for (int c = 0; c < 7; ++c) v[c] += sev[q][c];
                     double *ea = a.eatom + 8 * (size_t)(a0 + lane);
+                    #pragma unroll
                     for (int c = 0; c < 7; ++c) ea[c] = v[c];
                     ea[7] = 0.0;
                 }
@@ -831,7 +923,7 @@ __global__ void k_fixup_dropped(const int *__restrict__ ell, int cap, const int 
 // Sums the per-workgroup partials of the compute kernel (one workgroup of
 // 256 threads, fixed summation order) and raises kFlagAsym if a workgroup
 // reported it.
-__device__ void finalize_sums(const double *__restrict__ partials, const long long *__restrict__ counters,
+__device__ __forceinline__ void finalize_sums(const double *__restrict__ partials, const long long *__restrict__ counters,
                               int grid, double *__restrict__ out, long long *__restrict__ counts, int *flags)
 {
     __shared__ double sh[8][256];
@@ -839,19 +931,38 @@ __device__ void finalize_sums(const double *__restrict__ partials, const long lo
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     long long c0 = 0, c1 = 0;
     bool asym = false;
-    for (int b = threadIdx.x; b < grid; b += blockDim.x) {
-        for (int c = 0; c < 7; ++c) v[c] += partials[8 * (size_t)b + c];
-        asym |= partials[8 * (size_t)b + 7] != 0.0;
-        c0 += counters[2 * (size_t)b];
-        c1 += counters[2 * (size_t)b + 1];
+    // rows b = t, t + 256, ... in order; the loads of four rows are issued
+    // before their sums so the loop is not one memory latency per row
+    constexpr int kU = 4;
+    for (int b0 = threadIdx.x; b0 < grid; b0 += kU * blockDim.x) {
+        double pr[kU][8];
+        long long cr[kU][2];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int b = b0 + u * (int)blockDim.x;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) pr[u][c] = b < grid ? partials[8 * (size_t)b + c] : 0.0;
+            cr[u][0] = b < grid ? counters[2 * (size_t)b] : 0;
+            cr[u][1] = b < grid ? counters[2 * (size_t)b + 1] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) v[c] += pr[u][c];
+            asym |= pr[u][7] != 0.0;
+            c0 += cr[u][0];
+            c1 += cr[u][1];
+        }
     }
     if (asym) atomicOr(flags, kFlagAsym);
+    #pragma unroll
     for (int c = 0; c < 7; ++c) sh[c][threadIdx.x] = v[c];
     shc[0][threadIdx.x] = c0;
     shc[1][threadIdx.x] = c1;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) {
+            #pragma unroll
             for (int c = 0; c < 7; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + off];
             shc[0][threadIdx.x] += shc[0][threadIdx.x + off];
             shc[1][threadIdx.x] += shc[1][threadIdx.x + off];
@@ -859,6 +970,7 @@ __device__ void finalize_sums(const double *__restrict__ partials, const long lo
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        #pragma unroll
         for (int c = 0; c < 7; ++c) out[c] = sh[c][0];
         counts[0] = shc[0][0];
         counts[1] = shc[1][0];
@@ -911,11 +1023,14 @@ __global__ void k_reduce_systems(const SysDesc *__restrict__ sys, const BatchDim
         const int a0 = sys[s].atom_off, na = sys[s].natoms;
         double v[7] = {0, 0, 0, 0, 0, 0, 0};
         for (int k = threadIdx.x; k < na; k += blockDim.x)
+            #pragma unroll
             for (int c = 0; c < 7; ++c) v[c] += eatom[8 * (size_t)(a0 + k) + c];
+        #pragma unroll
         for (int c = 0; c < 7; ++c) sh[c][threadIdx.x] = v[c];
         __syncthreads();
         for (int off = 128; off > 0; off >>= 1) {
             if ((int)threadIdx.x < off)
+                #pragma unroll
                 for (int c = 0; c < 7; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + off];
             __syncthreads();
         }
@@ -923,6 +1038,7 @@ __global__ void k_reduce_systems(const SysDesc *__restrict__ sys, const BatchDim
             int st = sys_status[s];
             for (int q = 0; q < nd; ++q)
                 if (drop_list[q] >= a0 && drop_list[q] < a0 + na) st |= 2;
+            #pragma unroll
             for (int c = 0; c < 7; ++c) out[8 * (size_t)s + c] = sh[c][0];
             out[8 * (size_t)s + 7] = (double)st;
         }
