@@ -920,33 +920,37 @@ __global__ void k_fixup_dropped(const int *__restrict__ ell, int cap, const int 
     }
 }
 
-// Sums the per-workgroup partials of the compute kernel (one workgroup of
-// 256 threads, fixed summation order) and raises kFlagAsym if a workgroup
-// reported it.
-__device__ __forceinline__ void finalize_sums(const double *__restrict__ partials, const long long *__restrict__ counters,
-                              int grid, double *__restrict__ out, long long *__restrict__ counts, int *flags)
+// Sums the per-workgroup partials of the compute kernel in one workgroup of
+// kFinalThreads threads (fixed summation order: each thread its rows t,
+// t + kFinalThreads, ..., then a butterfly within each wavefront, then the
+// wavefront sums in order) and raises kFlagAsym if a workgroup reported it.
+constexpr int kFinalThreads = 1024;
+
+__device__ __forceinline__ void finalize_sums(const double *__restrict__ partials,
+                                              const long long *__restrict__ counters, int grid,
+                                              double *__restrict__ out, long long *__restrict__ counts, int *flags)
 {
-    __shared__ double sh[8][256];
-    __shared__ long long shc[2][256];
+    __shared__ double sh[kFinalThreads / kWave][7];
+    __shared__ long long shc[kFinalThreads / kWave][2];
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     long long c0 = 0, c1 = 0;
     bool asym = false;
-    // rows b = t, t + 256, ... in order; the loads of four rows are issued
-    // before their sums so the loop is not one memory latency per row
+    // the loads of four rows are issued before their sums
     constexpr int kU = 4;
-    for (int b0 = threadIdx.x; b0 < grid; b0 += kU * blockDim.x) {
+    for (int b0 = threadIdx.x; b0 < grid; b0 += kU * kFinalThreads) {
         double pr[kU][8];
         long long cr[kU][2];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const int b = b0 + u * (int)blockDim.x;
+            const int b = min(b0 + u * kFinalThreads, grid - 1);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) pr[u][c] = b < grid ? partials[8 * (size_t)b + c] : 0.0;
-            cr[u][0] = b < grid ? counters[2 * (size_t)b] : 0;
-            cr[u][1] = b < grid ? counters[2 * (size_t)b + 1] : 0;
+            for (int c = 0; c < 8; ++c) pr[u][c] = partials[8 * (size_t)b + c];
+            cr[u][0] = counters[2 * (size_t)b];
+            cr[u][1] = counters[2 * (size_t)b + 1];
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
+            if (b0 + u * kFinalThreads >= grid) break;
 #pragma unroll
             for (int c = 0; c < 7; ++c) v[c] += pr[u][c];
             asym |= pr[u][7] != 0.0;
@@ -955,25 +959,34 @@ __device__ __forceinline__ void finalize_sums(const double *__restrict__ partial
         }
     }
     if (asym) atomicOr(flags, kFlagAsym);
-    #pragma unroll
-    for (int c = 0; c < 7; ++c) sh[c][threadIdx.x] = v[c];
-    shc[0][threadIdx.x] = c0;
-    shc[1][threadIdx.x] = c1;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            #pragma unroll
-            for (int c = 0; c < 7; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + off];
-            shc[0][threadIdx.x] += shc[0][threadIdx.x + off];
-            shc[1][threadIdx.x] += shc[1][threadIdx.x + off];
-        }
-        __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] = wave_sum(v[c]);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        c0 += __shfl_xor(c0, off, kWave);
+        c1 += __shfl_xor(c1, off, kWave);
     }
+    const int w = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) sh[w][c] = v[c];
+        shc[w][0] = c0;
+        shc[w][1] = c1;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        #pragma unroll
-        for (int c = 0; c < 7; ++c) out[c] = sh[c][0];
-        counts[0] = shc[0][0];
-        counts[1] = shc[1][0];
+        double t[7] = {0, 0, 0, 0, 0, 0, 0};
+        long long n0 = 0, n1 = 0;
+        for (int q = 0; q < kFinalThreads / kWave; ++q) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) t[c] += sh[q][c];
+            n0 += shc[q][0];
+            n1 += shc[q][1];
+        }
+#pragma unroll
+        for (int c = 0; c < 7; ++c) out[c] = t[c];
+        counts[0] = n0;
+        counts[1] = n1;
     }
 }
 
@@ -1196,7 +1209,7 @@ hipError_t launch_fixup_finalize(const int *ell, int cap, const int *row_count, 
                                  const long long *counters, int grid, double *out7, long long *counts_out,
                                  int *flags, hipStream_t s)
 {
-    const dim3 G(kBigGrid + 1), W(256);
+    const dim3 G(kBigGrid + 1), W(kFinalThreads);
     if (prec != kPrecFP64)
         hipLaunchKernelGGL(k_fixup_finalize<float>, G, W, 0, s, ell, cap, row_count, kept, kept_more, drop_list,
                            drop_count, plane_stride, static_cast<float *>(planes), partials, counters, grid, out7,

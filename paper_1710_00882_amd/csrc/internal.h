@@ -215,6 +215,9 @@ hipError_t launch_scatter_cells(const ScatterLaunch &a, int grid_cap, hipStream_
 // are not written (row_count holds the true length, or 0 with bit 1 of the
 // system's status in a batch).  long_rows / n_long: scratch for rows too long
 // for the first pass (n_long must be 0 on entry).
+// Entries past the end of the cell-order FP32 positions that the search may
+// load (and discard); allocations of cell_posf hold n + kPosPad entries.
+constexpr int kPosPad = 4;
 struct SearchLaunch {
     CellGrid g;
     const SysDesc *sys;

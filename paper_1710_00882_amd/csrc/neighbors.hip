@@ -247,18 +247,24 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
         int ns = 0;
         // SH: add the stencil image shift (every axis has at least three
         // cells) or take the single-precision minimum image
-        auto scan = [&](auto sh_tag, int u0, int u1, float sx, float sy, float sz) {
+        // ZS: the range carries a z image shift.  The loads of a group of four
+        // may run up to three entries past the range (the array is padded by
+        // kPosPad entries); those candidates fail u < u1.
+        auto scan = [&](auto sh_tag, auto zs_tag, int u0, int u1, float sx, float sy, float sz) {
             constexpr bool SH = decltype(sh_tag)::value;
+            constexpr bool ZS = decltype(zs_tag)::value;
             for (int ub = u0; ub < u1; ub += 4) {
                 float4 fj[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) fj[r] = a.cell_posf[min(ub + r, u1 - 1)];
+                for (int r = 0; r < 4; ++r) fj[r] = a.cell_posf[ub + r];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int u = ub + r;
                     float d0 = fj[r].x - fi.x, d1 = fj[r].y - fi.y, d2 = fj[r].z - fi.z;
                     if constexpr (SH) {
-                        d0 += sx; d1 += sy; d2 += sz;
+                        d0 += sx;
+                        d1 += sy;
+                        if constexpr (ZS) d2 += sz;
                     } else {
                         d0 = fmaf(-rintf(d0 * g.invLf[0]), g.Lf[0], d0);
                         d1 = fmaf(-rintf(d1 * g.invLf[1]), g.Lf[1], d1);
@@ -276,6 +282,8 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
                 }
             }
         };
+        const std::integral_constant<bool, false> no_z{};
+        const std::integral_constant<bool, true> with_z{};
         auto walk = [&](auto sh_tag) {
             for (int q0 = 0; q0 < n0; ++q0) {
                 int x = n0 == 3 ? cx + q0 - 1 : q0;
@@ -288,17 +296,19 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
                     const int col = coff + (x * g.nc[1] + y) * g.nc[2];
                     if (n2 == 3) {
                         const int zlo = max(cz - 1, 0), zhi = min(cz + 1, g.nc[2] - 1);
-                        scan(sh_tag, a.cell_start[col + zlo], a.cell_start[col + zhi] + a.cell_count[col + zhi], sx,
-                             sy, 0.f);
+                        scan(sh_tag, no_z, a.cell_start[col + zlo], a.cell_start[col + zhi] + a.cell_count[col + zhi],
+                             sx, sy, 0.f);
                         if (cz == 0) {
                             const int cw = col + g.nc[2] - 1;
-                            scan(sh_tag, a.cell_start[cw], a.cell_start[cw] + a.cell_count[cw], sx, sy, -g.Lf[2]);
+                            scan(sh_tag, with_z, a.cell_start[cw], a.cell_start[cw] + a.cell_count[cw], sx, sy,
+                                 -g.Lf[2]);
                         }
                         if (cz == g.nc[2] - 1)
-                            scan(sh_tag, a.cell_start[col], a.cell_start[col] + a.cell_count[col], sx, sy, g.Lf[2]);
+                            scan(sh_tag, with_z, a.cell_start[col], a.cell_start[col] + a.cell_count[col], sx, sy,
+                                 g.Lf[2]);
                     } else {
                         // every cell of the column once (minimum image decides)
-                        scan(sh_tag, a.cell_start[col],
+                        scan(sh_tag, no_z, a.cell_start[col],
                              a.cell_start[col + g.nc[2] - 1] + a.cell_count[col + g.nc[2] - 1], sx, sy, 0.f);
                     }
                 }

@@ -247,7 +247,7 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.h_dims.alloc(1));
     SRV_TRY(L.pos.alloc(3 * A, tot));
     SRV_TRY(L.cell_pos.alloc(3 * A, tot));
-    SRV_TRY(L.cell_posf.alloc(A, tot));
+    SRV_TRY(L.cell_posf.alloc(A + kPosPad, tot));
     SRV_TRY(L.long_rows.alloc(A, tot));
     SRV_TRY(L.own.alloc(3 * A, tot));
     SRV_TRY(L.planes.alloc(3 * (size_t)kRecCap * A, tot));

@@ -379,7 +379,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, c->cell_start.ensure(ncell + 1));
     HIP_TRY(c, c->cell_atoms.ensure(N));
     HIP_TRY(c, c->cell_pos.ensure(3 * (size_t)N));
-    HIP_TRY(c, c->cell_posf.ensure((size_t)N));
+    HIP_TRY(c, c->cell_posf.ensure((size_t)N + kPosPad));
     HIP_TRY(c, c->long_rows.ensure((size_t)N));
     HIP_TRY(c, c->row_count.ensure(N));
     HIP_TRY(c, c->pcount.ensure(N));
