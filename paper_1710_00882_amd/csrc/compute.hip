@@ -921,28 +921,27 @@ __global__ void k_fixup_dropped(const int *__restrict__ ell, int cap, const int 
 }
 
 // Sums the per-workgroup partials of the compute kernel in one workgroup of
-// kFinalThreads threads (fixed summation order: each thread its rows t,
-// t + kFinalThreads, ..., then a butterfly within each wavefront, then the
-// wavefront sums in order) and raises kFlagAsym if a workgroup reported it.
-constexpr int kFinalThreads = 1024;
-
+// NT threads (fixed summation order: each thread its rows t, t + NT, ...,
+// then a butterfly within each wavefront, then the wavefront sums in order)
+// and raises kFlagAsym if a workgroup reported it.
+template <int NT>
 __device__ __forceinline__ void finalize_sums(const double *__restrict__ partials,
                                               const long long *__restrict__ counters, int grid,
                                               double *__restrict__ out, long long *__restrict__ counts, int *flags)
 {
-    __shared__ double sh[kFinalThreads / kWave][7];
-    __shared__ long long shc[kFinalThreads / kWave][2];
+    __shared__ double sh[NT / kWave][7];
+    __shared__ long long shc[NT / kWave][2];
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     long long c0 = 0, c1 = 0;
     bool asym = false;
     // the loads of four rows are issued before their sums
     constexpr int kU = 4;
-    for (int b0 = threadIdx.x; b0 < grid; b0 += kU * kFinalThreads) {
+    for (int b0 = threadIdx.x; b0 < grid; b0 += kU * NT) {
         double pr[kU][8];
         long long cr[kU][2];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const int b = min(b0 + u * kFinalThreads, grid - 1);
+            const int b = min(b0 + u * NT, grid - 1);
 #pragma unroll
             for (int c = 0; c < 8; ++c) pr[u][c] = partials[8 * (size_t)b + c];
             cr[u][0] = counters[2 * (size_t)b];
@@ -950,7 +949,7 @@ __device__ __forceinline__ void finalize_sums(const double *__restrict__ partial
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            if (b0 + u * kFinalThreads >= grid) break;
+            if (b0 + u * NT >= grid) break;
 #pragma unroll
             for (int c = 0; c < 7; ++c) v[c] += pr[u][c];
             asym |= pr[u][7] != 0.0;
@@ -977,7 +976,7 @@ __device__ __forceinline__ void finalize_sums(const double *__restrict__ partial
     if (threadIdx.x == 0) {
         double t[7] = {0, 0, 0, 0, 0, 0, 0};
         long long n0 = 0, n1 = 0;
-        for (int q = 0; q < kFinalThreads / kWave; ++q) {
+        for (int q = 0; q < NT / kWave; ++q) {
 #pragma unroll
             for (int c = 0; c < 7; ++c) t[c] += sh[q][c];
             n0 += shc[q][0];
@@ -987,36 +986,6 @@ __device__ __forceinline__ void finalize_sums(const double *__restrict__ partial
         for (int c = 0; c < 7; ++c) out[c] = t[c];
         counts[0] = n0;
         counts[1] = n1;
-    }
-}
-
-// After the compute kernel, in one launch: the last workgroup sums the
-// partials, the others run the dropped-atom fixup.
-template <typename T>
-__global__ void k_fixup_finalize(const int *__restrict__ ell, int cap, const int *__restrict__ row_count,
-                                 const int *__restrict__ kept, const int *__restrict__ kept_more,
-                                 const int *__restrict__ drop_list, const int *__restrict__ drop_count,
-                                 int plane_stride, T *__restrict__ planes, const double *__restrict__ partials,
-                                 const long long *__restrict__ counters, int grid, double *__restrict__ out,
-                                 long long *__restrict__ counts, int *flags)
-{
-    if (blockIdx.x == gridDim.x - 1) {
-        finalize_sums(partials, counters, grid, out, counts, flags);
-        return;
-    }
-    const int nd = *drop_count;
-    for (int q = blockIdx.x; q < nd; q += gridDim.x - 1) {
-        const int m = drop_list[q];
-        const int rc = row_count[m];
-        for (int q = (int)threadIdx.x; q < rc; q += blockDim.x) {
-            const int nb = ell[(size_t)m * cap + q];
-            bool ended;
-            const int k = kept_position(kept, kept_more, nb, m, ended);   // plane nb reserved for m
-            if (k >= 0) {
-                T *f = planes + 3 * ((size_t)k * plane_stride + (size_t)nb);
-                f[0] = f[1] = f[2] = T(0);
-            }
-        }
     }
 }
 
@@ -1063,22 +1032,45 @@ __global__ void k_reduce_systems(const SysDesc *__restrict__ sys, const BatchDim
 // plane k of m, k = rank of i among m's kept neighbours (k < pcount[m]).
 // One thread per atom; each plane read is coalesced across the wavefront.
 // Also empties the dropped-atom list for the next evaluation when
-// drop_count is given (every kernel reading it has run by now).
+// drop_count is given (every kernel reading it has run by now), and, when
+// fin.partials is given, sums the compute kernel's partials in one extra
+// workgroup -- the first, so that it runs beside the gather rather than
+// after it.
 template <typename T>
-__global__ void k_gather_forces(const int *__restrict__ pcount, const T *__restrict__ planes,
-                                const double *__restrict__ own, int n, const int *__restrict__ n_dev,
-                                int plane_stride, double *__restrict__ forces, int *drop_count)
+__global__ __launch_bounds__(kGatherThreads) void k_gather_forces(const int *__restrict__ pcount,
+                                                                  const T *__restrict__ planes,
+                                                                  const double *__restrict__ own, int n,
+                                                                  const int *__restrict__ n_dev, int plane_stride,
+                                                                  double *__restrict__ forces, int *drop_count,
+                                                                  FinalizeArgs fin)
 {
-    if (drop_count && blockIdx.x == 0 && threadIdx.x == 0) *drop_count = 0;
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (fin.partials && blockIdx.x == 0) {
+        finalize_sums<kGatherThreads>(fin.partials, fin.counters, fin.grid, fin.out, fin.counts, fin.flags);
+        return;
+    }
+    const int blk = blockIdx.x - (fin.partials ? 1 : 0);
+    if (drop_count && blk == 0 && threadIdx.x == 0) *drop_count = 0;
+    const int m = blk * (int)blockDim.x + (int)threadIdx.x;
     if (m >= (n_dev ? *n_dev : n)) return;
     double fx = own[3 * (size_t)m], fy = own[3 * (size_t)m + 1], fz = own[3 * (size_t)m + 2];
     const int pc = pcount[m];
-    for (int k = 0; k < pc; ++k) {
-        const T *f = planes + 3 * ((size_t)k * plane_stride + (size_t)m);
-        fx += (double)f[0];
-        fy += (double)f[1];
-        fz += (double)f[2];
+    // planes 0 .. pc-1 in order; the loads of four planes are issued together
+    for (int k0 = 0; k0 < pc; k0 += 4) {
+        T v[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T *f = planes + 3 * ((size_t)min(k0 + u, pc - 1) * plane_stride + (size_t)m);
+            v[u][0] = f[0];
+            v[u][1] = f[1];
+            v[u][2] = f[2];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (k0 + u >= pc) break;
+            fx += (double)v[u][0];
+            fy += (double)v[u][1];
+            fz += (double)v[u][2];
+        }
     }
     forces[3 * (size_t)m] = fx;
     forces[3 * (size_t)m + 1] = fy;
@@ -1203,24 +1195,6 @@ hipError_t launch_fixup_dropped(const int *ell, int cap, const int *row_count, c
     return hipGetLastError();
 }
 
-hipError_t launch_fixup_finalize(const int *ell, int cap, const int *row_count, const int *kept,
-                                 const int *kept_more, const int *drop_list, const int *drop_count,
-                                 int plane_stride, int prec, void *planes, const double *partials,
-                                 const long long *counters, int grid, double *out7, long long *counts_out,
-                                 int *flags, hipStream_t s)
-{
-    const dim3 G(kBigGrid + 1), W(kFinalThreads);
-    if (prec != kPrecFP64)
-        hipLaunchKernelGGL(k_fixup_finalize<float>, G, W, 0, s, ell, cap, row_count, kept, kept_more, drop_list,
-                           drop_count, plane_stride, static_cast<float *>(planes), partials, counters, grid, out7,
-                           counts_out, flags);
-    else
-        hipLaunchKernelGGL(k_fixup_finalize<double>, G, W, 0, s, ell, cap, row_count, kept, kept_more, drop_list,
-                           drop_count, plane_stride, static_cast<double *>(planes), partials, counters, grid, out7,
-                           counts_out, flags);
-    return hipGetLastError();
-}
-
 hipError_t launch_reduce_systems(const SysDesc *sys, const BatchDims *dims, int max_sys, const double *eatom,
                                  const int *drop_list, const int *drop_count, const int *sys_status,
                                  double *out, hipStream_t s)
@@ -1232,15 +1206,17 @@ hipError_t launch_reduce_systems(const SysDesc *sys, const BatchDims *dims, int 
 }
 
 hipError_t launch_gather_forces(const int *pcount, int prec, const void *planes, const double *own, int n,
-                                const int *n_dev, int plane_stride, double *forces, int *drop_count, hipStream_t s)
+                                const int *n_dev, int plane_stride, double *forces, int *drop_count,
+                                const FinalizeArgs &fin, hipStream_t s)
 {
-    const dim3 G(std::max(1, (n + 255) / 256)), W(256);
+    const int blocks = std::max(1, (n + kGatherThreads - 1) / kGatherThreads) + (fin.partials ? 1 : 0);
+    const dim3 G(blocks), W(kGatherThreads);
     if (prec != kPrecFP64)
         hipLaunchKernelGGL(k_gather_forces<float>, G, W, 0, s, pcount, static_cast<const float *>(planes), own, n,
-                           n_dev, plane_stride, forces, drop_count);
+                           n_dev, plane_stride, forces, drop_count, fin);
     else
         hipLaunchKernelGGL(k_gather_forces<double>, G, W, 0, s, pcount, static_cast<const double *>(planes), own,
-                           n, n_dev, plane_stride, forces, drop_count);
+                           n, n_dev, plane_stride, forces, drop_count, fin);
     return hipGetLastError();
 }
 

@@ -168,19 +168,25 @@ hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec
 hipError_t launch_fixup_dropped(const int *ell, int cap, const int *row_count, const int *kept,
                                 const int *kept_more, const int *drop_list, const int *drop_count,
                                 int plane_stride, int prec, void *planes, hipStream_t s);
-// Dropped-atom fixup and the sum of the compute kernel's partials into out7 /
-// counts_out, in one launch; *flags |= kFlagAsym when a partial carries it.
-hipError_t launch_fixup_finalize(const int *ell, int cap, const int *row_count, const int *kept,
-                                 const int *kept_more, const int *drop_list, const int *drop_count,
-                                 int plane_stride, int prec, void *planes, const double *partials,
-                                 const long long *counters, int grid, double *out7, long long *counts_out,
-                                 int *flags, hipStream_t s);
 hipError_t launch_fill_zero(double *p, size_t count, hipStream_t s);
+// The sum of the compute kernel's per-workgroup partials (grid rows of 8
+// doubles and 2 counts) into out7 / counts_out; kFlagAsym into *flags when a
+// partial carries it.  partials == nullptr: none (batched path).
+struct FinalizeArgs {
+    const double *partials;
+    const long long *counters;
+    int grid;
+    double *out;
+    long long *counts;
+    int *flags;
+};
+constexpr int kGatherThreads = 256;
 // drop_count, when not null, is reset to 0 (the dropped-atom list is empty
-// for the next evaluation).
+// for the next evaluation); fin.partials, when not null, adds the sum of the
+// partials (one extra workgroup).
 hipError_t launch_gather_forces(const int *pcount, int prec, const void *planes, const double *own, int n,
                                 const int *n_dev, int plane_stride, double *forces, int *drop_count,
-                                hipStream_t s);
+                                const FinalizeArgs &fin, hipStream_t s);
 // Per-system sums of the per-atom energy / virial of a batch and status bits
 // (1: a neighbour row over capacity, 2: an atom over the record capacity):
 // out[8 s + c] = E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, status.

@@ -541,10 +541,11 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     HIP_TRY(c, launch_compute(a, c->tab, prec, grid[1], s));
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
-    HIP_TRY(c, launch_fixup_finalize(c->ell.p, c->list_cap, c->row_count.p, c->kept.p, pk.kept_more, c->drop_list.p, c->misc.p + 3,
-                                     c->n, prec, c->planes.p, c->partials.p, c->counters.p, grid[1], energy_virial,
-                                     c->counts.p, c->misc.p, s));
-    HIP_TRY(c, launch_gather_forces(c->pcount.p, prec, c->planes.p, c->own.p, c->n, nullptr, c->n, f, c->misc.p + 3, s));
+    HIP_TRY(c, launch_fixup_dropped(c->ell.p, c->list_cap, c->row_count.p, c->kept.p, pk.kept_more, c->drop_list.p,
+                                    c->misc.p + 3, c->n, prec, c->planes.p, s));
+    const FinalizeArgs fin{c->partials.p, c->counters.p, grid[1], energy_virial, c->counts.p, c->misc.p};
+    HIP_TRY(c, launch_gather_forces(c->pcount.p, prec, c->planes.p, c->own.p, c->n, nullptr, c->n, f, c->misc.p + 3,
+                                    fin, s));
     if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
     if (c->profiling) {
         c->ev_pack.emplace_back(ev[0], ev[1]);
