@@ -284,6 +284,7 @@ static_assert(kMaxTypes <= 4, "two type bits and four third-atom bits per record
 __device__ __forceinline__ int rec_type(int jm) { return (jm >> kTypeShift) & 3; }
 
 constexpr int kChunks = 4;     // 64-entry chunks whose loads are issued together
+constexpr int kOwnerCap = 1024;   // batch entries whose atom is looked up in a table (the rest: binary search)
 static_assert(kKeptFast == 8, "the first block of a kept list is two 16-byte words");
 
 // Position of atom `who` in the kept-neighbour list of atom m (-1: absent);
@@ -359,6 +360,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
     __shared__ int ti[kWave], cnt[kWave];
     __shared__ int eoff[kWave + 1];
     __shared__ int kst[kKeptFast][kWave];   // first kept neighbours of the batch's atoms
+    __shared__ unsigned char owner[kOwnerCap];   // batch atom of each of the first kOwnerCap entries
     const int lane = threadIdx.x;
     Rec<real> *recs = static_cast<Rec<real> *>(a.recs);
     const int B = a.atoms_per_batch;
@@ -393,6 +395,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
             const int inc = wave_incl_scan(rc);
             if (lane < nb) eoff[lane + 1] = inc;
             if (lane == 0) eoff[0] = 0;
+            for (int e = inc - rc; e < min(inc, kOwnerCap); ++e) owner[e] = (unsigned char)lane;
         }
         __syncthreads();
         const int e_begin = eoff[0], e_end = eoff[nb];
@@ -408,7 +411,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 alv[c] = 0;
                 ev[c] = 0;
                 if (e < e_end) {
-                    const int al = find_seg(eoff, nb, e);
+                    const int al = e < kOwnerCap ? (int)owner[e] : find_seg(eoff, nb, e);
                     alv[c] = al;
                     ev[c] = (a0 + al) * a.cap + (e - eoff[al]);   // row-buffer index of the entry
                     jv[c] = a.ell[ev[c]];
@@ -518,6 +521,7 @@ struct Shared {
     int ti[kWave];
     int pcnt[kWave];
     int pstart[kWave + 1];
+    unsigned char owner[kScap];  // centre atom (batch index) of each slot
     // per packed slot (i, n)
     double fs[kScap][3];         // force on n from i's terms (FP64)
     real ux[kScap], uy[kScap], uz[kScap], r[kScap];
@@ -633,6 +637,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 sh.ti[lane] = tiv;
                 sh.pcnt[lane] = p;
                 sh.pstart[lane + 1] = ip;
+                for (int q = ip - p; q < ip; ++q) sh.owner[q] = (unsigned char)lane;
             }
             if (lane == 0) sh.pstart[0] = 0;
             const int npacked = __shfl(ip, cut - 1, kWave);
@@ -645,7 +650,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             int al = 0, jl = 0, pc = 0, sb = 0, j = 0, kpos = -1, mj = 0, ti = 0;
             real rj = 0, rjinv = 0, uj[3] = {0, 0, 0}, dj[3] = {0, 0, 0};
             if (has_slot) {
-                al = find_seg(sh.pstart, cut, s);
+                al = sh.owner[s];
                 sb = sh.pstart[al];
                 jl = s - sb;
                 pc = sh.pcnt[al];
