@@ -368,14 +368,35 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
     const int nbatch = (n + B - 1) / B;
 
     const ItemRange items = xcd_items(nbatch);
+    // the per-atom inputs of a batch, loaded one batch ahead so that their
+    // latency overlaps the previous batch
+    struct AtomIn {
+        double x, y, z, bx, by, bz;
+        int rc, t;
+    };
+    auto fetch = [&](int b, AtomIn &v) {
+        v.rc = 0;
+        if (b < items.end && lane < min(B, n - b * B)) {
+            const size_t i = (size_t)(b * B + lane);
+            v.x = a.pos[3 * i]; v.y = a.pos[3 * i + 1]; v.z = a.pos[3 * i + 2];
+            v.t = ONE ? 0 : a.types[i];
+            v.rc = a.row_count[i];
+            if constexpr (!BATCHED) {
+                v.bx = a.pos_build[3 * i]; v.by = a.pos_build[3 * i + 1]; v.bz = a.pos_build[3 * i + 2];
+            }
+        }
+    };
+    AtomIn nxt;
+    fetch(items.begin, nxt);
     for (int bt = items.begin; bt < items.end; bt += items.stride) {
         const int a0 = bt * B;
         const int nb = min(B, n - a0);
+        const AtomIn cur = nxt;
+        fetch(bt + items.stride, nxt);
         if (lane < nb) {
             const size_t i = (size_t)(a0 + lane);
-            const double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
-            xi[lane] = x; yi[lane] = y; zi[lane] = z;
-            ti[lane] = ONE ? 0 : a.types[i];
+            xi[lane] = cur.x; yi[lane] = cur.y; zi[lane] = cur.z;
+            ti[lane] = cur.t;
             cnt[lane] = 0;
             if constexpr (BATCHED) {
                 const CellGrid &g = a.sys[a.sys_of[i]].g;
@@ -384,14 +405,13 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                     biL[d][lane] = g.invL[d];
                 }
             } else {
-                const double dx = x - a.pos_build[3 * i], dy = y - a.pos_build[3 * i + 1],
-                             dz = z - a.pos_build[3 * i + 2];
+                const double dx = cur.x - cur.bx, dy = cur.y - cur.by, dz = cur.z - cur.bz;
                 if (!(dx * dx + dy * dy + dz * dz <= a.stale_sq)) atomicOr(a.flags, kFlagStale);
             }
         }
         {
             // local entry offsets of the batch's rows
-            const int rc = lane < nb ? a.row_count[a0 + lane] : 0;
+            const int rc = lane < nb ? cur.rc : 0;
             const int inc = wave_incl_scan(rc);
             if (lane < nb) eoff[lane + 1] = inc;
             if (lane == 0) eoff[0] = 0;
