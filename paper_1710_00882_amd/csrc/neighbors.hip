@@ -150,7 +150,7 @@ __device__ inline bool in_range(double xj, double yj, double zj, double xi, doub
 //   2  decide the survivors with the exact FP64 predicate, compacting the
 //      accepted neighbour ids in place;
 //   3  sort the row with a 32-element bitonic network in registers.
-// Atoms with more than kLRow - 1 survivors are listed for k_search_long.
+// Atoms with more than kLBuf - 1 survivors are listed for k_search_long.
 //
 // Pre-test bound: the wrapped single-precision coordinates and the rounded box
 // lengths are each within 2^-24 L of their exact values, and the difference
@@ -163,7 +163,10 @@ __device__ inline bool in_range(double xj, double yj, double zj, double xi, doub
 // the survivors in between take the FP64 test.  (The minimum-image form can
 // pick the other image for a pair at almost exactly half a box, so there
 // every survivor takes the FP64 test.)
-constexpr int kLRow = 32;          // LDS slots per thread: up to kLRow - 1 survivors, one scratch slot
+constexpr int kLRow = 32;          // width of the register sort
+constexpr int kLBuf = 24;          // LDS slots per thread: up to kLBuf - 1 survivors, one scratch slot
+                                   // (24 KB per workgroup: six workgroups per CU)
+static_assert(kLBuf <= kLRow, "a row fits the sort");
 constexpr int kSearchThreads = 256;
 
 struct StencilCell {
@@ -212,7 +215,7 @@ __device__ __forceinline__ void bitonic32(int (&v)[kLRow])
 template <bool BATCHED>
 __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
 {
-    __shared__ int buf[kLRow][kSearchThreads];
+    __shared__ int buf[kLBuf][kSearchThreads];
     const int tl = threadIdx.x;
     const int n = BATCHED ? a.dims->n_atoms : a.n;
     const ItemRange items = xcd_items((n + kSearchThreads - 1) / kSearchThreads);
@@ -275,9 +278,9 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
                     // survivors surely inside are stored as -(id + 1), the
                     // others as their cell-order slot for the exact test;
                     // the store is unconditional: a rejected candidate is
-                    // overwritten by the next survivor, slot kLRow - 1 takes
+                    // overwritten by the next survivor, slot kLBuf - 1 takes
                     // the overflow
-                    buf[min(ns, kLRow - 1)][tl] = (SH && r2 < sure2) ? -1 - __float_as_int(fj[r].w) : u;
+                    buf[min(ns, kLBuf - 1)][tl] = (SH && r2 < sure2) ? -1 - __float_as_int(fj[r].w) : u;
                     ns += keep ? 1 : 0;
                 }
             }
@@ -318,7 +321,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
         // taken when it holds for every thread of the wavefront
         if (__all(shifted ? 1 : 0)) walk(std::integral_constant<bool, true>{});
         else walk(std::integral_constant<bool, false>{});
-        if (ns > kLRow - 1) {
+        if (ns > kLBuf - 1) {
             // too many survivors for the LDS buffer: k_search_long writes this row
             a.long_rows[atomicAdd(a.n_long, 1)] = t;
             continue;
@@ -343,7 +346,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
         if (cnt <= a.cap) {
             int v[kLRow];
 #pragma unroll
-            for (int k = 0; k < kLRow; ++k) v[k] = k < cnt ? buf[k][tl] : INT_MAX;
+            for (int k = 0; k < kLRow; ++k) v[k] = (k < kLBuf && k < cnt) ? buf[k < kLBuf ? k : 0][tl] : INT_MAX;
             bitonic32(v);
             int *out = a.ell + (size_t)i * a.cap;
 #pragma unroll
