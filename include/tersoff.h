@@ -156,8 +156,10 @@ int tersoff_profile(tersoff_ctx *ctx, int32_t enable);
 int tersoff_profile_read(tersoff_ctx *ctx, double out[8]);
 
 /* Nominal centre atoms per wavefront batch of the compute kernel, in
- * [1, 64] (default 32).  Performance tuning only; results do not depend on
- * it beyond floating-point summation order.  E_INVALID outside the range. */
+ * [1, 64] (default: chosen by each build, 32, or 16 below 131,072 atoms;
+ * once set, kept for later builds).  Performance tuning only; results do not
+ * depend on it beyond floating-point summation order.  E_INVALID outside
+ * the range. */
 int tersoff_set_batch_atoms(tersoff_ctx *ctx, int32_t atoms);
 
 /* Number of atoms of the last build (0 if none). */

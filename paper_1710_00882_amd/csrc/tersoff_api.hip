@@ -60,6 +60,7 @@ struct tersoff_ctx {
     int ell_cap = 32;        // row capacity for the next build (multiple of 8)
     int list_cap = 0;        // row stride of the resident list
     int atoms_per_batch = 32;
+    bool batch_atoms_set = false;   // tersoff_set_batch_atoms was called (else chosen by the build)
     int grid[kNumPrec][3] = {};   // [precision] x {pack, compute, fixup}
 
     DevBuf<double> pos_build;
@@ -316,6 +317,7 @@ int tersoff_set_batch_atoms(tersoff_ctx *c, int32_t atoms)
     if (!c) return TERSOFF_E_INVALID;
     if (atoms < 1 || atoms > kWave) return fail(c, TERSOFF_E_INVALID, "batch atoms must be in [1, 64]");
     c->atoms_per_batch = atoms;
+    c->batch_atoms_set = true;
     if (c->built) {
         int gmax = 0;
         for (int pr = 0; pr < kNumPrec; ++pr) {
@@ -460,6 +462,10 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     for (int a = 0; a < 3; ++a) c->box[a] = box[a];
     c->cutoff = cutoff;
     c->skin = skin;
+    // default batch: 32 centre atoms; 16 below 128k atoms, where the number
+    // of batches rather than the work per batch limits the packing and
+    // compute kernels
+    if (!c->batch_atoms_set) c->atoms_per_batch = N < 131072 ? 16 : 32;
     int gmax = 0;
     for (int pr = 0; pr < kNumPrec; ++pr) {
         compute_grids(pr, c->ntypes == 1, false, N, c->atoms_per_batch, c->grid[pr]);

@@ -1,0 +1,112 @@
+"""GPU parity at the benchmark sizes, in the launch configuration bench.py
+times (default batch size, resident list, rebuild every 5th call): the
+32,000- and 2,048,000-atom silicon workloads and the 256,000-atom
+two-species disordered workload, against the FP64 oracle evaluated over
+every atom (its C implementation runs these sizes in seconds on the host
+cores).  Neighbour lists are compared bit for bit, work counts exactly,
+energy / forces / virial at the stated tolerances; the total force (zero
+for any periodic configuration) is checked as a size-independent property.
+
+All GPU calls go through the C ABI of libtersoff.so (ctypes binding)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1710_00882_amd import workloads as W
+
+from gpu_helpers import assert_parity, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _oracle(pos, types, box, table, off, idx):
+    return oracle.compute(pos, types, box, table, off, idx, threads=_threads())
+
+
+def _momentum_ok(F, n):
+    # |sum F| per atom far below the force scale (rounding only)
+    scale = float(np.sqrt(np.mean(F * F)))
+    return float(np.abs(F.sum(axis=0)).max()) <= 1e-5 * scale * np.sqrt(n)
+
+
+def _check_system(name, s, table, precisions=("mixed", "fp64")):
+    import torch
+    from paper_1710_00882_amd import Tersoff
+    cut = W.table_cutoff(table)
+    say(f"[full] {name} n={s.n}: oracle list")
+    off, idx = oracle.neighbors(s.pos, s.box, cut + W.SKIN)
+    pos, types = to_dev(s)
+    m = Tersoff(table)
+    try:
+        m.build_neighbors(pos, types, s.box, skin=W.SKIN)
+        goff, gidx = m.neighbors()
+        assert np.array_equal(goff, off), f"{name}: offsets differ"
+        assert np.array_equal(gidx, idx), f"{name}: neighbour indices differ"
+        say(f"[full] {name}: oracle compute")
+        Eo, Fo, Vo = _oracle(s.pos, s.types, s.box, table, off, idx)
+        counts_o = oracle.counts(s.pos, s.types, s.box, table, off, idx)
+        for prec in precisions:
+            out, f = m.compute(pos, prec)
+            torch.cuda.synchronize()
+            m.check()
+            o = out.cpu().numpy()
+            F = f.cpu().numpy()
+            assert_parity(float(o[0]), F, o[1:], Eo, Fo, Vo, s.n, prec, name)
+            assert m.counts() == counts_o
+            assert _momentum_ok(F, s.n), f"{name} {prec}: total force {F.sum(axis=0)}"
+    finally:
+        m.close()
+
+
+def test_si_32k_full_parity():
+    _check_system("si_32k", W.si_32k(), W.si_table())
+
+
+def test_si_2m_full_parity():
+    _check_system("si_2m", W.si_2m(), W.si_table())
+
+
+def test_si_2m_ten_call_sequence():
+    """The benchmark's sequence: 10 calls, positions perturbed by N(0, 0.01 A)
+    between calls, the list rebuilt before calls 0 and 5; call 9 (mixed) and
+    call 4 (FP64) against the oracle with the list of their build."""
+    import torch
+    from paper_1710_00882_amd import Tersoff
+    s = W.si_2m()
+    table = W.si_table()
+    cut = W.table_cutoff(table)
+    g = W.rng(1234)
+    sets = [s.pos]
+    for _ in range(9):
+        sets.append(W.perturb(sets[-1], 0.01, g))
+    types = torch.tensor(s.types, dtype=torch.int32, device="cuda")
+    m = Tersoff(table)
+    try:
+        checks = {4: "fp64", 9: "mixed"}
+        for k, p in enumerate(sets):
+            pos = torch.tensor(p, dtype=torch.float64, device="cuda")
+            if k % 5 == 0:
+                m.build_neighbors(pos, types, s.box, skin=W.SKIN)
+                build_pos = p
+            prec = checks.get(k, "mixed")
+            out, f = m.compute(pos, prec)
+            torch.cuda.synchronize()
+            m.check()
+            if k in checks:
+                say(f"[full] sequence call {k} ({prec}): oracle")
+                off, idx = oracle.neighbors(build_pos, s.box, cut + W.SKIN)
+                Eo, Fo, Vo = _oracle(p, s.types, s.box, table, off, idx)
+                o = out.cpu().numpy()
+                assert_parity(float(o[0]), f.cpu().numpy(), o[1:], Eo, Fo, Vo, s.n, prec, f"si_2m call {k}")
+    finally:
+        m.close()
+
+
+def test_disordered_256k_full_parity():
+    _check_system("disordered_256k", W.disordered_256k(), W.two_species_table())
