@@ -217,8 +217,9 @@ struct ScatterLaunch {
 };
 hipError_t launch_scatter_cells(const ScatterLaunch &a, int grid_cap, hipStream_t s);
 
-// Neighbour rows (sorted, stride cap) of every atom; rows longer than cap
-// are not written (row_count holds the true length, or 0 with bit 1 of the
+// Neighbour rows (sorted, stride cap, cap a multiple of 8; a row's last
+// group of four entries may carry padding past row_count) of every atom;
+// rows longer than cap are not written (row_count holds the true length, or 0 with bit 1 of the
 // system's status in a batch).  long_rows / n_long: scratch for rows too long
 // for the first pass (n_long must be 0 on entry).
 // Entries past the end of the cell-order FP32 positions that the search may

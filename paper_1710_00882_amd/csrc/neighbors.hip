@@ -153,9 +153,12 @@ __device__ inline bool in_range(double xj, double yj, double zj, double xi, doub
 // Atoms with more than kLBuf - 1 survivors are listed for k_search_long.
 //
 // Pre-test bound: the wrapped single-precision coordinates and the rounded box
-// lengths are each within 2^-24 L of their exact values, and the difference
-// plus image shift adds two more roundings of that size, so every component
-// is within 5 * 2^-24 L_a of the exact minimum-image displacement, and the
+// lengths are each within 2^-24 L of their exact values; the shift form
+// rounds the image-shifted centre (at most 2^-23 L: it lies in (-L, 2L))
+// and the minimum-image form the difference and its correction (at most
+// 2^-24 L each); the last difference of an in-range pair rounds by at most
+// 2^-24 (rc + delta), so every component is within 6 * 2^-24 L_a (plus that)
+// of the exact minimum-image displacement, and the
 // single-precision distance within delta = 4e-7 (Lx + Ly + Lz) + 1e-5 of the
 // exact one (the 1e-5 covers the rounding of r^2 and of the radius).  So no
 // neighbour is rejected by the test r < rc + delta, and, in the shift form, a
@@ -256,6 +259,8 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
         auto scan = [&](auto sh_tag, auto zs_tag, int u0, int u1, float sx, float sy, float sz) {
             constexpr bool SH = decltype(sh_tag)::value;
             constexpr bool ZS = decltype(zs_tag)::value;
+            // the centre with the stencil cell's image shift taken off
+            const float ox = fi.x - sx, oy = fi.y - sy, oz = ZS ? fi.z - sz : fi.z;
             for (int ub = u0; ub < u1; ub += 4) {
                 float4 fj[4];
 #pragma unroll
@@ -263,12 +268,15 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int u = ub + r;
-                    float d0 = fj[r].x - fi.x, d1 = fj[r].y - fi.y, d2 = fj[r].z - fi.z;
+                    float d0, d1, d2;
                     if constexpr (SH) {
-                        d0 += sx;
-                        d1 += sy;
-                        if constexpr (ZS) d2 += sz;
+                        d0 = fj[r].x - ox;
+                        d1 = fj[r].y - oy;
+                        d2 = fj[r].z - oz;
                     } else {
+                        d0 = fj[r].x - fi.x;
+                        d1 = fj[r].y - fi.y;
+                        d2 = fj[r].z - fi.z;
                         d0 = fmaf(-rintf(d0 * g.invLf[0]), g.Lf[0], d0);
                         d1 = fmaf(-rintf(d1 * g.invLf[1]), g.Lf[1], d1);
                         d2 = fmaf(-rintf(d2 * g.invLf[2]), g.Lf[2], d2);
@@ -348,10 +356,13 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
 #pragma unroll
             for (int k = 0; k < kLRow; ++k) v[k] = (k < kLBuf && k < cnt) ? buf[k < kLBuf ? k : 0][tl] : INT_MAX;
             bitonic32(v);
-            int *out = a.ell + (size_t)i * a.cap;
+            // 16-byte stores (cap is a multiple of 8, so the row's last
+            // partial group of four stays inside it; its padding entries lie
+            // past row_count and are never read)
+            int4 *out = reinterpret_cast<int4 *>(a.ell + (size_t)i * a.cap);
 #pragma unroll
-            for (int k = 0; k < kLRow; ++k)
-                if (k < cnt) out[k] = v[k];
+            for (int k = 0; k < kLRow; k += 4)
+                if (k < cnt) out[k / 4] = make_int4(v[k], v[k + 1], v[k + 2], v[k + 3]);
         }
         if (BATCHED && cnt > a.cap) {
             a.row_count[i] = 0;
@@ -614,6 +625,7 @@ hipError_t launch_scatter_cells(const ScatterLaunch &a, int grid_cap, hipStream_
 
 hipError_t launch_search(const SearchLaunch &a, int grid_cap, hipStream_t s)
 {
+    if (a.cap < 8 || a.cap % 8 != 0) return hipErrorInvalidValue;   // rows are written 16 bytes at a time
     int grid = std::max(1, blocks_for(a.n, kSearchThreads));
     if (a.dims) {
         grid = std::min(grid, grid_cap);
