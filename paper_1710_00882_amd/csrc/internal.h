@@ -210,6 +210,7 @@ struct ScatterLaunch {
     double *cell_pos;
     float4 *cell_posf;
     double *pos_copy;                // when not null: a copy of pos (atom order)
+    int *slot_cell;                  // cell of each cell-order slot
     CellGrid g;                      // one system
     const SysDesc *sys;              // batches
     const int *sys_of;
@@ -234,6 +235,7 @@ struct SearchLaunch {
     double rc2;
     float rcs;
     const int *cell_start, *cell_count, *cell_atoms, *cell_of;
+    const int *slot_cell;            // cell of each cell-order slot
     const double *cell_pos;
     const float4 *cell_posf;
     int cap;

@@ -93,7 +93,9 @@ __global__ void k_scatter(ScatterLaunch a)
     for (int it = r.begin; it < r.end; it += r.stride) {
         const int i = it * blockDim.x + threadIdx.x;
         if (i >= nn) continue;
-        const int slot = a.cell_start[a.cell_of[i]] + a.rank[i];
+        const int ci = a.cell_of[i];
+        const int slot = a.cell_start[ci] + a.rank[i];
+        a.slot_cell[slot] = ci;
         const double x = a.pos[3 * (size_t)i + 0], y = a.pos[3 * (size_t)i + 1], z = a.pos[3 * (size_t)i + 2];
         const CellGrid &g = BATCHED ? a.sys[a.sys_of[i]].g : a.g;
         a.cell_atoms[slot] = i;
@@ -222,10 +224,23 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
     const int tl = threadIdx.x;
     const int n = BATCHED ? a.dims->n_atoms : a.n;
     const ItemRange items = xcd_items((n + kSearchThreads - 1) / kSearchThreads);
+    // the atom of cell-order slot t and its cell, loaded one iteration ahead
+    float4 fi_next = make_float4(0.f, 0.f, 0.f, 0.f);
+    int cell_next = 0;
+    auto fetch = [&](int it2) {
+        const int t2 = it2 * kSearchThreads + tl;
+        if (it2 < items.end && t2 < n) {
+            fi_next = a.cell_posf[t2];
+            cell_next = a.slot_cell[t2];
+        }
+    };
+    fetch(items.begin);
     for (int it = items.begin; it < items.end; it += items.stride) {
         const int t = it * kSearchThreads + tl;
+        const float4 fi = fi_next;
+        const int cell_t = cell_next;
+        fetch(it + items.stride);
         if (t >= n) continue;
-        const float4 fi = a.cell_posf[t];
         const int i = __float_as_int(fi.w);
         int coff = 0;
         int *sys_flags = nullptr;
@@ -238,7 +253,7 @@ __global__ __launch_bounds__(kSearchThreads) void k_search_atoms(SearchLaunch a)
         } else {
             g = a.g;
         }
-        const int c = a.cell_of[i] - coff;
+        const int c = cell_t - coff;
         const int cz = c % g.nc[2], cy = (c / g.nc[2]) % g.nc[1], cx = c / (g.nc[1] * g.nc[2]);
         const int n0 = min(g.nc[0], 3), n1 = min(g.nc[1], 3), n2 = min(g.nc[2], 3);
         const bool shifted = n0 == 3 && n1 == 3 && n2 == 3;

@@ -167,7 +167,7 @@ struct Lane {
     Dev<double> pos, cell_pos, own, planes, forces, eatom, out;
     Dev<float4> cell_posf;
     Dev<int> long_rows;
-    Dev<int> types, sys_of, cell_of, rank, cell_count, cell_start, cell_atoms, scan_tmp;
+    Dev<int> types, sys_of, cell_of, rank, cell_count, cell_start, cell_atoms, slot_cell, scan_tmp;
     Dev<int> ell, row_count, pcount, drop_list;   // ell: neighbour rows, row i at i * cap
     Dev<int> kept;   // kept-neighbour lists: A x kKeptFast, then A x kRecCap
     Dev<int> ctl;   // [0] flags, [1] dropped count, [2] long rows, [3 ..] per-system status
@@ -261,6 +261,7 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.cell_count.alloc(NC, tot));
     SRV_TRY(L.cell_start.alloc(NC + 1, tot));
     SRV_TRY(L.cell_atoms.alloc(A, tot));
+    SRV_TRY(L.slot_cell.alloc(A, tot));
     SRV_TRY(L.scan_tmp.alloc(std::max(scan_tmp_size((int)NC), scan_tmp_size((int)A)), tot));
     SRV_TRY(L.ell.alloc(E, tot));
     SRV_TRY(L.row_count.alloc(A, tot));
@@ -288,6 +289,7 @@ void free_lane(Lane &L)
     L.cell_posf.release(); L.long_rows.release();
     L.eatom.release(); L.out.release(); L.types.release(); L.sys_of.release(); L.cell_of.release();
     L.rank.release(); L.cell_count.release(); L.cell_start.release(); L.cell_atoms.release();
+    L.slot_cell.release();
     L.scan_tmp.release(); L.ell.release(); L.row_count.release(); L.kept.release();
     L.pcount.release();
     L.drop_list.release(); L.ctl.release(); L.recs.release(); L.desc.release();
@@ -314,6 +316,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     sca.rank = L.rank.p;
     sca.cell_start = L.cell_start.p;
     sca.cell_atoms = L.cell_atoms.p;
+    sca.slot_cell = L.slot_cell.p;
     sca.cell_pos = L.cell_pos.p;
     sca.cell_posf = L.cell_posf.p;
     sca.sys = L.desc.p;
@@ -330,6 +333,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     sl.cell_start = L.cell_start.p;
     sl.cell_count = L.cell_count.p;
     sl.cell_atoms = L.cell_atoms.p;
+    sl.slot_cell = L.slot_cell.p;
     sl.cell_of = L.cell_of.p;
     sl.cell_pos = L.cell_pos.p;
     sl.cell_posf = L.cell_posf.p;

@@ -68,7 +68,7 @@ struct tersoff_ctx {
     DevBuf<int> kept;   // kept-neighbour lists: n x kKeptFast, then n x kRecCap
     DevBuf<unsigned char> recs;
     DevBuf<double> own, planes;
-    DevBuf<int> cell_of, rank, cell_count, cell_start, cell_atoms;
+    DevBuf<int> cell_of, rank, cell_count, cell_start, cell_atoms, slot_cell;
     DevBuf<double> cell_pos;
     DevBuf<float4> cell_posf;
     DevBuf<int> long_rows;
@@ -267,7 +267,7 @@ void tersoff_destroy(tersoff_ctx *c)
     c->kept.release(); c->own.release(); c->planes.release();
     c->pcount.release(); c->drop_list.release(); c->recs.release();
     c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
-    c->cell_atoms.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
+    c->cell_atoms.release(); c->slot_cell.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
     c->cell_posf.release(); c->long_rows.release();
     c->scan_tmp.release(); c->misc.release(); c->partials.release(); c->force_scratch.release();
     c->counters.release(); c->counts.release();
@@ -380,6 +380,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, c->cell_count.ensure(ncell));
     HIP_TRY(c, c->cell_start.ensure(ncell + 1));
     HIP_TRY(c, c->cell_atoms.ensure(N));
+    HIP_TRY(c, c->slot_cell.ensure(N));
     HIP_TRY(c, c->cell_pos.ensure(3 * (size_t)N));
     HIP_TRY(c, c->cell_posf.ensure((size_t)N + kPosPad));
     HIP_TRY(c, c->long_rows.ensure((size_t)N));
@@ -413,6 +414,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     sca.cell_pos = c->cell_pos.p;
     sca.cell_posf = c->cell_posf.p;
     sca.pos_copy = c->pos_build.p;
+    sca.slot_cell = c->slot_cell.p;
     sca.g = g;
     HIP_TRY(c, launch_scatter_cells(sca, 0, s));
     SearchLaunch sl{};
@@ -424,6 +426,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     sl.cell_count = c->cell_count.p;
     sl.cell_atoms = c->cell_atoms.p;
     sl.cell_of = c->cell_of.p;
+    sl.slot_cell = c->slot_cell.p;
     sl.cell_pos = c->cell_pos.p;
     sl.cell_posf = c->cell_posf.p;
     sl.row_count = c->row_count.p;
