@@ -158,6 +158,17 @@ def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None,
     return res
 
 
+def ablate(system, table, args, default_res, sigma=0.01):
+    """Lane-per-j of one centre atom (one atom per wavefront batch) against the
+    default lane-per-packed-pair mapping, mixed precision."""
+    log(f"[bench] n={system.n}: one centre atom per wavefront (J-scheme ablation)")
+    r = measure_workload(system, table, max(args.steps, 10), args.warmup, ("mixed",), batch_atoms=1,
+                         sigma=sigma)["mixed"]
+    return {"lane_per_pair_main_ms": default_res["main_ms"], "lane_per_j_main_ms": r["main_ms"],
+            "lane_per_j_slowdown": r["main_ms"] / default_res["main_ms"],
+            "lane_per_pair_ms_per_step": default_res["ms_per_step"], "lane_per_j_ms_per_step": r["ms_per_step"]}
+
+
 def cpu_baseline(system, table, target_s=12.0):
     """The FP64 oracle on the host cores: full neighbour list, then the
     compute over a leading sample of centre atoms sized to ~target_s."""
@@ -313,6 +324,8 @@ def main():
     ap.add_argument("--no-32k", action="store_true")
     ap.add_argument("--no-256k", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the lane-per-j vs lane-per-pair comparison on the 32k and 256k workloads")
     ap.add_argument("--batch-atoms", type=int, default=0)
     ap.add_argument("--precision", choices=("both", "mixed", "fp64", "single"), default="both",
                     help="profiling runs may time one precision of the 2M-atom workload only (no JSON line)")
@@ -342,6 +355,7 @@ def main():
     res = measure_workload(big, table, args.steps, args.warmup, ("mixed", "fp64", "single"), args.batch_atoms)
     mixed, fp64, single = res["mixed"], res["fp64"], res["single"]
 
+    ablation = {}
     extra_32k = None
     if not args.no_32k:
         small = W.si_32k()
@@ -351,6 +365,8 @@ def main():
                              compute_ms=r32[p]["compute_ms"], main_ms=r32[p]["main_ms"],
                              build_ms=r32[p]["build_ms"]) for p in r32}
         extra_32k["mixed_vs_fp64_speedup"] = r32["mixed"]["value"] / r32["fp64"]["value"]
+        if not args.no_ablation:
+            ablation["si_32k"] = ablate(small, table, args, r32["mixed"])
 
     extra_256k = None
     if not args.no_256k:
@@ -366,6 +382,8 @@ def main():
                               counts_per_atom={k: v / dis.n for k, v in r256[p]["counts"].items()})
                       for p in r256}
         extra_256k["mixed_vs_fp64_speedup"] = r256["mixed"]["value"] / r256["fp64"]["value"]
+        if not args.no_ablation:
+            ablation["disordered_256k"] = ablate(dis, t2, args, r256["mixed"], sigma=0.005)
 
     serve = None
     if not args.no_serve:
@@ -433,6 +451,10 @@ def main():
         "counts_per_atom": {k: v / big.n for k, v in mixed["counts"].items()},
         "si_32k": extra_32k,
         "disordered_256k_two_species": extra_256k,
+        "f3_ablation": dict(ablation, note=(
+            "compute-kernel time per evaluation (mixed) with one centre atom per wavefront, its packed "
+            "neighbours on the lanes (the paper's J scheme on a 64-lane wavefront), against the default "
+            "batches of centre atoms whose packed pairs fill the lanes (I and J together)")) if ablation else None,
         "serve": serve,
     }
     print(json.dumps(line), flush=True)
