@@ -611,10 +611,11 @@ __device__ __forceinline__ void exp_term(const ParamR<real> &q, real rj, real rk
 // SINGLE (with real = float): the all-FP32 variant -- the zeta -> b power and
 // each lane's sum of the force terms on j in FP32 as well; FP64 remains only
 // in the displacement (packing) and in the sums across lanes and atoms.
-template <typename real, bool ONE, bool BATCHED, bool SINGLE>
+template <typename real, bool ONE, bool BATCHED, bool SINGLE, bool NOL3>
 __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable tab)
 {
     static_assert(!SINGLE || sizeof(real) == 4, "the single-precision variant computes in float");
+    static_assert(!NOL3 || ONE, "the lambda3-free variant is a one-species kernel");
     using facc = typename std::conditional<SINGLE, float, double>::type;   // per-lane force sum
     __shared__ Shared<real, ONE> sh;
     __shared__ double sev[BATCHED ? kScap : 1][BATCHED ? 7 : 1];   // per-slot energy and virial
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
     // exp(lambda3 (r_ij - r_ik)) then separates into per-slot exponentials
     // (when they stay far from overflow)
     const ParamR<real> q0 = ptab[0];
-    const bool sep = ONE && q0.m == real(1) && q0.lam3 != real(0) &&
+    const bool sep = !NOL3 && ONE && q0.m == real(1) && q0.lam3 != real(0) &&
                      fabs((double)q0.lam3) * (2.0 * (double)q0.R - (double)q0.Rin) < 40.0;
 
     double e_acc = 0.0;
@@ -704,7 +705,10 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
 
             // exp((lambda3 (r_a - r_b))^m) and its derivative with respect to r_a
             auto ex_term = [&](const ParamR<real> &q, int sa, real ra, int sbb, real rbb, real &ex, real &dex) {
-                if (ONE && sep) {
+                if constexpr (NOL3) {
+                    ex = real(1);   // lambda3 = 0: the factor is 1 in every triplet
+                    dex = real(0);
+                } else if (ONE && sep) {
                     ex = sh.ep[sa] * sh.em[sbb];
                     dex = q0.lam3 * ex;
                 } else {
@@ -1126,29 +1130,47 @@ int occupancy_grid(const void *kern, long long work_items, int max_per_cu = 1 <<
     return (int)(g < 1 ? 1 : g);
 }
 
-template <typename real, bool ONE, bool BATCHED, bool SINGLE>
-void grids_for(int n, int atoms_per_batch, int grids[3])
+// Instances of the compute kernel: precision x kind, kind 0 several species,
+// 1 one species, 2 one species without the lambda3 term (lambda3 = 0).
+template <typename T>
+struct TypeTag {
+    using type = T;
+};
+template <typename R, bool O, bool S, bool N>
+struct KernelTag {
+    using real = R;
+    static constexpr bool one = O, single = S, nol3 = N;
+};
+
+int table_kind(const DeviceTable &t) { return t.ntypes != 1 ? 0 : (t.lam3_zero ? 2 : 1); }
+
+template <typename F>
+void with_kernel(int prec, int kind, F &&f)
 {
-    grids[0] = occupancy_grid((const void *)k_pack<real, ONE, BATCHED>,
-                              ((long long)n + atoms_per_batch - 1) / atoms_per_batch, kPackWavesPerCU);
-    grids[1] = occupancy_grid((const void *)k_tersoff<real, ONE, BATCHED, SINGLE>,
-                              ((long long)n + atoms_per_batch - 1) / atoms_per_batch);
-    grids[2] = kBigGrid;
+    auto by_kind = [&](auto r_tag, auto s_tag) {
+        using R = typename decltype(r_tag)::type;
+        constexpr bool S = decltype(s_tag)::value;
+        if (kind == 0) f(KernelTag<R, false, S, false>{});
+        else if (kind == 1) f(KernelTag<R, true, S, false>{});
+        else f(KernelTag<R, true, S, true>{});
+    };
+    if (prec == kPrecSingle) by_kind(TypeTag<float>{}, std::true_type{});
+    else if (prec == kPrecMixed) by_kind(TypeTag<float>{}, std::false_type{});
+    else by_kind(TypeTag<double>{}, std::false_type{});
 }
 
 template <bool BATCHED>
-void grids_dispatch(int prec, bool one_type, int n, int atoms_per_batch, int grids[3])
+void grids_dispatch(int prec, const DeviceTable &t, int n, int atoms_per_batch, int grids[3])
 {
-    if (prec == kPrecSingle) {
-        if (one_type) grids_for<float, true, BATCHED, true>(n, atoms_per_batch, grids);
-        else grids_for<float, false, BATCHED, true>(n, atoms_per_batch, grids);
-    } else if (prec == kPrecMixed) {
-        if (one_type) grids_for<float, true, BATCHED, false>(n, atoms_per_batch, grids);
-        else grids_for<float, false, BATCHED, false>(n, atoms_per_batch, grids);
-    } else {
-        if (one_type) grids_for<double, true, BATCHED, false>(n, atoms_per_batch, grids);
-        else grids_for<double, false, BATCHED, false>(n, atoms_per_batch, grids);
-    }
+    const long long batches = ((long long)n + atoms_per_batch - 1) / atoms_per_batch;
+    with_kernel(prec, table_kind(t), [&](auto tag) {
+        using K = decltype(tag);
+        grids[0] = occupancy_grid((const void *)k_pack<typename K::real, K::one, BATCHED>, batches,
+                                  kPackWavesPerCU);
+        grids[1] = occupancy_grid((const void *)k_tersoff<typename K::real, K::one, BATCHED, K::single, K::nol3>,
+                                  batches);
+    });
+    grids[2] = kBigGrid;
 }
 
 template <bool BATCHED>
@@ -1167,26 +1189,19 @@ void pack_dispatch(const PackLaunch &a, const DeviceTable &t, int prec, int grid
 template <bool BATCHED>
 void compute_dispatch(const ComputeLaunch &a, const DeviceTable &t, int prec, int grid, hipStream_t s)
 {
-    const bool one = t.ntypes == 1;
     const dim3 G(grid), W(kWave);
-    if (prec == kPrecSingle) {
-        if (one) hipLaunchKernelGGL((k_tersoff<float, true, BATCHED, true>), G, W, 0, s, a, t);
-        else hipLaunchKernelGGL((k_tersoff<float, false, BATCHED, true>), G, W, 0, s, a, t);
-    } else if (prec == kPrecMixed) {
-        if (one) hipLaunchKernelGGL((k_tersoff<float, true, BATCHED, false>), G, W, 0, s, a, t);
-        else hipLaunchKernelGGL((k_tersoff<float, false, BATCHED, false>), G, W, 0, s, a, t);
-    } else {
-        if (one) hipLaunchKernelGGL((k_tersoff<double, true, BATCHED, false>), G, W, 0, s, a, t);
-        else hipLaunchKernelGGL((k_tersoff<double, false, BATCHED, false>), G, W, 0, s, a, t);
-    }
+    with_kernel(prec, table_kind(t), [&](auto tag) {
+        using K = decltype(tag);
+        hipLaunchKernelGGL((k_tersoff<typename K::real, K::one, BATCHED, K::single, K::nol3>), G, W, 0, s, a, t);
+    });
 }
 
 }  // namespace
 
-void compute_grids(int prec, bool one_type, bool batched, int n, int atoms_per_batch, int grids[3])
+void compute_grids(int prec, const DeviceTable &t, bool batched, int n, int atoms_per_batch, int grids[3])
 {
-    if (batched) grids_dispatch<true>(prec, one_type, n, atoms_per_batch, grids);
-    else grids_dispatch<false>(prec, one_type, n, atoms_per_batch, grids);
+    if (batched) grids_dispatch<true>(prec, t, n, atoms_per_batch, grids);
+    else grids_dispatch<false>(prec, t, n, atoms_per_batch, grids);
 }
 
 size_t record_bytes(int prec) { return prec != kPrecFP64 ? sizeof(Rec<float>) : sizeof(Rec<double>); }

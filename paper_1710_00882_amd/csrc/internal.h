@@ -49,6 +49,7 @@ struct DeviceTable {
     const ParamR<double> *pd;   // ntypes^3 entries
     const ParamX *px;           // ntypes^3 entries
     const double *packsq;       // ntypes^2, symmetric: packing radius^2 of a (ti, tn) entry
+    int lam3_zero;              // one species with lambda3 = 0 (the exponential factor is 1)
 };
 
 // Cell grid of one periodic box (cells at least the list radius wide).
@@ -159,7 +160,7 @@ struct ComputeLaunch {
 // Precisions (the values of tersoff_precision).
 enum : int { kPrecFP64 = 0, kPrecMixed = 1, kPrecSingle = 2, kNumPrec = 3 };
 
-void compute_grids(int prec, bool one_type, bool batched, int n, int atoms_per_batch, int grids[3]);
+void compute_grids(int prec, const DeviceTable &t, bool batched, int n, int atoms_per_batch, int grids[3]);
 size_t record_bytes(int prec);
 hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, int prec, int grid, hipStream_t s);
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec,

@@ -601,7 +601,7 @@ int server_create(const ServerEnv &env, const tersoff_serve_config &cfg, Server 
     S->rc = cutoff + cfg.skin;
     S->max_queued = cfg.max_queued > 0 ? (size_t)cfg.max_queued : 65536;
     for (int pr = 0; pr < kNumPrec; ++pr)
-        compute_grids(pr, env.ntypes == 1, true, S->max_atoms, kServeBatchAtoms, S->grids[pr]);
+        compute_grids(pr, env.tab, true, S->max_atoms, kServeBatchAtoms, S->grids[pr]);
     hipError_t e = hipSetDevice(env.device);
     for (int l = 0; l < kLanes && e == hipSuccess; ++l) e = alloc_lane(*S, S->lanes[l]);
     for (int l = 0; l < kLanes && e == hipSuccess; ++l)

@@ -252,6 +252,7 @@ int tersoff_create(const double *params, int32_t ntypes, tersoff_ctx **out)
     c->tab.pd = reinterpret_cast<const ParamR<double> *>(base + off_pd);
     c->tab.px = reinterpret_cast<const ParamX *>(base + off_px);
     c->tab.packsq = reinterpret_cast<const double *>(base + off_pk);
+    c->tab.lam3_zero = ntypes == 1 && params[TERSOFF_P_LAMBDA3] == 0.0;
     *out = c;
     return TERSOFF_OK;
 }
@@ -321,7 +322,7 @@ int tersoff_set_batch_atoms(tersoff_ctx *c, int32_t atoms)
     if (c->built) {
         int gmax = 0;
         for (int pr = 0; pr < kNumPrec; ++pr) {
-            compute_grids(pr, c->ntypes == 1, false, c->n, atoms, c->grid[pr]);
+            compute_grids(pr, c->tab, false, c->n, atoms, c->grid[pr]);
             gmax = std::max(gmax, c->grid[pr][1]);
         }
         HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
@@ -471,7 +472,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     if (!c->batch_atoms_set) c->atoms_per_batch = N < 131072 ? 16 : 32;
     int gmax = 0;
     for (int pr = 0; pr < kNumPrec; ++pr) {
-        compute_grids(pr, c->ntypes == 1, false, N, c->atoms_per_batch, c->grid[pr]);
+        compute_grids(pr, c->tab, false, N, c->atoms_per_batch, c->grid[pr]);
         gmax = std::max(gmax, c->grid[pr][1]);
     }
     HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
