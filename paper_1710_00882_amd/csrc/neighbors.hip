@@ -528,7 +528,7 @@ __global__ void k_scan_tiles(const int *__restrict__ in, int *__restrict__ out, 
     sh[threadIdx.x] = mx;
     __syncthreads();
     for (int off = kScanThreads / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + off]);
+        if ((int)threadIdx.x < off) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + off]);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -557,7 +557,7 @@ __global__ void k_scan_tile_sums(int *__restrict__ tile_sum, const int *__restri
     sh[threadIdx.x] = mx;
     __syncthreads();
     for (int off = kScanThreads / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + off]);
+        if ((int)threadIdx.x < off) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + off]);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
