@@ -190,6 +190,30 @@ def test_error_paths():
         Tersoff(bad_tab)
 
 
+def test_atom_count_limits():
+    """n = 0 and n = 2^24 + 1 are rejected before any device access (the
+    pointers are never read); n = 1 (a lone atom) gives E = 0, F = 0."""
+    import ctypes
+    import torch
+    from paper_1710_00882_amd import Tersoff
+    m = Tersoff(W.si_table())
+    box = np.array([20.0, 20.0, 20.0])
+    bp = box.ctypes.data_as(ctypes.c_void_p)
+    pos = torch.tensor([[1.0, 2.0, 3.0]], dtype=torch.float64, device="cuda")
+    types = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for n in (0, (1 << 24) + 1):
+        st = m._lib.tersoff_build_neighbors(m._h, pos.data_ptr(), types.data_ptr(), n, bp, 3.0, 1.0, None)
+        assert st == -1, (n, st)
+        assert "n must be in" in m._lib.tersoff_last_error(m._h).decode()
+    m.build_neighbors(pos, types, box)
+    for prec in ("fp64", "mixed", "single"):
+        out, f = m.compute(pos, prec)
+        torch.cuda.synchronize()
+        assert np.all(out.cpu().numpy() == 0.0) and np.all(f.cpu().numpy() == 0.0)
+    assert m.counts() == (0, 0, 0)
+    m.close()
+
+
 def test_overflow_is_reported_not_crashing():
     import torch
     from paper_1710_00882_amd import Tersoff
