@@ -36,7 +36,6 @@ struct M<float> {
     static __device__ __forceinline__ float exp(float x) { return expf(x); }
     static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    static __device__ __forceinline__ void sincos(float x, float *s, float *c) { ::sincosf(x, s, c); }
 };
 
 template <>
@@ -44,7 +43,6 @@ struct M<double> {
     static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
     static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-    static __device__ __forceinline__ void sincos(double x, double *s, double *c) { ::sincos(x, s, c); }
 };
 
 // Minimum-image component: s = rint(t / L) evaluated as rint(t * (1/L)).
@@ -230,6 +228,36 @@ __device__ __forceinline__ void pair_terms(const ParamR<double> &q, double r, do
     dfa = -q.lam2 * fa;
 }
 
+constexpr double inv_factorial(int n)
+{
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return 1.0 / f;
+}
+
+// sin x and cos x for |x| <= pi/2 (the switching-function argument never
+// leaves that interval, up to rounding) from their Taylor series, by Horner's
+// rule in x^2: sin through the x^13 term and cos through x^14 in float
+// (truncation below 7e-10 on the interval), through x^23 and x^24 in double
+// (below 1e-20).  The general range reduction of the library routines,
+// several times longer than the polynomials, is not needed.
+template <typename real>
+__device__ __forceinline__ void sincos_halfpi(real x, real &s, real &c)
+{
+    constexpr int K = sizeof(real) == 4 ? 6 : 11;   // sin: terms k = 0..K of (-1)^k x^(2k+1) / (2k+1)!
+    const real z = x * x;
+    real ps = real((K & 1 ? -1.0 : 1.0) * inv_factorial(2 * K + 1));
+    real pc = real(((K + 1) & 1 ? -1.0 : 1.0) * inv_factorial(2 * K + 2));   // cos: k = 0..K+1
+#pragma unroll
+    for (int k = K; k >= 1; --k) {
+        ps = ps * z + real((k & 1 ? 1.0 : -1.0) * inv_factorial(2 * k - 1));
+        pc = pc * z + real((k & 1 ? -1.0 : 1.0) * inv_factorial(2 * k));
+    }
+    pc = pc * z + real(1);
+    s = x * ps;
+    c = pc;
+}
+
 // Switching function f_C(r) and its derivative.  r - R is exact in the
 // switching zone (Sterbenz), and the rounding errors of R and pi/(2D) in the
 // working precision are added back, so f_C carries no systematic bias.
@@ -242,7 +270,7 @@ __device__ __forceinline__ void cutoff_terms(const ParamR<real> &q, real r, real
         const real dr = (r - q.R) - q.R_lo;
         const real arg = dr * q.half_pi_D + dr * q.half_pi_D_lo;
         real sn, cn;
-        M<real>::sincos(arg, &sn, &cn);
+        sincos_halfpi(arg, sn, cn);
         fc = real(0.5) - real(0.5) * sn;
         dfc = real(-0.5) * (q.half_pi_D + q.half_pi_D_lo) * cn;
     }
@@ -283,7 +311,7 @@ constexpr int kThirdBit = 27;
 static_assert(kMaxTypes <= 4, "two type bits and four third-atom bits per record");
 __device__ __forceinline__ int rec_type(int jm) { return (jm >> kTypeShift) & 3; }
 
-constexpr int kChunks = 4;     // 64-entry chunks whose loads are issued together
+constexpr int kChunks = 8;     // 64-entry chunks whose loads are issued together
 constexpr int kOwnerCap = 1024;   // batch entries whose atom is looked up in a table (the rest: binary search)
 static_assert(kKeptFast == 8, "the first block of a kept list is two 16-byte words");
 
@@ -317,6 +345,7 @@ __device__ __forceinline__ int kept_position(const int *__restrict__ kept, const
     ended = len < kKeptFast;
     if (pos < 0 && !ended) {
         const int *km = kept_more + (size_t)m * kRecCap;
+#pragma unroll 1
         for (int q = kKeptFast; q < kRecCap; ++q) {
             const int x = km[q];
             if (x < 0) {
@@ -361,11 +390,21 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
     __shared__ int eoff[kWave + 1];
     __shared__ int kst[kKeptFast][kWave];   // first kept neighbours of the batch's atoms
     __shared__ unsigned char owner[kOwnerCap];   // batch atom of each of the first kOwnerCap entries
+    // radius tables, read before the first store so that no reload of them
+    // has to wait behind the record stores
+    __shared__ double psq_s[ONE ? 1 : kMaxTypes * kMaxTypes];
+    __shared__ double cut_s[ONE ? 1 : kMaxTypes * kMaxTypes * kMaxTypes];
     const int lane = threadIdx.x;
     Rec<real> *recs = static_cast<Rec<real> *>(a.recs);
     const int B = a.atoms_per_batch;
     const int n = BATCHED ? *a.n_dev : a.n;
     const int nbatch = (n + B - 1) / B;
+    const double psq0 = tab.packsq[0];
+    if constexpr (!ONE) {
+        const int nt = tab.ntypes;
+        for (int q = lane; q < nt * nt; q += kWave) psq_s[q] = tab.packsq[q];
+        for (int q = lane; q < nt * nt * nt; q += kWave) cut_s[q] = tab.px[q].cutsq;
+    }
 
     const ItemRange items = xcd_items(nbatch);
     // the per-atom inputs of a batch, loaded one batch ahead so that their
@@ -421,31 +460,26 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
         const int e_begin = eoff[0], e_end = eoff[nb];
         int npacked = 0;   // kept entries of the batch so far (records beyond an atom's cap excluded)
         for (int eb = e_begin; eb < e_end; eb += kWave * kChunks) {
+            // All loads of the kChunks chunks are issued unconditionally (lanes
+            // past the batch's last entry re-read that entry and are masked
+            // below): a load inside a branch is waited for at the branch's end,
+            // which would serialise the chunks' gathers.
             int jv[kChunks], tv[kChunks];
             double xv[kChunks], yv[kChunks], zv[kChunks];
-            int ev[kChunks], alv[kChunks];
+            int alv[kChunks];
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
-                const int e = eb + c * kWave + lane;
-                jv[c] = -1;
-                alv[c] = 0;
-                ev[c] = 0;
-                if (e < e_end) {
-                    const int al = e < kOwnerCap ? (int)owner[e] : find_seg(eoff, nb, e);
-                    alv[c] = al;
-                    ev[c] = (a0 + al) * a.cap + (e - eoff[al]);   // row-buffer index of the entry
-                    jv[c] = a.ell[ev[c]];
-                }
+                const int ec = min(eb + c * kWave + lane, e_end - 1);
+                const int al = ec < kOwnerCap ? (int)owner[ec] : find_seg(eoff, nb, ec);
+                alv[c] = al;
+                // row-buffer index of the entry
+                jv[c] = a.ell[(size_t)(a0 + al) * a.cap + (ec - eoff[al])];
             }
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
-                xv[c] = yv[c] = zv[c] = 0.0;
-                tv[c] = 0;
-                if (jv[c] >= 0) {
-                    const double *pj = a.pos + 3 * (size_t)jv[c];
-                    xv[c] = pj[0]; yv[c] = pj[1]; zv[c] = pj[2];
-                    if (!ONE) tv[c] = a.types[jv[c]];
-                }
+                const double *pj = a.pos + 3 * (size_t)jv[c];
+                xv[c] = pj[0]; yv[c] = pj[1]; zv[c] = pj[2];
+                tv[c] = ONE ? 0 : a.types[jv[c]];
             }
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
@@ -467,7 +501,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                         dz = image(zv[c] - zi[al], a.L[2], a.invL[2]);
                     }
                     rsq = norm2(dx, dy, dz);
-                    const double psq = ONE ? tab.packsq[0] : tab.packsq[ti[al] * tab.ntypes + tv[c]];
+                    const double psq = ONE ? psq0 : psq_s[ti[al] * tab.ntypes + tv[c]];
                     acc = rsq < psq;
                 }
                 const unsigned long long m = __ballot(acc);
@@ -487,9 +521,9 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                             mask |= (1 << kPairBit) | (1 << kThirdBit);
                         } else {
                             const int nt = tab.ntypes, t_i = ti[al], t_n = tv[c];
-                            if (rsq < tab.px[(t_i * nt + t_n) * nt + t_n].cutsq) mask |= 1 << kPairBit;
+                            if (rsq < cut_s[(t_i * nt + t_n) * nt + t_n]) mask |= 1 << kPairBit;
                             for (int t = 0; t < nt; ++t)
-                                if (rsq < tab.px[(t_i * nt + t) * nt + t_n].cutsq) mask |= 1 << (kThirdBit + t);
+                                if (rsq < cut_s[(t_i * nt + t) * nt + t_n]) mask |= 1 << (kThirdBit + t);
                         }
                         o.jm = mask;
                         o.dx = (real)dx;
