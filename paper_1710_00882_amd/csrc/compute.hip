@@ -20,6 +20,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 namespace tsf {
@@ -1150,15 +1152,32 @@ __global__ void k_fill_zero(T *p, size_t count)
 
 // Workgroups of a persistent grid: the resident limit per CU (at most
 // max_per_cu) times the CU count, at most one per work item.
+// Resident workgroups per CU of a kernel and the device's CU count, queried
+// once per (device, kernel) and kept: every build sizes its grids from them.
 int occupancy_grid(const void *kern, long long work_items, int max_per_cu = 1 << 20)
 {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    per_cu = std::min(per_cu, max_per_cu);
-    int dev = 0, cus = 256;
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, std::pair<int, int>> known;
+    int dev = 0;
     (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int per_cu = 0, cus = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = known.find({dev, kern});
+        if (it != known.end()) {
+            per_cu = it->second.first;
+            cus = it->second.second;
+        }
+    }
+    if (cus == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        cus = 256;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        std::lock_guard<std::mutex> lock(mu);
+        known[{dev, kern}] = {per_cu, cus};
+    }
+    per_cu = std::min(per_cu, max_per_cu);
     long long g = (long long)per_cu * cus;
     if (g > work_items) g = work_items;
     return (int)(g < 1 ? 1 : g);

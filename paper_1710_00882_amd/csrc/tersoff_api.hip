@@ -75,6 +75,7 @@ struct tersoff_ctx {
     DevBuf<int> ell, row_count, scan_tmp, misc;   // misc: [0] flags, [1] max row, [2] check flags
     DevBuf<double> partials, force_scratch;
     DevBuf<long long> counters, counts;
+    int *host_misc = nullptr;   // pinned: the build's status words, copied back without staging
 
     // profiling: event pairs recorded around compute / build launches
     bool profiling = false;
@@ -280,6 +281,7 @@ void tersoff_destroy(tersoff_ctx *c)
     for (auto &pr : c->ev_pack) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->d_table) (void)hipFree(c->d_table);
+    if (c->host_misc) (void)hipHostFree(c->host_misc);
     delete c;
 }
 
@@ -434,6 +436,9 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     sl.long_rows = c->long_rows.p;
     sl.n_long = c->misc.p + 4;
     HIP_TRY(c, c->own.ensure(3 * (size_t)N));
+    if (!c->host_misc) HIP_TRY(c, hipHostMalloc((void **)&c->host_misc, 16 * sizeof(int), hipHostMallocDefault));
+    HIP_TRY(c, c->counts.ensure(2));
+    HIP_TRY(c, hipMemsetAsync(c->counts.p, 0, 2 * sizeof(long long), s));
     int host[8] = {};
     for (int attempt = 0; attempt < 2; ++attempt) {
         if ((long long)N * c->ell_cap >= (1LL << 31)) return fail(c, TERSOFF_E_INVALID, "n x row capacity >= 2^31");
@@ -444,10 +449,11 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
         sl.ell = c->ell.p;
         HIP_TRY(c, launch_search(sl, 0, s));
         HIP_TRY(c, launch_exclusive_scan(c->row_count.p, c->offsets.p, N, c->scan_tmp.p, c->misc.p + 1, s));
-        HIP_TRY(c, hipMemcpyAsync(host, c->misc.p, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipMemcpyAsync(&host[5], c->offsets.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(c->host_misc, c->misc.p, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipMemcpyAsync(c->host_misc + 5, c->offsets.p + N, sizeof(int), hipMemcpyDeviceToHost, s));
         if (evb1) HIP_TRY(c, hipEventRecord(evb1, s));
         HIP_TRY(c, hipStreamSynchronize(s));
+        std::copy(c->host_misc, c->host_misc + 8, host);
         if (host[2] & 1) return fail(c, TERSOFF_E_INVALID, "non-finite position");
         if (host[2] & 2) return fail(c, TERSOFF_E_INVALID, "type out of range");
         if (host[1] <= c->ell_cap) break;
@@ -477,8 +483,6 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     }
     HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
     HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
-    HIP_TRY(c, c->counts.ensure(2));
-    HIP_TRY(c, hipMemset(c->counts.p, 0, 2 * sizeof(long long)));
     c->built = true;
     return TERSOFF_OK;
 }
