@@ -61,10 +61,10 @@ RECORD_BYTES = {"mixed": 16, "single": 16, "fp64": 32}
 # reads 0.5 of the bytes a copy moves, WRITE_SIZE 1.0).  Valid only for the
 # compute source it was measured on (its SHA-256 prefix).
 TRAFFIC_PROFILE = {
-    "source": "0e39a045e08a49a2",
-    "fetch_kib": 123007.6, "fetch_factor": 2.0,
-    "write_kib": 227264.1, "write_factor": 1.0,
-    "bytes_per_launch": 123007.6 * 1024 * 2.0 + 227264.1 * 1024 * 1.0,
+    "source": "48fc720dbc8268f5",
+    "fetch_kib": 123197.0, "fetch_factor": 2.0,
+    "write_kib": 227079.5, "write_factor": 1.0,
+    "bytes_per_launch": 123197.0 * 1024 * 2.0 + 227079.5 * 1024 * 1.0,
 }
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1710_00882_amd", "csrc", "compute.hip")
 
