@@ -3,7 +3,9 @@ times (default batch size, resident list, rebuild every 5th call): the
 32,000- and 2,048,000-atom silicon workloads and the 256,000-atom
 two-species disordered workload, against the FP64 oracle evaluated over
 every atom (its C implementation runs these sizes in seconds on the host
-cores).  Neighbour lists are compared bit for bit, work counts exactly,
+cores); and the serving benchmark's 4,096-configuration stream with its
+batch capacities, every result checked for status and total force and a
+sample across the size range against the oracle.  Neighbour lists are compared bit for bit, work counts exactly,
 energy / forces / virial at the stated tolerances; the total force (zero
 for any periodic configuration) is checked as a size-independent property.
 
@@ -110,3 +112,44 @@ def test_si_2m_ten_call_sequence():
 
 def test_disordered_256k_full_parity():
     _check_system("disordered_256k", W.disordered_256k(), W.two_species_table())
+
+
+def test_serve_stream_in_bench_configuration():
+    """The serving benchmark's stream (4,096 periodic Si cells of 64-4,096
+    atoms) with its capacities (262,144 atoms / 1,024 configurations per
+    batch): every configuration returns status 0 with a finite energy and a
+    near-zero total force, batches hold many configurations, and a sample of
+    configurations spanning the size range is at oracle parity, mixed and
+    FP64."""
+    from paper_1710_00882_amd import Tersoff
+    table = W.si_table()
+    systems = W.serve_stream(count=4096, seed=0)
+    sizes = np.array([s.n for s in systems])
+    order = np.argsort(sizes)
+    sample = sorted(set(order[np.linspace(0, len(systems) - 1, 20).astype(int)].tolist()))
+    m = Tersoff(table)
+    m.serve_start(max_batch_atoms=262144, max_batch_systems=1024, skin=W.SKIN)
+    try:
+        for prec in ("mixed", "fp64"):
+            say(f"[serve-full] {prec}: {len(systems)} configs, {int(sizes.sum())} atoms")
+            tickets, outs = [], []
+            for q, s in enumerate(systems):
+                f = np.zeros_like(s.pos)
+                tickets.append(m.submit(s.pos, s.types, s.box, prec, forces=f, tag=q))
+                outs.append(f)
+            res = [m.wait(t, 60000.0) for t in tickets]
+            assert all(r["status"] == 0 for r in res)
+            assert all(np.isfinite(r["energy"]) for r in res)
+            assert max(r["batch_systems"] for r in res) > 100
+            for s, r in zip(systems, res):
+                assert _momentum_ok(r["forces"], s.n), f"{prec} n={s.n}: total force {r['forces'].sum(axis=0)}"
+            for q in sample:
+                s, r = systems[q], res[q]
+                cut = W.table_cutoff(table)
+                off, idx = oracle.neighbors(s.pos, s.box, cut + W.SKIN)
+                Eo, Fo, Vo = _oracle(s.pos, s.types, s.box, table, off, idx)
+                assert_parity(r["energy"], r["forces"], r["virial"], Eo, Fo, Vo, s.n, prec,
+                              f"stream[{q}] n={s.n}")
+    finally:
+        m.serve_stop()
+        m.close()
