@@ -19,7 +19,8 @@
  * Readings where the paper is silent (it omits "trivial definitions"):
  *  - the factor 1/2 in Eq. (1) (each unordered bond is visited twice);
  *  - k != j in Eq. (3);
- *  - f_C(r) = 1 (r < R-D), 1/2 - 1/2 sin(pi/2 (r-R)/D) (R-D <= r < R+D), 0;
+ *  - f_C(r) = 1 (r < R-D), 1/2 - 1/2 sin(pi/2 (r-R)/D) (R-D <= r < R+D), 0
+ *    (evaluated as sin^2(pi/4 (R+D-r)/D), see cutoff_fn);
  *    f_R = A exp(-lambda1 r); f_A = -B exp(-lambda2 r);
  *    g(theta) = gamma (1 + c^2/d^2 - c^2/(d^2 + (cos theta - h)^2));
  *  - the exponent of Eq. (3) is (lambda3 (r_ij - r_ik))^m, m in {1, 3}
@@ -174,14 +175,21 @@ int64_t oracle_neighbors_cell(int64_t n, const double *pos, const double *box,
 
 /* --------------------------------------------------- functional forms */
 
+/* In the switching zone f_C = 1/2 - 1/2 sin(pi/2 (r-R)/D) is evaluated as
+ * sin^2(y), y = pi/4 (R+D-r)/D (the half-angle identity 1 - sin x =
+ * 2 sin^2(pi/4 - x/2)): the same function, without the cancellation of
+ * 1 - sin x near the cutoff, where f_C of a third atom is tiny but
+ * dV/dzeta ~ zeta^(eta-1) keeps its force term finite (the literal form
+ * loses all its digits within 1e-8 A of R + D).  f_C' = -pi/(4D) sin(2y). */
 static void cutoff_fn(double r, const double *p, double *fc, double *dfc)
 {
     double R = p[OR], D = p[ODC];
     if (r < R - D) { *fc = 1.0; *dfc = 0.0; }
     else if (r < R + D) {
-        double arg = ORACLE_PI / 2.0 * (r - R) / D;
-        *fc = 0.5 - 0.5 * sin(arg);
-        *dfc = -0.5 * cos(arg) * ORACLE_PI / (2.0 * D);
+        double y = ORACLE_PI / 4.0 * ((R + D) - r) / D;
+        double s = sin(y);
+        *fc = s * s;
+        *dfc = -ORACLE_PI / (4.0 * D) * sin(2.0 * y);
     } else { *fc = 0.0; *dfc = 0.0; }
 }
 

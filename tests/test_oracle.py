@@ -345,3 +345,81 @@ def test_partial_range_sums_to_whole():
     E2, F2, W2 = oracle.compute(s.pos, s.types, s.box, table, off, idx, 23, s.n, threads=4)
     assert E1 + E2 == pytest.approx(E, rel=1e-13)
     assert np.abs(F1 + F2 - F).max() < 1e-11
+
+
+def _trimer_energy_mp(pos, p):
+    """Energy of a three-atom cluster from Eq. 1-3 with the literal switching
+    function 1/2 - 1/2 sin(pi/2 (r - R)/D), in 50-digit arithmetic (mpmath),
+    where its cancellation near R + D costs nothing."""
+    import mpmath as mp
+    R, D = mp.mpf(p["R"]), mp.mpf(p["D"])
+
+    def fc(r):
+        if r < R - D:
+            return mp.mpf(1)
+        if r < R + D:
+            return mp.mpf("0.5") - mp.mpf("0.5") * mp.sin(mp.pi / 2 * (r - R) / D)
+        return mp.mpf(0)
+
+    def g(c):
+        c2, d2 = mp.mpf(p["c"]) ** 2, mp.mpf(p["d"]) ** 2
+        return mp.mpf(p["gamma"]) * (1 + c2 / d2 - c2 / (d2 + (mp.mpf(p["h"]) - c) ** 2))
+
+    def dist(a, b):
+        return mp.sqrt(sum((pos[b][x] - pos[a][x]) ** 2 for x in range(3)))
+
+    E = mp.mpf(0)
+    for i in range(3):
+        for j in range(3):
+            if j == i:
+                continue
+            rij = dist(i, j)
+            zeta = mp.mpf(0)
+            for k in range(3):
+                if k in (i, j):
+                    continue
+                rik = dist(i, k)
+                cos_t = sum((pos[j][x] - pos[i][x]) * (pos[k][x] - pos[i][x]) for x in range(3)) / (rij * rik)
+                zeta += fc(rik) * g(cos_t)
+            b = (1 + (mp.mpf(p["beta"]) * zeta) ** mp.mpf(p["eta"])) ** (-1 / (2 * mp.mpf(p["eta"])))
+            fr = mp.mpf(p["A"]) * mp.exp(-mp.mpf(p["lambda1"]) * rij)
+            fa = -mp.mpf(p["B"]) * mp.exp(-mp.mpf(p["lambda2"]) * rij)
+            E += fc(rij) * (fr + b * fa) / 2
+    return E
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6, 1e-8, 1e-10])
+def test_third_atom_near_cutoff_against_50_digits(eps):
+    """A bond at 2.35 A with a third atom eps inside R + D: f_C(r_ik) ~ eps^2
+    is tiny, but dV/dzeta ~ zeta^(eta - 1) keeps the third atom's force
+    finite (~ eps^(2 eta - 1)).  The oracle's forces must match the
+    derivative of the 50-digit energy to 1e-10 of the largest force, which
+    the literal 1/2 - 1/2 sin form misses by orders of magnitude below
+    eps ~ 1e-7 A (cancellation).  (The third atom's force is not checked
+    relative to itself: the FP64 rounding of r_ik alone moves it by
+    ~0.6 * 3e-16 / eps relative.)"""
+    import mpmath as mp
+    mp.mp.dps = 50
+    p = dict(W.SI)
+    cut = p["R"] + p["D"]
+    pos = [[0.0, 0.0, 0.0], [2.35, 0.0, 0.0], [0.3, cut - eps, 0.0]]
+    # place k exactly: r_ik = cut - eps in FP64 (the oracle sees FP64 positions)
+    y = math.sqrt((cut - eps) ** 2 - 0.09)
+    pos[2][1] = y
+    s = W.System(np.array(pos) + 10.0, np.zeros(3, np.int32), np.array([30.0, 30.0, 30.0]))
+    off, idx = oracle.neighbors(s.pos, s.box, cut + 1.0)
+    E, F, _ = oracle.compute(s.pos, s.types, s.box, W.si_table(), off, idx)
+    mpos = [[mp.mpf(v) for v in row] for row in s.pos]
+    Fref = np.zeros((3, 3))
+    for a in range(3):
+        for x in range(3):
+            def e_of(t, a=a, x=x):
+                q = [row[:] for row in mpos]
+                q[a][x] = t
+                return _trimer_energy_mp(q, p)
+            Fref[a, x] = -float(mp.diff(e_of, mpos[a][x]))
+    Eref = float(_trimer_energy_mp(mpos, p))
+    assert abs(E - Eref) < 1e-12 * abs(Eref)
+    fmax = np.abs(Fref).max()
+    assert np.abs(F - Fref).max() < 1e-10 * fmax
+    assert np.linalg.norm(Fref[2]) > 1e-5 * fmax   # the term really is there
