@@ -32,9 +32,13 @@ METRIC = "Tersoff E+F atoms/s mixed vs FP64 @32k–2M Si (VALU roofline %); serv
 UNIT = "atoms*evals/s"
 REBUILD_EVERY = 5
 
-# MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
-# Unpacked FP32 and FP64 issue at this rate; packed FP32 (twice the rate,
-# 157.3 TFLOP/s) is not generated: the HIP sources are compiled without it.
+# MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+# = 78.64 TFLOP/s for unpacked FP32 and FP64 instructions; packed FP32 issues
+# two per lane, the published FP32 vector peak of 157.3 TFLOP/s.  The roofline
+# fraction is reported against that FP32 vector peak (the figure the target
+# is stated against); the HIP sources are compiled without packed FP32, so
+# the unpacked issue rate, half of it, is the ceiling this code can reach and
+# is reported beside it.
 PEAK_ALU_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12      # 78.64
 PEAK_FP32_PACKED_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
@@ -67,6 +71,14 @@ TRAFFIC_PROFILE = {
     "bytes_per_launch": 123197.0 * 1024 * 2.0 + 227079.5 * 1024 * 1.0,
 }
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1710_00882_amd", "csrc", "compute.hip")
+
+
+def traffic_bytes():
+    """The measured HBM bytes per launch of the compute kernel, or None when
+    compute.hip has changed since the counters were taken."""
+    if TRAFFIC_PROFILE and TRAFFIC_PROFILE["source"] == source_hash(TRAFFIC_SOURCE):
+        return TRAFFIC_PROFILE["bytes_per_launch"]
+    return None
 
 
 def algorithmic_flops(P: int, T: int) -> float:
@@ -169,30 +181,60 @@ def ablate(system, table, args, default_res, sigma=0.01):
             "lane_per_pair_ms_per_step": default_res["ms_per_step"], "lane_per_j_ms_per_step": r["ms_per_step"]}
 
 
-def cpu_baseline(system, table, target_s=12.0):
-    """The FP64 oracle on the host cores: full neighbour list, then the
-    compute over a leading sample of centre atoms sized to ~target_s."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(system, table, runs=5, sample_s=0.8):
+    """The FP64 oracle on the host cores, as it stands: the cell-list build
+    (single-threaded) over the whole workload, and the compute over a leading
+    sample of centre atoms sized to ~sample_s per run, on all cores (at most
+    16, the host share of one GPU) and on one thread; each the median of
+    `runs` runs, scaled to the whole workload, the build amortised over the
+    rebuild interval."""
     import oracle
     from paper_1710_00882_amd import workloads as W
     threads = min(os.cpu_count() or 1, 16)
     cut = W.table_cutoff(table) + W.SKIN
-    t0 = time.perf_counter()
-    off, idx = oracle.neighbors(system.pos, system.box, cut)
-    t_nb = time.perf_counter() - t0
-    m0 = min(system.n, 20000)
-    t0 = time.perf_counter()
-    oracle.compute(system.pos, system.types, system.box, table, off, idx, 0, m0, threads=threads)
-    t_cal = time.perf_counter() - t0
-    m = int(min(system.n, max(m0, m0 * target_s / max(t_cal, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.compute(system.pos, system.types, system.box, table, off, idx, 0, m, threads=threads)
-    t_c = time.perf_counter() - t0
-    per_eval = t_c * system.n / m + t_nb / REBUILD_EVERY
-    return dict(value=system.n / per_eval, unit=UNIT, cores=threads, kind="oracle",
-                sample=(f"FP64 oracle, {threads} threads: compute over centre atoms [0, {m}) of the "
-                        f"{system.n}-atom workload took {t_c:.2f} s, scaled to all atoms; plus the "
-                        f"single-thread cell-list build ({t_nb:.2f} s) amortised over "
-                        f"{REBUILD_EVERY} evaluations"))
+    t_nb = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        off, idx = oracle.neighbors(system.pos, system.box, cut)
+        t_nb.append(time.perf_counter() - t0)
+    nb = float(np.median(t_nb))
+
+    def per_atom(th):
+        m0 = min(system.n, 2000 * th)
+        t0 = time.perf_counter()
+        oracle.compute(system.pos, system.types, system.box, table, off, idx, 0, m0, threads=th)
+        t_cal = time.perf_counter() - t0
+        m = int(min(system.n, max(m0, m0 * sample_s / max(t_cal, 1e-6))))
+        ts = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            oracle.compute(system.pos, system.types, system.box, table, off, idx, 0, m, threads=th)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)) / m, m
+
+    c_all, m_all = per_atom(threads)
+    c_one, m_one = per_atom(1)
+    per_eval_all = c_all * system.n + nb / REBUILD_EVERY
+    per_eval_one = c_one * system.n + nb / REBUILD_EVERY
+    return dict(value=system.n / per_eval_all, unit=UNIT, cores=threads, kind="oracle",
+                sample=(f"FP64 oracle on {cpu_model()}: compute over centre atoms [0, {m_all}) on {threads} "
+                        f"threads and [0, {m_one}) on 1 thread, each the median of {runs} runs, scaled to "
+                        f"the {system.n}-atom workload; plus the single-thread cell-list build over all atoms "
+                        f"(median {nb:.2f} s of {runs}) amortised over {REBUILD_EVERY} evaluations"),
+                value_1_thread=system.n / per_eval_one, cpu_model=cpu_model(), runs=runs,
+                compute_s_per_eval_all_cores=c_all * system.n, compute_s_per_eval_1_thread=c_one * system.n,
+                build_s=nb)
 
 
 # ---- serving ----------------------------------------------------------------
@@ -397,9 +439,7 @@ def main():
         log(f"[bench] cpu baseline {cpu['value']:.4g} atoms*evals/s on {cpu['cores']} threads")
 
     achieved = mixed["alg_tflops"]
-    traffic = None
-    if TRAFFIC_PROFILE and TRAFFIC_PROFILE["source"] == source_hash(TRAFFIC_SOURCE):
-        traffic = TRAFFIC_PROFILE["bytes_per_launch"]
+    traffic = traffic_bytes()
     line = {
         "metric": METRIC,
         "value": mixed["value"],
@@ -424,14 +464,15 @@ def main():
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
-            "peak": PEAK_ALU_TFLOPS,
+            "peak": PEAK_FP32_PACKED_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_ALU_TFLOPS,
+            "frac": achieved / PEAK_FP32_PACKED_TFLOPS,
             "traffic": traffic,
-            "kernel": "k_tersoff<float, single-type> (energy / force / virial)",
+            "kernel": "k_tersoff<float, one species, lambda3 = 0> (energy / force / virial)",
             "kernel_ms": mixed["main_ms"],
             "alg_flops_per_launch": mixed["alg_flops_per_launch"],
-            "frac_vs_packed_fp32_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
+            "peak_note": "FP32 vector peak (packed issue); 78.64 TFLOP/s unpacked FP32 / FP64 issue",
+            "frac_vs_unpacked_issue_peak": achieved / PEAK_ALU_TFLOPS,
         },
         "pack_roofline": {
             "bound": "hbm", "kernel": "k_pack<float, single-type>", "kernel_ms": mixed["pack_ms"],

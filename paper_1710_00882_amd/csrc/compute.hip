@@ -72,18 +72,23 @@ constexpr double kLn2Hi = 0x1.62e42p-1;
 constexpr double kLn2Lo = 0x1.fdf473de6af28p-22;
 constexpr double kLog2e = 1.4426950408889634;
 
-// 1/d in FP64: the hardware reciprocal estimate and two Newton steps.
+// 1/d in FP64: the hardware reciprocal estimate (at least 23 correct bits)
+// and one Newton step (relative error below 2^-46 + rounding).
 __device__ __forceinline__ double recip_f64(double d)
 {
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(fma(-d, r, 1.0), r, r);
+    const double r = __builtin_amdgcn_rcp(d);
     return fma(fma(-d, r, 1.0), r, r);
 }
 
+// The mixed path's power needs b to about 1e-9 relative: zeta arrives as an
+// FP32 sum (relative error ~1e-7), which already moves b by up to
+// x / (2 (1 + x)) * 1e-7, and 1e-9 of b is ~4e-9 eV per pair.  The series
+// below are cut where their truncation falls under that.
+//
 // Natural logarithm of y > 0 (+inf and NaN pass through): y = 2^e m with m in
 // [1/sqrt 2, sqrt 2), ln m = 2 atanh(s), s = (m - 1) / (m + 1), |s| < 0.172,
-// summed as 2 s sum_{k <= 8} s^(2k) / (2k + 1) (the first omitted term is
-// below 1e-15 relative), plus e ln 2 in two parts.
+// summed as 2 s sum_{k <= 4} s^(2k) / (2k + 1) (the first omitted term,
+// 2 s^11 / 11, is below 7e-10), plus e ln 2 in two parts.
 __device__ __forceinline__ double ln_f64(double y)
 {
     if (!(y < INFINITY)) return y;
@@ -96,11 +101,7 @@ __device__ __forceinline__ double ln_f64(double y)
     const double f = m - 1.0;                    // exact
     const double s = f * recip_f64(2.0 + f);
     const double s2 = s * s;
-    double p = 1.0 / 17.0;
-    p = fma(p, s2, 1.0 / 15.0);
-    p = fma(p, s2, 1.0 / 13.0);
-    p = fma(p, s2, 1.0 / 11.0);
-    p = fma(p, s2, 1.0 / 9.0);
+    double p = 1.0 / 9.0;
     p = fma(p, s2, 1.0 / 7.0);
     p = fma(p, s2, 1.0 / 5.0);
     p = fma(p, s2, 1.0 / 3.0);
@@ -111,7 +112,7 @@ __device__ __forceinline__ double ln_f64(double y)
 }
 
 // e^t: t = k ln 2 + r with k = rint(t / ln 2), |r| <= ln 2 / 2, e^r from its
-// Taylor series through r^12 (truncation below 2e-16 relative), scaled by
+// Taylor series through r^8 (truncation below 2.1e-10 relative), scaled by
 // 2^k.  t is clamped to [-760, 760], beyond which the result is 0 or +inf.
 __device__ __forceinline__ double exp_f64(double t)
 {
@@ -119,11 +120,7 @@ __device__ __forceinline__ double exp_f64(double t)
     const double kf = rint(t * kLog2e);
     double r = fma(-kf, kLn2Hi, t);
     r = fma(-kf, kLn2Lo, r);
-    double p = 1.0 / 479001600.0;               // 1/12!
-    p = fma(p, r, 1.0 / 39916800.0);
-    p = fma(p, r, 1.0 / 3628800.0);
-    p = fma(p, r, 1.0 / 362880.0);
-    p = fma(p, r, 1.0 / 40320.0);
+    double p = 1.0 / 40320.0;                   // 1/8!
     p = fma(p, r, 1.0 / 5040.0);
     p = fma(p, r, 1.0 / 720.0);
     p = fma(p, r, 1.0 / 120.0);
@@ -135,9 +132,9 @@ __device__ __forceinline__ double exp_f64(double t)
     return __builtin_amdgcn_ldexp(p, (int)kf);
 }
 
-// b(zeta) and db/dzeta of Eq. (2) in log form, zeta > 0 (mixed path; about a
-// third of the instructions of the library functions, relative error of b a
-// few 1e-16):
+// b(zeta) and db/dzeta of Eq. (2) in log form, zeta > 0 (mixed path; relative
+// error of b a few 1e-9, a third of the instructions of the library
+// functions):
 // x = exp(eta (ln beta + ln zeta)), b = exp(-ln(1 + x) / (2 eta)),
 // db/dzeta = -(1/2) b x / (zeta (1 + x)).
 __device__ __forceinline__ void bond_order_f64(const ParamX &px, double zeta, double &b, double &db)
@@ -187,6 +184,13 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+constexpr double inv_factorial(int n)
+{
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return 1.0 / f;
+}
+
 // ------------------------------------------------------------ parameters --
 
 template <typename real>
@@ -196,27 +200,116 @@ __device__ __forceinline__ const ParamR<float> *table_r<float>(const DeviceTable
 template <>
 __device__ __forceinline__ const ParamR<double> *table_r<double>(const DeviceTable &t) { return t.pd; }
 
-// f_R = A exp(-lambda1 r), f_A = -B exp(-lambda2 r) and their derivatives.
-// FP64: direct.  FP32: exp(ln A - lambda1 r) with the argument carried as an
-// unevaluated float pair (two-sum and fma error terms), so the rounding of
-// A and lambda1 to float leaves no systematic bias in the pair energy.
-__device__ __forceinline__ float exp_compensated(float a, float a_lo, float l, float l_lo, float r)
+// e^(a + a_lo) for |a_lo| <= ulp(a) and |a| <= 80, from FP32 operations,
+// returned in FP64 with a relative error near 2^-27 (an emulation of these
+// steps in exactly rounded float arithmetic measures 0.13 float ulp).
+// k = rint(a / ln 2); the reduced argument t = a - k ln 2 is kept as an
+// unevaluated float pair (ln 2 split into a 17-bit head, so that k * head is
+// exact, and a float tail; two-product and two-sum give the rounding
+// errors); e^t = 1 + t + t^2 q(t), q the Taylor series of (e^t - 1 - t) / t^2
+// through its t^6 term (truncation below 3e-10 on |t| <= ln 2 / 2), with
+// 1 + t as an exact pair and every smaller term summed into its tail.
+__device__ __forceinline__ void exp_pair_parts(float a, float a_lo, float &hi, float &lo, int &k)
 {
-    const float p = l * r;
-    const float pe = fmaf(l, r, -p);            // l r = p + pe exactly
-    const float s = a - p;                      // two-sum of a and -p
-    const float bb = s - a;
-    const float e = (a - (s - bb)) + (-p - bb);
-    const float lo = ((e + a_lo) - pe) - l_lo * r;
-    const float x = expf(s);
-    return fmaf(x, lo, x);
+#pragma clang fp contract(off)
+    constexpr float kLog2eF = 1.44269504f;
+    constexpr float kLn2HiF = 0x1.62e4p-1f;
+    constexpr float kLn2LoF = (float)(0.69314718055994530942 - (double)0x1.62e4p-1f);
+    const float kf = rintf(a * kLog2eF);
+    const float t1 = fmaf(-kf, kLn2HiF, a);      // exact
+    const float p = kf * kLn2LoF;
+    const float pe = fmaf(kf, kLn2LoF, -p);      // kf * kLn2LoF = p + pe
+    const float th = t1 - p;                     // two-sum of t1 and -p
+    const float bb = th - t1;
+    const float e1 = (t1 - (th - bb)) + (-p - bb);
+    const float tl = (e1 - pe) + a_lo;           // a - k ln 2 = th + tl
+    const float sq = th * th;
+    const float sqe = fmaf(th, th, -sq);         // th^2 = sq + sqe
+    float q = (float)inv_factorial(8);
+    q = fmaf(q, th, (float)inv_factorial(7));
+    q = fmaf(q, th, (float)inv_factorial(6));
+    q = fmaf(q, th, (float)inv_factorial(5));
+    q = fmaf(q, th, (float)inv_factorial(4));
+    q = fmaf(q, th, (float)inv_factorial(3));
+    q = fmaf(q, th, 0.5f);
+    const float eth = 1.0f + fmaf(sq, q, th);    // e^th to about one ulp (weights tl only)
+    const float tail = fmaf(tl, eth, fmaf(sq, q, sqe * q));
+    hi = 1.0f + th;
+    lo = ((1.0f - hi) + th) + tail;              // 1 + th = hi + ((1 - hi) + th) exactly
+    k = (int)kf;
 }
 
-__device__ __forceinline__ void pair_terms(const ParamR<float> &q, float r, float &fr, float &dfr,
-                                           float &fa, float &dfa)
+// The value 2^k (hi + lo) rounded once to float (the all-FP32 path).
+__device__ __forceinline__ float exp_pair_f32_rounded(float a, float a_lo)
 {
-    fr = exp_compensated(q.lnA, q.lnA_lo, q.lam1, q.lam1_lo, r);
-    fa = -exp_compensated(q.lnB, q.lnB_lo, q.lam2, q.lam2_lo, r);
+    float hi, lo;
+    int k;
+    exp_pair_parts(a, a_lo, hi, lo, k);
+    return __builtin_amdgcn_ldexpf(hi + lo, k);
+}
+
+// The argument ln A - lambda r of A exp(-lambda r) as a float pair s + lo
+// (all-FP32 path), for r = r + r_lo (FP64 distance as an unevaluated float
+// pair), ln A = lnA + lnA_lo, lambda = l + l_lo (two-product, two-sum).
+__device__ __forceinline__ void scaled_arg(float lnA, float lnA_lo, float l, float l_lo, float r, float r_lo,
+                                           float &s, float &lo)
+{
+#pragma clang fp contract(off)
+    const float p = l * r;
+    const float pe = fmaf(l, r, -p);
+    s = lnA - p;
+    const float bb = s - lnA;
+    const float e = (lnA - (s - bb)) + (-p - bb);
+    lo = (((e + lnA_lo) - pe) - l_lo * r) - l * r_lo;
+}
+
+// A exp(-lambda r) for the FP64 distance r + r_lo given as a float pair and
+// lambda = l + l_lo (mixed path), from FP32 operations: k = rint(-l r / ln 2);
+// t = -l r - k ln 2 is kept as th + tl, th = -p - k head exact (p = RN(l r),
+// the 17-bit head of ln 2 times k exact, Sterbenz) and tl the small rest
+// (|tl| < 2e-5: the rounding error of l r, the lo parts of lambda and r, and
+// k times the tail of ln 2); e^th (1 + tl) as in exp_pair_parts; the result
+// 2^k (hi + lo) A in FP64.  Relative error near 2^-27 (an emulation of these
+// steps in exactly rounded float arithmetic measures 0.13 float ulp).
+__device__ __forceinline__ double exp_decay_f32(double A, float l, float l_lo, float r, float r_lo)
+{
+#pragma clang fp contract(off)
+    constexpr float kLog2eF = 1.44269504f;
+    constexpr float kLn2HiF = 0x1.62e4p-1f;
+    constexpr float kLn2LoF = (float)(0.69314718055994530942 - (double)0x1.62e4p-1f);
+    const float p = l * r;
+    const float pe = fmaf(l, r, -p);             // l r = p + pe exactly
+    const float kf = rintf(-p * kLog2eF);
+    const float th = fmaf(kf, -kLn2HiF, -p);     // exact
+    const float tl = (((-pe) - l_lo * r) - l * r_lo) - kf * kLn2LoF;
+    const float sq = th * th;
+    const float sqe = fmaf(th, th, -sq);         // th^2 = sq + sqe
+    float q = (float)inv_factorial(8);
+    q = fmaf(q, th, (float)inv_factorial(7));
+    q = fmaf(q, th, (float)inv_factorial(6));
+    q = fmaf(q, th, (float)inv_factorial(5));
+    q = fmaf(q, th, (float)inv_factorial(4));
+    q = fmaf(q, th, (float)inv_factorial(3));
+    q = fmaf(q, th, 0.5f);
+    const float eth = 1.0f + fmaf(sq, q, th);    // e^th to about one ulp (weights tl only)
+    const float tail = fmaf(tl, eth, fmaf(sq, q, sqe * q));
+    const float hi = 1.0f + th;
+    const float lo = ((1.0f - hi) + th) + tail;  // 1 + th = hi + ((1 - hi) + th) exactly
+    return __builtin_amdgcn_ldexp((double)hi + (double)lo, (int)kf) * A;
+}
+
+// f_R = A exp(-lambda1 r), f_A = -B exp(-lambda2 r) and their derivatives
+// in the all-FP32 path: the exponentials of exp_pair_parts rounded once to
+// float (the mixed path takes them in FP64, and the FP64 path evaluates
+// them directly).
+__device__ __forceinline__ void pair_terms(const ParamR<float> &q, float r, float &fr, float &dfr,
+                                           float &fa, float &dfa, float r_lo = 0.f)
+{
+    float s, lo;
+    scaled_arg(q.lnA, q.lnA_lo, q.lam1, q.lam1_lo, r, r_lo, s, lo);
+    fr = exp_pair_f32_rounded(s, lo);
+    scaled_arg(q.lnB, q.lnB_lo, q.lam2, q.lam2_lo, r, r_lo, s, lo);
+    fa = -exp_pair_f32_rounded(s, lo);
     dfr = -fmaf(q.lam1, fr, q.lam1_lo * fr);
     dfa = -fmaf(q.lam2, fa, q.lam2_lo * fa);
 }
@@ -228,13 +321,6 @@ __device__ __forceinline__ void pair_terms(const ParamR<double> &q, double r, do
     fa = -q.B * ::exp(-q.lam2 * r);
     dfr = -q.lam1 * fr;
     dfa = -q.lam2 * fa;
-}
-
-constexpr double inv_factorial(int n)
-{
-    double f = 1.0;
-    for (int i = 2; i <= n; ++i) f *= i;
-    return 1.0 / f;
 }
 
 // sin x and cos x for |x| <= pi/2 (the switching-function argument never
@@ -260,21 +346,27 @@ __device__ __forceinline__ void sincos_halfpi(real x, real &s, real &c)
     c = pc;
 }
 
-// Switching function f_C(r) and its derivative.  r - R is exact in the
-// switching zone (Sterbenz), and the rounding errors of R and pi/(2D) in the
-// working precision are added back, so f_C carries no systematic bias.
+// Switching function f_C(r) = 1/2 - 1/2 sin(pi/2 (r - R)/D) and its
+// derivative, evaluated in the zone as sin^2(y), y = (pi/4)(R + D - r)/D --
+// the same function without the cancellation of 1/2 - 1/2 sin(x) as x nears
+// pi/2: near the cutoff f_C of a third atom k is tiny, yet the bond order's
+// b'(zeta) ~ zeta^(eta - 1) keeps dV/dzeta dzeta/dx_k finite, so f_C needs
+// its relative accuracy there (1/2 - 1/2 sin rounds to 0 in FP32 within
+// 1e-4 A of the cutoff).  R + D - r is exact (Sterbenz), and the rounding
+// errors of r (r_lo: the FP64 distance minus the working-precision one),
+// R + D and pi/(4D) are added back.
 template <typename real>
-__device__ __forceinline__ void cutoff_terms(const ParamR<real> &q, real r, real &fc, real &dfc)
+__device__ __forceinline__ void cutoff_terms(const ParamR<real> &q, real r, real &fc, real &dfc, real r_lo = real(0))
 {
     fc = real(1);
     dfc = real(0);
     if (r >= q.Rin) {
-        const real dr = (r - q.R) - q.R_lo;
-        const real arg = dr * q.half_pi_D + dr * q.half_pi_D_lo;
+        const real dr = (q.Rc - r) + (q.Rc_lo - r_lo);
+        const real y = dr * q.qpi_D + dr * q.qpi_D_lo;
         real sn, cn;
-        sincos_halfpi(arg, sn, cn);
-        fc = real(0.5) - real(0.5) * sn;
-        dfc = real(-0.5) * (q.half_pi_D + q.half_pi_D_lo) * cn;
+        sincos_halfpi(y, sn, cn);
+        fc = sn * sn;
+        dfc = real(-2) * (q.qpi_D + q.qpi_D_lo) * sn * cn;
     }
 }
 
@@ -533,7 +625,18 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                         o.dz = (real)dz;
                         if constexpr (sizeof(real) == 8) o.pad = 0;
                         // batch order: slot = kept entries of the batch before this one
-                        recs[(size_t)a0 * kRecCap + npacked + lanes_below(mrec)] = o;
+                        const size_t slot = (size_t)a0 * kRecCap + npacked + lanes_below(mrec);
+                        recs[slot] = o;
+                        if constexpr (sizeof(real) == 4) {
+                            // rounding error of the compute kernel's FP32 distance
+                            // (the same operations on the same float displacement)
+                            // (rsq - rf^2 is exact: rf^2 has 48 bits and the two
+                            // agree to ~1e-7, Sterbenz; r - rf = (rsq - rf^2) / (2 rf)
+                            // up to a relative 5e-8 of itself)
+                            const float rf = __builtin_amdgcn_sqrtf(norm2r(o.dx, o.dy, o.dz));
+                            const double rfd = (double)rf;
+                            a.rlo[slot] = (float)fma(-rfd, rfd, rsq) * (0.5f * __builtin_amdgcn_rcpf(rf));
+                        }
                     }
                 }
                 npacked += __popcll(mrec);
@@ -570,9 +673,22 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
 
 // ----------------------------------------------------------- compute kernel -
 
-template <typename real, bool ONE>
+// Three-body parameters of one table entry (the quantities of g(theta) and of
+// the exponential factor of Eq. 3), staged in LDS by the kernels for several
+// species.
+template <typename real>
+struct TripParam {
+    real h, gamma, c2d2, d2, two_c2, lam3, lam3m, m;
+};
+
+template <typename real>
+__device__ __forceinline__ TripParam<real> trip_of(const ParamR<real> &p)
+{
+    return {p.h, p.gamma, p.c2d2, p.d2, p.two_c2, p.lam3, p.lam3m, p.m};
+}
+
+template <typename real, int NT>
 struct Shared {
-    static constexpr int kT = ONE ? 1 : kMaxTypes;
     // per centre atom of the batch
     int ti[kWave];
     int pcnt[kWave];
@@ -583,8 +699,18 @@ struct Shared {
     real ux[kScap], uy[kScap], uz[kScap], r[kScap];
     real dzeta[kScap];           // dV(i,n,zeta_in)/dzeta
     int mask[kScap];
-    real fc[kT][kScap], dfc[kT][kScap];   // f_C(r_in), f_C'(r_in) of entry (t_i, t, t_n), per partner type t
+    real fc[NT][kScap], dfc[NT][kScap];   // f_C(r_in), f_C'(r_in) of entry (t_i, t, t_n), per partner type t
     real ep[kScap], em[kScap];            // exp(lambda3 r_in), exp(-lambda3 r_in) (one type, m = 1)
+};
+
+// The k-role quantities of triplet (i; k, j) -- pair (i, k) with j as its
+// third atom -- that the first K loop of lane (i, j) forms alongside its own
+// triplet (i; j, k) (same angle, same g and g' when the three-body parameters
+// are symmetric in j and k): v = g' e (u_k - cos u_j), s = g e, with e the
+// exponential factor of pair (i, k) and third atom j.
+template <typename real>
+struct alignas(4 * sizeof(real)) KCache {
+    real vx, vy, vz, s;
 };
 
 template <typename real>
@@ -593,21 +719,22 @@ struct Angular {
 };
 
 // g(theta) = gamma (1 + c^2/d^2 - c^2/(d^2 + (cos - h)^2)) written without
-// cancellation as gamma (1 + (c^2/d^2) t^2 / (d^2 + t^2)), t = cos - h.
-template <typename real>
-__device__ __forceinline__ Angular<real> angular(const ParamR<real> &q, real cs)
+// cancellation as gamma + (gamma c^2/d^2) t^2 / (d^2 + t^2), t = cos - h, and
+// g' = 2 gamma c^2 t / (d^2 + t^2)^2.
+template <typename real, typename Q>
+__device__ __forceinline__ Angular<real> angular(const Q &q, real cs)
 {
     const real t = cs - q.h;
     const real iden = M<real>::rcp(q.d2 + t * t);
     Angular<real> a;
-    a.g = q.gamma * (real(1) + q.c2d2 * t * t * iden);
-    a.dg = q.gamma * q.two_c2 * t * iden * iden;
+    a.g = q.gamma + q.c2d2 * (t * t) * iden;      // c2d2 = gamma c^2 / d^2
+    a.dg = q.two_c2 * t * (iden * iden);           // two_c2 = 2 gamma c^2
     return a;
 }
 
 // exp((lambda3 (rj - rk))^m) and its derivative with respect to rj.
-template <typename real>
-__device__ __forceinline__ void exp_term(const ParamR<real> &q, real rj, real rk, real &ex, real &dex)
+template <typename real, typename Q>
+__device__ __forceinline__ void exp_term(const Q &q, real rj, real rk, real &ex, real &dex)
 {
     ex = real(1);
     dex = real(0);
@@ -624,21 +751,42 @@ __device__ __forceinline__ void exp_term(const ParamR<real> &q, real rj, real rk
     }
 }
 
+// (d/d rj) exp((lambda3 (rj - rk))^m) / exp((lambda3 (rj - rk))^m).
+template <typename real, typename Q>
+__device__ __forceinline__ real exp_ratio(const Q &q, real rj, real rk)
+{
+    if (q.lam3 == real(0)) return real(0);
+    if (q.m == real(3)) {
+        const real dr = rj - rk;
+        return real(3) * q.lam3m * dr * dr;
+    }
+    return q.lam3;
+}
+
 // One 64-lane wavefront per workgroup walks batches of consecutive centre
 // atoms whose packed neighbours fill at most one slot per lane; a lane owns
 // the pair (i, j) of its slot (the pair-vectorised scheme of Section 3 with
 // pairs of several centre atoms side by side):
-//   1  zeta_ij: loop over the other slots k of centre i (first K loop);
+//   1  first K loop over the other slots k of centre i: zeta_ij, and with the
+//      same cos(theta_ijk), g and g' the derivative dzeta_ij/dx_j (Section 2:
+//      zeta and its derivatives formed once); CACHE also keeps, per k, the
+//      k-role quantities of triplet (i; k, j) in LDS;
 //   2  f_C, f_R, f_A, b_ij and db/dzeta in FP64 log form, energy, pair force,
-//      dV/dzeta_ij (shared through LDS);
-//   3  second K loop: the lane sums, in FP64, every force term on atom j of
-//      centre i's terms -- its j-role terms -dV/dzeta_ij dzeta(i,j,k)/dx_j and
-//      its k-role terms -dV/dzeta_ik dzeta(i,k,j)/dx_j -- so no two lanes
-//      ever update the same force;
+//      dV/dzeta_ij (shared through LDS); the j-role force
+//      -dV/dzeta_ij dzeta_ij/dx_j follows at once;
+//   3  second K loop: the k-role terms -dV/dzeta_ik dzeta(i,k,j)/dx_j, each
+//      a product of dV/dzeta_ik with the cached quantities (recomputed past
+//      the cache, or when the parameters are not symmetric in j and k); the
+//      lane sums every force term of centre i on atom j in FP64, so no two
+//      lanes ever update the same force;
 //   4  virial d_ij (x) F_j; the force on i is minus the sum over its slots.
 // Each slot's force goes to the slot atom j reserved for centre i (plane k
 // of the per-atom force planes, k the position of i in j's kept list), each
 // centre's own force to `own`; k_gather_forces sums them per atom.
+//
+// NT: 1 (one species: the single entry in registers), 2 or kMaxTypes (the
+// three-body part of the table staged in LDS).  CACHE: the three-body
+// parameters of (ti, tj, tk) and (ti, tk, tj) agree (always for one species).
 //
 // BATCHED: the batch holds several systems; each centre atom's energy and
 // virial (the sums over its slots) are stored per atom for the per-system
@@ -647,24 +795,41 @@ __device__ __forceinline__ void exp_term(const ParamR<real> &q, real rj, real rk
 // SINGLE (with real = float): the all-FP32 variant -- the zeta -> b power and
 // each lane's sum of the force terms on j in FP32 as well; FP64 remains only
 // in the displacement (packing) and in the sums across lanes and atoms.
-template <typename real, bool ONE, bool BATCHED, bool SINGLE, bool NOL3>
-__global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable tab)
+// The one-species float instances fit 128 VGPRs without spilling: ask for
+// four wavefronts per SIMD there.
+template <typename real, int NT, bool BATCHED, bool SINGLE, bool NOL3, bool CACHE>
+__global__ __launch_bounds__(kWave, (sizeof(real) == 4 && NT == 1) ? 4 : 1) void k_tersoff(ComputeLaunch a,
+                                                                                              DeviceTable tab)
 {
     static_assert(!SINGLE || sizeof(real) == 4, "the single-precision variant computes in float");
-    static_assert(!NOL3 || ONE, "the lambda3-free variant is a one-species kernel");
+    static_assert(!NOL3 || NT == 1, "the lambda3-free variant is a one-species kernel");
+    constexpr bool ONE = NT == 1;
     using facc = typename std::conditional<SINGLE, float, double>::type;   // per-lane force sum
-    __shared__ Shared<real, ONE> sh;
+    // float paths: the FP64 distance enters the pair terms as r + r_lo
+    constexpr bool kRlo = sizeof(real) == 4;
+    constexpr int KC = CACHE ? (sizeof(real) == 4 ? 4 : 3) : 1;   // cached k per lane
+    __shared__ Shared<real, NT> sh;
+    __shared__ KCache<real> kc[KC][kScap];
+    __shared__ TripParam<real> tp[ONE ? 1 : NT * NT * NT];
     __shared__ double sev[BATCHED ? kScap : 1][BATCHED ? 7 : 1];   // per-slot energy and virial
     const int lane = threadIdx.x;
     const ParamR<real> *ptab = table_r<real>(tab);
     const Rec<real> *recs = static_cast<const Rec<real> *>(a.recs);
     const int nt = ONE ? 1 : tab.ntypes;
+    if constexpr (!ONE) {
+        for (int e = lane; e < nt * nt * nt; e += kWave) tp[e] = trip_of(ptab[e]);
+    }
     // one species: the single entry, held in registers; the m = 1 factor
     // exp(lambda3 (r_ij - r_ik)) then separates into per-slot exponentials
     // (when they stay far from overflow)
     const ParamR<real> q0 = ptab[0];
+    const TripParam<real> t0 = trip_of(q0);
     const bool sep = !NOL3 && ONE && q0.m == real(1) && q0.lam3 != real(0) &&
-                     fabs((double)q0.lam3) * (2.0 * (double)q0.R - (double)q0.Rin) < 40.0;
+                     fabs((double)q0.lam3) * (double)q0.Rc < 40.0;
+    auto trip = [&](int e) -> TripParam<real> {
+        if constexpr (ONE) return t0;
+        else return tp[e];
+    };
 
     double e_acc = 0.0;
     double w_acc[6] = {0, 0, 0, 0, 0, 0};
@@ -680,6 +845,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
         int a0 = grp * B;
         const int a_end = min(a0 + B, n);
         const Rec<real> *region = recs + (size_t)a0 * kRecCap;   // this batch's records, in order
+        const float *rlo_region = kRlo ? a.rlo + (size_t)a0 * kRecCap : nullptr;
         while (a0 < a_end) {
             const int nb = a_end - a0;
             // ---- batch: the leading atoms whose slots fit one per lane
@@ -705,7 +871,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             const int s = lane;
             const bool has_slot = s < npacked;
             int al = 0, jl = 0, pc = 0, sb = 0, j = 0, kpos = -1, mj = 0, ti = 0;
-            real rj = 0, rjinv = 0, uj[3] = {0, 0, 0}, dj[3] = {0, 0, 0};
+            real rj = 0, rjinv = 0, rjlo = 0, uj[3] = {0, 0, 0}, dj[3] = {0, 0, 0};
             if (has_slot) {
                 al = sh.owner[s];
                 sb = sh.pstart[al];
@@ -713,6 +879,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 pc = sh.pcnt[al];
                 ti = ONE ? 0 : sh.ti[al];
                 const Rec<real> rc = region[s];
+                if constexpr (kRlo) rjlo = rlo_region[s];
                 j = rc.jm & kIdMask;
                 bool ended;
                 kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, ended);
@@ -728,7 +895,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 for (int t = 0; t < nt; ++t) {
                     real fc = real(0), dfc = real(0);
                     if ((mj >> (kThirdBit + t)) & 1)
-                        cutoff_terms(ONE ? q0 : ptab[(ti * nt + t) * nt + rec_type(mj)], rj, fc, dfc);
+                        cutoff_terms(ONE ? q0 : ptab[(ti * nt + t) * nt + rec_type(mj)], rj, fc, dfc, rjlo);
                     sh.fc[t][s] = fc;
                     sh.dfc[t][s] = dfc;
                 }
@@ -740,7 +907,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             __syncthreads();
 
             // exp((lambda3 (r_a - r_b))^m) and its derivative with respect to r_a
-            auto ex_term = [&](const ParamR<real> &q, int sa, real ra, int sbb, real rbb, real &ex, real &dex) {
+            auto ex_term = [&](const TripParam<real> &q, int sa, real ra, int sbb, real rbb, real &ex, real &dex) {
                 if constexpr (NOL3) {
                     ex = real(1);   // lambda3 = 0: the factor is 1 in every triplet
                     dex = real(0);
@@ -753,26 +920,45 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             };
 
             const int tj = rec_type(mj);
-            const bool j_pair = (mj >> kPairBit) & 1;
+            const bool j_pair = ONE || ((mj >> kPairBit) & 1);
             facc fx = 0, fy = 0, fz = 0;       // force on j from centre i's terms
             double e_pair = 0.0;   // energy of pair (i, j)
             if (has_slot) {
-                // ---- 1: zeta_ij over the other slots k of centre i (k = j skipped
-                // by the index map, not by an idle iteration)
-                real zr = real(0);
-                if (j_pair) {
+                // ---- 1: zeta_ij and dzeta_ij/dx_j = aj / r_ij + bj u_ij over the
+                // other slots k of centre i (k = j skipped by the index map)
+                real zr = real(0), aj[3] = {0, 0, 0}, bj = real(0);
+                if (CACHE || j_pair) {
                     for (int kk = 0; kk + 1 < pc; ++kk) {
                         const int sk = sb + kk + (kk >= jl ? 1 : 0);
                         const int mk = ONE ? 0 : sh.mask[sk];
-                        const ParamR<real> &q = ONE ? q0 : ptab[(ti * nt + tj) * nt + rec_type(mk)];
+                        const int tk = ONE ? 0 : rec_type(mk);
+                        const TripParam<real> q = trip((ti * nt + tj) * nt + tk);
                         const real rk = sh.r[sk];
-                        const real cs = uj[0] * sh.ux[sk] + uj[1] * sh.uy[sk] + uj[2] * sh.uz[sk];
+                        const real uk[3] = {sh.ux[sk], sh.uy[sk], sh.uz[sk]};
+                        const real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
+                        const Angular<real> an = angular(q, cs);
+                        // r_ij d cos(theta_ijk) / d x_j
+                        const real tv[3] = {uk[0] - cs * uj[0], uk[1] - cs * uj[1], uk[2] - cs * uj[2]};
                         real ex, dex;
                         ex_term(q, s, rj, sk, rk, ex, dex);
-                        const real term = sh.fc[ONE ? 0 : tj][sk] * angular(q, cs).g * ex;
-                        const bool member = ONE || ((mk >> (kThirdBit + tj)) & 1);
-                        zr += member ? term : real(0);
+                        const bool member = j_pair && (ONE || ((mk >> (kThirdBit + tj)) & 1));
+                        const real fck = member ? sh.fc[ONE ? 0 : tj][sk] : real(0);
+                        const real fg = fck * an.g;
+                        zr += fg * ex;
+                        const real w = fck * an.dg * ex;
+                        aj[0] += w * tv[0];
+                        aj[1] += w * tv[1];
+                        aj[2] += w * tv[2];
+                        bj += fg * dex;
                         n_trip += member ? 1 : 0;
+                        if constexpr (CACHE) {
+                            if (kk < KC) {
+                                real ex2, dex2;
+                                ex_term(q, sk, rk, s, rj, ex2, dex2);
+                                const real w2 = an.dg * ex2;
+                                kc[kk][s] = KCache<real>{w2 * tv[0], w2 * tv[1], w2 * tv[2], an.g * ex2};
+                            }
+                        }
                     }
                 }
                 // ---- 2: pair terms, bond order, dV/dzeta
@@ -783,21 +969,37 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                     const ParamR<real> &q = ONE ? q0 : ptab[e_ij];
                     const ParamX px = tab.px[e_ij];
                     const real fc = sh.fc[ONE ? 0 : tj][s], dfc = sh.dfc[ONE ? 0 : tj][s];
-                    real fr, fa, dfr, dfa;
-                    pair_terms(q, rj, fr, dfr, fa, dfa);
                     // Eq. (2) in log form: FP64, or FP32 in the single variant
-                    real br;
-                    if constexpr (SINGLE) {
+                    if constexpr (kRlo && !SINGLE) {
+                        // mixed: f_R and f_A from the FP32 pair exponential of
+                        // the FP64 distance, combined in FP64 (at short range
+                        // f_R' and b f_A' cancel to a few percent of either)
+                        const double fr = exp_decay_f32(px.A, q.lam1, q.lam1_lo, rj, rjlo);
+                        const double fa = -exp_decay_f32(px.B, q.lam2, q.lam2_lo, rj, rjlo);
+                        const double zeta = (double)zr;
+                        double b = 1.0, db = 0.0;
+                        if (zeta > 0.0) bond_order_f64(px, zeta, b, db);
+                        const double fc64 = (double)fc, vp = fr + b * fa;
+                        e_pair = 0.5 * fc64 * vp;
+                        dz_out = (real)(0.5 * fc64 * fa * db);
+                        const double dvdr = 0.5 * ((double)dfc * vp - fc64 * (px.lam1 * fr + b * (px.lam2 * fa)));
+                        fx = -dvdr * (double)uj[0];
+                        fy = -dvdr * (double)uj[1];
+                        fz = -dvdr * (double)uj[2];
+                    } else if constexpr (SINGLE) {
+                        real fr, fa, dfr, dfa;
+                        pair_terms(q, rj, fr, dfr, fa, dfa, rjlo);
                         // b - 1 is carried instead of b (b is within ~1e-4 of 1,
                         // and its FP32 rounding would bias the energy through
-                        // the large f_A at short range)
+                        // the large f_A at short range); ln(beta zeta) is taken
+                        // of the product (ln beta ~ -14 and ln zeta ~ 10 would
+                        // each carry a float rounding ~1e-6 into the sum)
                         float bm1 = 0.f, db = 0.f;
                         if (zr > 0.f) {
-                            const float x = expf((float)px.eta * ((float)px.logbeta + logf(zr)));
+                            const float x = expf((float)px.eta * logf(q.beta * zr));
                             bm1 = expm1f(-log1pf(x) * (float)px.inv2eta);
                             db = -0.5f * (1.f + bm1) * x / (zr * (1.f + x));
                         }
-                        br = 1.f + bm1;
                         e_pair = (double)(0.5f * fc * ((fr + fa) + bm1 * fa));
                         dz_out = 0.5f * fc * fa * db;
                         const real dvdr1 = real(0.5) * (dfc * ((fr + fa) + bm1 * fa) + fc * ((dfr + dfa) + bm1 * dfa));
@@ -805,87 +1007,78 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                         fy = -dvdr1 * uj[1];
                         fz = -dvdr1 * uj[2];
                     } else {
+                        // all-FP64 path, with the library's exp / log / log1p
+                        real fr, fa, dfr, dfa;
+                        pair_terms(q, rj, fr, dfr, fa, dfa);
                         const double zeta = (double)zr;
                         double b = 1.0, db = 0.0;
                         if (zeta > 0.0) {
-                            if constexpr (sizeof(real) == 4) {
-                                bond_order_f64(px, zeta, b, db);
-                            } else {
-                                // the all-FP64 path keeps the library's exp / log / log1p
-                                const double x = ::exp(px.eta * (px.logbeta + ::log(zeta)));
-                                b = ::exp(-::log1p(x) * px.inv2eta);
-                                db = -0.5 * b * x / (zeta * (1.0 + x));
-                            }
+                            const double x = ::exp(px.eta * (px.logbeta + ::log(zeta)));
+                            b = ::exp(-::log1p(x) * px.inv2eta);
+                            db = -0.5 * b * x / (zeta * (1.0 + x));
                         }
-                        br = (real)b;
-                        e_pair = 0.5 * (double)fc * ((double)fr + b * (double)fa);
-                        dz_out = (real)(0.5 * (double)fc * (double)fa * db);
+                        e_pair = 0.5 * fc * (fr + b * fa);
+                        dz_out = 0.5 * fc * fa * db;
+                        const real dvdr = real(0.5) * (dfc * (fr + b * fa) + fc * (dfr + b * dfa));
+                        fx = -dvdr * uj[0];
+                        fy = -dvdr * uj[1];
+                        fz = -dvdr * uj[2];
                     }
                     e_acc += e_pair;
-                    if constexpr (!SINGLE) {
-                        const real dvdr = real(0.5) * (dfc * (fr + br * fa) + fc * (dfr + br * dfa));
-                        fx = (facc)(-dvdr * uj[0]);
-                        fy = (facc)(-dvdr * uj[1]);
-                        fz = (facc)(-dvdr * uj[2]);
-                    }
+                    // j-role terms: -dV/dzeta_ij dzeta_ij/dx_j
+                    fx -= (facc)(dz_out * (aj[0] * rjinv + bj * uj[0]));
+                    fy -= (facc)(dz_out * (aj[1] * rjinv + bj * uj[1]));
+                    fz -= (facc)(dz_out * (aj[2] * rjinv + bj * uj[2]));
                 }
                 sh.dzeta[s] = dz_out;
             }
             __syncthreads();
 
             if (has_slot) {
-                // ---- 3: second K loop, every force term of centre i on atom j:
-                // its j-role terms in (i; j, k) and its k-role terms in (i; k, j)
-                const real dzj = sh.dzeta[s];
-                const real fcj0 = sh.fc[0][s], dfcj0 = sh.dfc[0][s];
+                // ---- 3: second K loop, the k-role terms of centre i on atom j:
+                // -dV/dzeta_ik dzeta(i,k,j)/dx_j over the bond partners k of i
+                // that have j as a third atom
+                facc ax = 0, ay = 0, az = 0, su = 0;
                 for (int kk = 0; kk + 1 < pc; ++kk) {
                     const int sk = sb + kk + (kk >= jl ? 1 : 0);
-                    const real rk = sh.r[sk];
-                    const real uk[3] = {sh.ux[sk], sh.uy[sk], sh.uz[sk]};
                     const real dzk = sh.dzeta[sk];
-                    const real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
-                    // d cos(theta_ijk) / d x_j
-                    const real dc[3] = {(uk[0] - cs * uj[0]) * rjinv, (uk[1] - cs * uj[1]) * rjinv,
-                                        (uk[2] - cs * uj[2]) * rjinv};
-                    real cdc, cu;   // F_j -= cdc * dc + cu * u_j
-                    if (ONE) {
-                        // one entry: g and g' shared by both roles; dV/dzeta
-                        // is zero for a slot that is no bond partner
-                        const Angular<real> an = angular(q0, cs);
-                        real ex1, dex1, ex2, dex2;
-                        ex_term(q0, s, rj, sk, rk, ex1, dex1);
-                        ex_term(q0, sk, rk, s, rj, ex2, dex2);
-                        const real w1 = dzj * sh.fc[0][sk];
-                        cdc = (w1 * ex1 + dzk * fcj0 * ex2) * an.dg;
-                        cu = an.g * (w1 * dex1 + dzk * (dfcj0 * ex2 - fcj0 * dex2));
+                    const int mk = ONE ? 0 : sh.mask[sk];
+                    const int tk = ONE ? 0 : rec_type(mk);
+                    const bool valid = dzk != real(0) && (ONE || ((mj >> (kThirdBit + tk)) & 1));
+                    const int e_kj = (ti * nt + tk) * nt + tj;
+                    const real rk = sh.r[sk];
+                    real v[3], sg, tg;   // dzeta(i,k,j)/dx_j = (fc_j v / r_j) + (fc'_j sg - fc_j tg) u_j
+                    if (CACHE && kk < KC) {
+                        const KCache<real> c = kc[kk][s];
+                        v[0] = c.vx; v[1] = c.vy; v[2] = c.vz;
+                        sg = c.s;
+                        if constexpr (NOL3) tg = real(0);
+                        else tg = sep ? q0.lam3 * sg : sg * exp_ratio(trip(e_kj), rk, rj);
                     } else {
-                        const int mk = sh.mask[sk];
-                        const int tk = rec_type(mk);
-                        cdc = real(0);
-                        cu = real(0);
-                        if (((mk >> (kThirdBit + tj)) & 1) && dzj != real(0)) {
-                            const ParamR<real> &q = ptab[(ti * nt + tj) * nt + tk];
-                            real ex, dex;
-                            ex_term(q, s, rj, sk, rk, ex, dex);
-                            const Angular<real> an = angular(q, cs);
-                            const real w1 = dzj * sh.fc[tj][sk];
-                            cdc += w1 * ex * an.dg;
-                            cu += w1 * an.g * dex;
-                        }
-                        if (((mj >> (kThirdBit + tk)) & 1) && dzk != real(0)) {
-                            const ParamR<real> &q = ptab[(ti * nt + tk) * nt + tj];
-                            real ex, dex;
-                            ex_term(q, sk, rk, s, rj, ex, dex);
-                            const Angular<real> an = angular(q, cs);
-                            const real fcj = sh.fc[tk][s], dfcj = sh.dfc[tk][s];
-                            cdc += dzk * fcj * ex * an.dg;
-                            cu += dzk * an.g * (dfcj * ex - fcj * dex);
-                        }
+                        const TripParam<real> q = trip(e_kj);
+                        const real uk[3] = {sh.ux[sk], sh.uy[sk], sh.uz[sk]};
+                        const real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
+                        const Angular<real> an = angular(q, cs);
+                        real ex2, dex2;
+                        ex_term(q, sk, rk, s, rj, ex2, dex2);
+                        const real w2 = an.dg * ex2;
+                        v[0] = w2 * (uk[0] - cs * uj[0]);
+                        v[1] = w2 * (uk[1] - cs * uj[1]);
+                        v[2] = w2 * (uk[2] - cs * uj[2]);
+                        sg = an.g * ex2;
+                        tg = an.g * dex2;
                     }
-                    fx -= (facc)(cdc * dc[0] + cu * uj[0]);
-                    fy -= (facc)(cdc * dc[1] + cu * uj[1]);
-                    fz -= (facc)(cdc * dc[2] + cu * uj[2]);
+                    const real fcj = valid ? sh.fc[ONE ? 0 : tk][s] : real(0);
+                    const real dfcj = valid ? sh.dfc[ONE ? 0 : tk][s] : real(0);
+                    const real wv = dzk * fcj * rjinv;
+                    ax += (facc)(wv * v[0]);
+                    ay += (facc)(wv * v[1]);
+                    az += (facc)(wv * v[2]);
+                    su += (facc)(dzk * (dfcj * sg - fcj * tg));
                 }
+                fx -= ax + su * (facc)uj[0];
+                fy -= ay + su * (facc)uj[1];
+                fz -= az + su * (facc)uj[2];
                 // ---- 4: virial and output (FP64 from here on)
                 const double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
                 const double dxj = (double)dj[0], dyj = (double)dj[1], dzj_ = (double)dj[2];
@@ -933,6 +1126,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             __syncthreads();
             a0 += cut;
             region += npacked;
+            if constexpr (kRlo) rlo_region += npacked;
         }
     }
 
@@ -1183,19 +1377,26 @@ int occupancy_grid(const void *kern, long long work_items, int max_per_cu = 1 <<
     return (int)(g < 1 ? 1 : g);
 }
 
-// Instances of the compute kernel: precision x kind, kind 0 several species,
-// 1 one species, 2 one species without the lambda3 term (lambda3 = 0).
+// Instances of the compute kernel: precision x kind.  Kind 0: up to
+// kMaxTypes species, any table; 1: one species; 2: one species without the
+// lambda3 term (lambda3 = 0); 3: up to two species whose three-body
+// parameters are symmetric in j and k (the k-role terms cached).
 template <typename T>
 struct TypeTag {
     using type = T;
 };
-template <typename R, bool O, bool S, bool N>
+template <typename R, int NT_, bool S, bool N, bool C>
 struct KernelTag {
     using real = R;
-    static constexpr bool one = O, single = S, nol3 = N;
+    static constexpr int nt = NT_;
+    static constexpr bool one = NT_ == 1, single = S, nol3 = N, cache = C;
 };
 
-int table_kind(const DeviceTable &t) { return t.ntypes != 1 ? 0 : (t.lam3_zero ? 2 : 1); }
+int table_kind(const DeviceTable &t)
+{
+    if (t.ntypes == 1) return t.lam3_zero ? 2 : 1;
+    return (t.ntypes == 2 && t.sym3) ? 3 : 0;
+}
 
 template <typename F>
 void with_kernel(int prec, int kind, F &&f)
@@ -1203,9 +1404,10 @@ void with_kernel(int prec, int kind, F &&f)
     auto by_kind = [&](auto r_tag, auto s_tag) {
         using R = typename decltype(r_tag)::type;
         constexpr bool S = decltype(s_tag)::value;
-        if (kind == 0) f(KernelTag<R, false, S, false>{});
-        else if (kind == 1) f(KernelTag<R, true, S, false>{});
-        else f(KernelTag<R, true, S, true>{});
+        if (kind == 0) f(KernelTag<R, kMaxTypes, S, false, false>{});
+        else if (kind == 1) f(KernelTag<R, 1, S, false, true>{});
+        else if (kind == 2) f(KernelTag<R, 1, S, true, true>{});
+        else f(KernelTag<R, 2, S, false, true>{});
     };
     if (prec == kPrecSingle) by_kind(TypeTag<float>{}, std::true_type{});
     else if (prec == kPrecMixed) by_kind(TypeTag<float>{}, std::false_type{});
@@ -1220,8 +1422,8 @@ void grids_dispatch(int prec, const DeviceTable &t, int n, int atoms_per_batch, 
         using K = decltype(tag);
         grids[0] = occupancy_grid((const void *)k_pack<typename K::real, K::one, BATCHED>, batches,
                                   kPackWavesPerCU);
-        grids[1] = occupancy_grid((const void *)k_tersoff<typename K::real, K::one, BATCHED, K::single, K::nol3>,
-                                  batches);
+        grids[1] = occupancy_grid(
+            (const void *)k_tersoff<typename K::real, K::nt, BATCHED, K::single, K::nol3, K::cache>, batches);
     });
     grids[2] = kBigGrid;
 }
@@ -1245,7 +1447,8 @@ void compute_dispatch(const ComputeLaunch &a, const DeviceTable &t, int prec, in
     const dim3 G(grid), W(kWave);
     with_kernel(prec, table_kind(t), [&](auto tag) {
         using K = decltype(tag);
-        hipLaunchKernelGGL((k_tersoff<typename K::real, K::one, BATCHED, K::single, K::nol3>), G, W, 0, s, a, t);
+        hipLaunchKernelGGL((k_tersoff<typename K::real, K::nt, BATCHED, K::single, K::nol3, K::cache>), G, W, 0, s,
+                           a, t);
     });
 }
 
@@ -1258,6 +1461,17 @@ void compute_grids(int prec, const DeviceTable &t, bool batched, int n, int atom
 }
 
 size_t record_bytes(int prec) { return prec != kPrecFP64 ? sizeof(Rec<float>) : sizeof(Rec<double>); }
+
+size_t record_region_bytes(int prec, size_t slots)
+{
+    return prec != kPrecFP64 ? slots * (sizeof(Rec<float>) + sizeof(float)) : slots * sizeof(Rec<double>);
+}
+
+float *rlo_of(void *recs, int prec, size_t slots)
+{
+    if (prec == kPrecFP64) return nullptr;
+    return reinterpret_cast<float *>(static_cast<unsigned char *>(recs) + slots * sizeof(Rec<float>));
+}
 
 hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, int prec, int grid, hipStream_t s)
 {

@@ -18,20 +18,20 @@ struct ParamR {
     real A, B, lam1, lam2;
     real lam3;        // lambda3
     real lam3m;       // lambda3^m (m = 1 or 3)
-    real c2d2;        // c^2 / d^2
+    real c2d2;        // gamma c^2 / d^2
     real d2;          // d^2
-    real two_c2;      // 2 c^2
+    real two_c2;      // 2 gamma c^2
     real h, gamma;
-    real R, Rin;      // R, R - D
-    real half_pi_D;   // pi / (2 D)
+    real Rc, Rin;     // R + D (the cutoff), R - D
+    real qpi_D;       // pi / (4 D)
     real m;           // 1 or 3
     // Error-compensated pair constants: ln A = lnA + lnA_lo, lambda1 =
     // lam1 + lam1_lo (likewise B, lambda2), each lo part the rounding error
     // of its hi part in this precision (zero in FP64).
     real lnA, lnA_lo, lam1_lo;
     real lnB, lnB_lo, lam2_lo;
-    real R_lo, half_pi_D_lo;  // likewise for the switching-function argument
-    real pad;
+    real Rc_lo, qpi_D_lo;     // likewise for the switching-function argument
+    real beta;                // beta (the all-FP32 path forms ln(beta zeta) from the product)
 };
 
 // FP64 quantities used by both precisions (membership tests and the
@@ -41,6 +41,7 @@ struct ParamX {
     double logbeta;   // log(beta) (-inf when beta == 0)
     double eta;
     double inv2eta;   // 1 / (2 eta)
+    double A, B, lam1, lam2;   // the mixed path scales its pair exponentials and sums the pair force in FP64
 };
 
 struct DeviceTable {
@@ -50,6 +51,7 @@ struct DeviceTable {
     const ParamX *px;           // ntypes^3 entries
     const double *packsq;       // ntypes^2, symmetric: packing radius^2 of a (ti, tn) entry
     int lam3_zero;              // one species with lambda3 = 0 (the exponential factor is 1)
+    int sym3;                   // three-body parameters of (ti, tj, tk) equal those of (ti, tk, tj)
 };
 
 // Cell grid of one periodic box (cells at least the list radius wide).
@@ -120,6 +122,7 @@ struct PackLaunch {
     int n;
     double L[3], invL[3];
     void *recs;                 // packed records: region of B * kRecCap per batch of B atoms
+    float *rlo;                 // float records: per record, r - (the compute kernel's FP32 r), or null
     int *pcount;                // n: records per atom
     int *kept;                  // n x kKeptFast: kept-neighbour lists (first entries)
     int *kept_more;             // n x kRecCap: kept-neighbour lists (entries kKeptFast ..)
@@ -139,6 +142,7 @@ struct PackLaunch {
 struct ComputeLaunch {
     const int *types;           // n
     const void *recs;           // packed records (batch regions)
+    const float *rlo;           // float records: FP64 r minus FP32 r, per record (same index)
     const int *pcount;          // n
     const int *kept;            // kept-neighbour lists of plane_stride atoms (kept_more follows)
     int n;
@@ -162,6 +166,10 @@ enum : int { kPrecFP64 = 0, kPrecMixed = 1, kPrecSingle = 2, kNumPrec = 3 };
 
 void compute_grids(int prec, const DeviceTable &t, bool batched, int n, int atoms_per_batch, int grids[3]);
 size_t record_bytes(int prec);
+// Bytes of a record region of `slots` records, the per-record r corrections
+// of the float records included (placed after the records; rlo_of gives them).
+size_t record_region_bytes(int prec, size_t slots);
+float *rlo_of(void *recs, int prec, size_t slots);
 hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, int prec, int grid, hipStream_t s);
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec,
                           int grid, hipStream_t s);

@@ -270,7 +270,9 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.drop_list.alloc(A, tot));
     SRV_TRY(L.ctl.alloc(3 + NS, tot));
     const size_t nbat = (A + kServeBatchAtoms - 1) / kServeBatchAtoms;
-    SRV_TRY(L.recs.alloc(record_bytes(kPrecFP64) * kRecCap * nbat * kServeBatchAtoms, tot));
+    const size_t slots = (size_t)kRecCap * nbat * kServeBatchAtoms;
+    SRV_TRY(L.recs.alloc(std::max(record_region_bytes(kPrecFP64, slots), record_region_bytes(kPrecMixed, slots)),
+                         tot));
     SRV_TRY(L.desc.alloc(NS, tot));
     SRV_TRY(L.dims.alloc(1, tot));
     // every kept list starts empty (-1)
@@ -353,6 +355,8 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     pk.cap = S.cap;
     pk.n = S.max_atoms;
     pk.recs = L.recs.p;
+    pk.rlo = rlo_of(L.recs.p, prec, (size_t)kRecCap * ((S.max_atoms + kServeBatchAtoms - 1) / kServeBatchAtoms) *
+                                        kServeBatchAtoms);
     pk.pcount = L.pcount.p;
     pk.kept = L.kept.p;
     pk.kept_more = L.kept.p + (size_t)kKeptFast * S.max_atoms;
@@ -371,6 +375,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     ComputeLaunch a{};
     a.types = L.types.p;
     a.recs = L.recs.p;
+    a.rlo = pk.rlo;
     a.pcount = L.pcount.p;
     a.kept = L.kept.p;
     a.n = S.max_atoms;

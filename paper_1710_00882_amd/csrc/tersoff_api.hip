@@ -120,14 +120,14 @@ ParamR<real> derive(const double *p)
     r.lam2 = (real)p[TERSOFF_P_LAMBDA2];
     r.lam3 = (real)l3;
     r.lam3m = (real)(m == 3.0 ? l3 * l3 * l3 : l3);
-    r.c2d2 = (real)(c * c / (d * d));
+    r.c2d2 = (real)(p[TERSOFF_P_GAMMA] * c * c / (d * d));
     r.d2 = (real)(d * d);
-    r.two_c2 = (real)(2.0 * c * c);
+    r.two_c2 = (real)(2.0 * p[TERSOFF_P_GAMMA] * c * c);
     r.h = (real)p[TERSOFF_P_H];
     r.gamma = (real)p[TERSOFF_P_GAMMA];
-    r.R = (real)R;
+    r.Rc = (real)(R + D);
     r.Rin = (real)(R - D);
-    r.half_pi_D = (real)(M_PI / (2.0 * D));
+    r.qpi_D = (real)(M_PI / (4.0 * D));
     r.m = (real)m;
     const double lnA = std::log(p[TERSOFF_P_A]), lnB = std::log(p[TERSOFF_P_B]);
     r.lnA = (real)lnA;
@@ -136,9 +136,9 @@ ParamR<real> derive(const double *p)
     r.lnB = (real)lnB;
     r.lnB_lo = (real)(lnB - (double)r.lnB);
     r.lam2_lo = (real)(p[TERSOFF_P_LAMBDA2] - (double)r.lam2);
-    r.R_lo = (real)(R - (double)r.R);
-    r.half_pi_D_lo = (real)(M_PI / (2.0 * D) - (double)r.half_pi_D);
-    r.pad = (real)0;
+    r.Rc_lo = (real)((R + D) - (double)r.Rc);
+    r.qpi_D_lo = (real)(M_PI / (4.0 * D) - (double)r.qpi_D);
+    r.beta = (real)p[TERSOFF_P_BETA];
     return r;
 }
 
@@ -152,6 +152,104 @@ hipError_t take_event(tersoff_ctx *c, hipEvent_t *e)
         return hipSuccess;
     }
     return hipEventCreate(e);
+}
+
+int check_compute_args(tersoff_ctx *c, const double *pos, int32_t precision, const double *energy_virial)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    if (!c->built) return fail(c, TERSOFF_E_STATE, "compute before build_neighbors");
+    if (!pos || !energy_virial) return fail(c, TERSOFF_E_INVALID, "null pointer");
+    if (precision != TERSOFF_FP64 && precision != TERSOFF_MIXED && precision != TERSOFF_SINGLE)
+        return fail(c, TERSOFF_E_INVALID, "precision must be TERSOFF_FP64, TERSOFF_MIXED or TERSOFF_SINGLE");
+    return TERSOFF_OK;
+}
+
+// Records of one evaluation: kRecCap per atom of every (padded) batch.
+size_t record_slots(const tersoff_ctx *c)
+{
+    const size_t nbat = ((size_t)c->n + c->atoms_per_batch - 1) / c->atoms_per_batch;
+    return (size_t)kRecCap * nbat * c->atoms_per_batch;
+}
+
+// Device buffers one evaluation writes and reads back (beyond the inputs,
+// the outputs and the resident neighbour list).
+struct EvalBuffers {
+    void *recs;          // record_region_bytes(prec, record_slots(c))
+    double *planes;      // 3 kRecCap n
+    double *own;         // 3 n
+    int *pcount;         // n
+    int *kept;           // (kKeptFast + kRecCap) n
+    int *drop_list;      // n
+    double *partials;    // 8 x compute grid
+    long long *counters; // 2 x compute grid
+};
+
+// Packing, compute, dropped-atom fixup and force gather of one evaluation on
+// stream s (no synchronisation, no allocation when profile is false).
+int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energy_virial, double *f, hipStream_t s,
+                      const EvalBuffers &b, bool profile)
+{
+    const int *grid = c->grid[prec];
+    PackLaunch pk{};
+    pk.pos = pos;
+    pk.types = c->types.p;
+    pk.row_count = c->row_count.p;
+    pk.ell = c->ell.p;
+    pk.cap = c->list_cap;
+    pk.n = c->n;
+    for (int d = 0; d < 3; ++d) {
+        pk.L[d] = c->box[d];
+        pk.invL[d] = 1.0 / c->box[d];
+    }
+    pk.recs = b.recs;
+    pk.rlo = rlo_of(b.recs, prec, record_slots(c));
+    pk.pcount = b.pcount;
+    pk.kept = b.kept;
+    pk.kept_more = b.kept + (size_t)kKeptFast * c->n;
+    pk.own = b.own;
+    pk.flags = c->misc.p;
+    pk.drop_list = b.drop_list;
+    pk.drop_count = c->misc.p + 3;
+    pk.pos_build = c->pos_build.p;
+    pk.stale_sq = 0.25 * c->skin * c->skin;
+    pk.atoms_per_batch = c->atoms_per_batch;
+
+    ComputeLaunch a{};
+    a.types = c->types.p;
+    a.recs = b.recs;
+    a.rlo = pk.rlo;
+    a.pcount = b.pcount;
+    a.kept = b.kept;
+    a.n = c->n;
+    a.own = b.own;
+    a.planes = b.planes;
+    a.partials = b.partials;
+    a.counters = b.counters;
+    a.atoms_per_batch = c->atoms_per_batch;
+    a.plane_stride = c->n;
+
+    // event pairs (profiling only): pack, main kernel, fixup + gather
+    hipEvent_t ev[6] = {};
+    if (profile)
+        for (int q = 0; q < 6; ++q) HIP_TRY(c, take_event(c, &ev[q]));
+    if (ev[0]) HIP_TRY(c, hipEventRecord(ev[0], s));
+    HIP_TRY(c, launch_pack(pk, c->tab, prec, grid[0], s));
+    if (ev[1]) HIP_TRY(c, hipEventRecord(ev[1], s));
+    if (ev[2]) HIP_TRY(c, hipEventRecord(ev[2], s));
+    HIP_TRY(c, launch_compute(a, c->tab, prec, grid[1], s));
+    if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
+    if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
+    HIP_TRY(c, launch_fixup_dropped(c->ell.p, c->list_cap, c->row_count.p, b.kept, pk.kept_more, b.drop_list,
+                                    c->misc.p + 3, c->n, prec, b.planes, s));
+    const FinalizeArgs fin{b.partials, b.counters, grid[1], energy_virial, c->counts.p, c->misc.p};
+    HIP_TRY(c, launch_gather_forces(b.pcount, prec, b.planes, b.own, c->n, nullptr, c->n, f, c->misc.p + 3, fin, s));
+    if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
+    if (profile) {
+        c->ev_pack.emplace_back(ev[0], ev[1]);
+        c->ev_compute.emplace_back(ev[2], ev[3]);
+        c->ev_gather.emplace_back(ev[4], ev[5]);
+    }
+    return TERSOFF_OK;
 }
 
 }  // namespace
@@ -215,6 +313,10 @@ int tersoff_create(const double *params, int32_t ntypes, tersoff_ctx **out)
         px[e].logbeta = p[TERSOFF_P_BETA] > 0 ? std::log(p[TERSOFF_P_BETA]) : -INFINITY;
         px[e].eta = p[TERSOFF_P_ETA];
         px[e].inv2eta = 1.0 / (2.0 * p[TERSOFF_P_ETA]);
+        px[e].A = p[TERSOFF_P_A];
+        px[e].B = p[TERSOFF_P_B];
+        px[e].lam1 = p[TERSOFF_P_LAMBDA1];
+        px[e].lam2 = p[TERSOFF_P_LAMBDA2];
         c->max_cut = std::max(c->max_cut, cut);
     }
     // packing radius of neighbour n of centre i: every entry (ti, *, tn)
@@ -254,6 +356,18 @@ int tersoff_create(const double *params, int32_t ntypes, tersoff_ctx **out)
     c->tab.px = reinterpret_cast<const ParamX *>(base + off_px);
     c->tab.packsq = reinterpret_cast<const double *>(base + off_pk);
     c->tab.lam3_zero = ntypes == 1 && params[TERSOFF_P_LAMBDA3] == 0.0;
+    // g(theta) and the exponential factor of triplet (i; j, k) equal those of
+    // (i; k, j) when these parameters agree (the compute kernel then forms
+    // both roles of a triplet from one evaluation)
+    c->tab.sym3 = 1;
+    for (int ti = 0; ti < ntypes; ++ti)
+        for (int tj = 0; tj < ntypes; ++tj)
+            for (int tk = 0; tk < ntypes; ++tk) {
+                const double *p = params + (size_t)((ti * ntypes + tj) * ntypes + tk) * TERSOFF_NPARAM;
+                const double *q = params + (size_t)((ti * ntypes + tk) * ntypes + tj) * TERSOFF_NPARAM;
+                for (int f : {TERSOFF_P_C, TERSOFF_P_D, TERSOFF_P_H, TERSOFF_P_GAMMA, TERSOFF_P_LAMBDA3, TERSOFF_P_M})
+                    if (p[f] != q[f]) c->tab.sym3 = 0;
+            }
     *out = c;
     return TERSOFF_OK;
 }
@@ -490,83 +604,28 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
 int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double *energy_virial,
                     double *forces, void *stream)
 {
-    if (!c) return TERSOFF_E_INVALID;
-    if (!c->built) return fail(c, TERSOFF_E_STATE, "compute before build_neighbors");
-    if (!pos || !energy_virial) return fail(c, TERSOFF_E_INVALID, "null pointer");
-    if (precision != TERSOFF_FP64 && precision != TERSOFF_MIXED && precision != TERSOFF_SINGLE)
-        return fail(c, TERSOFF_E_INVALID, "precision must be TERSOFF_FP64, TERSOFF_MIXED or TERSOFF_SINGLE");
+    const int st = check_compute_args(c, pos, precision, energy_virial);
+    if (st != TERSOFF_OK) return st;
     HIP_TRY(c, hipSetDevice(c->device));
-    hipStream_t s = as_stream(stream);
     const int prec = precision;
-    const int *grid = c->grid[prec];
     double *f = forces;
     if (!f) {
         HIP_TRY(c, c->force_scratch.ensure(3 * (size_t)c->n));
         f = c->force_scratch.p;
     }
-    const size_t nbat = ((size_t)c->n + c->atoms_per_batch - 1) / c->atoms_per_batch;
-    HIP_TRY(c, c->recs.ensure(record_bytes(prec) * kRecCap * nbat * c->atoms_per_batch));
+    const size_t slots = record_slots(c);
+    HIP_TRY(c, c->recs.ensure(record_region_bytes(prec, slots)));
     HIP_TRY(c, c->planes.ensure(3 * (size_t)kRecCap * (size_t)c->n));
-
-    PackLaunch pk{};
-    pk.pos = pos;
-    pk.types = c->types.p;
-    pk.row_count = c->row_count.p;
-    pk.ell = c->ell.p;
-    pk.cap = c->list_cap;
-    pk.n = c->n;
-    for (int d = 0; d < 3; ++d) {
-        pk.L[d] = c->box[d];
-        pk.invL[d] = 1.0 / c->box[d];
-    }
-    pk.recs = c->recs.p;
-    pk.pcount = c->pcount.p;
-    pk.kept = c->kept.p;
-    pk.kept_more = c->kept.p + (size_t)kKeptFast * c->n;
-    pk.own = c->own.p;
-    pk.flags = c->misc.p;
-    pk.drop_list = c->drop_list.p;
-    pk.drop_count = c->misc.p + 3;
-    pk.pos_build = c->pos_build.p;
-    pk.stale_sq = 0.25 * c->skin * c->skin;
-    pk.atoms_per_batch = c->atoms_per_batch;
-
-    ComputeLaunch a{};
-    a.types = c->types.p;
-    a.recs = c->recs.p;
-    a.pcount = c->pcount.p;
-    a.kept = c->kept.p;
-    a.n = c->n;
-    a.own = c->own.p;
-    a.planes = c->planes.p;
-    a.partials = c->partials.p;
-    a.counters = c->counters.p;
-    a.atoms_per_batch = c->atoms_per_batch;
-    a.plane_stride = c->n;
-
-    // event pairs (profiling only): pack, main kernel, fixup + gather
-    hipEvent_t ev[6] = {};
-    if (c->profiling)
-        for (int q = 0; q < 6; ++q) HIP_TRY(c, take_event(c, &ev[q]));
-    if (ev[0]) HIP_TRY(c, hipEventRecord(ev[0], s));
-    HIP_TRY(c, launch_pack(pk, c->tab, prec, grid[0], s));
-    if (ev[1]) HIP_TRY(c, hipEventRecord(ev[1], s));
-    if (ev[2]) HIP_TRY(c, hipEventRecord(ev[2], s));
-    HIP_TRY(c, launch_compute(a, c->tab, prec, grid[1], s));
-    if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
-    if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
-    HIP_TRY(c, launch_fixup_dropped(c->ell.p, c->list_cap, c->row_count.p, c->kept.p, pk.kept_more, c->drop_list.p,
-                                    c->misc.p + 3, c->n, prec, c->planes.p, s));
-    const FinalizeArgs fin{c->partials.p, c->counters.p, grid[1], energy_virial, c->counts.p, c->misc.p};
-    HIP_TRY(c, launch_gather_forces(c->pcount.p, prec, c->planes.p, c->own.p, c->n, nullptr, c->n, f, c->misc.p + 3,
-                                    fin, s));
-    if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
-    if (c->profiling) {
-        c->ev_pack.emplace_back(ev[0], ev[1]);
-        c->ev_compute.emplace_back(ev[2], ev[3]);
-        c->ev_gather.emplace_back(ev[4], ev[5]);
-    }
-    return TERSOFF_OK;
+    EvalBuffers b{};
+    b.recs = c->recs.p;
+    b.planes = c->planes.p;
+    b.own = c->own.p;
+    b.pcount = c->pcount.p;
+    b.kept = c->kept.p;
+    b.drop_list = c->drop_list.p;
+    b.partials = c->partials.p;
+    b.counters = c->counters.p;
+    return launch_evaluation(c, pos, prec, energy_virial, f, as_stream(stream), b, c->profiling);
 }
 
 int tersoff_check(tersoff_ctx *c, void *stream)

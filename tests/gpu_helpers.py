@@ -3,13 +3,18 @@ oracle on the same seeded inputs, and compare with the stated error metrics.
 
 Tolerances:
   forces: RMS relative error over all 3N components, <= 1e-11 (FP64 path),
-          <= 1e-5 (mixed and single paths);
+          <= 1e-5 (mixed and single paths); and, so that one atom's error
+          cannot hide in the average, the largest per-atom error relative to
+          the largest force, max_i |F_i - F_ref,i| / max_i |F_ref,i|, within
+          the same bound;
   energy: |E - E_ref| / N <= 1e-12 eV (FP64), <= 1e-6 eV (mixed), <= 5e-6 eV
           (single);
-  virial: max_ab |W_ab - W_ref,ab| <= max(rel * max_ab |W_ref,ab|, abs * N) with
-          rel = the force tolerance (the virial is a sum of the same force
-          terms times FP64 relative vectors, so it carries their relative
-          error) and abs = the energy tolerance (floor for a near-zero virial).
+  virial: max_ab |W_ab - W_ref,ab| <= tol_E * max(N, max_ab |W_ref,ab| / 1 eV),
+          tol_E the energy bound per atom (1e-12 eV FP64, 1e-6 eV mixed,
+          5e-6 eV single): the energy bound per atom wherever |W| / N stays
+          below 1 eV (every bulk workload), and the same number as a relative
+          bound for small, strongly strained clusters, where one FP32-rounded
+          term of |W| / N ~ 10 eV already carries ~1e-6 eV.
 """
 from __future__ import annotations
 
@@ -70,17 +75,27 @@ def errors(E, F, V, Eo, Fo, Vo, n):
     return ferr, eerr, verr
 
 
+def max_atom_error(F, Fo):
+    """max_i |F_i - F_ref,i| / max_i |F_ref,i| (0 when every force is 0)."""
+    F = np.asarray(F).reshape(-1, 3)
+    Fo = np.asarray(Fo).reshape(-1, 3)
+    den = float(np.linalg.norm(Fo, axis=1).max()) if len(Fo) else 0.0
+    num = float(np.linalg.norm(F - Fo, axis=1).max()) if len(Fo) else 0.0
+    return num / den if den > 0 else num
+
+
 def virial_tol(Vo, n, precision):
-    t = TOL[precision]
-    return max(t["force"] * float(np.abs(Vo).max()), t["energy"] * n)
+    return TOL[precision]["energy"] * max(n, float(np.abs(Vo).max()))
 
 
 def assert_parity(E, F, V, Eo, Fo, Vo, n, precision, label=""):
     ferr, eerr, verr = errors(E, F, V, Eo, Fo, Vo, n)
+    merr = max_atom_error(F, Fo)
     tol = TOL[precision]
     vtol = virial_tol(Vo, n, precision)
-    say(f"[parity] {label} {precision}: force_rms_rel={ferr:.3e} energy/atom={eerr:.3e} "
-        f"virial_abs={verr:.3e} (tol {vtol:.2e})")
+    say(f"[parity] {label} {precision}: force_rms_rel={ferr:.3e} max_atom_rel={merr:.3e} "
+        f"energy/atom={eerr:.3e} virial/atom={verr / n:.3e} (tol {tol['energy']:.0e})")
     assert ferr <= tol["force"], f"force RMS rel {ferr:.3e} > {tol['force']}"
+    assert merr <= tol["force"], f"largest per-atom force error {merr:.3e} of max|F| > {tol['force']}"
     assert eerr <= tol["energy"], f"energy/atom {eerr:.3e} > {tol['energy']}"
     assert verr <= vtol, f"virial error {verr:.3e} > {vtol:.3e}"

@@ -1,9 +1,12 @@
 """CPU check of the numerical method behind the mixed path's FP64 log and exp
 (the zeta -> b power of Eq. 2): the same steps -- range reduction, the atanh
-series of ln m through s^17, the Taylor series of e^r through r^12, ln 2
-split into a 21-bit head and a tail -- evaluated here with exactly rounded
-IEEE arithmetic (fma emulated through rationals) and compared with
-50-digit references.  The GPU parity tests check the kernel itself."""
+series of ln m through s^9, the Taylor series of e^r through r^8, ln 2 split
+into a 21-bit head and a tail, reciprocals from an estimate good to a float
+ulp plus one Newton step -- evaluated here with exactly rounded IEEE
+arithmetic (fma emulated through rationals) and compared with 50-digit
+references.  The series are cut for the accuracy the mixed path can use: zeta
+itself is an FP32 sum, so b is only known to ~1e-8 relative there.  The GPU
+parity tests check the kernel itself."""
 import decimal
 import math
 import random
@@ -20,8 +23,10 @@ def fma(a, b, c):
 
 
 def recip(d):
+    # the hardware estimate, modelled as 1/d to within a float ulp (the
+    # largest error that one Newton step still takes below 2^-46)
     r = 1.0 / d
-    r = fma(fma(-d, r, 1.0), r, r)
+    r *= 1.0 + 2.0 ** -23
     return fma(fma(-d, r, 1.0), r, r)
 
 
@@ -33,8 +38,8 @@ def ln_steps(y):
     f = m - 1.0
     s = f * recip(2.0 + f)
     s2 = s * s
-    p = 1.0 / 17.0
-    for k in (15, 13, 11, 9, 7, 5, 3):
+    p = 1.0 / 9.0
+    for k in (7, 5, 3):
         p = fma(p, s2, 1.0 / k)
     t = s + s
     lnm = fma(t, s2 * p, t)
@@ -46,8 +51,8 @@ def exp_steps(t):
     kf = float(round(t * LOG2E))
     r = fma(-kf, LN2_HI, t)
     r = fma(-kf, LN2_LO, r)
-    p = 1.0 / math.factorial(12)
-    for n in range(11, -1, -1):
+    p = 1.0 / math.factorial(8)
+    for n in range(7, -1, -1):
         p = fma(p, r, 1.0 / math.factorial(n))
     return math.ldexp(p, int(kf))
 
@@ -70,15 +75,16 @@ def test_log_and_exp_relative_error():
         t = rng.uniform(-700.0, 700.0)
         ref = decimal.Decimal(t).exp()
         worst_exp = max(worst_exp, float(abs((decimal.Decimal(exp_steps(t)) - ref) / ref)))
-    assert worst_ln < 2e-15
-    assert worst_exp < 1e-15
+    # truncation: 2 s^11 / 11 against ln m (|s| < 0.172) and r^9 / 9!
+    assert worst_ln < 3e-9
+    assert worst_exp < 4e-10
 
 
 def test_log_near_one_absolute_error():
     rng = random.Random(8)
     for _ in range(2000):
         y = 1.0 + rng.uniform(-0.3, 0.3)
-        assert abs(float(decimal.Decimal(ln_steps(y)) - decimal.Decimal(y).ln())) < 1e-15
+        assert abs(float(decimal.Decimal(ln_steps(y)) - decimal.Decimal(y).ln())) < 1e-9
 
 
 def test_bond_order_power():
@@ -91,4 +97,4 @@ def test_bond_order_power():
         b = exp_steps(-ln_steps(1.0 + x) / (2.0 * eta))
         ref = (1 + (decimal.Decimal(beta) * decimal.Decimal(zeta)) ** decimal.Decimal(eta)) ** (
             -1 / (2 * decimal.Decimal(eta)))
-        assert abs(decimal.Decimal(b) - ref) / ref < decimal.Decimal("1e-14")
+        assert abs(decimal.Decimal(b) - ref) / ref < decimal.Decimal("5e-9")
