@@ -124,6 +124,25 @@ int tersoff_build_neighbors(tersoff_ctx *ctx, const double *pos, const int32_t *
 int tersoff_compute(tersoff_ctx *ctx, const double *pos, int32_t precision,
                     double *energy_virial, double *forces, void *stream);
 
+/* tersoff_compute without allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The same evaluation as tersoff_compute
+ * (the same kernels in the same launch configuration: results identical bit
+ * for bit), with every per-evaluation buffer -- records, force planes,
+ * per-atom forces and counts, kept-neighbour lists, partial sums, and the
+ * force output when forces is NULL -- taken from one fixed device array of
+ * the library (about 34 MB on each GPU it runs on, held from the first use of
+ * the library's device code on that GPU until the process ends) instead of
+ * the context.  The call allocates nothing; the neighbour list comes from
+ * tersoff_build_neighbors (which does allocate), for at most
+ * TERSOFF_STATIC_MAX_ATOMS atoms.  Every call on one GPU shares the array
+ * (whatever its context or stream): calls that overlap on one GPU race.
+ * Arguments, ownership and errors as tersoff_compute, plus E_INVALID when the
+ * last build has more than TERSOFF_STATIC_MAX_ATOMS atoms. */
+#define TERSOFF_STATIC_MAX_ATOMS 16384
+int tersoff_compute_static(tersoff_ctx *ctx, const double *pos, int32_t precision,
+                           double *energy_virial, double *forces, void *stream);
+
 /* Synchronise `stream` and report the device-side status of every compute
  * since the previous check: OK, E_OVERFLOW (an atom exceeded the per-batch
  * neighbour capacity; its terms were skipped), E_STALE (an atom moved more

@@ -26,7 +26,7 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_BOX", -4: "E_OVERFLOW"
 
 # exported symbols (the declarations of include/tersoff.h)
 SYMBOLS = ("tersoff_create", "tersoff_destroy", "tersoff_build_neighbors", "tersoff_compute",
-           "tersoff_check", "tersoff_get_neighbors", "tersoff_get_counts", "tersoff_num_atoms",
+           "tersoff_compute_static", "tersoff_check", "tersoff_get_neighbors", "tersoff_get_counts", "tersoff_num_atoms",
            "tersoff_strerror", "tersoff_last_error", "tersoff_profile", "tersoff_profile_read",
            "tersoff_set_batch_atoms", "tersoff_serve_start", "tersoff_serve_stop", "tersoff_submit",
            "tersoff_poll", "tersoff_serve_stats", "tersoff_clock_ns", "tersoff_parse_params",
@@ -83,6 +83,8 @@ def load():
     lib.tersoff_build_neighbors.restype = ctypes.c_int
     lib.tersoff_compute.argtypes = [P, P, i32, P, P, P]
     lib.tersoff_compute.restype = ctypes.c_int
+    lib.tersoff_compute_static.argtypes = [P, P, i32, P, P, P]
+    lib.tersoff_compute_static.restype = ctypes.c_int
     lib.tersoff_check.argtypes = [P, P]
     lib.tersoff_check.restype = ctypes.c_int
     lib.tersoff_get_neighbors.argtypes = [P, P, P, i64, P]
@@ -190,8 +192,10 @@ class Tersoff:
         if st != OK:
             self._raise(st, "tersoff_build_neighbors")
 
-    def compute(self, pos, precision="mixed", forces=None, out=None, want_forces=True):
-        """Returns (out, forces): out = [E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz] (device)."""
+    def compute(self, pos, precision="mixed", forces=None, out=None, want_forces=True, static=False):
+        """Returns (out, forces): out = [E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz] (device).
+        static=True calls tersoff_compute_static (no allocation by the library;
+        the caller's out and forces tensors are allocated here when not given)."""
         import torch
         _check_dev(pos, torch.float64, (3,), "pos")
         if out is None:
@@ -200,11 +204,11 @@ class Tersoff:
             forces = torch.empty_like(pos)
         if forces is not None:
             _check_dev(forces, torch.float64, (3,), "forces")
-        st = self._lib.tersoff_compute(self._h, pos.data_ptr(), PRECISIONS[precision], out.data_ptr(),
-                                       forces.data_ptr() if forces is not None else None,
-                                       _stream_ptr(torch, pos.device))
+        fn = self._lib.tersoff_compute_static if static else self._lib.tersoff_compute
+        st = fn(self._h, pos.data_ptr(), PRECISIONS[precision], out.data_ptr(),
+                forces.data_ptr() if forces is not None else None, _stream_ptr(torch, pos.device))
         if st != OK:
-            self._raise(st, "tersoff_compute")
+            self._raise(st, "tersoff_compute_static" if static else "tersoff_compute")
         return out, forces
 
     def check(self):

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -252,6 +253,57 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     return TERSOFF_OK;
 }
 
+}  // namespace
+
+// ---- The evaluation without allocation ----------------------------------
+//
+// tersoff_compute_static runs the kernels of tersoff_compute with every
+// per-evaluation buffer (records, force planes, per-atom forces and counts,
+// kept-neighbour lists, dropped-atom list, per-workgroup partial sums) taken
+// from one file-scope device array, for builds of at most
+// TERSOFF_STATIC_MAX_ATOMS atoms.  Every GPU the library runs on holds its own
+// copy of the array until the process ends; host code reaches it only through
+// the address hipGetSymbolAddress returns on that device.
+namespace {
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t kStaticAtoms = TERSOFF_STATIC_MAX_ATOMS;
+constexpr size_t kStaticGrid = 8192;   // compute workgroups: at most one per batch of atoms
+// records of padded batches (fewer than kWave padding atoms), at the largest
+// record size (32 bytes, FP64) -- above the 20 bytes per float record
+constexpr size_t kStaticRecBytes = align256((size_t)kRecCap * (kStaticAtoms + kWave) * 32);
+constexpr size_t kStaticPlaneBytes = align256(3 * (size_t)kRecCap * kStaticAtoms * sizeof(double));
+constexpr size_t kStaticOwnBytes = align256(3 * kStaticAtoms * sizeof(double));
+constexpr size_t kStaticIntBytes = align256(kStaticAtoms * sizeof(int));
+constexpr size_t kStaticKeptBytes = align256((size_t)(kKeptFast + kRecCap) * kStaticAtoms * sizeof(int));
+constexpr size_t kStaticPartialBytes = align256(8 * kStaticGrid * sizeof(double));
+constexpr size_t kStaticCounterBytes = align256(2 * kStaticGrid * sizeof(long long));
+constexpr size_t kStaticBytes = kStaticRecBytes + kStaticPlaneBytes + 2 * kStaticOwnBytes + 2 * kStaticIntBytes +
+                                kStaticKeptBytes + kStaticPartialBytes + kStaticCounterBytes;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// The address of `scratch` on device dev (current), looked up once per device.
+hipError_t static_scratch(int dev, unsigned char **out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 }  // namespace
 
 extern "C" {
@@ -626,6 +678,39 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     b.partials = c->partials.p;
     b.counters = c->counters.p;
     return launch_evaluation(c, pos, prec, energy_virial, f, as_stream(stream), b, c->profiling);
+}
+
+int tersoff_compute_static(tersoff_ctx *c, const double *pos, int32_t precision, double *energy_virial,
+                           double *forces, void *stream)
+{
+    const int st = check_compute_args(c, pos, precision, energy_virial);
+    if (st != TERSOFF_OK) return st;
+    const int prec = precision;
+    if (c->n > TERSOFF_STATIC_MAX_ATOMS)
+        return fail(c, TERSOFF_E_INVALID, "tersoff_compute_static: the build has more than TERSOFF_STATIC_MAX_ATOMS atoms");
+    if (record_region_bytes(prec, record_slots(c)) > kStaticRecBytes || c->grid[prec][1] > (int)kStaticGrid)
+        return fail(c, TERSOFF_E_INVALID, "tersoff_compute_static: batch layout beyond the static scratch");
+    HIP_TRY(c, hipSetDevice(c->device));
+    unsigned char *base = nullptr;
+    HIP_TRY(c, static_scratch(c->device, &base));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = base + off;
+        off += bytes;
+        return p;
+    };
+    EvalBuffers b{};
+    b.recs = take(kStaticRecBytes);
+    b.planes = reinterpret_cast<double *>(take(kStaticPlaneBytes));
+    b.own = reinterpret_cast<double *>(take(kStaticOwnBytes));
+    double *force_scratch = reinterpret_cast<double *>(take(kStaticOwnBytes));
+    b.pcount = reinterpret_cast<int *>(take(kStaticIntBytes));
+    b.drop_list = reinterpret_cast<int *>(take(kStaticIntBytes));
+    b.kept = reinterpret_cast<int *>(take(kStaticKeptBytes));
+    b.partials = reinterpret_cast<double *>(take(kStaticPartialBytes));
+    b.counters = reinterpret_cast<long long *>(take(kStaticCounterBytes));
+    return launch_evaluation(c, pos, prec, energy_virial, forces ? forces : force_scratch, as_stream(stream), b,
+                             false);
 }
 
 int tersoff_check(tersoff_ctx *c, void *stream)
