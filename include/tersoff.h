@@ -200,8 +200,11 @@ const char *tersoff_last_error(const tersoff_ctx *ctx);
  * evaluates the whole batch with one replay of a captured HIP graph, while
  * the next batch is formed from requests that arrived in the meantime.  A
  * configuration's result does not depend on which other configurations share
- * its batch.  Buffers are host memory; the device memory of two batches in
- * flight is allocated once, at start, from the capacities. */
+ * its batch.  A request's buffers may be host memory or device memory of the
+ * context's GPU (told apart with hipPointerGetAttributes): host inputs are
+ * staged through pinned memory, device inputs copied into the batch on the
+ * device, forces written back to either.  The device memory of two batches
+ * in flight is allocated once, at start, from the capacities. */
 typedef struct {
     int64_t max_batch_atoms;    /* atoms per batch, in [1, 2^24]; also the largest request  */
     int32_t max_batch_systems;  /* configurations per batch (slots), in [1, 2^20]           */
@@ -216,12 +219,14 @@ typedef struct {
 } tersoff_serve_config;
 
 typedef struct {
-    const double *pos;      /* host, n x 3 float64; read when the request joins a batch  */
-    const int32_t *types;   /* host, n int32 in [0, ntypes)                              */
+    const double *pos;      /* host or device, n x 3 float64; read when the request
+                               joins a batch                                             */
+    const int32_t *types;   /* host or device, n int32 in [0, ntypes)                    */
     int64_t n;
     double box[3];          /* orthorhombic periodic lengths, each >= 2 (cutoff + skin)  */
     int32_t precision;      /* a tersoff_precision                                       */
-    double *forces;         /* host, n x 3, written before the result is ready; or NULL  */
+    double *forces;         /* host or device, n x 3, written before the result is
+                               ready; or NULL                                            */
     uint64_t tag;           /* returned unchanged                                        */
     int64_t release_ns;     /* tersoff_clock_ns() time before which the request is not
                                started (0: at once); latency counts from the later of
@@ -231,7 +236,8 @@ typedef struct {
 typedef struct {
     int32_t status;         /* OK, or E_OVERFLOW (a row above max_neighbors or an atom
                                above the per-atom record capacity: values invalid),
-                               or E_DEVICE                                               */
+                               E_INVALID (device-resident input with a type out of range
+                               or a non-finite position), or E_DEVICE                    */
     int32_t batch_systems;  /* configurations in the batch that evaluated it             */
     int64_t n;
     double energy;          /* eV                                                        */
@@ -253,9 +259,12 @@ int tersoff_serve_stop(tersoff_ctx *ctx);
 /* Queue one configuration.  pos, types and forces must stay valid until its
  * result has been collected.  Thread-safe.
  * Errors: E_INVALID (null pointer, n < 1 or above max_batch_atoms, type out
- *   of range, non-finite position or box, precision, a box with more cells
- *   than a batch holds), E_BOX (a box length < 2 (cutoff + skin)), E_AGAIN
- *   (queue full), E_STATE (serving not started or stopping). */
+ *   of range or non-finite position in host memory, non-finite box,
+ *   precision, a box with more cells than a batch holds, a buffer in the
+ *   memory of another GPU), E_BOX (a box length < 2 (cutoff + skin)),
+ *   E_AGAIN (max_queued requests waiting), E_STATE (serving not started or
+ *   stopping).  Device-resident inputs are checked on the device: a bad one
+ *   yields a result with status E_INVALID. */
 int tersoff_submit(tersoff_ctx *ctx, const tersoff_request *req, uint64_t *ticket);
 
 /* Collect the result of a ticket, waiting up to timeout_ms (0: do not wait).

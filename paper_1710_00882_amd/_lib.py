@@ -306,24 +306,46 @@ class Tersoff:
             self._raise(st, "tersoff_serve_stop")
 
     def submit(self, pos, types, box, precision="mixed", forces=None, tag=0, release_ns=0):
-        """Queue one configuration (host numpy arrays, kept alive here until
-        its result is collected).  Returns the ticket; raises TersoffError
-        (status E_AGAIN when the queue is full)."""
-        pos = np.ascontiguousarray(pos, dtype=np.float64)
-        types = np.ascontiguousarray(types, dtype=np.int32)
-        if pos.ndim != 2 or pos.shape[1] != 3 or types.shape != (pos.shape[0],):
+        """Queue one configuration: host numpy arrays, or torch tensors on the
+        context's GPU (device-resident buffers), kept alive here until its
+        result is collected.  Returns the ticket; raises TersoffError (status
+        E_AGAIN when the queue is full)."""
+        def dev(t):
+            return hasattr(t, "is_cuda") and t.is_cuda
+
+        def ptr(t):
+            return t.data_ptr() if dev(t) else t.ctypes.data
+
+        if dev(pos):
+            import torch
+            _check_dev(pos, torch.float64, (3,), "pos")
+        if dev(types):
+            import torch
+            if types.dtype != torch.int32 or not types.is_contiguous():
+                raise ValueError("device types must be a contiguous int32 tensor")
+        if not dev(pos):
+            pos = np.ascontiguousarray(pos, dtype=np.float64)
+        if not dev(types):
+            types = np.ascontiguousarray(types, dtype=np.int32)
+        n = pos.shape[0]
+        if len(pos.shape) != 2 or pos.shape[1] != 3 or tuple(types.shape) != (n,):
             raise ValueError("pos must be (n, 3) and types (n,)")
         if forces is not None:
-            if forces.dtype != np.float64 or forces.shape != pos.shape or not forces.flags.c_contiguous:
+            if dev(forces):
+                import torch
+                _check_dev(forces, torch.float64, (3,), "forces")
+                if tuple(forces.shape) != (n, 3):
+                    raise ValueError("forces must be shaped like pos")
+            elif forces.dtype != np.float64 or forces.shape != (n, 3) or not forces.flags.c_contiguous:
                 raise ValueError("forces must be a C-contiguous float64 array shaped like pos")
         req = Request()
-        req.pos = pos.ctypes.data
-        req.types = types.ctypes.data
-        req.n = pos.shape[0]
+        req.pos = ptr(pos)
+        req.types = ptr(types)
+        req.n = n
         for a, v in enumerate(np.asarray(box, dtype=np.float64).reshape(3)):
             req.box[a] = float(v)
         req.precision = PRECISIONS[precision]
-        req.forces = forces.ctypes.data if forces is not None else None
+        req.forces = ptr(forces) if forces is not None else None
         req.tag = int(tag)
         req.release_ns = int(release_ns)
         t = ctypes.c_uint64(0)

@@ -410,55 +410,56 @@ constexpr int kOwnerCap = 1024;   // batch entries whose atom is looked up in a 
 static_assert(kKeptFast == 8, "the first block of a kept list is two 16-byte words");
 
 // Position of atom `who` in the kept-neighbour list of atom m (-1: absent);
-// `ended` tells whether the list ends (end marker) before kRecCap entries.
+// `absent` tells that `who` is certainly not in the list (a list truncated
+// at kRecCap entries, whose tail is unknown, leaves it false).  A kept list
+// is in ascending order (the order of the sorted neighbour row), so the
+// position is the number of entries below `who`; the -1 end markers compare
+// above every index as unsigned.  Both 16-byte words of the first block are
+// loaded together.
 __device__ __forceinline__ int kept_position(const int *__restrict__ kept, const int *__restrict__ kept_more,
-                                             int m, int who, bool &ended)
+                                             int m, int who, bool &absent)
 {
     const int4 *kb = reinterpret_cast<const int4 *>(kept + (size_t)m * kKeptFast);
-    int len = kKeptFast, pos = -1;
-    {
-        const int4 v0 = kb[0];
-        const int v[4] = {v0.x, v0.y, v0.z, v0.w};
+    const int4 v0 = kb[0], v1 = kb[1];
+    const unsigned w = (unsigned)who;
+    const int v[kKeptFast] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    int pos = 0;
+    bool hit = false;
 #pragma unroll
-        for (int q = 3; q >= 0; --q)
-            if (v[q] < 0) len = q;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (q < len && v[q] == who) pos = q;
+    for (int q = 0; q < kKeptFast; ++q) {
+        pos += (unsigned)v[q] < w ? 1 : 0;
+        hit |= v[q] == who;
     }
-    if (pos < 0 && len == kKeptFast) {
-        const int4 v1 = kb[1];
-        const int v[4] = {v1.x, v1.y, v1.z, v1.w};
-#pragma unroll
-        for (int q = 3; q >= 0; --q)
-            if (v[q] < 0) len = 4 + q;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (4 + q < len && v[q] == who) pos = 4 + q;
+    absent = false;
+    if (hit) return pos;
+    if (v1.w < 0 || pos < kKeptFast) {
+        absent = true;   // the list ended, or passed who
+        return -1;
     }
-    ended = len < kKeptFast;
-    if (pos < 0 && !ended) {
-        const int *km = kept_more + (size_t)m * kRecCap;
+    // the list goes on past its first block and every entry so far is below who
+    const int *km = kept_more + (size_t)m * kRecCap;
 #pragma unroll 1
-        for (int q = kKeptFast; q < kRecCap; ++q) {
-            const int x = km[q];
-            if (x < 0) {
-                ended = true;
-                break;
-            }
-            if (x == who) {
-                pos = q;
-                break;
-            }
+    for (int q = kKeptFast; q < kRecCap; ++q) {
+        const int x = km[q];
+        if (x == who) return q;
+        if (x < 0 || x > who) {
+            absent = true;
+            return -1;
         }
     }
-    return pos;
+    return -1;
 }
 constexpr int kScap = 64;      // packed slots per compute batch (one per lane)
 // Resident packing wavefronts per CU: more than this only adds contention for
 // the CU's vector-memory path (the kernel is bound by its neighbour-position
 // gathers, not by latency).
 constexpr int kPackWavesPerCU = 24;
+// Resident compute wavefronts per CU (the grid is persistent), by precision:
+// past these the extra wavefronts cost more than they hide in latency
+// (measured on the 2M-atom silicon workload, caps of 8/10/12/16 and none:
+// mixed and all-FP32 fastest at 16, four per SIMD; FP64 at 10 -- 369 us
+// against 465 us at 12 or more).
+constexpr int kComputeWavesPerCU[kNumPrec] = {10, 16, 16};   // FP64, mixed, single
 
 // ------------------------------------------------------------- pack kernel -
 //
@@ -795,11 +796,8 @@ __device__ __forceinline__ real exp_ratio(const Q &q, real rj, real rk)
 // SINGLE (with real = float): the all-FP32 variant -- the zeta -> b power and
 // each lane's sum of the force terms on j in FP32 as well; FP64 remains only
 // in the displacement (packing) and in the sums across lanes and atoms.
-// The one-species float instances fit 128 VGPRs without spilling: ask for
-// four wavefronts per SIMD there.
 template <typename real, int NT, bool BATCHED, bool SINGLE, bool NOL3, bool CACHE>
-__global__ __launch_bounds__(kWave, (sizeof(real) == 4 && NT == 1) ? 4 : 1) void k_tersoff(ComputeLaunch a,
-                                                                                              DeviceTable tab)
+__global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable tab)
 {
     static_assert(!SINGLE || sizeof(real) == 4, "the single-precision variant computes in float");
     static_assert(!NOL3 || NT == 1, "the lambda3-free variant is a one-species kernel");
@@ -833,7 +831,7 @@ __global__ __launch_bounds__(kWave, (sizeof(real) == 4 && NT == 1) ? 4 : 1) void
 
     double e_acc = 0.0;
     double w_acc[6] = {0, 0, 0, 0, 0, 0};
-    long long n_pairs = 0, n_trip = 0;
+    int n_pairs = 0, n_trip = 0;   // this lane's (well below 2^31 per lane)
     bool asym = false;   // a kept neighbour whose (complete) kept list lacks the centre
 
     const int B = a.atoms_per_batch;
@@ -881,9 +879,9 @@ __global__ __launch_bounds__(kWave, (sizeof(real) == 4 && NT == 1) ? 4 : 1) void
                 const Rec<real> rc = region[s];
                 if constexpr (kRlo) rjlo = rlo_region[s];
                 j = rc.jm & kIdMask;
-                bool ended;
-                kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, ended);
-                asym |= kpos < 0 && ended;
+                bool absent;
+                kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, absent);
+                asym |= absent;
                 mj = rc.jm;
                 dj[0] = rc.dx; dj[1] = rc.dy; dj[2] = rc.dz;
                 rj = M<real>::sqrt(norm2r(dj[0], dj[1], dj[2]));
@@ -950,7 +948,7 @@ __global__ __launch_bounds__(kWave, (sizeof(real) == 4 && NT == 1) ? 4 : 1) void
                         aj[1] += w * tv[1];
                         aj[2] += w * tv[2];
                         bj += fg * dex;
-                        n_trip += member ? 1 : 0;
+                        if constexpr (!ONE) n_trip += member ? 1 : 0;
                         if constexpr (CACHE) {
                             if (kk < KC) {
                                 real ex2, dex2;
@@ -965,6 +963,7 @@ __global__ __launch_bounds__(kWave, (sizeof(real) == 4 && NT == 1) ? 4 : 1) void
                 real dz_out = real(0);
                 if (j_pair) {
                     ++n_pairs;
+                    if constexpr (ONE) n_trip += pc - 1;   // every other slot is a third atom
                     const int e_ij = ONE ? 0 : (ti * nt + tj) * nt + tj;
                     const ParamR<real> &q = ONE ? q0 : ptab[e_ij];
                     const ParamX px = tab.px[e_ij];
@@ -1037,8 +1036,10 @@ __global__ __launch_bounds__(kWave, (sizeof(real) == 4 && NT == 1) ? 4 : 1) void
             if (has_slot) {
                 // ---- 3: second K loop, the k-role terms of centre i on atom j:
                 // -dV/dzeta_ik dzeta(i,k,j)/dx_j over the bond partners k of i
-                // that have j as a third atom
-                facc ax = 0, ay = 0, az = 0, su = 0;
+                // that have j as a third atom, summed in the working precision
+                // (a handful of triplet terms; the pair's total is stored in
+                // the working precision as well)
+                real ax = 0, ay = 0, az = 0, su = 0;
                 for (int kk = 0; kk + 1 < pc; ++kk) {
                     const int sk = sb + kk + (kk >= jl ? 1 : 0);
                     const real dzk = sh.dzeta[sk];
@@ -1071,14 +1072,14 @@ __global__ __launch_bounds__(kWave, (sizeof(real) == 4 && NT == 1) ? 4 : 1) void
                     const real fcj = valid ? sh.fc[ONE ? 0 : tk][s] : real(0);
                     const real dfcj = valid ? sh.dfc[ONE ? 0 : tk][s] : real(0);
                     const real wv = dzk * fcj * rjinv;
-                    ax += (facc)(wv * v[0]);
-                    ay += (facc)(wv * v[1]);
-                    az += (facc)(wv * v[2]);
-                    su += (facc)(dzk * (dfcj * sg - fcj * tg));
+                    ax += wv * v[0];
+                    ay += wv * v[1];
+                    az += wv * v[2];
+                    su += dzk * (dfcj * sg - fcj * tg);
                 }
-                fx -= ax + su * (facc)uj[0];
-                fy -= ay + su * (facc)uj[1];
-                fz -= az + su * (facc)uj[2];
+                fx -= (facc)(ax + su * uj[0]);
+                fy -= (facc)(ay + su * uj[1]);
+                fz -= (facc)(az + su * uj[2]);
                 // ---- 4: virial and output (FP64 from here on)
                 const double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
                 const double dxj = (double)dj[0], dyj = (double)dj[1], dzj_ = (double)dj[2];
@@ -1135,7 +1136,7 @@ __global__ __launch_bounds__(kWave, (sizeof(real) == 4 && NT == 1) ? 4 : 1) void
     double v[7] = {e_acc, w_acc[0], w_acc[1], w_acc[2], w_acc[3], w_acc[4], w_acc[5]};
 #pragma unroll
     for (int c = 0; c < 7; ++c) v[c] = wave_sum(v[c]);
-    long long np = n_pairs, ntr = n_trip;
+    long long np = n_pairs, ntr = n_trip;   // summed across the wavefront in 64 bits
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
         np += __shfl_xor(np, off, kWave);
@@ -1169,8 +1170,8 @@ __global__ void k_fixup_dropped(const int *__restrict__ ell, int cap, const int 
         const int rc = row_count[m];
         for (int q = (int)threadIdx.x; q < rc; q += blockDim.x) {
             const int nb = ell[(size_t)m * cap + q];
-            bool ended;
-            const int k = kept_position(kept, kept_more, nb, m, ended);   // plane nb reserved for m
+            bool absent;
+            const int k = kept_position(kept, kept_more, nb, m, absent);   // plane nb reserved for m
             if (k >= 0) {
                 T *f = planes + 3 * ((size_t)k * plane_stride + (size_t)nb);
                 f[0] = f[1] = f[2] = T(0);
@@ -1423,7 +1424,8 @@ void grids_dispatch(int prec, const DeviceTable &t, int n, int atoms_per_batch, 
         grids[0] = occupancy_grid((const void *)k_pack<typename K::real, K::one, BATCHED>, batches,
                                   kPackWavesPerCU);
         grids[1] = occupancy_grid(
-            (const void *)k_tersoff<typename K::real, K::nt, BATCHED, K::single, K::nol3, K::cache>, batches);
+            (const void *)k_tersoff<typename K::real, K::nt, BATCHED, K::single, K::nol3, K::cache>, batches,
+            kComputeWavesPerCU[prec]);
     });
     grids[2] = kBigGrid;
 }

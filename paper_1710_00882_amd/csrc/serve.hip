@@ -154,7 +154,68 @@ struct Pending {
     int64_t t_start;   // max(submit time, release time)
     CellGrid g;
     int ncell;
+    bool pos_dev, types_dev, forces_dev;   // the request's buffers in this GPU's memory
 };
+
+// One configuration of a batch with a buffer in device memory: its device
+// positions and / or types (null: staged from host memory) are copied into
+// the batch by k_copy_inputs, its forces (null: returned through host
+// staging) out of the batch by k_copy_outputs.
+struct DevCopy {
+    const double *pos;
+    const int *types;
+    double *forces;
+    int off, n;
+};
+
+// Device-resident inputs into the batch arrays, one workgroup per
+// configuration: positions and types copied as they are, a non-finite
+// position (replaced by 0) or a type outside [0, ntypes) (replaced by 0)
+// marks the configuration invalid in status[c] (written for every listed
+// configuration), so no kernel of the batch ever indexes the parameter table
+// with an unchecked type.
+__global__ void k_copy_inputs(const DevCopy *__restrict__ list, int count, int ntypes, double *__restrict__ pos,
+                              int *__restrict__ types, int *__restrict__ status)
+{
+    for (int c = blockIdx.x; c < count; c += gridDim.x) {
+        const DevCopy d = list[c];
+        int bad = 0;
+        for (int a = threadIdx.x; a < d.n; a += blockDim.x) {
+            const size_t o = (size_t)(d.off + a);
+            if (d.pos) {
+                double x = d.pos[3 * (size_t)a], y = d.pos[3 * (size_t)a + 1], z = d.pos[3 * (size_t)a + 2];
+                if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+                    bad = 1;
+                    x = y = z = 0.0;
+                }
+                pos[3 * o] = x;
+                pos[3 * o + 1] = y;
+                pos[3 * o + 2] = z;
+            }
+            if (d.types) {
+                int t = d.types[a];
+                if (t < 0 || t >= ntypes) {
+                    bad = 1;
+                    t = 0;
+                }
+                types[o] = t;
+            }
+        }
+        bad = __syncthreads_or(bad);
+        if (threadIdx.x == 0) status[c] = bad;
+        __syncthreads();
+    }
+}
+
+// Forces of the batch out to device-resident force arrays.
+__global__ void k_copy_outputs(const DevCopy *__restrict__ list, int count, const double *__restrict__ forces)
+{
+    for (int c = blockIdx.x; c < count; c += gridDim.x) {
+        const DevCopy d = list[c];
+        if (!d.forces) continue;
+        for (int k = threadIdx.x; k < 3 * d.n; k += blockDim.x) d.forces[k] = forces[3 * (size_t)d.off + k];
+    }
+}
 
 struct Lane {
     hipStream_t stream = nullptr;
@@ -164,6 +225,13 @@ struct Lane {
     Pinned<int> h_types, h_sys_of;
     Pinned<SysDesc> h_desc;
     Pinned<BatchDims> h_dims;
+    Pinned<DevCopy> h_copies;    // configurations of the batch with device-resident buffers
+    Pinned<int> h_in_status;     // their input status (k_copy_inputs)
+    Dev<DevCopy> copies;
+    Dev<int> in_status;
+    int ncopies = 0;
+    bool dev_outputs = false;
+    std::vector<int> copy_of;    // batch index -> copy list index (-1: none)
     Dev<double> pos, cell_pos, own, planes, forces, eatom, out;
     Dev<float4> cell_posf;
     Dev<int> long_rows;
@@ -177,7 +245,7 @@ struct Lane {
     std::vector<Pending> batch;
     int natoms = 0;
     int prec = 0;
-    bool want_forces = false;
+    bool want_forces = false;    // some configuration returns forces through host staging
     bool busy = false;
 };
 
@@ -245,6 +313,8 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.h_sys_of.alloc(A));
     SRV_TRY(L.h_desc.alloc(NS));
     SRV_TRY(L.h_dims.alloc(1));
+    SRV_TRY(L.h_copies.alloc(NS));
+    SRV_TRY(L.h_in_status.alloc(NS));
     SRV_TRY(L.pos.alloc(3 * A, tot));
     SRV_TRY(L.cell_pos.alloc(3 * A, tot));
     SRV_TRY(L.cell_posf.alloc(A + kPosPad, tot));
@@ -274,6 +344,8 @@ hipError_t alloc_lane(Server &S, Lane &L)
     SRV_TRY(L.recs.alloc(std::max(record_region_bytes(kPrecFP64, slots), record_region_bytes(kPrecMixed, slots)),
                          tot));
     SRV_TRY(L.desc.alloc(NS, tot));
+    SRV_TRY(L.copies.alloc(NS, tot));
+    SRV_TRY(L.in_status.alloc(NS, tot));
     SRV_TRY(L.dims.alloc(1, tot));
     // every kept list starts empty (-1)
     SRV_TRY(hipMemsetAsync(L.kept.p, 0xff, sizeof(int) * (kKeptFast + kRecCap) * A, L.stream));
@@ -286,7 +358,7 @@ void free_lane(Lane &L)
     for (auto &x : L.exec)
         if (x) (void)hipGraphExecDestroy(x), x = nullptr;
     L.h_pos.release(); L.h_forces.release(); L.h_out.release(); L.h_types.release();
-    L.h_sys_of.release(); L.h_desc.release(); L.h_dims.release();
+    L.h_sys_of.release(); L.h_desc.release(); L.h_dims.release(); L.h_copies.release(); L.h_in_status.release();
     L.pos.release(); L.cell_pos.release(); L.own.release(); L.planes.release(); L.forces.release();
     L.cell_posf.release(); L.long_rows.release();
     L.eatom.release(); L.out.release(); L.types.release(); L.sys_of.release(); L.cell_of.release();
@@ -294,7 +366,8 @@ void free_lane(Lane &L)
     L.slot_cell.release();
     L.scan_tmp.release(); L.ell.release(); L.row_count.release(); L.kept.release();
     L.pcount.release();
-    L.drop_list.release(); L.ctl.release(); L.recs.release(); L.desc.release();
+    L.drop_list.release(); L.ctl.release(); L.recs.release(); L.desc.release(); L.copies.release();
+    L.in_status.release();
     L.dims.release();
     if (L.done) (void)hipEventDestroy(L.done), L.done = nullptr;
     if (L.stream) (void)hipStreamDestroy(L.stream), L.stream = nullptr;
@@ -435,7 +508,10 @@ hipError_t launch_lane(Server &S, Lane &L)
 {
     int off = 0, coff = 0;
     L.want_forces = false;
+    L.dev_outputs = false;
+    L.ncopies = 0;
     const int nsys = (int)L.batch.size();
+    L.copy_of.assign(nsys, -1);
     for (int q = 0; q < nsys; ++q) {
         const Pending &p = L.batch[q];
         const int n = (int)p.req.n;
@@ -445,15 +521,27 @@ hipError_t launch_lane(Server &S, Lane &L)
         d.natoms = n;
         d.cell_off = coff;
         d.pad = 0;
+        if (p.pos_dev || p.types_dev || p.forces_dev) {
+            DevCopy &c = L.h_copies.p[L.ncopies];
+            c.pos = p.pos_dev ? p.req.pos : nullptr;
+            c.types = p.types_dev ? p.req.types : nullptr;
+            c.forces = p.forces_dev ? p.req.forces : nullptr;
+            c.off = off;
+            c.n = n;
+            L.copy_of[q] = L.ncopies++;
+            L.dev_outputs |= p.forces_dev;
+        }
         off += n;
         coff += p.ncell;
-        L.want_forces |= p.req.forces != nullptr;
+        L.want_forces |= p.req.forces != nullptr && !p.forces_dev;
     }
+    // host-resident inputs into pinned staging (device-resident ones are
+    // copied on the device after the bulk upload, over the same range)
     S.pool->run(nsys, [&](int q) {
         const Pending &p = L.batch[q];
         const size_t n = (size_t)p.req.n, o = (size_t)L.h_desc.p[q].atom_off;
-        std::memcpy(L.h_pos.p + 3 * o, p.req.pos, sizeof(double) * 3 * n);
-        std::memcpy(L.h_types.p + o, p.req.types, sizeof(int) * n);
+        if (!p.pos_dev) std::memcpy(L.h_pos.p + 3 * o, p.req.pos, sizeof(double) * 3 * n);
+        if (!p.types_dev) std::memcpy(L.h_types.p + o, p.req.types, sizeof(int) * n);
         std::fill(L.h_sys_of.p + o, L.h_sys_of.p + o + n, q);
     });
     L.natoms = off;
@@ -464,11 +552,26 @@ hipError_t launch_lane(Server &S, Lane &L)
     SRV_TRY(hipMemcpyAsync(L.sys_of.p, L.h_sys_of.p, sizeof(int) * (size_t)off, hipMemcpyHostToDevice, s));
     SRV_TRY(hipMemcpyAsync(L.desc.p, L.h_desc.p, sizeof(SysDesc) * (size_t)nsys, hipMemcpyHostToDevice, s));
     SRV_TRY(hipMemcpyAsync(L.dims.p, L.h_dims.p, sizeof(BatchDims), hipMemcpyHostToDevice, s));
+    if (L.ncopies) {
+        SRV_TRY(hipMemcpyAsync(L.copies.p, L.h_copies.p, sizeof(DevCopy) * (size_t)L.ncopies, hipMemcpyHostToDevice,
+                               s));
+        hipLaunchKernelGGL(k_copy_inputs, dim3(std::min(L.ncopies, kBatchGrid)), dim3(256), 0, s, L.copies.p,
+                           L.ncopies, S.env.ntypes, L.pos.p, L.types.p, L.in_status.p);
+        SRV_TRY(hipGetLastError());
+    }
     SRV_TRY(hipGraphLaunch(L.exec[L.prec], s));
     SRV_TRY(hipMemcpyAsync(L.h_out.p, L.out.p, sizeof(double) * 8 * (size_t)nsys, hipMemcpyDeviceToHost, s));
+    if (L.ncopies)
+        SRV_TRY(hipMemcpyAsync(L.h_in_status.p, L.in_status.p, sizeof(int) * (size_t)L.ncopies,
+                               hipMemcpyDeviceToHost, s));
     if (L.want_forces)
         SRV_TRY(hipMemcpyAsync(L.h_forces.p, L.forces.p, sizeof(double) * 3 * (size_t)off, hipMemcpyDeviceToHost,
                                s));
+    if (L.dev_outputs) {
+        hipLaunchKernelGGL(k_copy_outputs, dim3(std::min(L.ncopies, kBatchGrid)), dim3(256), 0, s, L.copies.p,
+                           L.ncopies, L.forces.p);
+        SRV_TRY(hipGetLastError());
+    }
     return hipEventRecord(L.done, s);
 }
 
@@ -488,10 +591,12 @@ void retire(Server &S, Lane &L, hipError_t status)
         } else {
             const double *o = L.h_out.p + 8 * (size_t)q;
             const int st = (int)o[7];
-            r.status = st ? TERSOFF_E_OVERFLOW : TERSOFF_OK;
+            const int cq = L.copy_of[q];
+            if (cq >= 0 && L.h_in_status.p[cq]) r.status = TERSOFF_E_INVALID;   // device input rejected
+            else r.status = st ? TERSOFF_E_OVERFLOW : TERSOFF_OK;
             r.energy = o[0];
             for (int c = 0; c < 6; ++c) r.virial[c] = o[1 + c];
-            if (p.req.forces)
+            if (p.req.forces && !p.forces_dev)
                 std::memcpy(p.req.forces, L.h_forces.p + 3 * (size_t)L.h_desc.p[q].atom_off,
                             sizeof(double) * 3 * (size_t)p.req.n);
         }
@@ -647,6 +752,20 @@ void server_destroy(Server *S)
     delete S;
 }
 
+// Where a buffer lives: 1 in the memory of `device`, 0 host memory (also
+// memory the runtime does not know, and managed memory, which the host
+// reads directly), -1 the memory of another GPU.
+static int residency(const void *ptr, int device)
+{
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+        (void)hipGetLastError();   // an unregistered host pointer
+        return 0;
+    }
+    if (at.type != hipMemoryTypeDevice || at.isManaged) return 0;
+    return at.device == device ? 1 : -1;
+}
+
 int server_submit(Server *S, const tersoff_request &req, uint64_t *ticket, std::string &err)
 {
     if (!req.pos || !req.types || req.n < 1) {
@@ -671,18 +790,32 @@ int server_submit(Server *S, const tersoff_request &req, uint64_t *ticket, std::
             return TERSOFF_E_BOX;
         }
     }
+    Pending p{};
+    int res[3];
+    const void *ptrs[3] = {req.pos, req.types, req.forces};
+    for (int k = 0; k < 3; ++k) {
+        res[k] = ptrs[k] ? residency(ptrs[k], S->env.device) : 0;
+        if (res[k] < 0) {
+            err = "a request buffer is device memory of another GPU";
+            return TERSOFF_E_INVALID;
+        }
+    }
+    p.pos_dev = res[0] == 1;
+    p.types_dev = res[1] == 1;
+    p.forces_dev = res[2] == 1;
+    // host-resident inputs are checked here; device-resident ones by
+    // k_copy_inputs (the result then reports E_INVALID)
     for (int64_t i = 0; i < req.n; ++i) {
-        if (req.types[i] < 0 || req.types[i] >= S->env.ntypes) {
+        if (!p.types_dev && (req.types[i] < 0 || req.types[i] >= S->env.ntypes)) {
             err = "type out of range";
             return TERSOFF_E_INVALID;
         }
-        if (!std::isfinite(req.pos[3 * i]) || !std::isfinite(req.pos[3 * i + 1]) ||
-            !std::isfinite(req.pos[3 * i + 2])) {
+        if (!p.pos_dev && (!std::isfinite(req.pos[3 * i]) || !std::isfinite(req.pos[3 * i + 1]) ||
+                           !std::isfinite(req.pos[3 * i + 2]))) {
             err = "non-finite position";
             return TERSOFF_E_INVALID;
         }
     }
-    Pending p{};
     p.req = req;
     long long ncell = 0;
     p.g = grid_of(req.box, S->rc, ncell);

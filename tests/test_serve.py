@@ -191,3 +191,82 @@ def test_release_time_and_latency(server):
     assert r["status"] == 0
     assert clock_ns() - t0 >= 50_000_000
     assert 0.0 <= r["latency_ms"] < 5000.0
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_device_resident_requests(server, precision):
+    """Requests whose positions, types and forces live in GPU memory (torch
+    tensors) give the same results, bit for bit, as the same configurations
+    submitted from host memory -- also when host and device requests share a
+    batch."""
+    import torch
+    systems = _stream(10, seed=21)
+    host = _submit_all(server, systems, precision, tag0=300)
+    tickets, dev_forces = [], []
+    for q, s in enumerate(systems):
+        if q % 3 == 2:   # every third one from host memory, in the same stream
+            f = np.zeros_like(s.pos)
+            tickets.append(server.submit(s.pos, s.types, s.box, precision, forces=f, tag=400 + q))
+            dev_forces.append(None)
+            continue
+        pos = torch.tensor(s.pos, dtype=torch.float64, device="cuda")
+        types = torch.tensor(s.types, dtype=torch.int32, device="cuda")
+        f = torch.zeros_like(pos)
+        tickets.append(server.submit(pos, types, s.box, precision, forces=f, tag=400 + q))
+        dev_forces.append(f)
+    res = [server.wait(t, 60000.0) for t in tickets]
+    assert max(r["batch_systems"] for r in res) > 1
+    for q, (r, h) in enumerate(zip(res, host)):
+        assert r["status"] == 0 and r["tag"] == 400 + q
+        assert r["energy"] == h["energy"]
+        assert np.array_equal(r["virial"], h["virial"])
+        F = dev_forces[q].cpu().numpy() if dev_forces[q] is not None else r["forces"]
+        assert np.array_equal(F, h["forces"])
+    say(f"[serve] device-resident {precision}: {len(systems)} configurations bit-identical to host submission")
+
+
+def test_device_resident_bad_input_reported(server):
+    """A device-resident type out of range is caught on the device (the
+    configuration's result has status E_INVALID, its neighbours in the batch
+    are unaffected); host-resident ones are refused at submission."""
+    import torch
+    from paper_1710_00882_amd._lib import TersoffError
+    good, bad = _stream(2, seed=22)
+    t_bad = torch.tensor(bad.types, dtype=torch.int32, device="cuda")
+    t_bad[3] = 7                                   # the table has one species
+    pos_bad = torch.tensor(bad.pos, dtype=torch.float64, device="cuda")
+    tk_good = server.submit(good.pos, good.types, good.box, "mixed", forces=np.zeros_like(good.pos))
+    tk_bad = server.submit(pos_bad, t_bad, bad.box, "mixed", forces=torch.zeros_like(pos_bad))
+    r_good, r_bad = server.wait(tk_good), server.wait(tk_bad)
+    assert r_bad["status"] == -1
+    assert r_good["status"] == 0
+    ref = _submit_all(server, [good], "mixed")[0]
+    assert r_good["energy"] == ref["energy"]
+    host_types = bad.types.copy()
+    host_types[3] = 7
+    with pytest.raises(TersoffError) as e:
+        server.submit(bad.pos, host_types, bad.box, "mixed")
+    assert e.value.status == -1
+
+
+def test_queue_full_returns_again():
+    """With max_queued = 2, a third request waiting for its release time is
+    refused with E_AGAIN; the queued ones still complete."""
+    from paper_1710_00882_amd import Tersoff, clock_ns
+    from paper_1710_00882_amd._lib import TersoffError
+    m = Tersoff(W.si_table())
+    m.serve_start(max_batch_atoms=4096, max_batch_systems=4, max_queued=2)
+    try:
+        systems = _stream(3, seed=23, nmax=500)
+        release = clock_ns() + 300_000_000          # held in the queue for 0.3 s
+        t0 = m.submit(systems[0].pos, systems[0].types, systems[0].box, "mixed", release_ns=release)
+        t1 = m.submit(systems[1].pos, systems[1].types, systems[1].box, "mixed", release_ns=release)
+        with pytest.raises(TersoffError) as e:
+            m.submit(systems[2].pos, systems[2].types, systems[2].box, "mixed", release_ns=release)
+        assert e.value.status == -7
+        assert m.wait(t0)["status"] == 0 and m.wait(t1)["status"] == 0
+        # room again once the queue drained
+        m.wait(m.submit(systems[2].pos, systems[2].types, systems[2].box, "mixed"))
+    finally:
+        m.serve_stop()
+        m.close()
