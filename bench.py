@@ -121,7 +121,8 @@ def timed_run(model, pos_dev, types_dev, box, precision, nsteps, forces, out, sk
     return t1 - t0, prof
 
 
-def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None, sigma=0.01):
+def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None, sigma=0.01, force_sum="planes",
+                     mapping="pair"):
     import torch
     from paper_1710_00882_amd import Tersoff
     from paper_1710_00882_amd import workloads as W
@@ -130,6 +131,8 @@ def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None,
     pos_dev = [torch.tensor(p, dtype=torch.float64, device="cuda") for p in host_sets]
     types_dev = torch.tensor(system.types, dtype=torch.int32, device="cuda")
     model = Tersoff(table)
+    model.set_force_sum(force_sum)
+    model.set_mapping(mapping)
     if batch_atoms:
         model.build_neighbors(pos_dev[0], types_dev, system.box, skin=W.SKIN)
         model.set_batch_atoms(batch_atoms)
@@ -171,14 +174,37 @@ def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None,
 
 
 def ablate(system, table, args, default_res, sigma=0.01):
-    """Lane-per-j of one centre atom (one atom per wavefront batch) against the
-    default lane-per-packed-pair mapping, mixed precision."""
+    """The three mappings of the triplet loop onto a wavefront, mixed
+    precision: lane per neighbour of one centre atom (one atom per batch),
+    lane per triplet, and the default lane per packed pair."""
     log(f"[bench] n={system.n}: one centre atom per wavefront (J-scheme ablation)")
-    r = measure_workload(system, table, max(args.steps, 10), args.warmup, ("mixed",), batch_atoms=1,
-                         sigma=sigma)["mixed"]
+    steps = max(args.steps, 10)
+    r = measure_workload(system, table, steps, args.warmup, ("mixed",), batch_atoms=1, sigma=sigma)["mixed"]
+    log(f"[bench] n={system.n}: a lane per triplet")
+    t = measure_workload(system, table, steps, args.warmup, ("mixed",), sigma=sigma, mapping="triplet")["mixed"]
     return {"lane_per_pair_main_ms": default_res["main_ms"], "lane_per_j_main_ms": r["main_ms"],
             "lane_per_j_slowdown": r["main_ms"] / default_res["main_ms"],
-            "lane_per_pair_ms_per_step": default_res["ms_per_step"], "lane_per_j_ms_per_step": r["ms_per_step"]}
+            "lane_per_triplet_main_ms": t["main_ms"],
+            "lane_per_triplet_slowdown": t["main_ms"] / default_res["main_ms"],
+            "lane_per_pair_ms_per_step": default_res["ms_per_step"], "lane_per_j_ms_per_step": r["ms_per_step"],
+            "lane_per_triplet_ms_per_step": t["ms_per_step"]}
+
+
+def f1_comparison(system, table, args, default_res):
+    """The atomic-free force sum (force planes + gather, the default) against
+    an FP64 atomic scatter of the same force terms (Section 3's conflicting
+    updates), mixed and FP64 on the 2M-atom workload: whole-step times and
+    the kernels of each."""
+    log(f"[bench] n={system.n}: FP64 atomic scatter of the force terms (f1 comparison)")
+    r = measure_workload(system, table, args.steps, args.warmup, ("mixed", "fp64"), force_sum="atomic")
+    out = {}
+    for p in ("mixed", "fp64"):
+        d, a = default_res[p], r[p]
+        out[p] = {"planes_ms_per_step": d["ms_per_step"], "atomic_ms_per_step": a["ms_per_step"],
+                  "planes_kernels_ms": {"pack": d["pack_ms"], "main": d["main_ms"], "gather": d["gather_ms"]},
+                  "atomic_kernels_ms": {"zero+pack": a["pack_ms"], "main": a["main_ms"], "sums": a["gather_ms"]},
+                  "atomic_vs_planes_step": a["ms_per_step"] / d["ms_per_step"]}
+    return out
 
 
 def cpu_model() -> str:
@@ -406,6 +432,7 @@ def main():
     mixed, fp64, single = res["mixed"], res["fp64"], res["single"]
 
     ablation = {}
+    f1 = None if args.no_ablation else f1_comparison(big, table, args, res)
     extra_32k = None
     if not args.no_32k:
         small = W.si_32k()
@@ -502,9 +529,14 @@ def main():
         "disordered_256k_two_species": extra_256k,
         "f3_ablation": dict(ablation, note=(
             "compute-kernel time per evaluation (mixed) with one centre atom per wavefront, its packed "
-            "neighbours on the lanes (the paper's J scheme on a 64-lane wavefront), against the default "
+            "neighbours on the lanes (the paper's J scheme on a 64-lane wavefront), and with the triplets of "
+            "each batch on the lanes (zeta and force terms summed by LDS atomics), against the default "
             "batches of centre atoms whose packed pairs fill the lanes (I and J together)")) if ablation else None,
         "serve": serve,
+        "f1_force_sum": dict(f1, note=(
+            "default: every force term of centre i on atom j summed by the lane of pair (i, j) into a force plane "
+            "of j, planes added per atom in a fixed order (no atomics, bitwise reproducible); compared with the "
+            "same terms added by FP64 atomics into zeroed forces (no planes, no gather)")) if f1 else None,
     }
     print(json.dumps(line), flush=True)
 

@@ -181,6 +181,32 @@ int tersoff_profile_read(tersoff_ctx *ctx, double out[8]);
  * the range. */
 int tersoff_set_batch_atoms(tersoff_ctx *ctx, int32_t atoms);
 
+/* How tersoff_compute sums the force terms (Section 3: the pair-vectorised
+ * scheme makes lanes of one vector update the same atoms).  mode 0 (the
+ * default): every term of centre i on atom j is summed by the lane of pair
+ * (i, j) and stored in a force plane of j, then each atom adds its planes in
+ * a fixed order -- no atomics, results reproducible bit for bit.  mode 1: the
+ * same terms added with FP64 atomics into the zeroed force array (no planes,
+ * no gather; the summation order, hence the last bits, vary from run to run)
+ * -- the comparison point of mode 0.  Both agree within the stated
+ * tolerances.  E_INVALID for another mode. */
+int tersoff_set_force_sum(tersoff_ctx *ctx, int32_t mode);
+
+/* How tersoff_compute maps the triplet loop onto the 64 lanes of a
+ * wavefront (Section 3 compares vectorising over centre atoms with
+ * vectorising over their neighbours; Table 2).  mode 0 (the default): a lane
+ * per packed pair (i, j), with the pairs of several centre atoms side by side
+ * in one batch; the lane runs the K loops of its pair.  mode 1: the same
+ * batches with the lanes taken by the triplets (i; j, k) of the batch, zeta
+ * and the force terms summed with LDS atomics (the order of those sums, hence
+ * the last bits, vary from run to run) -- a comparison point, for
+ * TERSOFF_FP64 and TERSOFF_MIXED with the force planes (tersoff_set_force_sum
+ * mode 0).  A lane per neighbour of one centre atom is mode 0 with
+ * tersoff_set_batch_atoms(ctx, 1).  E_INVALID for another mode; a later
+ * tersoff_compute with TERSOFF_SINGLE or the atomic scatter under mode 1
+ * returns E_INVALID. */
+int tersoff_set_mapping(tersoff_ctx *ctx, int32_t mode);
+
 /* Number of atoms of the last build (0 if none). */
 int64_t tersoff_num_atoms(const tersoff_ctx *ctx);
 

@@ -26,7 +26,7 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_BOX", -4: "E_OVERFLOW"
 
 # exported symbols (the declarations of include/tersoff.h)
 SYMBOLS = ("tersoff_create", "tersoff_destroy", "tersoff_build_neighbors", "tersoff_compute",
-           "tersoff_compute_static", "tersoff_check", "tersoff_get_neighbors", "tersoff_get_counts", "tersoff_num_atoms",
+           "tersoff_compute_static", "tersoff_set_force_sum", "tersoff_set_mapping", "tersoff_check", "tersoff_get_neighbors", "tersoff_get_counts", "tersoff_num_atoms",
            "tersoff_strerror", "tersoff_last_error", "tersoff_profile", "tersoff_profile_read",
            "tersoff_set_batch_atoms", "tersoff_serve_start", "tersoff_serve_stop", "tersoff_submit",
            "tersoff_poll", "tersoff_serve_stats", "tersoff_clock_ns", "tersoff_parse_params",
@@ -85,6 +85,10 @@ def load():
     lib.tersoff_compute.restype = ctypes.c_int
     lib.tersoff_compute_static.argtypes = [P, P, i32, P, P, P]
     lib.tersoff_compute_static.restype = ctypes.c_int
+    lib.tersoff_set_force_sum.argtypes = [P, i32]
+    lib.tersoff_set_force_sum.restype = ctypes.c_int
+    lib.tersoff_set_mapping.argtypes = [P, i32]
+    lib.tersoff_set_mapping.restype = ctypes.c_int
     lib.tersoff_check.argtypes = [P, P]
     lib.tersoff_check.restype = ctypes.c_int
     lib.tersoff_get_neighbors.argtypes = [P, P, P, i64, P]
@@ -252,6 +256,20 @@ class Tersoff:
         return dict(kernel_ms=float(out[0]), kernels=int(out[1]), build_ms=float(out[2]),
                     builds=int(out[3]), gather_ms=float(out[4]), gathers=int(out[5]),
                     pack_ms=float(out[6]), packs=int(out[7]))
+
+    def set_force_sum(self, mode: str):
+        """'planes' (default: atomic-free, reproducible) or 'atomic' (FP64
+        atomic scatter, the comparison point)."""
+        st = self._lib.tersoff_set_force_sum(self._h, {"planes": 0, "atomic": 1}[mode])
+        if st != OK:
+            self._raise(st, "tersoff_set_force_sum")
+
+    def set_mapping(self, mode: str):
+        """'pair' (default: a lane per packed pair) or 'triplet' (a lane per
+        triplet, the comparison point; FP64 and mixed)."""
+        st = self._lib.tersoff_set_mapping(self._h, {"pair": 0, "triplet": 1}[mode])
+        if st != OK:
+            self._raise(st, "tersoff_set_mapping")
 
     def set_batch_atoms(self, atoms: int):
         st = self._lib.tersoff_set_batch_atoms(self._h, int(atoms))

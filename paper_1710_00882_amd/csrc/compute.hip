@@ -764,6 +764,97 @@ __device__ __forceinline__ real exp_ratio(const Q &q, real rj, real rk)
     return q.lam3;
 }
 
+// Eq. (2) of pair (i, j) once zeta_ij is known: the pair's energy (half of
+// f_C (f_R + b f_A); each bond is visited from both ends), dV/dzeta_ij, and
+// the pair force on j (along u_ij), in FP64, or in FP32 in the single variant.
+template <typename real, bool SINGLE, typename facc>
+__device__ __forceinline__ void pair_step(const ParamR<real> &q, const ParamX &px, real zr, real fc, real dfc,
+                                          real rj, real rjlo, const real uj[3], double &e_pair, real &dz_out,
+                                          facc &fx, facc &fy, facc &fz)
+{
+    // Eq. (2) in log form: FP64, or FP32 in the single variant
+    if constexpr (sizeof(real) == 4 && !SINGLE) {
+        // mixed: f_R and f_A from the FP32 pair exponential of
+        // the FP64 distance, combined in FP64 (at short range
+        // f_R' and b f_A' cancel to a few percent of either)
+        const double fr = exp_decay_f32(px.A, q.lam1, q.lam1_lo, rj, rjlo);
+        const double fa = -exp_decay_f32(px.B, q.lam2, q.lam2_lo, rj, rjlo);
+        const double zeta = (double)zr;
+        double b = 1.0, db = 0.0;
+        if (zeta > 0.0) bond_order_f64(px, zeta, b, db);
+        const double fc64 = (double)fc, vp = fr + b * fa;
+        e_pair = 0.5 * fc64 * vp;
+        dz_out = (real)(0.5 * fc64 * fa * db);
+        const double dvdr = 0.5 * ((double)dfc * vp - fc64 * (px.lam1 * fr + b * (px.lam2 * fa)));
+        fx = -dvdr * (double)uj[0];
+        fy = -dvdr * (double)uj[1];
+        fz = -dvdr * (double)uj[2];
+    } else if constexpr (SINGLE) {
+        real fr, fa, dfr, dfa;
+        pair_terms(q, rj, fr, dfr, fa, dfa, rjlo);
+        // b - 1 is carried instead of b (b is within ~1e-4 of 1,
+        // and its FP32 rounding would bias the energy through
+        // the large f_A at short range); ln(beta zeta) is taken
+        // of the product (ln beta ~ -14 and ln zeta ~ 10 would
+        // each carry a float rounding ~1e-6 into the sum)
+        float bm1 = 0.f, db = 0.f;
+        if (zr > 0.f) {
+            const float x = expf((float)px.eta * logf(q.beta * zr));
+            bm1 = expm1f(-log1pf(x) * (float)px.inv2eta);
+            db = -0.5f * (1.f + bm1) * x / (zr * (1.f + x));
+        }
+        e_pair = (double)(0.5f * fc * ((fr + fa) + bm1 * fa));
+        dz_out = 0.5f * fc * fa * db;
+        const real dvdr1 = real(0.5) * (dfc * ((fr + fa) + bm1 * fa) + fc * ((dfr + dfa) + bm1 * dfa));
+        fx = -dvdr1 * uj[0];
+        fy = -dvdr1 * uj[1];
+        fz = -dvdr1 * uj[2];
+    } else {
+        // all-FP64 path, with the library's exp / log / log1p
+        real fr, fa, dfr, dfa;
+        pair_terms(q, rj, fr, dfr, fa, dfa);
+        const double zeta = (double)zr;
+        double b = 1.0, db = 0.0;
+        if (zeta > 0.0) {
+            const double x = ::exp(px.eta * (px.logbeta + ::log(zeta)));
+            b = ::exp(-::log1p(x) * px.inv2eta);
+            db = -0.5 * b * x / (zeta * (1.0 + x));
+        }
+        e_pair = 0.5 * fc * (fr + b * fa);
+        dz_out = 0.5 * fc * fa * db;
+        const real dvdr = real(0.5) * (dfc * (fr + b * fa) + fc * (dfr + b * dfa));
+        fx = -dvdr * uj[0];
+        fy = -dvdr * uj[1];
+        fz = -dvdr * uj[2];
+    }
+}
+
+// The workgroup's partial sums of energy and virial, its pair and triplet
+// counts and its asymmetry flag, summed across the wavefront and stored by
+// lane 0 at the workgroup's index (reduced by the gather kernel).
+__device__ __forceinline__ void store_partials(const ComputeLaunch &a, double e_acc, const double w_acc[6],
+                                               int n_pairs, int n_trip, bool asym)
+{
+    double v[7] = {e_acc, w_acc[0], w_acc[1], w_acc[2], w_acc[3], w_acc[4], w_acc[5]};
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] = wave_sum(v[c]);
+    long long np = n_pairs, ntr = n_trip;   // summed across the wavefront in 64 bits
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        np += __shfl_xor(np, off, kWave);
+        ntr += __shfl_xor(ntr, off, kWave);
+    }
+    const bool any_asym = __ballot(asym) != 0ull;
+    if (threadIdx.x == 0) {
+        double *pp = a.partials + 8 * (size_t)blockIdx.x;
+        pp[7] = any_asym ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) pp[c] = v[c];
+        a.counters[2 * (size_t)blockIdx.x] = np;
+        a.counters[2 * (size_t)blockIdx.x + 1] = ntr;
+    }
+}
+
 // One 64-lane wavefront per workgroup walks batches of consecutive centre
 // atoms whose packed neighbours fill at most one slot per lane; a lane owns
 // the pair (i, j) of its slot (the pair-vectorised scheme of Section 3 with
@@ -796,9 +887,10 @@ __device__ __forceinline__ real exp_ratio(const Q &q, real rj, real rk)
 // SINGLE (with real = float): the all-FP32 variant -- the zeta -> b power and
 // each lane's sum of the force terms on j in FP32 as well; FP64 remains only
 // in the displacement (packing) and in the sums across lanes and atoms.
-template <typename real, int NT, bool BATCHED, bool SINGLE, bool NOL3, bool CACHE>
+template <typename real, int NT, bool BATCHED, bool SINGLE, bool NOL3, bool CACHE, bool ATOMIC = false>
 __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable tab)
 {
+    static_assert(!(ATOMIC && BATCHED), "the atomic scatter serves one system");
     static_assert(!SINGLE || sizeof(real) == 4, "the single-precision variant computes in float");
     static_assert(!NOL3 || NT == 1, "the lambda3-free variant is a one-species kernel");
     constexpr bool ONE = NT == 1;
@@ -839,19 +931,51 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
     const int ngroups = (n + B - 1) / B;
 
     const ItemRange items = xcd_items(ngroups);
-    for (int grp = items.begin; grp < items.end; grp += items.stride) {
-        int a0 = grp * B;
-        const int a_end = min(a0 + B, n);
-        const Rec<real> *region = recs + (size_t)a0 * kRecCap;   // this batch's records, in order
-        const float *rlo_region = kRlo ? a.rlo + (size_t)a0 * kRecCap : nullptr;
-        while (a0 < a_end) {
+    // The inputs of a batch are loaded one batch ahead, while the previous
+    // batch computes: its atoms' record counts and types, and the first kScap
+    // records of its place in the group's region (its own slots: records are
+    // stored in batch order).  A group of B atoms owns B * kRecCap records;
+    // loads never pass its end.
+    struct Ahead {
+        int grp, a0, a_end;   // group, first atom, end of the group's atoms
+        size_t rec;           // index of the batch's first record
+        int p, t;             // this lane's atom: record count, type
+        Rec<real> rc;         // this lane's slot record
+        float rlo;
+    };
+    auto fetch = [&](Ahead &f) {
+        f.p = 0;
+        f.t = 0;
+        if (lane < f.a_end - f.a0) {
+            f.p = a.pcount[f.a0 + lane];
+            f.t = ONE ? 0 : a.types[f.a0 + lane];
+        }
+        if (f.rec + lane < (size_t)(f.grp + 1) * B * kRecCap) {
+            f.rc = recs[f.rec + lane];
+            if constexpr (kRlo) f.rlo = a.rlo[f.rec + lane];
+        }
+    };
+    auto group_start = [&](Ahead &f, int g) {
+        f.grp = g;
+        f.a0 = g * B;
+        f.a_end = min(f.a0 + B, n);
+        f.rec = (size_t)f.a0 * kRecCap;
+    };
+    Ahead nx{};
+    nx.grp = items.end;   // an empty range (more XCD slices than groups) runs no batch
+    if (items.begin < items.end) {
+        group_start(nx, items.begin);
+        fetch(nx);
+    }
+    while (nx.grp < items.end) {
+        const int a0 = nx.a0, a_end = nx.a_end;
+        const size_t rec0 = nx.rec;
+        {
             const int nb = a_end - a0;
             // ---- batch: the leading atoms whose slots fit one per lane
-            int p = 0, tiv = 0;
-            if (lane < nb) {
-                p = a.pcount[a0 + lane];
-                tiv = ONE ? 0 : a.types[a0 + lane];
-            }
+            const int p = nx.p, tiv = nx.t;
+            const Rec<real> rc_ahead = nx.rc;
+            const float rlo_ahead = nx.rlo;
             const int ip = wave_incl_scan(p);
             const int cut = __popcll(__ballot(lane < nb && ip <= kScap));   // >= 1: p <= kRecCap
             if (lane < cut) {
@@ -863,6 +987,10 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
             if (lane == 0) sh.pstart[0] = 0;
             const int npacked = __shfl(ip, cut - 1, kWave);
             __syncthreads();
+            // the next batch: the rest of this group, or the next group
+            nx.a0 = a0 + cut;
+            nx.rec = rec0 + npacked;
+            if (nx.a0 >= a_end) group_start(nx, nx.grp + items.stride);
 
             // ---- slot lanes: load the packed record of pair (i, j), and the
             // switching function of the slot for every partner type
@@ -876,12 +1004,14 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 jl = s - sb;
                 pc = sh.pcnt[al];
                 ti = ONE ? 0 : sh.ti[al];
-                const Rec<real> rc = region[s];
-                if constexpr (kRlo) rjlo = rlo_region[s];
+                const Rec<real> rc = rc_ahead;
+                if constexpr (kRlo) rjlo = rlo_ahead;
                 j = rc.jm & kIdMask;
-                bool absent;
-                kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, absent);
-                asym |= absent;
+                if constexpr (!ATOMIC) {
+                    bool absent;
+                    kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, absent);
+                    asym |= absent;
+                }
                 mj = rc.jm;
                 dj[0] = rc.dx; dj[1] = rc.dy; dj[2] = rc.dz;
                 rj = M<real>::sqrt(norm2r(dj[0], dj[1], dj[2]));
@@ -902,6 +1032,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                     sh.em[s] = M<real>::exp(-q0.lam3 * rj);
                 }
             }
+            if (nx.grp < items.end) fetch(nx);   // this batch's inputs are consumed
             __syncthreads();
 
             // exp((lambda3 (r_a - r_b))^m) and its derivative with respect to r_a
@@ -968,61 +1099,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                     const ParamR<real> &q = ONE ? q0 : ptab[e_ij];
                     const ParamX px = tab.px[e_ij];
                     const real fc = sh.fc[ONE ? 0 : tj][s], dfc = sh.dfc[ONE ? 0 : tj][s];
-                    // Eq. (2) in log form: FP64, or FP32 in the single variant
-                    if constexpr (kRlo && !SINGLE) {
-                        // mixed: f_R and f_A from the FP32 pair exponential of
-                        // the FP64 distance, combined in FP64 (at short range
-                        // f_R' and b f_A' cancel to a few percent of either)
-                        const double fr = exp_decay_f32(px.A, q.lam1, q.lam1_lo, rj, rjlo);
-                        const double fa = -exp_decay_f32(px.B, q.lam2, q.lam2_lo, rj, rjlo);
-                        const double zeta = (double)zr;
-                        double b = 1.0, db = 0.0;
-                        if (zeta > 0.0) bond_order_f64(px, zeta, b, db);
-                        const double fc64 = (double)fc, vp = fr + b * fa;
-                        e_pair = 0.5 * fc64 * vp;
-                        dz_out = (real)(0.5 * fc64 * fa * db);
-                        const double dvdr = 0.5 * ((double)dfc * vp - fc64 * (px.lam1 * fr + b * (px.lam2 * fa)));
-                        fx = -dvdr * (double)uj[0];
-                        fy = -dvdr * (double)uj[1];
-                        fz = -dvdr * (double)uj[2];
-                    } else if constexpr (SINGLE) {
-                        real fr, fa, dfr, dfa;
-                        pair_terms(q, rj, fr, dfr, fa, dfa, rjlo);
-                        // b - 1 is carried instead of b (b is within ~1e-4 of 1,
-                        // and its FP32 rounding would bias the energy through
-                        // the large f_A at short range); ln(beta zeta) is taken
-                        // of the product (ln beta ~ -14 and ln zeta ~ 10 would
-                        // each carry a float rounding ~1e-6 into the sum)
-                        float bm1 = 0.f, db = 0.f;
-                        if (zr > 0.f) {
-                            const float x = expf((float)px.eta * logf(q.beta * zr));
-                            bm1 = expm1f(-log1pf(x) * (float)px.inv2eta);
-                            db = -0.5f * (1.f + bm1) * x / (zr * (1.f + x));
-                        }
-                        e_pair = (double)(0.5f * fc * ((fr + fa) + bm1 * fa));
-                        dz_out = 0.5f * fc * fa * db;
-                        const real dvdr1 = real(0.5) * (dfc * ((fr + fa) + bm1 * fa) + fc * ((dfr + dfa) + bm1 * dfa));
-                        fx = -dvdr1 * uj[0];
-                        fy = -dvdr1 * uj[1];
-                        fz = -dvdr1 * uj[2];
-                    } else {
-                        // all-FP64 path, with the library's exp / log / log1p
-                        real fr, fa, dfr, dfa;
-                        pair_terms(q, rj, fr, dfr, fa, dfa);
-                        const double zeta = (double)zr;
-                        double b = 1.0, db = 0.0;
-                        if (zeta > 0.0) {
-                            const double x = ::exp(px.eta * (px.logbeta + ::log(zeta)));
-                            b = ::exp(-::log1p(x) * px.inv2eta);
-                            db = -0.5 * b * x / (zeta * (1.0 + x));
-                        }
-                        e_pair = 0.5 * fc * (fr + b * fa);
-                        dz_out = 0.5 * fc * fa * db;
-                        const real dvdr = real(0.5) * (dfc * (fr + b * fa) + fc * (dfr + b * dfa));
-                        fx = -dvdr * uj[0];
-                        fy = -dvdr * uj[1];
-                        fz = -dvdr * uj[2];
-                    }
+                    pair_step<real, SINGLE>(q, px, zr, fc, dfc, rj, rjlo, uj, e_pair, dz_out, fx, fy, fz);
                     e_acc += e_pair;
                     // j-role terms: -dV/dzeta_ij dzeta_ij/dx_j
                     fx -= (facc)(dz_out * (aj[0] * rjinv + bj * uj[0]));
@@ -1089,7 +1166,12 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 w_acc[3] += dxj * Fy;
                 w_acc[4] += dxj * Fz;
                 w_acc[5] += dyj * Fz;
-                if ((unsigned)kpos < (unsigned)kRecCap) {
+                if constexpr (ATOMIC) {
+                    double *f = a.forces_atomic + 3 * (size_t)j;
+                    atomicAdd(f, Fx);
+                    atomicAdd(f + 1, Fy);
+                    atomicAdd(f + 2, Fz);
+                } else if ((unsigned)kpos < (unsigned)kRecCap) {
                     real *f = static_cast<real *>(a.planes) + 3 * ((size_t)kpos * a.plane_stride + (size_t)j);
                     f[0] = (real)Fx; f[1] = (real)Fy; f[2] = (real)Fz;
                 }
@@ -1111,8 +1193,15 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 for (int q = s0; q < s1; ++q) {
                     ox -= sh.fs[q][0]; oy -= sh.fs[q][1]; oz -= sh.fs[q][2];
                 }
-                double *o = a.own + 3 * (size_t)(a0 + lane);
-                o[0] = ox; o[1] = oy; o[2] = oz;
+                if constexpr (ATOMIC) {
+                    double *o = a.forces_atomic + 3 * (size_t)(a0 + lane);
+                    atomicAdd(o, ox);
+                    atomicAdd(o + 1, oy);
+                    atomicAdd(o + 2, oz);
+                } else {
+                    double *o = a.own + 3 * (size_t)(a0 + lane);
+                    o[0] = ox; o[1] = oy; o[2] = oz;
+                }
                 if constexpr (BATCHED) {
                     double v[7] = {0, 0, 0, 0, 0, 0, 0};
                     for (int q = s0; q < s1; ++q)
@@ -1125,32 +1214,274 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 }
             }
             __syncthreads();
-            a0 += cut;
-            region += npacked;
-            if constexpr (kRlo) rlo_region += npacked;
         }
     }
 
     if constexpr (BATCHED) return;
-    // ---- per-workgroup partial sums of energy, virial and counts
-    double v[7] = {e_acc, w_acc[0], w_acc[1], w_acc[2], w_acc[3], w_acc[4], w_acc[5]};
+    store_partials(a, e_acc, w_acc, n_pairs, n_trip, asym);
+}
+
+// ------------------------------------------ lane-per-triplet (comparison) -
+//
+// The third way to map the triplet loop onto a wavefront (Section 3 weighs
+// vectorising over centres and over neighbours; here the lanes take the
+// triplets themselves).  Same batches of packed slots, records and outputs as
+// k_tersoff, with the work of a batch split by lanes as:
+//   slot lanes     record, r_ij, u_ij and f_C of each slot;
+//   triplet lanes  the term f_C(r_ik) g(theta_ijk) e(r_ij, r_ik) of zeta_ij,
+//                  added into the slot's zeta in LDS (atomics), and the
+//                  triplet's derivatives with respect to x_j and x_k;
+//   slot lanes     Eq. (2) of the pair: energy, pair force, dV/dzeta_ij;
+//   triplet lanes  -dV/dzeta_ij times those derivatives, added (FP64 LDS
+//                  atomics) into the forces of slots j and k;
+//   slot lanes     virial and the force-plane store; atom lanes the centre's
+//                  own force (minus the sum over its slots).
+// A lane keeps the derivatives of its first kTripKeep triplets of a batch in
+// registers and forms those of later triplets again.  The atomics leave the
+// order of the LDS sums, hence their last bits, free from run to run: this
+// mapping is a comparison point, not the default.
+constexpr int kTripKeep = 4;
+
+template <typename real>
+struct TripShared {
+    int ti[kWave];
+    int pcnt[kWave];
+    int pstart[kWave + 1];       // first slot of each centre atom
+    int tstart[kWave + 1];       // first triplet of each centre atom
+    unsigned char owner[kScap];
+    double fs[kScap][3];         // triplet forces on each slot's atom, then the slot's total
+    real ux[kScap], uy[kScap], uz[kScap], r[kScap];
+    real zeta[kScap], dzeta[kScap];
+    int mask[kScap];
+    real fc[kMaxTypes][kScap], dfc[kMaxTypes][kScap];
+};
+
+// floor(x / d) for 0 <= x < 2^11 and 1 <= d <= 64: (x + 1/2) / d lies at
+// least 1/(2d) from every integer, far beyond the rounding of one FP32
+// reciprocal and product (relative 2^-22, absolute below 2^-10 here).
+__device__ __forceinline__ int small_div(int x, int d)
+{
+    return (int)(((float)x + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+}
+
+template <typename real>
+__global__ __launch_bounds__(kWave) void k_tersoff_trip(ComputeLaunch a, DeviceTable tab)
+{
+    constexpr bool kRlo = sizeof(real) == 4;
+    __shared__ TripShared<real> sh;
+    __shared__ TripParam<real> tp[kMaxTypes * kMaxTypes * kMaxTypes];
+    const int lane = threadIdx.x;
+    const ParamR<real> *ptab = table_r<real>(tab);
+    const Rec<real> *recs = static_cast<const Rec<real> *>(a.recs);
+    const int nt = tab.ntypes;
+    for (int e = lane; e < nt * nt * nt; e += kWave) tp[e] = trip_of(ptab[e]);
+
+    double e_acc = 0.0;
+    double w_acc[6] = {0, 0, 0, 0, 0, 0};
+    int n_pairs = 0, n_trip = 0;
+    bool asym = false;
+
+    // Triplet t of the batch: centre (binary search of the triplet starts),
+    // slots j and k (t's place among the centre's p (p - 1) ordered pairs of
+    // distinct slots), the term of zeta_ij and its derivatives with respect to
+    // x_j and x_k.  False when k is not a third atom of pair (i, j) or (i, j)
+    // is no bonded pair: then the triplet contributes nothing.
+    auto triplet = [&](int t, int cut, int &sj, int &sk, real &z, real dzj[3], real dzk[3]) -> bool {
+        int lo = 0, hi = cut - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sh.tstart[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int al = lo, pm1 = sh.pcnt[al] - 1, loc = t - sh.tstart[al];
+        const int jl = small_div(loc, pm1), kk = loc - jl * pm1;
+        sj = sh.pstart[al] + jl;
+        sk = sh.pstart[al] + kk + (kk >= jl ? 1 : 0);
+        const int mj = sh.mask[sj], mk = sh.mask[sk];
+        const int ti = sh.ti[al], tj = rec_type(mj), tk = rec_type(mk);
+        if (!((mj >> kPairBit) & 1) || !((mk >> (kThirdBit + tj)) & 1)) return false;
+        const TripParam<real> q = tp[(ti * nt + tj) * nt + tk];
+        const real rj = sh.r[sj], rk = sh.r[sk];
+        const real uj[3] = {sh.ux[sj], sh.uy[sj], sh.uz[sj]};
+        const real uk[3] = {sh.ux[sk], sh.uy[sk], sh.uz[sk]};
+        const real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
+        const Angular<real> an = angular(q, cs);
+        real ex, dex;
+        exp_term(q, rj, rk, ex, dex);
+        const real fck = sh.fc[tj][sk], dfck = sh.dfc[tj][sk];
+        z = fck * an.g * ex;
+        // d cos / d x_j = (u_k - cos u_j) / r_j, d cos / d x_k = (u_j - cos u_k) / r_k;
+        // the exponential factor moves with r_j as dex and with r_k as -dex
+        const real w = fck * an.dg * ex;
+        const real aj = w * M<real>::rcp(rj), bj = fck * an.g * dex;
+        const real ak = w * M<real>::rcp(rk), bk = an.g * (dfck * ex - fck * dex);
 #pragma unroll
-    for (int c = 0; c < 7; ++c) v[c] = wave_sum(v[c]);
-    long long np = n_pairs, ntr = n_trip;   // summed across the wavefront in 64 bits
+        for (int c = 0; c < 3; ++c) {
+            dzj[c] = aj * (uk[c] - cs * uj[c]) + bj * uj[c];
+            dzk[c] = ak * (uj[c] - cs * uk[c]) + bk * uk[c];
+        }
+        return true;
+    };
+    auto scatter = [&](int sj, int sk, const real dzj[3], const real dzk[3]) {
+        const real dz = sh.dzeta[sj];
+        if (dz == real(0)) return;
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        np += __shfl_xor(np, off, kWave);
-        ntr += __shfl_xor(ntr, off, kWave);
+        for (int c = 0; c < 3; ++c) {
+            atomicAdd(&sh.fs[sj][c], (double)(-dz * dzj[c]));
+            atomicAdd(&sh.fs[sk][c], (double)(-dz * dzk[c]));
+        }
+    };
+
+    const int B = a.atoms_per_batch;
+    const int n = a.n;
+    const int ngroups = (n + B - 1) / B;
+    const ItemRange items = xcd_items(ngroups);
+    for (int grp = items.begin; grp < items.end; grp += items.stride) {
+        const int g_end = min((grp + 1) * B, n);
+        size_t rec0 = (size_t)grp * B * kRecCap;   // records of a group: in batch order
+        for (int a0 = grp * B; a0 < g_end;) {
+            // ---- batch: the leading atoms whose slots fit one per lane
+            const int nb = g_end - a0;
+            int p = 0, tiv = 0;
+            if (lane < nb) {
+                p = a.pcount[a0 + lane];
+                tiv = nt == 1 ? 0 : a.types[a0 + lane];
+            }
+            const int ip = wave_incl_scan(p);
+            const int cut = __popcll(__ballot(lane < nb && ip <= kScap));   // >= 1: p <= kRecCap
+            const int it = wave_incl_scan(lane < cut ? p * (p - 1) : 0);
+            if (lane < cut) {
+                sh.ti[lane] = tiv;
+                sh.pcnt[lane] = p;
+                sh.pstart[lane + 1] = ip;
+                sh.tstart[lane + 1] = it;
+                for (int q = ip - p; q < ip; ++q) sh.owner[q] = (unsigned char)lane;
+            }
+            if (lane == 0) {
+                sh.pstart[0] = 0;
+                sh.tstart[0] = 0;
+            }
+            const int npacked = __shfl(ip, cut - 1, kWave);
+            const int T = __shfl(it, cut - 1, kWave);
+            __syncthreads();
+
+            // ---- slot lanes
+            const int s = lane;
+            const bool has_slot = s < npacked;
+            int al = 0, j = 0, kpos = -1, mj = 0, ti = 0;
+            real rj = 0, rjlo = 0, uj[3] = {0, 0, 0}, dj[3] = {0, 0, 0};
+            if (has_slot) {
+                al = sh.owner[s];
+                ti = sh.ti[al];
+                const Rec<real> rc = recs[rec0 + s];
+                if constexpr (kRlo) rjlo = a.rlo[rec0 + s];
+                j = rc.jm & kIdMask;
+                bool absent;
+                kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, absent);
+                asym |= absent;
+                mj = rc.jm;
+                dj[0] = rc.dx; dj[1] = rc.dy; dj[2] = rc.dz;
+                rj = M<real>::sqrt(norm2r(dj[0], dj[1], dj[2]));
+                const real rinv = M<real>::rcp(rj);
+                uj[0] = dj[0] * rinv; uj[1] = dj[1] * rinv; uj[2] = dj[2] * rinv;
+                sh.ux[s] = uj[0]; sh.uy[s] = uj[1]; sh.uz[s] = uj[2];
+                sh.r[s] = rj;
+                sh.mask[s] = mj;
+                for (int t = 0; t < nt; ++t) {
+                    real fc = real(0), dfc = real(0);
+                    if ((mj >> (kThirdBit + t)) & 1)
+                        cutoff_terms(ptab[(ti * nt + t) * nt + rec_type(mj)], rj, fc, dfc, rjlo);
+                    sh.fc[t][s] = fc;
+                    sh.dfc[t][s] = dfc;
+                }
+                sh.zeta[s] = real(0);
+                sh.fs[s][0] = 0.0; sh.fs[s][1] = 0.0; sh.fs[s][2] = 0.0;
+            }
+            __syncthreads();
+
+            // ---- triplet lanes: zeta_ij, and the derivatives of each term
+            int keep_s[kTripKeep];
+            real keep_j[kTripKeep][3], keep_k[kTripKeep][3];
+#pragma unroll
+            for (int q = 0; q < kTripKeep; ++q) {
+                keep_s[q] = -1;
+                const int t = q * kWave + lane;
+                int sj, sk;
+                real z;
+                if (t < T && triplet(t, cut, sj, sk, z, keep_j[q], keep_k[q])) {
+                    ++n_trip;
+                    keep_s[q] = sj | (sk << 8);
+                    atomicAdd(&sh.zeta[sj], z);
+                }
+            }
+            for (int t = kTripKeep * kWave + lane; t < T; t += kWave) {
+                int sj, sk;
+                real z, vj[3], vk[3];
+                if (triplet(t, cut, sj, sk, z, vj, vk)) {
+                    ++n_trip;
+                    atomicAdd(&sh.zeta[sj], z);
+                }
+            }
+            __syncthreads();
+
+            // ---- slot lanes: Eq. (2) of the pair
+            const int tj = rec_type(mj);
+            double fx = 0, fy = 0, fz = 0, e_pair = 0.0;
+            if (has_slot) {
+                real dz_out = real(0);
+                if ((mj >> kPairBit) & 1) {
+                    ++n_pairs;
+                    const int e_ij = (ti * nt + tj) * nt + tj;
+                    pair_step<real, false>(ptab[e_ij], tab.px[e_ij], sh.zeta[s], sh.fc[tj][s], sh.dfc[tj][s], rj,
+                                           rjlo, uj, e_pair, dz_out, fx, fy, fz);
+                    e_acc += e_pair;
+                }
+                sh.dzeta[s] = dz_out;
+            }
+            __syncthreads();
+
+            // ---- triplet lanes: the force terms of every triplet on j and k
+#pragma unroll
+            for (int q = 0; q < kTripKeep; ++q)
+                if (keep_s[q] >= 0) scatter(keep_s[q] & 255, keep_s[q] >> 8, keep_j[q], keep_k[q]);
+            for (int t = kTripKeep * kWave + lane; t < T; t += kWave) {
+                int sj, sk;
+                real z, vj[3], vk[3];
+                if (triplet(t, cut, sj, sk, z, vj, vk)) scatter(sj, sk, vj, vk);
+            }
+            __syncthreads();
+
+            // ---- slot lanes: total force of centre i on j, virial, plane store
+            if (has_slot) {
+                const double Fx = fx + sh.fs[s][0], Fy = fy + sh.fs[s][1], Fz = fz + sh.fs[s][2];
+                const double dxj = (double)dj[0], dyj = (double)dj[1], dzj = (double)dj[2];
+                w_acc[0] += dxj * Fx;
+                w_acc[1] += dyj * Fy;
+                w_acc[2] += dzj * Fz;
+                w_acc[3] += dxj * Fy;
+                w_acc[4] += dxj * Fz;
+                w_acc[5] += dyj * Fz;
+                if ((unsigned)kpos < (unsigned)kRecCap) {
+                    real *f = static_cast<real *>(a.planes) + 3 * ((size_t)kpos * a.plane_stride + (size_t)j);
+                    f[0] = (real)Fx; f[1] = (real)Fy; f[2] = (real)Fz;
+                }
+                sh.fs[s][0] = Fx; sh.fs[s][1] = Fy; sh.fs[s][2] = Fz;
+            }
+            __syncthreads();
+            if (lane < cut) {
+                double ox = 0, oy = 0, oz = 0;
+                for (int q = sh.pstart[lane]; q < sh.pstart[lane + 1]; ++q) {
+                    ox -= sh.fs[q][0]; oy -= sh.fs[q][1]; oz -= sh.fs[q][2];
+                }
+                double *o = a.own + 3 * (size_t)(a0 + lane);
+                o[0] = ox; o[1] = oy; o[2] = oz;
+            }
+            __syncthreads();
+            a0 += cut;
+            rec0 += npacked;
+        }
     }
-    const bool any_asym = __ballot(asym) != 0ull;
-    if (lane == 0) {
-        double *pp = a.partials + 8 * (size_t)blockIdx.x;
-        pp[7] = any_asym ? 1.0 : 0.0;
-#pragma unroll
-        for (int c = 0; c < 7; ++c) pp[c] = v[c];
-        a.counters[2 * (size_t)blockIdx.x] = np;
-        a.counters[2 * (size_t)blockIdx.x + 1] = ntr;
-    }
+    store_partials(a, e_acc, w_acc, n_pairs, n_trip, asym);
 }
 
 // Atoms dropped by k_pack (more kept neighbours than a record row holds) are
@@ -1449,6 +1780,13 @@ void compute_dispatch(const ComputeLaunch &a, const DeviceTable &t, int prec, in
     const dim3 G(grid), W(kWave);
     with_kernel(prec, table_kind(t), [&](auto tag) {
         using K = decltype(tag);
+        if constexpr (!BATCHED) {
+            if (a.forces_atomic) {
+                hipLaunchKernelGGL((k_tersoff<typename K::real, K::nt, false, K::single, K::nol3, K::cache, true>), G,
+                                   W, 0, s, a, t);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_tersoff<typename K::real, K::nt, BATCHED, K::single, K::nol3, K::cache>), G, W, 0, s,
                            a, t);
     });
@@ -1488,6 +1826,21 @@ hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec
     if (a.atoms_per_batch < 1 || a.atoms_per_batch > kWave) return hipErrorInvalidValue;
     if (a.n_dev) compute_dispatch<true>(a, t, prec, grid, s);
     else compute_dispatch<false>(a, t, prec, grid, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_compute_triplet(const ComputeLaunch &a, const DeviceTable &t, int prec, int max_grid,
+                                  hipStream_t s, int *grid_used)
+{
+    if (a.n_dev || a.forces_atomic || prec == kPrecSingle || a.atoms_per_batch < 1 || a.atoms_per_batch > kWave ||
+        max_grid < 1)
+        return hipErrorInvalidValue;
+    const long long batches = ((long long)a.n + a.atoms_per_batch - 1) / a.atoms_per_batch;
+    const void *k = prec == kPrecMixed ? (const void *)k_tersoff_trip<float> : (const void *)k_tersoff_trip<double>;
+    const int g = std::min(max_grid, occupancy_grid(k, batches, kComputeWavesPerCU[prec]));
+    if (prec == kPrecMixed) hipLaunchKernelGGL(k_tersoff_trip<float>, dim3(g), dim3(kWave), 0, s, a, t);
+    else hipLaunchKernelGGL(k_tersoff_trip<double>, dim3(g), dim3(kWave), 0, s, a, t);
+    *grid_used = g;
     return hipGetLastError();
 }
 

@@ -157,6 +157,10 @@ struct ComputeLaunch {
     // and virial (8 doubles per atom) in place of the per-workgroup partials
     const int *n_dev;
     double *eatom;
+    // one system, atomic scatter (the comparison point of the force planes):
+    // when not null, every force term is added with FP64 atomics into this
+    // n x 3 array (zeroed beforehand), and own / planes / kept are not used
+    double *forces_atomic;
 };
 
 // Launchers (compute.hip).  grids = {pack, compute} workgroup counts plus
@@ -173,6 +177,10 @@ float *rlo_of(void *recs, int prec, size_t slots);
 hipError_t launch_pack(const PackLaunch &a, const DeviceTable &t, int prec, int grid, hipStream_t s);
 hipError_t launch_compute(const ComputeLaunch &a, const DeviceTable &t, int prec,
                           int grid, hipStream_t s);
+// The lane-per-triplet kernel (one system, FP64 or mixed, force planes) on at
+// most max_grid workgroups; *grid_used: the workgroups launched (partial sums).
+hipError_t launch_compute_triplet(const ComputeLaunch &a, const DeviceTable &t, int prec, int max_grid,
+                                  hipStream_t s, int *grid_used);
 // Force planes hold float for the mixed and single paths, double for FP64.
 hipError_t launch_fixup_dropped(const int *ell, int cap, const int *row_count, const int *kept,
                                 const int *kept_more, const int *drop_list, const int *drop_count,

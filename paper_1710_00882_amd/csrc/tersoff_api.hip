@@ -62,6 +62,8 @@ struct tersoff_ctx {
     int list_cap = 0;        // row stride of the resident list
     int atoms_per_batch = 32;
     bool batch_atoms_set = false;   // tersoff_set_batch_atoms was called (else chosen by the build)
+    int force_sum = 0;              // 0: force planes + gather; 1: FP64 atomic scatter (tersoff_set_force_sum)
+    int mapping = 0;                // 0: lane per packed pair; 1: lane per triplet (tersoff_set_mapping)
     int grid[kNumPrec][3] = {};   // [precision] x {pack, compute, fixup}
 
     DevBuf<double> pos_build;
@@ -162,6 +164,9 @@ int check_compute_args(tersoff_ctx *c, const double *pos, int32_t precision, con
     if (!pos || !energy_virial) return fail(c, TERSOFF_E_INVALID, "null pointer");
     if (precision != TERSOFF_FP64 && precision != TERSOFF_MIXED && precision != TERSOFF_SINGLE)
         return fail(c, TERSOFF_E_INVALID, "precision must be TERSOFF_FP64, TERSOFF_MIXED or TERSOFF_SINGLE");
+    if (c->mapping == 1 && (precision == TERSOFF_SINGLE || c->force_sum == 1))
+        return fail(c, TERSOFF_E_INVALID, "the lane-per-triplet mapping runs TERSOFF_FP64 and TERSOFF_MIXED "
+                                          "with the force planes");
     return TERSOFF_OK;
 }
 
@@ -229,21 +234,36 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     a.atoms_per_batch = c->atoms_per_batch;
     a.plane_stride = c->n;
 
-    // event pairs (profiling only): pack, main kernel, fixup + gather
+    // atomic scatter (comparison point): forces summed with FP64 atomics
+    // into the zeroed output; no planes, no gather, only the partial sums
+    const bool atomic = c->force_sum == 1;
+    if (atomic) a.forces_atomic = f;
+
+    // event pairs (profiling only): pack (with the zeroing of the forces in
+    // the atomic scatter), main kernel, fixup + gather (or the partial sums)
     hipEvent_t ev[6] = {};
     if (profile)
         for (int q = 0; q < 6; ++q) HIP_TRY(c, take_event(c, &ev[q]));
     if (ev[0]) HIP_TRY(c, hipEventRecord(ev[0], s));
+    if (atomic) HIP_TRY(c, launch_fill_zero(f, 3 * (size_t)c->n, s));
     HIP_TRY(c, launch_pack(pk, c->tab, prec, grid[0], s));
     if (ev[1]) HIP_TRY(c, hipEventRecord(ev[1], s));
     if (ev[2]) HIP_TRY(c, hipEventRecord(ev[2], s));
-    HIP_TRY(c, launch_compute(a, c->tab, prec, grid[1], s));
+    int compute_grid = grid[1];
+    if (c->mapping == 1) HIP_TRY(c, launch_compute_triplet(a, c->tab, prec, grid[1], s, &compute_grid));
+    else HIP_TRY(c, launch_compute(a, c->tab, prec, grid[1], s));
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
-    HIP_TRY(c, launch_fixup_dropped(c->ell.p, c->list_cap, c->row_count.p, b.kept, pk.kept_more, b.drop_list,
-                                    c->misc.p + 3, c->n, prec, b.planes, s));
-    const FinalizeArgs fin{b.partials, b.counters, grid[1], energy_virial, c->counts.p, c->misc.p};
-    HIP_TRY(c, launch_gather_forces(b.pcount, prec, b.planes, b.own, c->n, nullptr, c->n, f, c->misc.p + 3, fin, s));
+    const FinalizeArgs fin{b.partials, b.counters, compute_grid, energy_virial, c->counts.p, c->misc.p};
+    if (atomic) {
+        // the partial sums alone (no rows to gather); resets the dropped count
+        HIP_TRY(c, launch_gather_forces(b.pcount, prec, b.planes, b.own, 0, nullptr, c->n, f, c->misc.p + 3, fin, s));
+    } else {
+        HIP_TRY(c, launch_fixup_dropped(c->ell.p, c->list_cap, c->row_count.p, b.kept, pk.kept_more, b.drop_list,
+                                        c->misc.p + 3, c->n, prec, b.planes, s));
+        HIP_TRY(c, launch_gather_forces(b.pcount, prec, b.planes, b.own, c->n, nullptr, c->n, f, c->misc.p + 3, fin,
+                                        s));
+    }
     if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
     if (profile) {
         c->ev_pack.emplace_back(ev[0], ev[1]);
@@ -496,6 +516,22 @@ int tersoff_set_batch_atoms(tersoff_ctx *c, int32_t atoms)
         HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
         HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
     }
+    return TERSOFF_OK;
+}
+
+int tersoff_set_force_sum(tersoff_ctx *c, int32_t mode)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    if (mode != 0 && mode != 1) return fail(c, TERSOFF_E_INVALID, "force-sum mode must be 0 or 1");
+    c->force_sum = mode;
+    return TERSOFF_OK;
+}
+
+int tersoff_set_mapping(tersoff_ctx *c, int32_t mode)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    if (mode != 0 && mode != 1) return fail(c, TERSOFF_E_INVALID, "mapping must be 0 or 1");
+    c->mapping = mode;
     return TERSOFF_OK;
 }
 

@@ -317,3 +317,91 @@ def test_third_atom_at_cutoff_edge(precision):
         Eo, Fo, Vo, _, _ = oracle_eval(s, W.si_table())
         E, F, V, _ = gpu_eval(s, W.si_table(), precision)
         assert_parity(E, F, V, Eo, Fo, Vo, s.n, precision, f"edge eps={eps:g}")
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("case", ["si512", "two_species", "disordered_small"])
+def test_atomic_scatter_matches_oracle_and_planes(case, precision):
+    """The FP64 atomic scatter of the force terms (the comparison point of the
+    atomic-free force planes) meets the same tolerances, and agrees with the
+    planes to within summation order."""
+    import torch
+    from paper_1710_00882_amd import Tersoff
+    sysf, tabf = CASES[case]
+    s, table = sysf(), tabf()
+    m = Tersoff(table)
+    pos, types = to_dev(s)
+    m.build_neighbors(pos, types, s.box)
+    out_p, F_p = m.compute(pos, precision)
+    m.set_force_sum("atomic")
+    out_a, F_a = m.compute(pos, precision)
+    torch.cuda.synchronize()
+    m.check()
+    o_p, o_a = out_p.cpu().numpy(), out_a.cpu().numpy()
+    F_p, F_a = F_p.cpu().numpy(), F_a.cpu().numpy()
+    Eo, Fo, Vo, _, _ = oracle_eval(s, table)
+    assert_parity(o_a[0], F_a, o_a[1:], Eo, Fo, Vo, s.n, precision, f"{case} atomic")
+    # the energy is not part of the scatter (equal up to the rounding of
+    # the kernel instance's own instruction selection)
+    assert abs(o_a[0] - o_p[0]) <= 1e-13 * abs(o_p[0])
+    # mixed stores each pair's force term in the planes as FP32 (one rounding,
+    # 2^-24 relative, per term of up to a dozen per atom); FP64 stores it exactly
+    rel = 1e-6 if precision == "mixed" else 1e-12
+    assert np.abs(F_a - F_p).max() <= rel * max(np.abs(F_p).max(), 1.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", list(CASES) + ["dense"])
+def test_triplet_mapping_matches_oracle(case, precision):
+    """A lane per triplet (the comparison mapping) meets the oracle's
+    tolerances with the work counts of the default mapping, also where a
+    batch holds more triplets than the lanes keep (dense), and at one and at
+    64 centre atoms per batch."""
+    import torch
+    from paper_1710_00882_amd import Tersoff
+    if case == "dense":
+        s, table = W.disordered(2000, density=0.09, dmin=1.7, seed=13), W.two_species_table()
+    else:
+        sysf, tabf = CASES[case]
+        s, table = sysf(), tabf()
+    Eo, Fo, Vo, off, idx = oracle_eval(s, table)
+    counts_o = oracle.counts(s.pos, s.types, s.box, table, off, idx)
+    m = Tersoff(table)
+    try:
+        pos, types = to_dev(s)
+        m.build_neighbors(pos, types, s.box)
+        m.set_mapping("triplet")
+        for B in ((32, 1, 64) if case in ("si512", "dense") else (32,)):
+            m.set_batch_atoms(B)
+            say(f"[triplet] {case} n={s.n} {precision} B={B}")
+            out, f = m.compute(pos, precision)
+            torch.cuda.synchronize()
+            m.check()
+            o = out.cpu().numpy()
+            assert_parity(float(o[0]), f.cpu().numpy(), o[1:], Eo, Fo, Vo, s.n, precision, f"{case} triplet B={B}")
+            assert m.counts() == counts_o
+    finally:
+        m.close()
+
+
+def test_triplet_mapping_rejects_single_and_atomic():
+    from paper_1710_00882_amd import Tersoff, TersoffError
+    s = W.diamond(2, 2, 2, jitter=0.05, seed=1)
+    m = Tersoff(W.si_table())
+    try:
+        pos, types = to_dev(s)
+        m.build_neighbors(pos, types, s.box)
+        m.set_mapping("triplet")
+        with pytest.raises(TersoffError) as e:
+            m.compute(pos, "single")
+        assert e.value.status == -1
+        m.set_force_sum("atomic")
+        with pytest.raises(TersoffError) as e:
+            m.compute(pos, "mixed")
+        assert e.value.status == -1
+        m.set_force_sum("planes")
+        m.set_mapping("pair")
+        m.compute(pos, "single")
+        m.check()
+    finally:
+        m.close()
