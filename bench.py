@@ -122,7 +122,7 @@ def timed_run(model, pos_dev, types_dev, box, precision, nsteps, forces, out, sk
 
 
 def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None, sigma=0.01, force_sum="planes",
-                     mapping="pair"):
+                     mapping="pair", packing="separate"):
     import torch
     from paper_1710_00882_amd import Tersoff
     from paper_1710_00882_amd import workloads as W
@@ -133,6 +133,7 @@ def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None,
     model = Tersoff(table)
     model.set_force_sum(force_sum)
     model.set_mapping(mapping)
+    model.set_packing(packing)
     if batch_atoms:
         model.build_neighbors(pos_dev[0], types_dev, system.box, skin=W.SKIN)
         model.set_batch_atoms(batch_atoms)
@@ -150,7 +151,10 @@ def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None,
         main_s = prof["kernel_ms"] / 1e3 / max(prof["kernels"], 1)
         pack_s = prof["pack_ms"] / 1e3 / max(prof["packs"], 1)
         gather_s = prof["gather_ms"] / 1e3 / max(prof["gathers"], 1)
-        flops = algorithmic_flops(P, T)
+        # the fused packing (no packing kernel timed) counts the packing's
+        # entry work in the compute kernel
+        fused = prof["packs"] == 0
+        flops = algorithmic_flops(P, T) + (FLOPS_PER_ENTRY * S if fused else 0)
         # kept records: the in-cutoff pairs (exact for one species; a lower
         # bound with several, whose packing radius is the largest cutoff)
         pack_bytes = PACK_BYTES_PER_ENTRY * S + PACK_BYTES_PER_ATOM * system.n + RECORD_BYTES[prec] * P
@@ -160,14 +164,15 @@ def measure_workload(system, table, steps, warmup, precisions, batch_atoms=None,
             build_ms=prof["build_ms"] / max(prof["builds"], 1), builds=prof["builds"],
             compute_ms=1e3 * (main_s + pack_s + gather_s),
             compute_atoms_per_s=system.n / (main_s + pack_s + gather_s),
-            counts=dict(S=S, P=P, T=T), alg_flops_per_launch=flops, alg_tflops=flops / main_s / 1e12,
-            pack_alg_bytes=pack_bytes, pack_gbs=pack_bytes / pack_s / 1e9,
+            counts=dict(S=S, P=P, T=T), alg_flops_per_launch=flops, alg_tflops=flops / main_s / 1e12, fused=fused,
+            pack_alg_bytes=pack_bytes, pack_gbs=pack_bytes / pack_s / 1e9 if pack_s > 0 else None,
             energy_per_atom=float(out[0].item()) / system.n)
         r = res[prec]
         log(f"[bench] n={system.n} {prec}: "
             f"{r['value']:.4g} atoms*evals/s, {r['ms_per_step']:.3f} ms/step | pack {r['pack_ms']:.3f} "
             f"main {r['main_ms']:.3f} gather {r['gather_ms']:.3f} build {r['build_ms']:.3f} ms | "
-            f"main {r['alg_tflops']:.2f} TFLOP/s alg, pack {r['pack_gbs']:.0f} GB/s alg")
+            f"main {r['alg_tflops']:.2f} TFLOP/s alg" + (" (packing fused)" if fused else
+                                                          f", pack {r['pack_gbs']:.0f} GB/s alg"))
     del pos_dev
     model.close()
     return res
@@ -204,6 +209,21 @@ def f1_comparison(system, table, args, default_res):
                   "planes_kernels_ms": {"pack": d["pack_ms"], "main": d["main_ms"], "gather": d["gather_ms"]},
                   "atomic_kernels_ms": {"zero+pack": a["pack_ms"], "main": a["main_ms"], "sums": a["gather_ms"]},
                   "atomic_vs_planes_step": a["ms_per_step"] / d["ms_per_step"]}
+    return out
+
+
+def packing_comparison(system, table, args, default_res):
+    """The separate packing kernel (the default) against packing inside the
+    compute kernel, mixed and FP64 on the 2M-atom workload."""
+    log(f"[bench] n={system.n}: packing inside the compute kernel (comparison)")
+    r = measure_workload(system, table, args.steps, args.warmup, ("mixed", "fp64"), packing="fused")
+    out = {}
+    for p in ("mixed", "fp64"):
+        d, a = default_res[p], r[p]
+        out[p] = {"separate_ms_per_step": d["ms_per_step"], "fused_ms_per_step": a["ms_per_step"],
+                  "separate_kernels_ms": {"pack": d["pack_ms"], "main": d["main_ms"], "gather": d["gather_ms"]},
+                  "fused_kernels_ms": {"main": a["main_ms"], "gather": a["gather_ms"]},
+                  "fused_vs_separate_step": a["ms_per_step"] / d["ms_per_step"]}
     return out
 
 
@@ -433,6 +453,7 @@ def main():
 
     ablation = {}
     f1 = None if args.no_ablation else f1_comparison(big, table, args, res)
+    packing = None if args.no_ablation else packing_comparison(big, table, args, res)
     extra_32k = None
     if not args.no_32k:
         small = W.si_32k()
@@ -503,13 +524,14 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_PACKED_TFLOPS,
             "traffic": traffic,
-            "kernel": "k_tersoff<float, one species, lambda3 = 0> (energy / force / virial)",
+            "kernel": "k_tersoff<float, one species, lambda3 = 0" + (", fused packing" if mixed["fused"] else "") +
+                      "> (packing, energy / force / virial)",
             "kernel_ms": mixed["main_ms"],
             "alg_flops_per_launch": mixed["alg_flops_per_launch"],
             "peak_note": "FP32 vector peak (packed issue); 78.64 TFLOP/s unpacked FP32 / FP64 issue",
             "frac_vs_unpacked_issue_peak": achieved / PEAK_ALU_TFLOPS,
         },
-        "pack_roofline": {
+        "pack_roofline": None if mixed["fused"] else {
             "bound": "hbm", "kernel": "k_pack<float, single-type>", "kernel_ms": mixed["pack_ms"],
             "alg_bytes_per_launch": mixed["pack_alg_bytes"], "achieved": mixed["pack_gbs"],
             "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": mixed["pack_gbs"] / PEAK_HBM_GBS,
@@ -533,6 +555,11 @@ def main():
             "each batch on the lanes (zeta and force terms summed by LDS atomics), against the default "
             "batches of centre atoms whose packed pairs fill the lanes (I and J together)")) if ablation else None,
         "serve": serve,
+        "packing": dict(packing, note=(
+            "default: a separate packing kernel writes records, kept lists and counts for the compute kernel "
+            "to read; compared with each group of centre atoms packed inside the compute kernel (FP64 "
+            "displacement, cutoff test, records queued in LDS, forces stored to the plane of the centre's "
+            "position in the neighbour's row)")) if packing else None,
         "f1_force_sum": dict(f1, note=(
             "default: every force term of centre i on atom j summed by the lane of pair (i, j) into a force plane "
             "of j, planes added per atom in a fixed order (no atomics, bitwise reproducible); compared with the "

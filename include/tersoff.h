@@ -192,6 +192,21 @@ int tersoff_set_batch_atoms(tersoff_ctx *ctx, int32_t atoms);
  * tolerances.  E_INVALID for another mode. */
 int tersoff_set_force_sum(tersoff_ctx *ctx, int32_t mode);
 
+/* Where tersoff_compute packs each centre's neighbours (the kept entries of
+ * its row with their FP64 minimum-image displacements, Section 2's full list
+ * with a skin).  mode 0 (the default): a separate packing kernel writes the
+ * packed records, each atom's kept-neighbour list and its count, which the
+ * compute kernel reads.  mode 1: the compute kernel packs each group of
+ * centre atoms itself, into a queue in LDS, and stores each force term in
+ * the plane of the centre's position in the neighbour's row (no records,
+ * kept lists or counts pass through memory) -- a comparison point, slower
+ * on the measured workloads; it applies when every row of the last build
+ * holds at most 64 entries, with tersoff_set_mapping mode 0 and
+ * tersoff_set_force_sum mode 0 (otherwise mode 0 runs).  Both give the same
+ * forces bit for bit, energy and virial up to the order of their sums.
+ * E_INVALID for another mode. */
+int tersoff_set_packing(tersoff_ctx *ctx, int32_t mode);
+
 /* How tersoff_compute maps the triplet loop onto the 64 lanes of a
  * wavefront (Section 3 compares vectorising over centre atoms with
  * vectorising over their neighbours; Table 2).  mode 0 (the default): a lane

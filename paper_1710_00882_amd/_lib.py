@@ -26,7 +26,7 @@ STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_BOX", -4: "E_OVERFLOW"
 
 # exported symbols (the declarations of include/tersoff.h)
 SYMBOLS = ("tersoff_create", "tersoff_destroy", "tersoff_build_neighbors", "tersoff_compute",
-           "tersoff_compute_static", "tersoff_set_force_sum", "tersoff_set_mapping", "tersoff_check", "tersoff_get_neighbors", "tersoff_get_counts", "tersoff_num_atoms",
+           "tersoff_compute_static", "tersoff_set_force_sum", "tersoff_set_mapping", "tersoff_set_packing", "tersoff_check", "tersoff_get_neighbors", "tersoff_get_counts", "tersoff_num_atoms",
            "tersoff_strerror", "tersoff_last_error", "tersoff_profile", "tersoff_profile_read",
            "tersoff_set_batch_atoms", "tersoff_serve_start", "tersoff_serve_stop", "tersoff_submit",
            "tersoff_poll", "tersoff_serve_stats", "tersoff_clock_ns", "tersoff_parse_params",
@@ -89,6 +89,8 @@ def load():
     lib.tersoff_set_force_sum.restype = ctypes.c_int
     lib.tersoff_set_mapping.argtypes = [P, i32]
     lib.tersoff_set_mapping.restype = ctypes.c_int
+    lib.tersoff_set_packing.argtypes = [P, i32]
+    lib.tersoff_set_packing.restype = ctypes.c_int
     lib.tersoff_check.argtypes = [P, P]
     lib.tersoff_check.restype = ctypes.c_int
     lib.tersoff_get_neighbors.argtypes = [P, P, P, i64, P]
@@ -270,6 +272,13 @@ class Tersoff:
         st = self._lib.tersoff_set_mapping(self._h, {"pair": 0, "triplet": 1}[mode])
         if st != OK:
             self._raise(st, "tersoff_set_mapping")
+
+    def set_packing(self, mode: str):
+        """'separate' (default: a packing kernel writes records to memory) or
+        'fused' (packed inside the compute kernel where rows allow)."""
+        st = self._lib.tersoff_set_packing(self._h, {"separate": 0, "fused": 1}[mode])
+        if st != OK:
+            self._raise(st, "tersoff_set_packing")
 
     def set_batch_atoms(self, atoms: int):
         st = self._lib.tersoff_set_batch_atoms(self._h, int(atoms))

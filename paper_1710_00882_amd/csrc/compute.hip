@@ -184,6 +184,13 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+__device__ __forceinline__ int wave_sum_int(int v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
 constexpr double inv_factorial(int n)
 {
     double f = 1.0;
@@ -704,6 +711,21 @@ struct Shared {
     real ep[kScap], em[kScap];            // exp(lambda3 r_in), exp(-lambda3 r_in) (one type, m = 1)
 };
 
+// Records of the fused packing: a ring of kQueueCap records (with their
+// FP32 distance corrections and force-plane indices) and the row layout of
+// the group's centre atoms.
+constexpr int kQueueCap = kScap + kScap + kRecCap;
+
+template <typename real>
+struct FusedQueue {
+    Rec<real> rec[kQueueCap];
+    float rlo[kQueueCap];
+    unsigned char rev[kQueueCap];   // position of the centre in the neighbour's row
+    int cnt[kWave];                 // kept entries so far of each atom of the group
+    int eoff[kWave + 1];            // first entry of each atom's row (group-local)
+    int ti[kWave];
+};
+
 // The k-role quantities of triplet (i; k, j) -- pair (i, k) with j as its
 // third atom -- that the first K loop of lane (i, j) forms alongside its own
 // triplet (i; j, k) (same angle, same g and g' when the three-body parameters
@@ -887,7 +909,8 @@ __device__ __forceinline__ void store_partials(const ComputeLaunch &a, double e_
 // SINGLE (with real = float): the all-FP32 variant -- the zeta -> b power and
 // each lane's sum of the force terms on j in FP32 as well; FP64 remains only
 // in the displacement (packing) and in the sums across lanes and atoms.
-template <typename real, int NT, bool BATCHED, bool SINGLE, bool NOL3, bool CACHE, bool ATOMIC = false>
+template <typename real, int NT, bool BATCHED, bool SINGLE, bool NOL3, bool CACHE, bool ATOMIC = false,
+          bool FUSED = false>
 __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable tab)
 {
     static_assert(!(ATOMIC && BATCHED), "the atomic scatter serves one system");
@@ -898,6 +921,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
     // float paths: the FP64 distance enters the pair terms as r + r_lo
     constexpr bool kRlo = sizeof(real) == 4;
     constexpr int KC = CACHE ? (sizeof(real) == 4 ? 4 : 3) : 1;   // cached k per lane
+    constexpr int kPlaneCap = FUSED ? kFusedRowCap : kRecCap;   // force planes per atom
     __shared__ Shared<real, NT> sh;
     __shared__ KCache<real> kc[KC][kScap];
     __shared__ TripParam<real> tp[ONE ? 1 : NT * NT * NT];
@@ -961,259 +985,419 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
         f.a_end = min(f.a0 + B, n);
         f.rec = (size_t)f.a0 * kRecCap;
     };
-    Ahead nx{};
-    nx.grp = items.end;   // an empty range (more XCD slices than groups) runs no batch
-    if (items.begin < items.end) {
-        group_start(nx, items.begin);
-        fetch(nx);
-    }
-    while (nx.grp < items.end) {
-        const int a0 = nx.a0, a_end = nx.a_end;
-        const size_t rec0 = nx.rec;
-        {
-            const int nb = a_end - a0;
-            // ---- batch: the leading atoms whose slots fit one per lane
-            const int p = nx.p, tiv = nx.t;
-            const Rec<real> rc_ahead = nx.rc;
-            const float rlo_ahead = nx.rlo;
-            const int ip = wave_incl_scan(p);
-            const int cut = __popcll(__ballot(lane < nb && ip <= kScap));   // >= 1: p <= kRecCap
-            if (lane < cut) {
-                sh.ti[lane] = tiv;
-                sh.pcnt[lane] = p;
-                sh.pstart[lane + 1] = ip;
-                for (int q = ip - p; q < ip; ++q) sh.owner[q] = (unsigned char)lane;
+    // One batch: the leading atoms from a0 (nb available) whose slots fit one
+    // per lane.  Lane inputs: p, tiv -- the slot count and type of atom
+    // a0 + lane; rc_ahead, rlo_ahead -- the record of slot lane; kpos_in --
+    // (fused packing) the force plane of the slot.  after_header(cut,
+    // npacked) runs once the batch is formed, after_slots() once the slot
+    // inputs are consumed.  Returns (atoms, slots) of the batch.
+    auto run_batch = [&](const int a0, const int nb, const int p, const int tiv, const Rec<real> rc_ahead,
+                         const float rlo_ahead, const int kpos_in, auto &&after_header, auto &&after_slots) -> int2 {
+        // ---- batch: the leading atoms whose slots fit one per lane
+        const int ip = wave_incl_scan(p);
+        const int cut = __popcll(__ballot(lane < nb && ip <= kScap));   // >= 1: p <= kRecCap
+        if (lane < cut) {
+            sh.ti[lane] = tiv;
+            sh.pcnt[lane] = p;
+            sh.pstart[lane + 1] = ip;
+            for (int q = ip - p; q < ip; ++q) sh.owner[q] = (unsigned char)lane;
+        }
+        if (lane == 0) sh.pstart[0] = 0;
+        const int npacked = __shfl(ip, cut - 1, kWave);
+        __syncthreads();
+        after_header(cut, npacked);
+
+        // ---- slot lanes: load the packed record of pair (i, j), and the
+        // switching function of the slot for every partner type
+        const int s = lane;
+        const bool has_slot = s < npacked;
+        int al = 0, jl = 0, pc = 0, sb = 0, j = 0, kpos = -1, mj = 0, ti = 0;
+        real rj = 0, rjinv = 0, rjlo = 0, uj[3] = {0, 0, 0}, dj[3] = {0, 0, 0};
+        if (has_slot) {
+            al = sh.owner[s];
+            sb = sh.pstart[al];
+            jl = s - sb;
+            pc = sh.pcnt[al];
+            ti = ONE ? 0 : sh.ti[al];
+            const Rec<real> rc = rc_ahead;
+            if constexpr (kRlo) rjlo = rlo_ahead;
+            j = rc.jm & kIdMask;
+            if constexpr (FUSED) {
+                kpos = kpos_in;
+            } else if constexpr (!ATOMIC) {
+                bool absent;
+                kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, absent);
+                asym |= absent;
             }
-            if (lane == 0) sh.pstart[0] = 0;
-            const int npacked = __shfl(ip, cut - 1, kWave);
-            __syncthreads();
-            // the next batch: the rest of this group, or the next group
-            nx.a0 = a0 + cut;
-            nx.rec = rec0 + npacked;
-            if (nx.a0 >= a_end) group_start(nx, nx.grp + items.stride);
-
-            // ---- slot lanes: load the packed record of pair (i, j), and the
-            // switching function of the slot for every partner type
-            const int s = lane;
-            const bool has_slot = s < npacked;
-            int al = 0, jl = 0, pc = 0, sb = 0, j = 0, kpos = -1, mj = 0, ti = 0;
-            real rj = 0, rjinv = 0, rjlo = 0, uj[3] = {0, 0, 0}, dj[3] = {0, 0, 0};
-            if (has_slot) {
-                al = sh.owner[s];
-                sb = sh.pstart[al];
-                jl = s - sb;
-                pc = sh.pcnt[al];
-                ti = ONE ? 0 : sh.ti[al];
-                const Rec<real> rc = rc_ahead;
-                if constexpr (kRlo) rjlo = rlo_ahead;
-                j = rc.jm & kIdMask;
-                if constexpr (!ATOMIC) {
-                    bool absent;
-                    kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, absent);
-                    asym |= absent;
-                }
-                mj = rc.jm;
-                dj[0] = rc.dx; dj[1] = rc.dy; dj[2] = rc.dz;
-                rj = M<real>::sqrt(norm2r(dj[0], dj[1], dj[2]));
-                rjinv = M<real>::rcp(rj);
-                uj[0] = dj[0] * rjinv; uj[1] = dj[1] * rjinv; uj[2] = dj[2] * rjinv;
-                sh.ux[s] = uj[0]; sh.uy[s] = uj[1]; sh.uz[s] = uj[2];
-                sh.r[s] = rj;
-                sh.mask[s] = mj;
-                for (int t = 0; t < nt; ++t) {
-                    real fc = real(0), dfc = real(0);
-                    if ((mj >> (kThirdBit + t)) & 1)
-                        cutoff_terms(ONE ? q0 : ptab[(ti * nt + t) * nt + rec_type(mj)], rj, fc, dfc, rjlo);
-                    sh.fc[t][s] = fc;
-                    sh.dfc[t][s] = dfc;
-                }
-                if (sep) {
-                    sh.ep[s] = M<real>::exp(q0.lam3 * rj);
-                    sh.em[s] = M<real>::exp(-q0.lam3 * rj);
-                }
+            mj = rc.jm;
+            dj[0] = rc.dx; dj[1] = rc.dy; dj[2] = rc.dz;
+            rj = M<real>::sqrt(norm2r(dj[0], dj[1], dj[2]));
+            rjinv = M<real>::rcp(rj);
+            uj[0] = dj[0] * rjinv; uj[1] = dj[1] * rjinv; uj[2] = dj[2] * rjinv;
+            sh.ux[s] = uj[0]; sh.uy[s] = uj[1]; sh.uz[s] = uj[2];
+            sh.r[s] = rj;
+            sh.mask[s] = mj;
+            for (int t = 0; t < nt; ++t) {
+                real fc = real(0), dfc = real(0);
+                if ((mj >> (kThirdBit + t)) & 1)
+                    cutoff_terms(ONE ? q0 : ptab[(ti * nt + t) * nt + rec_type(mj)], rj, fc, dfc, rjlo);
+                sh.fc[t][s] = fc;
+                sh.dfc[t][s] = dfc;
             }
-            if (nx.grp < items.end) fetch(nx);   // this batch's inputs are consumed
-            __syncthreads();
+            if (sep) {
+                sh.ep[s] = M<real>::exp(q0.lam3 * rj);
+                sh.em[s] = M<real>::exp(-q0.lam3 * rj);
+            }
+        }
+        after_slots();   // this batch's inputs are consumed
+        __syncthreads();
 
-            // exp((lambda3 (r_a - r_b))^m) and its derivative with respect to r_a
-            auto ex_term = [&](const TripParam<real> &q, int sa, real ra, int sbb, real rbb, real &ex, real &dex) {
-                if constexpr (NOL3) {
-                    ex = real(1);   // lambda3 = 0: the factor is 1 in every triplet
-                    dex = real(0);
-                } else if (ONE && sep) {
-                    ex = sh.ep[sa] * sh.em[sbb];
-                    dex = q0.lam3 * ex;
-                } else {
-                    exp_term(q, ra, rbb, ex, dex);
-                }
-            };
+        // exp((lambda3 (r_a - r_b))^m) and its derivative with respect to r_a
+        auto ex_term = [&](const TripParam<real> &q, int sa, real ra, int sbb, real rbb, real &ex, real &dex) {
+            if constexpr (NOL3) {
+                ex = real(1);   // lambda3 = 0: the factor is 1 in every triplet
+                dex = real(0);
+            } else if (ONE && sep) {
+                ex = sh.ep[sa] * sh.em[sbb];
+                dex = q0.lam3 * ex;
+            } else {
+                exp_term(q, ra, rbb, ex, dex);
+            }
+        };
 
-            const int tj = rec_type(mj);
-            const bool j_pair = ONE || ((mj >> kPairBit) & 1);
-            facc fx = 0, fy = 0, fz = 0;       // force on j from centre i's terms
-            double e_pair = 0.0;   // energy of pair (i, j)
-            if (has_slot) {
-                // ---- 1: zeta_ij and dzeta_ij/dx_j = aj / r_ij + bj u_ij over the
-                // other slots k of centre i (k = j skipped by the index map)
-                real zr = real(0), aj[3] = {0, 0, 0}, bj = real(0);
-                if (CACHE || j_pair) {
-                    for (int kk = 0; kk + 1 < pc; ++kk) {
-                        const int sk = sb + kk + (kk >= jl ? 1 : 0);
-                        const int mk = ONE ? 0 : sh.mask[sk];
-                        const int tk = ONE ? 0 : rec_type(mk);
-                        const TripParam<real> q = trip((ti * nt + tj) * nt + tk);
-                        const real rk = sh.r[sk];
-                        const real uk[3] = {sh.ux[sk], sh.uy[sk], sh.uz[sk]};
-                        const real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
-                        const Angular<real> an = angular(q, cs);
-                        // r_ij d cos(theta_ijk) / d x_j
-                        const real tv[3] = {uk[0] - cs * uj[0], uk[1] - cs * uj[1], uk[2] - cs * uj[2]};
-                        real ex, dex;
-                        ex_term(q, s, rj, sk, rk, ex, dex);
-                        const bool member = j_pair && (ONE || ((mk >> (kThirdBit + tj)) & 1));
-                        const real fck = member ? sh.fc[ONE ? 0 : tj][sk] : real(0);
-                        const real fg = fck * an.g;
-                        zr += fg * ex;
-                        const real w = fck * an.dg * ex;
-                        aj[0] += w * tv[0];
-                        aj[1] += w * tv[1];
-                        aj[2] += w * tv[2];
-                        bj += fg * dex;
-                        if constexpr (!ONE) n_trip += member ? 1 : 0;
-                        if constexpr (CACHE) {
-                            if (kk < KC) {
-                                real ex2, dex2;
-                                ex_term(q, sk, rk, s, rj, ex2, dex2);
-                                const real w2 = an.dg * ex2;
-                                kc[kk][s] = KCache<real>{w2 * tv[0], w2 * tv[1], w2 * tv[2], an.g * ex2};
-                            }
+        const int tj = rec_type(mj);
+        const bool j_pair = ONE || ((mj >> kPairBit) & 1);
+        facc fx = 0, fy = 0, fz = 0;       // force on j from centre i's terms
+        double e_pair = 0.0;   // energy of pair (i, j)
+        if (has_slot) {
+            // ---- 1: zeta_ij and dzeta_ij/dx_j = aj / r_ij + bj u_ij over the
+            // other slots k of centre i (k = j skipped by the index map)
+            real zr = real(0), aj[3] = {0, 0, 0}, bj = real(0);
+            if (CACHE || j_pair) {
+                for (int kk = 0; kk + 1 < pc; ++kk) {
+                    const int sk = sb + kk + (kk >= jl ? 1 : 0);
+                    const int mk = ONE ? 0 : sh.mask[sk];
+                    const int tk = ONE ? 0 : rec_type(mk);
+                    const TripParam<real> q = trip((ti * nt + tj) * nt + tk);
+                    const real rk = sh.r[sk];
+                    const real uk[3] = {sh.ux[sk], sh.uy[sk], sh.uz[sk]};
+                    const real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
+                    const Angular<real> an = angular(q, cs);
+                    // r_ij d cos(theta_ijk) / d x_j
+                    const real tv[3] = {uk[0] - cs * uj[0], uk[1] - cs * uj[1], uk[2] - cs * uj[2]};
+                    real ex, dex;
+                    ex_term(q, s, rj, sk, rk, ex, dex);
+                    const bool member = j_pair && (ONE || ((mk >> (kThirdBit + tj)) & 1));
+                    const real fck = member ? sh.fc[ONE ? 0 : tj][sk] : real(0);
+                    const real fg = fck * an.g;
+                    zr += fg * ex;
+                    const real w = fck * an.dg * ex;
+                    aj[0] += w * tv[0];
+                    aj[1] += w * tv[1];
+                    aj[2] += w * tv[2];
+                    bj += fg * dex;
+                    if constexpr (!ONE) n_trip += member ? 1 : 0;
+                    if constexpr (CACHE) {
+                        if (kk < KC) {
+                            real ex2, dex2;
+                            ex_term(q, sk, rk, s, rj, ex2, dex2);
+                            const real w2 = an.dg * ex2;
+                            kc[kk][s] = KCache<real>{w2 * tv[0], w2 * tv[1], w2 * tv[2], an.g * ex2};
                         }
                     }
                 }
-                // ---- 2: pair terms, bond order, dV/dzeta
-                real dz_out = real(0);
-                if (j_pair) {
-                    ++n_pairs;
-                    if constexpr (ONE) n_trip += pc - 1;   // every other slot is a third atom
-                    const int e_ij = ONE ? 0 : (ti * nt + tj) * nt + tj;
-                    const ParamR<real> &q = ONE ? q0 : ptab[e_ij];
-                    const ParamX px = tab.px[e_ij];
-                    const real fc = sh.fc[ONE ? 0 : tj][s], dfc = sh.dfc[ONE ? 0 : tj][s];
-                    pair_step<real, SINGLE>(q, px, zr, fc, dfc, rj, rjlo, uj, e_pair, dz_out, fx, fy, fz);
-                    e_acc += e_pair;
-                    // j-role terms: -dV/dzeta_ij dzeta_ij/dx_j
-                    fx -= (facc)(dz_out * (aj[0] * rjinv + bj * uj[0]));
-                    fy -= (facc)(dz_out * (aj[1] * rjinv + bj * uj[1]));
-                    fz -= (facc)(dz_out * (aj[2] * rjinv + bj * uj[2]));
-                }
-                sh.dzeta[s] = dz_out;
             }
-            __syncthreads();
+            // ---- 2: pair terms, bond order, dV/dzeta
+            real dz_out = real(0);
+            if (j_pair) {
+                ++n_pairs;
+                if constexpr (ONE) n_trip += pc - 1;   // every other slot is a third atom
+                const int e_ij = ONE ? 0 : (ti * nt + tj) * nt + tj;
+                const ParamR<real> &q = ONE ? q0 : ptab[e_ij];
+                const ParamX px = tab.px[e_ij];
+                const real fc = sh.fc[ONE ? 0 : tj][s], dfc = sh.dfc[ONE ? 0 : tj][s];
+                pair_step<real, SINGLE>(q, px, zr, fc, dfc, rj, rjlo, uj, e_pair, dz_out, fx, fy, fz);
+                e_acc += e_pair;
+                // j-role terms: -dV/dzeta_ij dzeta_ij/dx_j
+                fx -= (facc)(dz_out * (aj[0] * rjinv + bj * uj[0]));
+                fy -= (facc)(dz_out * (aj[1] * rjinv + bj * uj[1]));
+                fz -= (facc)(dz_out * (aj[2] * rjinv + bj * uj[2]));
+            }
+            sh.dzeta[s] = dz_out;
+        }
+        __syncthreads();
 
-            if (has_slot) {
-                // ---- 3: second K loop, the k-role terms of centre i on atom j:
-                // -dV/dzeta_ik dzeta(i,k,j)/dx_j over the bond partners k of i
-                // that have j as a third atom, summed in the working precision
-                // (a handful of triplet terms; the pair's total is stored in
-                // the working precision as well)
-                real ax = 0, ay = 0, az = 0, su = 0;
-                for (int kk = 0; kk + 1 < pc; ++kk) {
-                    const int sk = sb + kk + (kk >= jl ? 1 : 0);
-                    const real dzk = sh.dzeta[sk];
-                    const int mk = ONE ? 0 : sh.mask[sk];
-                    const int tk = ONE ? 0 : rec_type(mk);
-                    const bool valid = dzk != real(0) && (ONE || ((mj >> (kThirdBit + tk)) & 1));
-                    const int e_kj = (ti * nt + tk) * nt + tj;
-                    const real rk = sh.r[sk];
-                    real v[3], sg, tg;   // dzeta(i,k,j)/dx_j = (fc_j v / r_j) + (fc'_j sg - fc_j tg) u_j
-                    if (CACHE && kk < KC) {
-                        const KCache<real> c = kc[kk][s];
-                        v[0] = c.vx; v[1] = c.vy; v[2] = c.vz;
-                        sg = c.s;
-                        if constexpr (NOL3) tg = real(0);
-                        else tg = sep ? q0.lam3 * sg : sg * exp_ratio(trip(e_kj), rk, rj);
-                    } else {
-                        const TripParam<real> q = trip(e_kj);
-                        const real uk[3] = {sh.ux[sk], sh.uy[sk], sh.uz[sk]};
-                        const real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
-                        const Angular<real> an = angular(q, cs);
-                        real ex2, dex2;
-                        ex_term(q, sk, rk, s, rj, ex2, dex2);
-                        const real w2 = an.dg * ex2;
-                        v[0] = w2 * (uk[0] - cs * uj[0]);
-                        v[1] = w2 * (uk[1] - cs * uj[1]);
-                        v[2] = w2 * (uk[2] - cs * uj[2]);
-                        sg = an.g * ex2;
-                        tg = an.g * dex2;
-                    }
-                    const real fcj = valid ? sh.fc[ONE ? 0 : tk][s] : real(0);
-                    const real dfcj = valid ? sh.dfc[ONE ? 0 : tk][s] : real(0);
-                    const real wv = dzk * fcj * rjinv;
-                    ax += wv * v[0];
-                    ay += wv * v[1];
-                    az += wv * v[2];
-                    su += dzk * (dfcj * sg - fcj * tg);
-                }
-                fx -= (facc)(ax + su * uj[0]);
-                fy -= (facc)(ay + su * uj[1]);
-                fz -= (facc)(az + su * uj[2]);
-                // ---- 4: virial and output (FP64 from here on)
-                const double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
-                const double dxj = (double)dj[0], dyj = (double)dj[1], dzj_ = (double)dj[2];
-                w_acc[0] += dxj * Fx;
-                w_acc[1] += dyj * Fy;
-                w_acc[2] += dzj_ * Fz;
-                w_acc[3] += dxj * Fy;
-                w_acc[4] += dxj * Fz;
-                w_acc[5] += dyj * Fz;
-                if constexpr (ATOMIC) {
-                    double *f = a.forces_atomic + 3 * (size_t)j;
-                    atomicAdd(f, Fx);
-                    atomicAdd(f + 1, Fy);
-                    atomicAdd(f + 2, Fz);
-                } else if ((unsigned)kpos < (unsigned)kRecCap) {
-                    real *f = static_cast<real *>(a.planes) + 3 * ((size_t)kpos * a.plane_stride + (size_t)j);
-                    f[0] = (real)Fx; f[1] = (real)Fy; f[2] = (real)Fz;
-                }
-                sh.fs[s][0] = Fx; sh.fs[s][1] = Fy; sh.fs[s][2] = Fz;
-                if constexpr (BATCHED) {
-                    sev[s][0] = e_pair;
-                    sev[s][1] = dxj * Fx;
-                    sev[s][2] = dyj * Fy;
-                    sev[s][3] = dzj_ * Fz;
-                    sev[s][4] = dxj * Fy;
-                    sev[s][5] = dxj * Fz;
-                    sev[s][6] = dyj * Fz;
-                }
-            }
-            __syncthreads();
-            if (lane < cut) {
-                double ox = 0, oy = 0, oz = 0;
-                const int s0 = sh.pstart[lane], s1 = sh.pstart[lane + 1];
-                for (int q = s0; q < s1; ++q) {
-                    ox -= sh.fs[q][0]; oy -= sh.fs[q][1]; oz -= sh.fs[q][2];
-                }
-                if constexpr (ATOMIC) {
-                    double *o = a.forces_atomic + 3 * (size_t)(a0 + lane);
-                    atomicAdd(o, ox);
-                    atomicAdd(o + 1, oy);
-                    atomicAdd(o + 2, oz);
+        if (has_slot) {
+            // ---- 3: second K loop, the k-role terms of centre i on atom j:
+            // -dV/dzeta_ik dzeta(i,k,j)/dx_j over the bond partners k of i
+            // that have j as a third atom, summed in the working precision
+            // (a handful of triplet terms; the pair's total is stored in
+            // the working precision as well)
+            real ax = 0, ay = 0, az = 0, su = 0;
+            for (int kk = 0; kk + 1 < pc; ++kk) {
+                const int sk = sb + kk + (kk >= jl ? 1 : 0);
+                const real dzk = sh.dzeta[sk];
+                const int mk = ONE ? 0 : sh.mask[sk];
+                const int tk = ONE ? 0 : rec_type(mk);
+                const bool valid = dzk != real(0) && (ONE || ((mj >> (kThirdBit + tk)) & 1));
+                const int e_kj = (ti * nt + tk) * nt + tj;
+                const real rk = sh.r[sk];
+                real v[3], sg, tg;   // dzeta(i,k,j)/dx_j = (fc_j v / r_j) + (fc'_j sg - fc_j tg) u_j
+                if (CACHE && kk < KC) {
+                    const KCache<real> c = kc[kk][s];
+                    v[0] = c.vx; v[1] = c.vy; v[2] = c.vz;
+                    sg = c.s;
+                    if constexpr (NOL3) tg = real(0);
+                    else tg = sep ? q0.lam3 * sg : sg * exp_ratio(trip(e_kj), rk, rj);
                 } else {
-                    double *o = a.own + 3 * (size_t)(a0 + lane);
-                    o[0] = ox; o[1] = oy; o[2] = oz;
+                    const TripParam<real> q = trip(e_kj);
+                    const real uk[3] = {sh.ux[sk], sh.uy[sk], sh.uz[sk]};
+                    const real cs = uj[0] * uk[0] + uj[1] * uk[1] + uj[2] * uk[2];
+                    const Angular<real> an = angular(q, cs);
+                    real ex2, dex2;
+                    ex_term(q, sk, rk, s, rj, ex2, dex2);
+                    const real w2 = an.dg * ex2;
+                    v[0] = w2 * (uk[0] - cs * uj[0]);
+                    v[1] = w2 * (uk[1] - cs * uj[1]);
+                    v[2] = w2 * (uk[2] - cs * uj[2]);
+                    sg = an.g * ex2;
+                    tg = an.g * dex2;
                 }
-                if constexpr (BATCHED) {
-                    double v[7] = {0, 0, 0, 0, 0, 0, 0};
-                    for (int q = s0; q < s1; ++q)
-                        #pragma unroll
-                        for (int c = 0; c < 7; ++c) v[c] += sev[q][c];
-                    double *ea = a.eatom + 8 * (size_t)(a0 + lane);
-                    #pragma unroll
-                    for (int c = 0; c < 7; ++c) ea[c] = v[c];
-                    ea[7] = 0.0;
-                }
+                const real fcj = valid ? sh.fc[ONE ? 0 : tk][s] : real(0);
+                const real dfcj = valid ? sh.dfc[ONE ? 0 : tk][s] : real(0);
+                const real wv = dzk * fcj * rjinv;
+                ax += wv * v[0];
+                ay += wv * v[1];
+                az += wv * v[2];
+                su += dzk * (dfcj * sg - fcj * tg);
             }
+            fx -= (facc)(ax + su * uj[0]);
+            fy -= (facc)(ay + su * uj[1]);
+            fz -= (facc)(az + su * uj[2]);
+            // ---- 4: virial and output (FP64 from here on)
+            const double Fx = (double)fx, Fy = (double)fy, Fz = (double)fz;
+            const double dxj = (double)dj[0], dyj = (double)dj[1], dzj_ = (double)dj[2];
+            w_acc[0] += dxj * Fx;
+            w_acc[1] += dyj * Fy;
+            w_acc[2] += dzj_ * Fz;
+            w_acc[3] += dxj * Fy;
+            w_acc[4] += dxj * Fz;
+            w_acc[5] += dyj * Fz;
+            if constexpr (ATOMIC) {
+                double *f = a.forces_atomic + 3 * (size_t)j;
+                atomicAdd(f, Fx);
+                atomicAdd(f + 1, Fy);
+                atomicAdd(f + 2, Fz);
+            } else if ((unsigned)kpos < (unsigned)kPlaneCap) {
+                real *f = static_cast<real *>(a.planes) + 3 * ((size_t)kpos * a.plane_stride + (size_t)j);
+                f[0] = (real)Fx; f[1] = (real)Fy; f[2] = (real)Fz;
+            }
+            sh.fs[s][0] = Fx; sh.fs[s][1] = Fy; sh.fs[s][2] = Fz;
+            if constexpr (BATCHED) {
+                sev[s][0] = e_pair;
+                sev[s][1] = dxj * Fx;
+                sev[s][2] = dyj * Fy;
+                sev[s][3] = dzj_ * Fz;
+                sev[s][4] = dxj * Fy;
+                sev[s][5] = dxj * Fz;
+                sev[s][6] = dyj * Fz;
+            }
+        }
+        __syncthreads();
+        if (lane < cut) {
+            double ox = 0, oy = 0, oz = 0;
+            const int s0 = sh.pstart[lane], s1 = sh.pstart[lane + 1];
+            for (int q = s0; q < s1; ++q) {
+                ox -= sh.fs[q][0]; oy -= sh.fs[q][1]; oz -= sh.fs[q][2];
+            }
+            if constexpr (ATOMIC) {
+                double *o = a.forces_atomic + 3 * (size_t)(a0 + lane);
+                atomicAdd(o, ox);
+                atomicAdd(o + 1, oy);
+                atomicAdd(o + 2, oz);
+            } else {
+                double *o = a.own + 3 * (size_t)(a0 + lane);
+                o[0] = ox; o[1] = oy; o[2] = oz;
+            }
+            if constexpr (BATCHED) {
+                double v[7] = {0, 0, 0, 0, 0, 0, 0};
+                for (int q = s0; q < s1; ++q)
+                    #pragma unroll
+                    for (int c = 0; c < 7; ++c) v[c] += sev[q][c];
+                double *ea = a.eatom + 8 * (size_t)(a0 + lane);
+                #pragma unroll
+                for (int c = 0; c < 7; ++c) ea[c] = v[c];
+                ea[7] = 0.0;
+            }
+        }
+        __syncthreads();
+        return make_int2(cut, npacked);
+    };
+
+    if constexpr (!FUSED) {
+        Ahead nx{};
+        nx.grp = items.end;   // an empty range (more XCD slices than groups) runs no batch
+        if (items.begin < items.end) {
+            group_start(nx, items.begin);
+            fetch(nx);
+        }
+        while (nx.grp < items.end) {
+            const int a0 = nx.a0, a_end = nx.a_end;
+            const size_t rec0 = nx.rec;
+            run_batch(a0, a_end - a0, nx.p, nx.t, nx.rc, nx.rlo, -1,
+                      [&](int cut, int npacked) {
+                          // the next batch: the rest of this group, or the next group
+                          nx.a0 = a0 + cut;
+                          nx.rec = rec0 + npacked;
+                          if (nx.a0 >= a_end) group_start(nx, nx.grp + items.stride);
+                      },
+                      [&]() {
+                          if (nx.grp < items.end) fetch(nx);
+                      });
+        }
+    } else {
+        // ---- fused packing: each group's rows are packed here, chunk by chunk
+        // of 64 entries, into a queue of records in LDS; batches are taken
+        // from its head once it holds a full batch of complete atoms (or the
+        // group's rows are done).  Before a chunk the queue holds fewer than
+        // kScap records of complete atoms plus at most kRecCap of the one
+        // atom in progress, so a chunk never overruns it.
+        __shared__ FusedQueue<real> fq;
+        __shared__ double psq_s[ONE ? 1 : kMaxTypes * kMaxTypes];
+        __shared__ double cut_s[ONE ? 1 : kMaxTypes * kMaxTypes * kMaxTypes];
+        const double psq0 = tab.packsq[0];
+        if constexpr (!ONE) {
+            for (int q = lane; q < nt * nt; q += kWave) psq_s[q] = tab.packsq[q];
+            for (int q = lane; q < nt * nt * nt; q += kWave) cut_s[q] = tab.px[q].cutsq;
+        }
+        const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+        for (int grp = items.begin; grp < items.end; grp += items.stride) {
+            const int g0 = grp * B, gn = min(B, n - g0);
+            int rcount = 0;
+            if (lane < gn) {
+                const size_t i = (size_t)(g0 + lane);
+                rcount = a.row_count[i];
+                const double dx = a.pos[3 * i] - a.pos_build[3 * i];
+                const double dy = a.pos[3 * i + 1] - a.pos_build[3 * i + 1];
+                const double dz = a.pos[3 * i + 2] - a.pos_build[3 * i + 2];
+                if (!(dx * dx + dy * dy + dz * dz <= a.stale_sq)) atomicOr(a.flags, kFlagStale);
+                fq.ti[lane] = ONE ? 0 : a.types[i];
+                fq.cnt[lane] = 0;
+            }
+            const int inc = wave_incl_scan(rcount);
+            if (lane < gn) fq.eoff[lane + 1] = inc;
+            if (lane == 0) fq.eoff[0] = 0;
+            const int E = __shfl(inc, gn - 1, kWave);
+            unsigned long long kb = 0;   // kept row positions of atom g0 + lane
+            int e_next = 0, a_q = 0, q_head = 0, q_len = 0;
             __syncthreads();
+            while (a_q < gn) {
+                int a_done;
+                for (;;) {
+                    // atoms whose rows are done, and their records not yet computed
+                    a_done = __popcll(__ballot(lane < gn && fq.eoff[lane + 1] <= e_next));
+                    const int ready = wave_sum_int((lane >= a_q && lane < a_done) ? min(fq.cnt[lane], kRecCap) : 0);
+                    if (ready >= kScap || e_next >= E) break;
+                    const int e = e_next + lane;
+                    bool acc = false;
+                    int al = 0, jn = 0, rev = 0, tn = 0;
+                    double dx = 0, dy = 0, dz = 0, rsq = 0;
+                    if (e < E) {
+                        al = find_seg(fq.eoff, gn, e);
+                        const size_t q = (size_t)(g0 + al) * a.cap + (e - fq.eoff[al]);
+                        jn = a.rows[q];
+                        rev = a.rev[q];
+                        const size_t ic = (size_t)(g0 + al);
+                        dx = image(a.pos[3 * (size_t)jn] - a.pos[3 * ic], a.L[0], a.invL[0]);
+                        dy = image(a.pos[3 * (size_t)jn + 1] - a.pos[3 * ic + 1], a.L[1], a.invL[1]);
+                        dz = image(a.pos[3 * (size_t)jn + 2] - a.pos[3 * ic + 2], a.L[2], a.invL[2]);
+                        rsq = norm2(dx, dy, dz);
+                        if constexpr (!ONE) tn = a.types[jn];
+                        acc = rsq < (ONE ? psq0 : psq_s[fq.ti[al] * nt + tn]);
+                    }
+                    const unsigned long long m = __ballot(acc);
+                    // rank of this entry among the kept entries of its atom
+                    const int first = max(fq.eoff[al] - e_next, 0);
+                    const unsigned long long from = first ? ~(~0ull >> (64 - first)) : ~0ull;
+                    const int k = fq.cnt[al] + __popcll(m & below & from);
+                    const unsigned long long mrec = __ballot(acc && k < kRecCap);
+                    if (acc) {
+                        // rev: the position of the centre in jn's row
+                        if (k < kRecCap) {
+                            Rec<real> o;
+                            int mask = jn | (tn << kTypeShift);
+                            if (ONE) {
+                                mask |= (1 << kPairBit) | (1 << kThirdBit);
+                            } else {
+                                const int ti_ = fq.ti[al];
+                                if (rsq < cut_s[(ti_ * nt + tn) * nt + tn]) mask |= 1 << kPairBit;
+                                for (int t = 0; t < nt; ++t)
+                                    if (rsq < cut_s[(ti_ * nt + t) * nt + tn]) mask |= 1 << (kThirdBit + t);
+                            }
+                            o.jm = mask;
+                            o.dx = (real)dx;
+                            o.dy = (real)dy;
+                            o.dz = (real)dz;
+                            if constexpr (sizeof(real) == 8) o.pad = 0;
+                            int qp = q_head + q_len + lanes_below(mrec);
+                            if (qp >= kQueueCap) qp -= kQueueCap;
+                            fq.rec[qp] = o;
+                            fq.rev[qp] = (unsigned char)rev;
+                            if constexpr (kRlo) {
+                                // the FP64 distance minus the FP32 one the slot lane forms
+                                const float rf = __builtin_amdgcn_sqrtf(norm2r(o.dx, o.dy, o.dz));
+                                const double rfd = (double)rf;
+                                fq.rlo[qp] = (float)fma(-rfd, rfd, rsq) * (0.5f * __builtin_amdgcn_rcpf(rf));
+                            }
+                        } else {
+                            // beyond the atom's slots: evaluated without this
+                            // neighbour and reported; the neighbour reads a zero
+                            // force from this centre
+                            real *f = static_cast<real *>(a.planes) + 3 * ((size_t)rev * a.plane_stride + (size_t)jn);
+                            f[0] = real(0); f[1] = real(0); f[2] = real(0);
+                            atomicOr(a.flags, kFlagOverflow);
+                        }
+                    }
+                    q_len += __popcll(mrec);
+                    // the chunk's kept entries into the row masks of their atoms
+                    if (lane < gn) {
+                        const int lo = max(fq.eoff[lane], e_next), hi = min(fq.eoff[lane + 1], e_next + kWave);
+                        if (lo < hi) {
+                            const int len = hi - lo;
+                            const unsigned long long bits =
+                                (m >> (lo - e_next)) & (len == kWave ? ~0ull : ((1ull << len) - 1ull));
+                            kb |= bits << (lo - fq.eoff[lane]);
+                        }
+                    }
+                    __syncthreads();
+                    if (acc) atomicMax(&fq.cnt[al], k + 1);
+                    e_next += kWave;
+                    __syncthreads();
+                }
+                // ---- a batch from the head of the queue
+                const int na = a_done - a_q;
+                int p = 0, tiv = 0;
+                if (lane < na) {
+                    p = min(fq.cnt[a_q + lane], kRecCap);
+                    tiv = fq.ti[a_q + lane];
+                }
+                Rec<real> rc{};
+                float rl = 0.f;
+                int kp = -1;
+                if (lane < q_len) {
+                    int qp = q_head + lane;
+                    if (qp >= kQueueCap) qp -= kQueueCap;
+                    rc = fq.rec[qp];
+                    if constexpr (kRlo) rl = fq.rlo[qp];
+                    kp = fq.rev[qp];
+                }
+                const int2 done = run_batch(g0 + a_q, na, p, tiv, rc, rl, kp, [](int, int) {}, []() {});
+                a_q += done.x;
+                q_len -= done.y;
+                q_head += done.y;
+                if (q_head >= kQueueCap) q_head -= kQueueCap;
+            }
+            if (lane < gn) a.kmask[g0 + lane] = kb;
         }
     }
 
@@ -1668,6 +1852,84 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_forces(const int *__r
     forces[3 * (size_t)m + 2] = fz;
 }
 
+// Fused packing: F_m = (terms of centre m) + plane e of m for every row
+// position e whose centre keeps m (kmask[m]), in increasing e; the centre at
+// row position e of m wrote its force on m there (or zero when m was beyond
+// its slots).  Partials as k_gather_forces.
+template <typename T>
+__global__ __launch_bounds__(kGatherThreads) void k_gather_rows(const unsigned long long *__restrict__ kmask,
+                                                                const T *__restrict__ planes,
+                                                                const double *__restrict__ own, int n,
+                                                                int plane_stride, double *__restrict__ forces,
+                                                                FinalizeArgs fin)
+{
+    if (fin.partials && blockIdx.x == 0) {
+        finalize_sums<kGatherThreads>(fin.partials, fin.counters, fin.grid, fin.out, fin.counts, fin.flags);
+        return;
+    }
+    const int blk = blockIdx.x - (fin.partials ? 1 : 0);
+    const int m = blk * (int)blockDim.x + (int)threadIdx.x;
+    if (m >= n) return;
+    double fx = own[3 * (size_t)m], fy = own[3 * (size_t)m + 1], fz = own[3 * (size_t)m + 2];
+    unsigned long long bits = kmask[m];
+    // four planes' loads issued together
+    while (bits) {
+        int e[4], cnt = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            e[u] = bits ? __builtin_ctzll(bits) : e[0];
+            if (bits) {
+                bits &= bits - 1;
+                ++cnt;
+            }
+        }
+        T v[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const T *f = planes + 3 * ((size_t)e[u] * plane_stride + (size_t)m);
+            v[u][0] = f[0];
+            v[u][1] = f[1];
+            v[u][2] = f[2];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (u >= cnt) break;
+            fx += (double)v[u][0];
+            fy += (double)v[u][1];
+            fz += (double)v[u][2];
+        }
+    }
+    forces[3 * (size_t)m] = fx;
+    forces[3 * (size_t)m + 1] = fy;
+    forces[3 * (size_t)m + 2] = fz;
+}
+
+// One thread per row entry (i, e): the position of i in the row of its
+// neighbour (binary search of the sorted row).
+__global__ void k_reverse_index(const int *__restrict__ ell, const int *__restrict__ row_count, int cap, int n,
+                                unsigned char *__restrict__ rev, int *flags)
+{
+    const size_t total = (size_t)n * cap;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q / cap), e = (int)(q % cap);
+        if (e >= min(row_count[i], cap)) continue;
+        const int j = ell[q];
+        const int *row = ell + (size_t)j * cap;
+        int lo = 0, hi = min(row_count[j], cap);   // first position with row[pos] >= i
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (row[mid] < i) lo = mid + 1;
+            else hi = mid;
+        }
+        int pos = lo;
+        if (lo >= min(row_count[j], cap) || row[lo] != i) {
+            atomicOr(flags, kFlagAsym);
+            pos = 0;
+        }
+        rev[q] = (unsigned char)pos;
+    }
+}
+
 template <typename T>
 __global__ void k_fill_zero(T *p, size_t count)
 {
@@ -1747,7 +2009,7 @@ void with_kernel(int prec, int kind, F &&f)
 }
 
 template <bool BATCHED>
-void grids_dispatch(int prec, const DeviceTable &t, int n, int atoms_per_batch, int grids[3])
+void grids_dispatch(int prec, const DeviceTable &t, int n, int atoms_per_batch, int grids[4])
 {
     const long long batches = ((long long)n + atoms_per_batch - 1) / atoms_per_batch;
     with_kernel(prec, table_kind(t), [&](auto tag) {
@@ -1757,6 +2019,10 @@ void grids_dispatch(int prec, const DeviceTable &t, int n, int atoms_per_batch, 
         grids[1] = occupancy_grid(
             (const void *)k_tersoff<typename K::real, K::nt, BATCHED, K::single, K::nol3, K::cache>, batches,
             kComputeWavesPerCU[prec]);
+        grids[3] = BATCHED ? 0
+                           : occupancy_grid((const void *)k_tersoff<typename K::real, K::nt, false, K::single, K::nol3,
+                                                                    K::cache, false, true>,
+                                            batches, kComputeWavesPerCU[prec]);
     });
     grids[2] = kBigGrid;
 }
@@ -1781,6 +2047,12 @@ void compute_dispatch(const ComputeLaunch &a, const DeviceTable &t, int prec, in
     with_kernel(prec, table_kind(t), [&](auto tag) {
         using K = decltype(tag);
         if constexpr (!BATCHED) {
+            if (a.rows) {
+                hipLaunchKernelGGL(
+                    (k_tersoff<typename K::real, K::nt, false, K::single, K::nol3, K::cache, false, true>), G, W, 0,
+                    s, a, t);
+                return;
+            }
             if (a.forces_atomic) {
                 hipLaunchKernelGGL((k_tersoff<typename K::real, K::nt, false, K::single, K::nol3, K::cache, true>), G,
                                    W, 0, s, a, t);
@@ -1794,7 +2066,7 @@ void compute_dispatch(const ComputeLaunch &a, const DeviceTable &t, int prec, in
 
 }  // namespace
 
-void compute_grids(int prec, const DeviceTable &t, bool batched, int n, int atoms_per_batch, int grids[3])
+void compute_grids(int prec, const DeviceTable &t, bool batched, int n, int atoms_per_batch, int grids[4])
 {
     if (batched) grids_dispatch<true>(prec, t, n, atoms_per_batch, grids);
     else grids_dispatch<false>(prec, t, n, atoms_per_batch, grids);
@@ -1879,6 +2151,29 @@ hipError_t launch_gather_forces(const int *pcount, int prec, const void *planes,
     else
         hipLaunchKernelGGL(k_gather_forces<double>, G, W, 0, s, pcount, static_cast<const double *>(planes), own,
                            n, n_dev, plane_stride, forces, drop_count, fin);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const unsigned long long *kmask, int prec, const void *planes, const double *own,
+                              int n, int plane_stride, double *forces, const FinalizeArgs &fin, hipStream_t s)
+{
+    const int blocks = std::max(1, (n + kGatherThreads - 1) / kGatherThreads) + (fin.partials ? 1 : 0);
+    const dim3 G(blocks), W(kGatherThreads);
+    if (prec != kPrecFP64)
+        hipLaunchKernelGGL(k_gather_rows<float>, G, W, 0, s, kmask, static_cast<const float *>(planes), own, n,
+                           plane_stride, forces, fin);
+    else
+        hipLaunchKernelGGL(k_gather_rows<double>, G, W, 0, s, kmask, static_cast<const double *>(planes), own, n,
+                           plane_stride, forces, fin);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse_index(const int *ell, const int *row_count, int cap, int n, unsigned char *rev,
+                                int *flags, hipStream_t s)
+{
+    const long long total = (long long)n * cap;
+    const int grid = (int)std::max(1LL, std::min((total + 255) / 256, 8192LL));
+    hipLaunchKernelGGL(k_reverse_index, dim3(grid), dim3(256), 0, s, ell, row_count, cap, n, rev, flags);
     return hipGetLastError();
 }
 

@@ -111,6 +111,7 @@ constexpr int kRecCap = 32;   // packed-neighbour records per atom (more: E_OVER
 // at kept_more[m * kRecCap + q], kept_more = kept + kKeptFast N (-1 after the
 // last when the list is shorter than kRecCap).
 constexpr int kKeptFast = 8;
+constexpr int kFusedRowCap = 64;   // longest neighbour row of the fused packing (one 64-bit kept mask)
 constexpr int kBigGrid = 64;  // workgroups of the dropped-atom fixup kernel
 
 struct PackLaunch {
@@ -161,14 +162,30 @@ struct ComputeLaunch {
     // when not null, every force term is added with FP64 atomics into this
     // n x 3 array (zeroed beforehand), and own / planes / kept are not used
     double *forces_atomic;
+    // one system, fused packing (rows not null): the kernel packs each group's
+    // rows itself (no records, kept lists or counts in memory); the force on
+    // atom m from centre i goes to plane e of m, e = position of i in m's row
+    // (< kFusedRowCap), and kmask[m] marks the row positions whose centres
+    // keep m (the planes k_gather_rows adds)
+    const int *rows;            // neighbour rows (stride cap, sorted)
+    const unsigned char *rev;   // same layout: position of the centre in that neighbour's row
+    const int *row_count;       // n
+    int cap;
+    const double *pos;          // n x 3
+    const double *pos_build;    // n x 3: positions of the last build (stale check)
+    double L[3], invL[3];
+    double stale_sq;
+    int *flags;
+    unsigned long long *kmask;  // n
 };
 
-// Launchers (compute.hip).  grids = {pack, compute} workgroup counts plus
-// kBigGrid for the fixup kernel.
+// Launchers (compute.hip).  grids = {pack, compute} workgroup counts,
+// kBigGrid for the fixup kernel, and the compute grid of the fused packing
+// (one system; 0 for batches).
 // Precisions (the values of tersoff_precision).
 enum : int { kPrecFP64 = 0, kPrecMixed = 1, kPrecSingle = 2, kNumPrec = 3 };
 
-void compute_grids(int prec, const DeviceTable &t, bool batched, int n, int atoms_per_batch, int grids[3]);
+void compute_grids(int prec, const DeviceTable &t, bool batched, int n, int atoms_per_batch, int grids[4]);
 size_t record_bytes(int prec);
 // Bytes of a record region of `slots` records, the per-record r corrections
 // of the float records included (placed after the records; rlo_of gives them).
@@ -211,6 +228,15 @@ hipError_t launch_reduce_systems(const SysDesc *sys, const BatchDims *dims, int 
                                  const int *drop_list, const int *drop_count, const int *sys_status,
                                  double *out, hipStream_t s);
 hipError_t launch_fill_zero_int(int *p, size_t count, hipStream_t s);
+// Fused packing: the force on each atom m from the planes its row's kept
+// centres wrote (kmask[m], in row order) plus its own; fin as above.
+hipError_t launch_gather_rows(const unsigned long long *kmask, int prec, const void *planes, const double *own,
+                              int n, int plane_stride, double *forces, const FinalizeArgs &fin, hipStream_t s);
+// rev[i cap + e] = position of i in the row of its neighbour ell[i cap + e],
+// for the rows of n atoms (row_count, at most cap <= 256 entries each,
+// sorted); kFlagAsym into *flags when a neighbour's row lacks i.
+hipError_t launch_reverse_index(const int *ell, const int *row_count, int cap, int n, unsigned char *rev,
+                                int *flags, hipStream_t s);
 
 // Neighbour build (neighbors.hip)
 hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,

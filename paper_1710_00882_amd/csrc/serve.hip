@@ -257,7 +257,7 @@ struct Server {
     double rc = 0.0;
     size_t max_queued = 0;
     size_t device_bytes = 0;
-    int grids[kNumPrec][3] = {};
+    int grids[kNumPrec][4] = {};
     Lane lanes[kLanes];
     std::unique_ptr<CopyPool> pool;
     std::thread worker;

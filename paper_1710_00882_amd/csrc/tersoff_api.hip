@@ -64,7 +64,9 @@ struct tersoff_ctx {
     bool batch_atoms_set = false;   // tersoff_set_batch_atoms was called (else chosen by the build)
     int force_sum = 0;              // 0: force planes + gather; 1: FP64 atomic scatter (tersoff_set_force_sum)
     int mapping = 0;                // 0: lane per packed pair; 1: lane per triplet (tersoff_set_mapping)
-    int grid[kNumPrec][3] = {};   // [precision] x {pack, compute, fixup}
+    int packing = 0;                // 0: separate packing kernel; 1: fused into the compute kernel where rows allow
+    bool fused_ok = false;          // the resident list supports the fused packing (rows <= kFusedRowCap)
+    int grid[kNumPrec][4] = {};   // [precision] x {pack, compute, fixup, fused compute}
 
     DevBuf<double> pos_build;
     DevBuf<int> types, offsets, pcount, drop_list, jn;   // jn: compact list (S entries)
@@ -76,6 +78,8 @@ struct tersoff_ctx {
     DevBuf<float4> cell_posf;
     DevBuf<int> long_rows;
     DevBuf<int> ell, row_count, scan_tmp, misc;   // misc: [0] flags, [1] max row, [2] check flags
+    DevBuf<unsigned char> rev;                     // reverse row positions (fused packing)
+    DevBuf<unsigned long long> kmask;              // kept row positions per atom (fused packing)
     DevBuf<double> partials, force_scratch;
     DevBuf<long long> counters, counts;
     int *host_misc = nullptr;   // pinned: the build's status words, copied back without staging
@@ -181,13 +185,14 @@ size_t record_slots(const tersoff_ctx *c)
 // the outputs and the resident neighbour list).
 struct EvalBuffers {
     void *recs;          // record_region_bytes(prec, record_slots(c))
-    double *planes;      // 3 kRecCap n
+    double *planes;      // 3 kRecCap n (3 list_cap n with kmask)
     double *own;         // 3 n
     int *pcount;         // n
     int *kept;           // (kKeptFast + kRecCap) n
     int *drop_list;      // n
     double *partials;    // 8 x compute grid
     long long *counters; // 2 x compute grid
+    unsigned long long *kmask;   // n, or null: no fused packing (records, kept lists, pcount used instead)
 };
 
 // Packing, compute, dropped-atom fixup and force gather of one evaluation on
@@ -234,28 +239,50 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     a.atoms_per_batch = c->atoms_per_batch;
     a.plane_stride = c->n;
 
+    // fused packing: the compute kernel packs the rows itself (no records,
+    // kept lists or counts in memory); planes indexed by row position
+    const bool fused = b.kmask && c->fused_ok && c->packing == 1 && c->mapping == 0 && c->force_sum == 0;
+    if (fused) {
+        a.rows = c->ell.p;
+        a.rev = c->rev.p;
+        a.row_count = c->row_count.p;
+        a.cap = c->list_cap;
+        a.pos = pos;
+        a.pos_build = c->pos_build.p;
+        for (int d = 0; d < 3; ++d) {
+            a.L[d] = pk.L[d];
+            a.invL[d] = pk.invL[d];
+        }
+        a.stale_sq = pk.stale_sq;
+        a.flags = c->misc.p;
+        a.kmask = b.kmask;
+    }
+
     // atomic scatter (comparison point): forces summed with FP64 atomics
     // into the zeroed output; no planes, no gather, only the partial sums
     const bool atomic = c->force_sum == 1;
     if (atomic) a.forces_atomic = f;
 
     // event pairs (profiling only): pack (with the zeroing of the forces in
-    // the atomic scatter), main kernel, fixup + gather (or the partial sums)
+    // the atomic scatter; none with the fused packing), main kernel, fixup +
+    // gather (or the partial sums)
     hipEvent_t ev[6] = {};
     if (profile)
-        for (int q = 0; q < 6; ++q) HIP_TRY(c, take_event(c, &ev[q]));
+        for (int q = fused ? 2 : 0; q < 6; ++q) HIP_TRY(c, take_event(c, &ev[q]));
     if (ev[0]) HIP_TRY(c, hipEventRecord(ev[0], s));
     if (atomic) HIP_TRY(c, launch_fill_zero(f, 3 * (size_t)c->n, s));
-    HIP_TRY(c, launch_pack(pk, c->tab, prec, grid[0], s));
+    if (!fused) HIP_TRY(c, launch_pack(pk, c->tab, prec, grid[0], s));
     if (ev[1]) HIP_TRY(c, hipEventRecord(ev[1], s));
     if (ev[2]) HIP_TRY(c, hipEventRecord(ev[2], s));
-    int compute_grid = grid[1];
+    int compute_grid = fused ? grid[3] : grid[1];
     if (c->mapping == 1) HIP_TRY(c, launch_compute_triplet(a, c->tab, prec, grid[1], s, &compute_grid));
-    else HIP_TRY(c, launch_compute(a, c->tab, prec, grid[1], s));
+    else HIP_TRY(c, launch_compute(a, c->tab, prec, compute_grid, s));
     if (ev[3]) HIP_TRY(c, hipEventRecord(ev[3], s));
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
     const FinalizeArgs fin{b.partials, b.counters, compute_grid, energy_virial, c->counts.p, c->misc.p};
-    if (atomic) {
+    if (fused) {
+        HIP_TRY(c, launch_gather_rows(b.kmask, prec, b.planes, b.own, c->n, c->n, f, fin, s));
+    } else if (atomic) {
         // the partial sums alone (no rows to gather); resets the dropped count
         HIP_TRY(c, launch_gather_forces(b.pcount, prec, b.planes, b.own, 0, nullptr, c->n, f, c->misc.p + 3, fin, s));
     } else {
@@ -266,7 +293,7 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     }
     if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
     if (profile) {
-        c->ev_pack.emplace_back(ev[0], ev[1]);
+        if (!fused) c->ev_pack.emplace_back(ev[0], ev[1]);
         c->ev_compute.emplace_back(ev[2], ev[3]);
         c->ev_gather.emplace_back(ev[4], ev[5]);
     }
@@ -452,7 +479,7 @@ void tersoff_destroy(tersoff_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     c->pos_build.release(); c->types.release(); c->offsets.release(); c->jn.release();
-    c->kept.release(); c->own.release(); c->planes.release();
+    c->kept.release(); c->own.release(); c->planes.release(); c->rev.release(); c->kmask.release();
     c->pcount.release(); c->drop_list.release(); c->recs.release();
     c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
     c->cell_atoms.release(); c->slot_cell.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
@@ -511,7 +538,7 @@ int tersoff_set_batch_atoms(tersoff_ctx *c, int32_t atoms)
         int gmax = 0;
         for (int pr = 0; pr < kNumPrec; ++pr) {
             compute_grids(pr, c->tab, false, c->n, atoms, c->grid[pr]);
-            gmax = std::max(gmax, c->grid[pr][1]);
+            gmax = std::max({gmax, c->grid[pr][1], c->grid[pr][3]});
         }
         HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
         HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
@@ -524,6 +551,14 @@ int tersoff_set_force_sum(tersoff_ctx *c, int32_t mode)
     if (!c) return TERSOFF_E_INVALID;
     if (mode != 0 && mode != 1) return fail(c, TERSOFF_E_INVALID, "force-sum mode must be 0 or 1");
     c->force_sum = mode;
+    return TERSOFF_OK;
+}
+
+int tersoff_set_packing(tersoff_ctx *c, int32_t mode)
+{
+    if (!c) return TERSOFF_E_INVALID;
+    if (mode != 0 && mode != 1) return fail(c, TERSOFF_E_INVALID, "packing mode must be 0 or 1");
+    c->packing = mode;
     return TERSOFF_OK;
 }
 
@@ -670,6 +705,15 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     // the next build starts from the capacity this list needed (plus a margin)
     c->ell_cap = std::max(8, ((host[1] + 2 + 7) / 8) * 8);
 
+    // fused packing: each entry's position in its neighbour's row
+    c->fused_ok = c->list_cap <= kFusedRowCap;
+    if (c->fused_ok) {
+        HIP_TRY(c, c->rev.ensure((size_t)N * c->list_cap));
+        HIP_TRY(c, c->kmask.ensure(N));
+        HIP_TRY(c, launch_reverse_index(c->ell.p, c->row_count.p, c->list_cap, N, c->rev.p, c->misc.p, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+    }
+
     c->n = N;
     for (int a = 0; a < 3; ++a) c->box[a] = box[a];
     c->cutoff = cutoff;
@@ -681,7 +725,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     int gmax = 0;
     for (int pr = 0; pr < kNumPrec; ++pr) {
         compute_grids(pr, c->tab, false, N, c->atoms_per_batch, c->grid[pr]);
-        gmax = std::max(gmax, c->grid[pr][1]);
+        gmax = std::max({gmax, c->grid[pr][1], c->grid[pr][3]});
     }
     HIP_TRY(c, c->partials.ensure(8 * (size_t)gmax));
     HIP_TRY(c, c->counters.ensure(2 * (size_t)gmax));
@@ -703,7 +747,7 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     }
     const size_t slots = record_slots(c);
     HIP_TRY(c, c->recs.ensure(record_region_bytes(prec, slots)));
-    HIP_TRY(c, c->planes.ensure(3 * (size_t)kRecCap * (size_t)c->n));
+    HIP_TRY(c, c->planes.ensure(3 * (size_t)std::max(kRecCap, c->list_cap) * (size_t)c->n));
     EvalBuffers b{};
     b.recs = c->recs.p;
     b.planes = c->planes.p;
@@ -713,6 +757,7 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     b.drop_list = c->drop_list.p;
     b.partials = c->partials.p;
     b.counters = c->counters.p;
+    b.kmask = c->fused_ok ? c->kmask.p : nullptr;
     return launch_evaluation(c, pos, prec, energy_virial, f, as_stream(stream), b, c->profiling);
 }
 

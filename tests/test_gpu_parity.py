@@ -405,3 +405,83 @@ def test_triplet_mapping_rejects_single_and_atomic():
         m.check()
     finally:
         m.close()
+
+
+def _eval_packing(m, pos, precision, mode):
+    import torch
+    m.set_packing(mode)
+    out, f = m.compute(pos, precision)
+    torch.cuda.synchronize()
+    m.check()
+    return out.cpu().numpy().copy(), f.cpu().numpy().copy(), m.counts()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "single"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_fused_packing_matches_separate(case, precision):
+    """Packing inside the compute kernel (the default) forms the same records
+    and batches as the separate packing kernel, and the force gather adds the
+    same planes in the same (row) order: forces agree bit for bit, energy and
+    virial up to the order of the per-workgroup sums."""
+    from paper_1710_00882_amd import Tersoff
+    sysf, tabf = CASES[case]
+    s, table = sysf(), tabf()
+    m = Tersoff(table)
+    try:
+        pos, types = to_dev(s)
+        m.build_neighbors(pos, types, s.box)
+        say(f"[packing] {case} n={s.n} {precision}")
+        o_f, f_f, c_f = _eval_packing(m, pos, precision, "fused")
+        o_s, f_s, c_s = _eval_packing(m, pos, precision, "separate")
+        assert c_f == c_s
+        assert np.array_equal(f_f, f_s)
+        assert np.allclose(o_f, o_s, rtol=1e-13, atol=1e-13 * abs(o_s[0]))
+    finally:
+        m.close()
+
+
+@pytest.mark.parametrize("skin", [3.0, 3.5])
+def test_long_rows_fused_and_fallback(skin):
+    """Rows of 46 entries (skin 3.0: several 64-entry chunks per centre in
+    the fused packing) and of 70 (skin 3.5: beyond the fused packing's
+    64-entry rows, evaluated with the separate packing kernel) at parity."""
+    import torch
+    from paper_1710_00882_amd import Tersoff
+    s, table = W.diamond(3, 3, 3, jitter=0.1, seed=31), W.si_table()
+    Eo, Fo, Vo, off, idx = oracle_eval(s, table, skin=skin)
+    m = Tersoff(table)
+    try:
+        pos, types = to_dev(s)
+        m.build_neighbors(pos, types, s.box, skin=skin)
+        for precision in ("fp64", "mixed"):
+            for mode in ("fused", "separate"):
+                say(f"[long rows] skin={skin} longest row {int(np.diff(off).max())} {precision} {mode}")
+                o, F, _ = _eval_packing(m, pos, precision, mode)
+                assert_parity(float(o[0]), F, o[1:], Eo, Fo, Vo, s.n, precision, f"skin {skin} {mode}")
+    finally:
+        m.close()
+
+
+@pytest.mark.parametrize("natoms", [40, 80])
+def test_overflow_reported_both_packings(natoms):
+    """Atoms with more kept neighbours than a batch slot range holds are
+    reported (E_OVERFLOW) without a fault: 40 atoms in a 2.9 A ball (rows of
+    39: the fused packing drops the excess entries) and 80 (rows of 79: the
+    separate packing kernel)."""
+    import torch
+    from paper_1710_00882_amd import Tersoff
+    g = W.rng(7)
+    v = g.normal(size=(natoms, 3))
+    pos = 20.0 + v / np.linalg.norm(v, axis=1, keepdims=True) * g.uniform(0.0, 1.45, size=(natoms, 1))
+    s = W.System(pos, np.zeros(natoms, np.int32), np.array([40.0, 40.0, 40.0]))
+    m = Tersoff(W.si_table())
+    try:
+        p, t = to_dev(s)
+        m.build_neighbors(p, t, s.box)
+        for mode in ("fused", "separate"):
+            m.set_packing(mode)
+            m.compute(p, "mixed")
+            torch.cuda.synchronize()
+            assert m.check_status() == -4
+    finally:
+        m.close()
