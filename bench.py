@@ -65,10 +65,10 @@ RECORD_BYTES = {"mixed": 16, "single": 16, "fp64": 32}
 # reads 0.5 of the bytes a copy moves, WRITE_SIZE 1.0).  Valid only for the
 # compute source it was measured on (its SHA-256 prefix).
 TRAFFIC_PROFILE = {
-    "source": "48fc720dbc8268f5",
-    "fetch_kib": 123197.0, "fetch_factor": 2.0,
-    "write_kib": 227079.5, "write_factor": 1.0,
-    "bytes_per_launch": 123197.0 * 1024 * 2.0 + 227079.5 * 1024 * 1.0,
+    "source": "134ccf9a506de761",
+    "fetch_kib": 140614.4, "fetch_factor": 2.0,
+    "write_kib": 230534.0, "write_factor": 1.0,
+    "bytes_per_launch": 140614.4 * 1024 * 2.0 + 230534.0 * 1024 * 1.0,
 }
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1710_00882_amd", "csrc", "compute.hip")
 
@@ -424,7 +424,9 @@ def main():
                     help="skip the lane-per-j vs lane-per-pair comparison on the 32k and 256k workloads")
     ap.add_argument("--batch-atoms", type=int, default=0)
     ap.add_argument("--precision", choices=("both", "mixed", "fp64", "single"), default="both",
-                    help="profiling runs may time one precision of the 2M-atom workload only (no JSON line)")
+                    help="profiling runs may time one precision of one workload only (no JSON line)")
+    ap.add_argument("--workload", choices=("si_2m", "disordered_256k"), default="si_2m",
+                    help="with --precision: the workload of the profiling run")
     ap.add_argument("--serve-only", action="store_true", help="profiling: the serving benchmark only")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 256 MiB device copy kernel (HBM counter calibration)")
@@ -442,6 +444,11 @@ def main():
     table = W.si_table()
     if args.serve_only:
         serve_bench(table)
+        return
+    if args.precision != "both" and args.workload == "disordered_256k":
+        log("[bench] generating the 256,000-atom two-species disordered workload")
+        measure_workload(W.disordered_256k(), W.two_species_table(), args.steps, args.warmup, (args.precision,),
+                         args.batch_atoms, sigma=0.005)
         return
     log("[bench] generating the 2,048,000-atom Si workload")
     big = W.si_2m()
@@ -524,8 +531,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_PACKED_TFLOPS,
             "traffic": traffic,
-            "kernel": "k_tersoff<float, one species, lambda3 = 0" + (", fused packing" if mixed["fused"] else "") +
-                      "> (packing, energy / force / virial)",
+            "kernel": "k_tersoff<float, one species, lambda3 = 0" + (", fused packing> (packing, " if mixed["fused"]
+                                                                       else "> (") + "energy / force / virial)",
             "kernel_ms": mixed["main_ms"],
             "alg_flops_per_launch": mixed["alg_flops_per_launch"],
             "peak_note": "FP32 vector peak (packed issue); 78.64 TFLOP/s unpacked FP32 / FP64 issue",

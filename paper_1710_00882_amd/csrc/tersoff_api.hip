@@ -66,6 +66,7 @@ struct tersoff_ctx {
     int mapping = 0;                // 0: lane per packed pair; 1: lane per triplet (tersoff_set_mapping)
     int packing = 0;                // 0: separate packing kernel; 1: fused into the compute kernel where rows allow
     bool fused_ok = false;          // the resident list supports the fused packing (rows <= kFusedRowCap)
+    bool rev_ready = false;         // rev holds the reverse row positions of the resident list
     int grid[kNumPrec][4] = {};   // [precision] x {pack, compute, fixup, fused compute}
 
     DevBuf<double> pos_build;
@@ -243,6 +244,10 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     // kept lists or counts in memory); planes indexed by row position
     const bool fused = b.kmask && c->fused_ok && c->packing == 1 && c->mapping == 0 && c->force_sum == 0;
     if (fused) {
+        if (!c->rev_ready) {
+            HIP_TRY(c, launch_reverse_index(c->ell.p, c->row_count.p, c->list_cap, c->n, c->rev.p, c->misc.p, s));
+            c->rev_ready = true;
+        }
         a.rows = c->ell.p;
         a.rev = c->rev.p;
         a.row_count = c->row_count.p;
@@ -705,14 +710,10 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     // the next build starts from the capacity this list needed (plus a margin)
     c->ell_cap = std::max(8, ((host[1] + 2 + 7) / 8) * 8);
 
-    // fused packing: each entry's position in its neighbour's row
+    // the fused packing (a comparison point) needs each entry's position in
+    // its neighbour's row; formed by the first fused evaluation of this list
     c->fused_ok = c->list_cap <= kFusedRowCap;
-    if (c->fused_ok) {
-        HIP_TRY(c, c->rev.ensure((size_t)N * c->list_cap));
-        HIP_TRY(c, c->kmask.ensure(N));
-        HIP_TRY(c, launch_reverse_index(c->ell.p, c->row_count.p, c->list_cap, N, c->rev.p, c->misc.p, s));
-        HIP_TRY(c, hipStreamSynchronize(s));
-    }
+    c->rev_ready = false;
 
     c->n = N;
     for (int a = 0; a < 3; ++a) c->box[a] = box[a];
@@ -757,7 +758,11 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     b.drop_list = c->drop_list.p;
     b.partials = c->partials.p;
     b.counters = c->counters.p;
-    b.kmask = c->fused_ok ? c->kmask.p : nullptr;
+    if (c->fused_ok && c->packing == 1) {
+        HIP_TRY(c, c->rev.ensure((size_t)c->n * c->list_cap));
+        HIP_TRY(c, c->kmask.ensure(c->n));
+        b.kmask = c->kmask.p;
+    }
     return launch_evaluation(c, pos, prec, energy_virial, f, as_stream(stream), b, c->profiling);
 }
 
