@@ -488,7 +488,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
 {
     __shared__ double xi[kWave], yi[kWave], zi[kWave];
     __shared__ double bL[BATCHED ? 3 : 1][BATCHED ? kWave : 1], biL[BATCHED ? 3 : 1][BATCHED ? kWave : 1];
-    __shared__ int ti[kWave], cnt[kWave];
+    __shared__ int ti[kWave], cnt[kWave], cid[kWave];   // type, kept count and atom of each batch slot
     __shared__ int eoff[kWave + 1];
     __shared__ int kst[kKeptFast][kWave];   // first kept neighbours of the batch's atoms
     __shared__ unsigned char owner[kOwnerCap];   // batch atom of each of the first kOwnerCap entries
@@ -513,12 +513,14 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
     // latency overlaps the previous batch
     struct AtomIn {
         double x, y, z, bx, by, bz;
-        int rc, t;
+        int rc, t, id;
     };
     auto fetch = [&](int b, AtomIn &v) {
         v.rc = 0;
         if (b < items.end && lane < min(B, n - b * B)) {
-            const size_t i = (size_t)(b * B + lane);
+            const int slot = b * B + lane;
+            const size_t i = (size_t)((!BATCHED && a.order) ? a.order[slot] : slot);
+            v.id = (int)i;
             v.x = a.pos[3 * i]; v.y = a.pos[3 * i + 1]; v.z = a.pos[3 * i + 2];
             v.t = ONE ? 0 : a.types[i];
             v.rc = a.row_count[i];
@@ -535,9 +537,10 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
         const AtomIn cur = nxt;
         fetch(bt + items.stride, nxt);
         if (lane < nb) {
-            const size_t i = (size_t)(a0 + lane);
+            const size_t i = (size_t)cur.id;
             xi[lane] = cur.x; yi[lane] = cur.y; zi[lane] = cur.z;
             ti[lane] = cur.t;
+            cid[lane] = cur.id;
             cnt[lane] = 0;
             if constexpr (BATCHED) {
                 const CellGrid &g = a.sys[a.sys_of[i]].g;
@@ -575,7 +578,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 const int al = ec < kOwnerCap ? (int)owner[ec] : find_seg(eoff, nb, ec);
                 alv[c] = al;
                 // row-buffer index of the entry
-                jv[c] = a.ell[(size_t)(a0 + al) * a.cap + (ec - eoff[al])];
+                jv[c] = a.ell[(size_t)cid[al] * a.cap + (ec - eoff[al])];
             }
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
@@ -616,7 +619,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 if (acc) {
                     if (k < kRecCap) {
                         if (k < kKeptFast) kst[k][al] = jv[c];
-                        else a.kept_more[(size_t)(a0 + al) * kRecCap + k] = jv[c];
+                        else a.kept_more[(size_t)cid[al] * kRecCap + k] = jv[c];
                         Rec<real> o;
                         int mask = jv[c] | (tv[c] << kTypeShift);
                         if (ONE) {
@@ -654,7 +657,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
             }
         }
         if (lane < nb) {
-            const int i = a0 + lane;
+            const int i = cur.id;
             int c = cnt[lane];
             // the kept list: its first block, and the end marker
             int4 *kb = reinterpret_cast<int4 *>(a.kept + (size_t)i * kKeptFast);
@@ -699,6 +702,7 @@ template <typename real, int NT>
 struct Shared {
     // per centre atom of the batch
     int ti[kWave];
+    int cid[kWave];              // its atom index
     int pcnt[kWave];
     int pstart[kWave + 1];
     unsigned char owner[kScap];  // centre atom (batch index) of each slot
@@ -963,16 +967,19 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
     struct Ahead {
         int grp, a0, a_end;   // group, first atom, end of the group's atoms
         size_t rec;           // index of the batch's first record
-        int p, t;             // this lane's atom: record count, type
+        int p, t, id;         // this lane's atom: record count, type, index
         Rec<real> rc;         // this lane's slot record
         float rlo;
     };
     auto fetch = [&](Ahead &f) {
         f.p = 0;
         f.t = 0;
+        f.id = 0;
         if (lane < f.a_end - f.a0) {
-            f.p = a.pcount[f.a0 + lane];
-            f.t = ONE ? 0 : a.types[f.a0 + lane];
+            const int slot = f.a0 + lane;
+            f.id = (!BATCHED && a.order) ? a.order[slot] : slot;
+            f.p = a.pcount[f.id];
+            f.t = ONE ? 0 : a.types[f.id];
         }
         if (f.rec + lane < (size_t)(f.grp + 1) * B * kRecCap) {
             f.rc = recs[f.rec + lane];
@@ -985,19 +992,22 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
         f.a_end = min(f.a0 + B, n);
         f.rec = (size_t)f.a0 * kRecCap;
     };
-    // One batch: the leading atoms from a0 (nb available) whose slots fit one
-    // per lane.  Lane inputs: p, tiv -- the slot count and type of atom
-    // a0 + lane; rc_ahead, rlo_ahead -- the record of slot lane; kpos_in --
-    // (fused packing) the force plane of the slot.  after_header(cut,
-    // npacked) runs once the batch is formed, after_slots() once the slot
-    // inputs are consumed.  Returns (atoms, slots) of the batch.
-    auto run_batch = [&](const int a0, const int nb, const int p, const int tiv, const Rec<real> rc_ahead,
-                         const float rlo_ahead, const int kpos_in, auto &&after_header, auto &&after_slots) -> int2 {
+    // One batch: the leading atoms from batch slot a0 (nb available) whose
+    // slots fit one per lane.  Lane inputs: p, tiv, cid_in -- the slot count,
+    // type and index of the atom at batch slot a0 + lane; rc_ahead, rlo_ahead
+    // -- the record of slot lane; kpos_in -- (fused packing) the force plane
+    // of the slot.  after_header(cut, npacked) runs once the batch is formed,
+    // after_slots() once the slot inputs are consumed.  Returns (atoms,
+    // slots) of the batch.
+    auto run_batch = [&](const int a0, const int nb, const int p, const int tiv, const int cid_in,
+                         const Rec<real> rc_ahead, const float rlo_ahead, const int kpos_in, auto &&after_header,
+                         auto &&after_slots) -> int2 {
         // ---- batch: the leading atoms whose slots fit one per lane
         const int ip = wave_incl_scan(p);
         const int cut = __popcll(__ballot(lane < nb && ip <= kScap));   // >= 1: p <= kRecCap
         if (lane < cut) {
             sh.ti[lane] = tiv;
+            sh.cid[lane] = cid_in;
             sh.pcnt[lane] = p;
             sh.pstart[lane + 1] = ip;
             for (int q = ip - p; q < ip; ++q) sh.owner[q] = (unsigned char)lane;
@@ -1026,7 +1036,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 kpos = kpos_in;
             } else if constexpr (!ATOMIC) {
                 bool absent;
-                kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, absent);
+                kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, sh.cid[al], absent);
                 asym |= absent;
             }
             mj = rc.jm;
@@ -1211,12 +1221,12 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                 ox -= sh.fs[q][0]; oy -= sh.fs[q][1]; oz -= sh.fs[q][2];
             }
             if constexpr (ATOMIC) {
-                double *o = a.forces_atomic + 3 * (size_t)(a0 + lane);
+                double *o = a.forces_atomic + 3 * (size_t)cid_in;
                 atomicAdd(o, ox);
                 atomicAdd(o + 1, oy);
                 atomicAdd(o + 2, oz);
             } else {
-                double *o = a.own + 3 * (size_t)(a0 + lane);
+                double *o = a.own + 3 * (size_t)cid_in;
                 o[0] = ox; o[1] = oy; o[2] = oz;
             }
             if constexpr (BATCHED) {
@@ -1244,7 +1254,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
         while (nx.grp < items.end) {
             const int a0 = nx.a0, a_end = nx.a_end;
             const size_t rec0 = nx.rec;
-            run_batch(a0, a_end - a0, nx.p, nx.t, nx.rc, nx.rlo, -1,
+            run_batch(a0, a_end - a0, nx.p, nx.t, nx.id, nx.rc, nx.rlo, -1,
                       [&](int cut, int npacked) {
                           // the next batch: the rest of this group, or the next group
                           nx.a0 = a0 + cut;
@@ -1391,7 +1401,8 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
                     if constexpr (kRlo) rl = fq.rlo[qp];
                     kp = fq.rev[qp];
                 }
-                const int2 done = run_batch(g0 + a_q, na, p, tiv, rc, rl, kp, [](int, int) {}, []() {});
+                const int2 done =
+                    run_batch(g0 + a_q, na, p, tiv, g0 + a_q + lane, rc, rl, kp, [](int, int) {}, []() {});
                 a_q += done.x;
                 q_len -= done.y;
                 q_head += done.y;
@@ -1429,6 +1440,7 @@ constexpr int kTripKeep = 4;
 template <typename real>
 struct TripShared {
     int ti[kWave];
+    int cid[kWave];              // atom index of each centre of the batch
     int pcnt[kWave];
     int pstart[kWave + 1];       // first slot of each centre atom
     int tstart[kWave + 1];       // first triplet of each centre atom
@@ -1526,16 +1538,18 @@ __global__ __launch_bounds__(kWave) void k_tersoff_trip(ComputeLaunch a, DeviceT
         for (int a0 = grp * B; a0 < g_end;) {
             // ---- batch: the leading atoms whose slots fit one per lane
             const int nb = g_end - a0;
-            int p = 0, tiv = 0;
+            int p = 0, tiv = 0, cid = 0;
             if (lane < nb) {
-                p = a.pcount[a0 + lane];
-                tiv = nt == 1 ? 0 : a.types[a0 + lane];
+                cid = a.order ? a.order[a0 + lane] : a0 + lane;
+                p = a.pcount[cid];
+                tiv = nt == 1 ? 0 : a.types[cid];
             }
             const int ip = wave_incl_scan(p);
             const int cut = __popcll(__ballot(lane < nb && ip <= kScap));   // >= 1: p <= kRecCap
             const int it = wave_incl_scan(lane < cut ? p * (p - 1) : 0);
             if (lane < cut) {
                 sh.ti[lane] = tiv;
+                sh.cid[lane] = cid;
                 sh.pcnt[lane] = p;
                 sh.pstart[lane + 1] = ip;
                 sh.tstart[lane + 1] = it;
@@ -1561,7 +1575,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff_trip(ComputeLaunch a, DeviceT
                 if constexpr (kRlo) rjlo = a.rlo[rec0 + s];
                 j = rc.jm & kIdMask;
                 bool absent;
-                kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, a0 + al, absent);
+                kpos = kept_position(a.kept, a.kept + (size_t)kKeptFast * a.plane_stride, j, sh.cid[al], absent);
                 asym |= absent;
                 mj = rc.jm;
                 dj[0] = rc.dx; dj[1] = rc.dy; dj[2] = rc.dz;
@@ -1657,7 +1671,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff_trip(ComputeLaunch a, DeviceT
                 for (int q = sh.pstart[lane]; q < sh.pstart[lane + 1]; ++q) {
                     ox -= sh.fs[q][0]; oy -= sh.fs[q][1]; oz -= sh.fs[q][2];
                 }
-                double *o = a.own + 3 * (size_t)(a0 + lane);
+                double *o = a.own + 3 * (size_t)cid;
                 o[0] = ox; o[1] = oy; o[2] = oz;
             }
             __syncthreads();

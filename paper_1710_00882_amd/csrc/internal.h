@@ -134,6 +134,10 @@ struct PackLaunch {
     const double *pos_build;    // n x 3 positions of the last build (stale check)
     double stale_sq;            // (skin / 2)^2
     int atoms_per_batch;        // B: centre atoms per batch (<= kWave), shared with the compute kernel
+    // one system: the order in which centre atoms are taken (batch slot s is
+    // atom order[s], a permutation of 0 .. n-1; the build's cell order), or
+    // null for atom order
+    const int *order;
     // batches of systems (null for one system): atom count, box of each atom's system
     const int *n_dev;
     const SysDesc *sys;
@@ -154,6 +158,7 @@ struct ComputeLaunch {
     long long *counters;        // grid x 2 (pairs, triplets)
     int atoms_per_batch;        // nominal atoms per batch (<= kWave)
     int plane_stride;           // atoms per force plane (n, or the batch capacity)
+    const int *order;           // one system: centre atom of each batch slot (as PackLaunch), or null
     // batches of systems (null for one system): atom count; per-atom energy
     // and virial (8 doubles per atom) in place of the per-workgroup partials
     const int *n_dev;
@@ -242,6 +247,9 @@ hipError_t launch_reverse_index(const int *ell, const int *row_count, int cap, i
 hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,
                             int *cell_of, int *rank_in_cell, int *cell_count, int *flags, int *types_out,
                             hipStream_t s);
+// Consecutive atoms (i, i + 1) in the same or adjacent cells, added into
+// *count: how coherent in space the caller's atom order is.
+hipError_t launch_order_locality(const int *cell_of, int n, const CellGrid &g, int *count, hipStream_t s);
 // Cell-order copies of the atoms (ids, FP64 positions, wrapped FP32
 // positions with the id in the fourth word).  Batches: dims and the
 // per-atom system set, n the capacity the grid is sized for.

@@ -617,6 +617,41 @@ hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntyp
     return hipGetLastError();
 }
 
+// How spatially coherent the caller's atom order is: the number of
+// consecutive atoms (i, i + 1) whose cells are the same or adjacent
+// (periodic), added into *count (one atomic per workgroup).
+__global__ void k_order_locality(const int *__restrict__ cell_of, int n, CellGrid g, int *count)
+{
+    __shared__ int part[256 / kWave];
+    int c = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i + 1 < n; i += gridDim.x * blockDim.x) {
+        const int a = cell_of[i], b = cell_of[i + 1];
+        const int az = a % g.nc[2], ay = (a / g.nc[2]) % g.nc[1], ax = a / (g.nc[2] * g.nc[1]);
+        const int bz = b % g.nc[2], by = (b / g.nc[2]) % g.nc[1], bx = b / (g.nc[2] * g.nc[1]);
+        auto near = [](int u, int v, int m) {
+            const int d = u > v ? u - v : v - u;
+            return d <= 1 || d == m - 1;
+        };
+        c += near(ax, bx, g.nc[0]) && near(ay, by, g.nc[1]) && near(az, bz, g.nc[2]);
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+    if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < (int)blockDim.x / kWave; ++w) t += part[w];
+        atomicAdd(count, t);
+    }
+}
+
+hipError_t launch_order_locality(const int *cell_of, int n, const CellGrid &g, int *count, hipStream_t s)
+{
+    const int grid = std::max(1, std::min(blocks_for(n, 256), 1024));
+    hipLaunchKernelGGL(k_order_locality, dim3(grid), dim3(256), 0, s, cell_of, n, g, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_bin_systems(const double *pos, const int *sys_of, const SysDesc *sys, const BatchDims *dims,
                               int max_atoms, int *cell_of, int *rank_in_cell, int *cell_count, hipStream_t s)
 {

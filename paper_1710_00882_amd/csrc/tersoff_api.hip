@@ -67,6 +67,7 @@ struct tersoff_ctx {
     int packing = 0;                // 0: separate packing kernel; 1: fused into the compute kernel where rows allow
     bool fused_ok = false;          // the resident list supports the fused packing (rows <= kFusedRowCap)
     bool rev_ready = false;         // rev holds the reverse row positions of the resident list
+    bool cell_order = false;        // centre atoms taken in the build's cell order (caller's order incoherent)
     int grid[kNumPrec][4] = {};   // [precision] x {pack, compute, fixup, fused compute}
 
     DevBuf<double> pos_build;
@@ -225,6 +226,13 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     pk.pos_build = c->pos_build.p;
     pk.stale_sq = 0.25 * c->skin * c->skin;
     pk.atoms_per_batch = c->atoms_per_batch;
+    // centre atoms in the build's cell order when the caller's order is not
+    // coherent in space: the atoms of a batch, and of the batches one XCD
+    // takes, then lie close together, so their neighbours' positions and
+    // kept lists are shared in the caches (an order that already is coherent,
+    // such as a lattice's, is kept: it packs a batch more tightly than the
+    // cell order's lines of cells)
+    pk.order = c->cell_order ? c->cell_atoms.p : nullptr;
 
     ComputeLaunch a{};
     a.types = c->types.p;
@@ -239,6 +247,7 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     a.counters = b.counters;
     a.atoms_per_batch = c->atoms_per_batch;
     a.plane_stride = c->n;
+    a.order = pk.order;
 
     // fused packing: the compute kernel packs the rows itself (no records,
     // kept lists or counts in memory); planes indexed by row position
@@ -639,7 +648,8 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, c->types.ensure(N));
 
     // misc: [0] compute flags, [1] longest row, [2] build flags, [3] dropped
-    // count, [4] rows left to the long-row search.  One host
+    // count, [4] rows left to the long-row search, [6] consecutive atoms in
+    // the same or adjacent cells.  One host
     // synchronisation at the end: a row longer than the capacity of the
     // attempt (known only from the scan) repeats it with the needed one.
     // The evaluation reads the row buffer itself (row i at i * cap); the
@@ -648,6 +658,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, hipMemsetAsync(c->cell_count.p, 0, sizeof(int) * ncell, s));
     HIP_TRY(c, launch_bin_atoms(pos, types, N, c->ntypes, g, c->cell_of.p, c->rank.p, c->cell_count.p,
                                 c->misc.p + 2, c->types.p, s));
+    HIP_TRY(c, launch_order_locality(c->cell_of.p, N, g, c->misc.p + 6, s));
     HIP_TRY(c, launch_exclusive_scan(c->cell_count.p, c->cell_start.p, (int)ncell, c->scan_tmp.p, nullptr, s));
     ScatterLaunch sca{};
     sca.pos = pos;
@@ -714,6 +725,9 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     // its neighbour's row; formed by the first fused evaluation of this list
     c->fused_ok = c->list_cap <= kFusedRowCap;
     c->rev_ready = false;
+    // the caller's order is kept when at least half of its consecutive atoms
+    // share or neighbour a cell
+    c->cell_order = 2LL * host[6] < (long long)N - 1;
 
     c->n = N;
     for (int a = 0; a < 3; ++a) c->box[a] = box[a];
