@@ -4,8 +4,9 @@ Only the tests, the smoke check and the CPU-baseline leg of the benchmark use
 this package.  The GPU library never imports, links or calls it, and it never
 imports the GPU library.
 
-``tersoff_oracle.c`` is the plain C implementation of Eq. (1)-(3) and
-Algorithm 1 (Section 2); ``brute.py`` is an independent numpy evaluation of
+``tersoff_oracle.c`` is the plain C implementation of Eq. (1)-(3) (Section
+2): the energy, and the forces as its gradient by the chain rule;
+``brute.py`` is an independent numpy evaluation of
 the energy with no neighbour list.  This module compiles the C file with gcc
 (once, on first use, or from ``build()``) and wraps it with ctypes.
 """

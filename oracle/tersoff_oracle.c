@@ -11,10 +11,8 @@
  *   Eq. (1)  E = 1/2 sum_i sum_{j != i, r_ij < R+D} f_C(r_ij) [f_R(r_ij) + b_ij f_A(r_ij)]
  *   Eq. (2)  b_ij = (1 + beta^eta zeta_ij^eta)^(-1/(2 eta))
  *   Eq. (3)  zeta_ij = sum_{k != i,j, r_ik < R+D} f_C(r_ik) g(theta_ijk) exp((lambda3 (r_ij - r_ik))^m)
- * and the forces F = -dE/dx in the loop order of Algorithm 1 (Section 2):
- * per pair (i,j) a first K loop accumulates zeta_ij, the pair term V and its
- * distance derivative are applied to F_i and F_j, and a second K loop
- * applies dV/dzeta * d zeta(i,j,k)/dx to F_i, F_j and F_k.
+ * and the forces F = -dE/dx by the chain rule through r_ij, zeta_ij and the
+ * r_ik and angles that zeta_ij depends on (see oracle_compute).
  *
  * Readings where the paper is silent (it omits "trivial definitions"):
  *  - the factor 1/2 in Eq. (1) (each unordered bond is visited twice);
@@ -241,11 +239,21 @@ static double zeta_term(const double *p, double rij, const double dij[3],
     return fc * g * e;
 }
 
-/* ----------------------------------------------------------- Algorithm 1 */
+/* ------------------------------------------------ energy and its gradient */
 
-/* Energy, forces and virial from a neighbour list, summing the contributions
- * of centre atoms i in [i0, i1).  forces (n x 3) and virial (6: xx yy zz xy
- * xz yz) are overwritten.  Returns 0, or -1 on a type out of range. */
+/* E of Eq. (1) and F = -dE/dx by the chain rule, centre by centre, summing
+ * the contributions of centre atoms i in [i0, i1).  For a centre i, the
+ * displacements of its list entries are formed once.  For each bond (i, j)
+ * within the cutoff of entry (t_i, t_j, t_j), the terms of zeta_ij (Eq. 3)
+ * over the third atoms k are formed together with their gradients with
+ * respect to x_j and x_k; b_ij (Eq. 2) and the bond energy
+ * V_ij = 1/2 f_C [f_R + b_ij f_A] follow, and dE/dx takes
+ *   dV/dr_ij u_ij + dV/dzeta_ij sum_k dzeta(i,j,k)/dx_j   on j,
+ *   dV/dzeta_ij dzeta(i,j,k)/dx_k                        on each k,
+ * and minus their sum on i (V depends on positions relative to x_i only).
+ * The virial sums r (x) F over these terms, r the vector from x_i.
+ * forces (n x 3) and virial (6: xx yy zz xy xz yz) are overwritten.
+ * Returns 0, -1 on a type out of range, -2 when out of memory. */
 int oracle_compute(int64_t n, const double *pos, const int32_t *types, const double *box,
                    const double *table, int32_t nt, const int64_t *offsets,
                    const int32_t *idx, int64_t i0, int64_t i1, int32_t nthreads,
@@ -255,6 +263,9 @@ int oracle_compute(int64_t n, const double *pos, const int32_t *types, const dou
         if (types[i] < 0 || types[i] >= nt) return -1;
     if (i0 < 0) i0 = 0;
     if (i1 > n) i1 = n;
+    int64_t maxrow = 1;
+    for (int64_t i = i0; i < i1; ++i)
+        if (offsets[i + 1] - offsets[i] > maxrow) maxrow = offsets[i + 1] - offsets[i];
     int nth = nthreads > 0 ? nthreads : 1;
 #ifdef _OPENMP
     if (nth > omp_get_max_threads()) nth = omp_get_max_threads();
@@ -263,7 +274,13 @@ int oracle_compute(int64_t n, const double *pos, const int32_t *types, const dou
 #endif
     if (nth > 64) nth = 64;
     double *fpriv = calloc((size_t)nth * (size_t)(3 * n > 0 ? 3 * n : 1), sizeof(double));
-    if (!fpriv) return -2;
+    /* per thread: each entry's displacement (3), r^2 and dE/dx_k (3) */
+    double *scratch = malloc((size_t)nth * (size_t)maxrow * 7 * sizeof(double));
+    if (!fpriv || !scratch) {
+        free(fpriv);
+        free(scratch);
+        return -2;
+    }
     double epriv[64] = {0}, wpriv[64][6];
     memset(wpriv, 0, sizeof(wpriv));
 
@@ -277,92 +294,91 @@ int oracle_compute(int64_t n, const double *pos, const int32_t *types, const dou
         int tid = 0;
 #endif
         double *F = fpriv + (size_t)tid * 3 * (size_t)n;
+        double *dsp = scratch + (size_t)tid * (size_t)maxrow * 7;   /* displacements */
+        double *rsq = dsp + 3 * maxrow;                               /* r^2 */
+        double *gk = rsq + maxrow;                                    /* dE/dx_k of one bond */
         double E = 0.0, W[6] = {0, 0, 0, 0, 0, 0};
 #ifdef _OPENMP
 #pragma omp for schedule(dynamic, 256)
 #endif
         for (int64_t i = i0; i < i1; ++i) {
-            int ti = types[i];
-            for (int64_t jj = offsets[i]; jj < offsets[i + 1]; ++jj) {
-                int64_t j = idx[jj];
-                int tj = types[j];
+            const int ti = types[i];
+            const int64_t e0 = offsets[i], m = offsets[i + 1] - offsets[i];
+            for (int64_t q = 0; q < m; ++q) {
+                min_image(pos + 3 * i, pos + 3 * idx[e0 + q], box, dsp + 3 * q);
+                rsq[q] = norm2(dsp + 3 * q);
+            }
+            for (int64_t jq = 0; jq < m; ++jq) {
+                const int64_t j = idx[e0 + jq];
+                const int tj = types[j];
                 const double *pij = table + (size_t)((ti * nt + tj) * nt + tj) * ONP;
-                double dij[3];
-                min_image(pos + 3 * i, pos + 3 * j, box, dij);
-                double rsq = norm2(dij);
-                double cut = pij[OR] + pij[ODC];
-                if (!(rsq < cut * cut)) continue;
-                double rij = sqrt(rsq);
+                const double cut = pij[OR] + pij[ODC];
+                if (!(rsq[jq] < cut * cut)) continue;
+                const double *dij = dsp + 3 * jq;
+                const double rij = sqrt(rsq[jq]);
 
-                /* first K loop: zeta_ij */
-                double zeta = 0.0;
-                for (int64_t kk = offsets[i]; kk < offsets[i + 1]; ++kk) {
-                    int64_t k = idx[kk];
-                    if (k == j) continue;
-                    const double *pk = table + (size_t)((ti * nt + tj) * nt + types[k]) * ONP;
-                    double dik[3];
-                    min_image(pos + 3 * i, pos + 3 * k, box, dik);
-                    double rsqk = norm2(dik);
-                    double cutk = pk[OR] + pk[ODC];
-                    if (!(rsqk < cutk * cutk)) continue;
-                    zeta += zeta_term(pk, rij, dij, sqrt(rsqk), dik, NULL, NULL);
+                /* zeta_ij, sum_k dzeta/dx_j, and each dzeta/dx_k */
+                double zeta = 0.0, gj_sum[3] = {0, 0, 0};
+                for (int64_t kq = 0; kq < m; ++kq) {
+                    gk[3 * kq] = gk[3 * kq + 1] = gk[3 * kq + 2] = 0.0;
+                    if (kq == jq) continue;
+                    const double *pk = table + (size_t)((ti * nt + tj) * nt + types[idx[e0 + kq]]) * ONP;
+                    const double cutk = pk[OR] + pk[ODC];
+                    if (!(rsq[kq] < cutk * cutk)) continue;
+                    double gj[3];
+                    zeta += zeta_term(pk, rij, dij, sqrt(rsq[kq]), dsp + 3 * kq, gj, gk + 3 * kq);
+                    for (int a = 0; a < 3; ++a) gj_sum[a] += gj[a];
                 }
 
-                /* V(i,j,zeta) with the 1/2 of Eq. (1) */
+                /* Eq. (1)-(2): the bond's energy and its derivatives */
                 double fc, dfc;
                 cutoff_fn(rij, pij, &fc, &dfc);
-                double fr = pij[OA] * exp(-pij[OL1] * rij), dfr = -pij[OL1] * fr;
-                double fa = -pij[OB] * exp(-pij[OL2] * rij), dfa = -pij[OL2] * fa;
-                double beta = pij[OBETA], eta = pij[OETA];
-                double x = pow(beta * zeta, eta);
-                double b = pow(1.0 + x, -1.0 / (2.0 * eta));
+                const double fr = pij[OA] * exp(-pij[OL1] * rij), dfr = -pij[OL1] * fr;
+                const double fa = -pij[OB] * exp(-pij[OL2] * rij), dfa = -pij[OL2] * fa;
+                const double beta = pij[OBETA], eta = pij[OETA];
+                const double x = pow(beta * zeta, eta);
+                const double b = pow(1.0 + x, -1.0 / (2.0 * eta));
                 double db = 0.0;
                 if (zeta > 0.0)
                     db = -0.5 * pow(1.0 + x, -1.0 / (2.0 * eta) - 1.0) * pow(beta, eta) * pow(zeta, eta - 1.0);
                 E += 0.5 * fc * (fr + b * fa);
-                double dVdr = 0.5 * (dfc * (fr + b * fa) + fc * (dfr + b * dfa));
-                for (int a = 0; a < 3; ++a) {
-                    double f = dVdr * dij[a] / rij;   /* dV/dx_j */
-                    F[3 * j + a] -= f;
-                    F[3 * i + a] += f;
-                }
-                W[0] -= dij[0] * dVdr * dij[0] / rij;
-                W[1] -= dij[1] * dVdr * dij[1] / rij;
-                W[2] -= dij[2] * dVdr * dij[2] / rij;
-                W[3] -= dij[0] * dVdr * dij[1] / rij;
-                W[4] -= dij[0] * dVdr * dij[2] / rij;
-                W[5] -= dij[1] * dVdr * dij[2] / rij;
-                double dzeta = 0.5 * fc * fa * db;   /* dV/dzeta */
+                const double dVdr = 0.5 * (dfc * (fr + b * fa) + fc * (dfr + b * dfa));
+                const double dVdz = 0.5 * fc * fa * db;
 
-                /* second K loop: dzeta * d zeta(i,j,k)/dx */
-                if (dzeta != 0.0) {
-                    for (int64_t kk = offsets[i]; kk < offsets[i + 1]; ++kk) {
-                        int64_t k = idx[kk];
-                        if (k == j) continue;
-                        const double *pk = table + (size_t)((ti * nt + tj) * nt + types[k]) * ONP;
-                        double dik[3];
-                        min_image(pos + 3 * i, pos + 3 * k, box, dik);
-                        double rsqk = norm2(dik);
-                        double cutk = pk[OR] + pk[ODC];
-                        if (!(rsqk < cutk * cutk)) continue;
-                        double gj[3], gk[3];
-                        zeta_term(pk, rij, dij, sqrt(rsqk), dik, gj, gk);
-                        double fj[3], fk[3];
+                /* dE/dx on j and on each k; minus their sum on i */
+                double dEj[3], dEi[3];
+                for (int a = 0; a < 3; ++a) {
+                    dEj[a] = dVdr * dij[a] / rij + dVdz * gj_sum[a];
+                    dEi[a] = -dEj[a];
+                    F[3 * j + a] -= dEj[a];
+                }
+                W[0] -= dij[0] * dEj[0];
+                W[1] -= dij[1] * dEj[1];
+                W[2] -= dij[2] * dEj[2];
+                W[3] -= dij[0] * dEj[1];
+                W[4] -= dij[0] * dEj[2];
+                W[5] -= dij[1] * dEj[2];
+                if (dVdz != 0.0) {
+                    for (int64_t kq = 0; kq < m; ++kq) {
+                        const double *g = gk + 3 * kq;
+                        if (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0) continue;
+                        const int64_t k = idx[e0 + kq];
+                        const double *dik = dsp + 3 * kq;
+                        double dEk[3];
                         for (int a = 0; a < 3; ++a) {
-                            fj[a] = -dzeta * gj[a];
-                            fk[a] = -dzeta * gk[a];
-                            F[3 * j + a] += fj[a];
-                            F[3 * k + a] += fk[a];
-                            F[3 * i + a] -= fj[a] + fk[a];
+                            dEk[a] = dVdz * g[a];
+                            dEi[a] -= dEk[a];
+                            F[3 * k + a] -= dEk[a];
                         }
-                        W[0] += dij[0] * fj[0] + dik[0] * fk[0];
-                        W[1] += dij[1] * fj[1] + dik[1] * fk[1];
-                        W[2] += dij[2] * fj[2] + dik[2] * fk[2];
-                        W[3] += dij[0] * fj[1] + dik[0] * fk[1];
-                        W[4] += dij[0] * fj[2] + dik[0] * fk[2];
-                        W[5] += dij[1] * fj[2] + dik[1] * fk[2];
+                        W[0] -= dik[0] * dEk[0];
+                        W[1] -= dik[1] * dEk[1];
+                        W[2] -= dik[2] * dEk[2];
+                        W[3] -= dik[0] * dEk[1];
+                        W[4] -= dik[0] * dEk[2];
+                        W[5] -= dik[1] * dEk[2];
                     }
                 }
+                for (int a = 0; a < 3; ++a) F[3 * i + a] -= dEi[a];
             }
         }
         epriv[tid] = E;
@@ -382,6 +398,7 @@ int oracle_compute(int64_t n, const double *pos, const int32_t *types, const dou
     }
     *energy = E;
     free(fpriv);
+    free(scratch);
     return 0;
 }
 
