@@ -485,3 +485,27 @@ def test_overflow_reported_both_packings(natoms):
             assert m.check_status() == -4
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["si512", "two_species"])
+def test_atom_order_does_not_matter(case, precision):
+    """The same configuration with its atoms in a random order (the kernels
+    then take the centre atoms in the build's cell order instead of the
+    caller's): the same energy and virial, and the permuted forces, to the
+    stated tolerances; both orders at parity with the oracle."""
+    from paper_1710_00882_amd import workloads as Wl
+    sysf, tabf = CASES[case]
+    s, table = sysf(), tabf()
+    perm = np.random.default_rng(77).permutation(s.n)
+    sp = Wl.System(s.pos[perm].copy(), s.types[perm].copy(), s.box.copy())
+    Eo, Fo, Vo, _, _ = oracle_eval(s, table)
+    E, F, V, m = gpu_eval(s, table, precision)
+    m.close()
+    Ep, Fp, Vp, mp = gpu_eval(sp, table, precision)
+    mp.close()
+    assert_parity(E, F, V, Eo, Fo, Vo, s.n, precision, f"{case} given order")
+    assert_parity(Ep, Fp, Vp, Eo, Fo[perm], Vo, s.n, precision, f"{case} permuted")
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert abs(Ep - E) <= tol * abs(E)
+    assert np.abs(Fp - F[perm]).max() <= tol * max(np.abs(F).max(), 1.0) * (1 if precision == "fp64" else 10)
