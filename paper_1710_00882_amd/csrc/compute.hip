@@ -429,16 +429,21 @@ __device__ __forceinline__ int kept_position(const int *__restrict__ kept, const
     const int4 *kb = reinterpret_cast<const int4 *>(kept + (size_t)m * kKeptFast);
     const int4 v0 = kb[0], v1 = kb[1];
     const unsigned w = (unsigned)who;
-    const int v[kKeptFast] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-    int pos = 0;
-    bool hit = false;
+    const unsigned v[kKeptFast] = {(unsigned)v0.x, (unsigned)v0.y, (unsigned)v0.z, (unsigned)v0.w,
+                                   (unsigned)v1.x, (unsigned)v1.y, (unsigned)v1.z, (unsigned)v1.w};
+    // entries below who: the sign bit of min(v, 2^31 - 1) - who (indices < 2^24;
+    // the -1 end markers clamp to 2^31 - 1, above every index); who is in the
+    // list when the smallest v xor who is 0
+    unsigned b[kKeptFast], x[kKeptFast];
 #pragma unroll
     for (int q = 0; q < kKeptFast; ++q) {
-        pos += (unsigned)v[q] < w ? 1 : 0;
-        hit |= v[q] == who;
+        b[q] = (min(v[q], 0x7fffffffu) - w) >> 31;
+        x[q] = v[q] ^ w;
     }
+    const int pos = (int)(b[0] + b[1] + b[2] + b[3] + b[4] + b[5] + b[6] + b[7]);
+    const unsigned mn = min(min(min(x[0], x[1]), min(x[2], x[3])), min(min(x[4], x[5]), min(x[6], x[7])));
     absent = false;
-    if (hit) return pos;
+    if (mn == 0u) return pos;
     if (v1.w < 0 || pos < kKeptFast) {
         absent = true;   // the list ended, or passed who
         return -1;
@@ -447,9 +452,9 @@ __device__ __forceinline__ int kept_position(const int *__restrict__ kept, const
     const int *km = kept_more + (size_t)m * kRecCap;
 #pragma unroll 1
     for (int q = kKeptFast; q < kRecCap; ++q) {
-        const int x = km[q];
-        if (x == who) return q;
-        if (x < 0 || x > who) {
+        const int xx = km[q];
+        if (xx == who) return q;
+        if (xx < 0 || xx > who) {
             absent = true;
             return -1;
         }
