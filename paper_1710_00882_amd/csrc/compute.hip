@@ -524,7 +524,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
         v.rc = 0;
         if (b < items.end && lane < min(B, n - b * B)) {
             const int slot = b * B + lane;
-            const size_t i = (size_t)((!BATCHED && a.order) ? a.order[slot] : slot);
+            const size_t i = (size_t)slot;
             v.id = (int)i;
             v.x = a.pos[3 * i]; v.y = a.pos[3 * i + 1]; v.z = a.pos[3 * i + 2];
             v.t = ONE ? 0 : a.types[i];
@@ -982,7 +982,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff(ComputeLaunch a, DeviceTable 
         f.id = 0;
         if (lane < f.a_end - f.a0) {
             const int slot = f.a0 + lane;
-            f.id = (!BATCHED && a.order) ? a.order[slot] : slot;
+            f.id = slot;
             f.p = a.pcount[f.id];
             f.t = ONE ? 0 : a.types[f.id];
         }
@@ -1545,7 +1545,7 @@ __global__ __launch_bounds__(kWave) void k_tersoff_trip(ComputeLaunch a, DeviceT
             const int nb = g_end - a0;
             int p = 0, tiv = 0, cid = 0;
             if (lane < nb) {
-                cid = a.order ? a.order[a0 + lane] : a0 + lane;
+                cid = a0 + lane;
                 p = a.pcount[cid];
                 tiv = nt == 1 ? 0 : a.types[cid];
             }
@@ -1823,7 +1823,9 @@ __global__ void k_reduce_systems(const SysDesc *__restrict__ sys, const BatchDim
 }
 
 // F_m = (terms of centre m) + the force each centre i that keeps m put into
-// plane k of m, k = rank of i among m's kept neighbours (k < pcount[m]).
+// plane k of m, k = rank of i among m's kept neighbours (k < pcount[m]),
+// stored at forces[perm[m]] (perm: the caller's index of each atom of the
+// internal numbering; null: the same numbering).
 // One thread per atom; each plane read is coalesced across the wavefront.
 // Also empties the dropped-atom list for the next evaluation when
 // drop_count is given (every kernel reading it has run by now), and, when
@@ -1835,7 +1837,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_forces(const int *__r
                                                                   const T *__restrict__ planes,
                                                                   const double *__restrict__ own, int n,
                                                                   const int *__restrict__ n_dev, int plane_stride,
-                                                                  double *__restrict__ forces, int *drop_count,
+                                                                  double *__restrict__ forces,
+                                                                  const int *__restrict__ perm, int *drop_count,
                                                                   FinalizeArgs fin)
 {
     if (fin.partials && blockIdx.x == 0) {
@@ -1866,21 +1869,22 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_forces(const int *__r
             fz += (double)v[u][2];
         }
     }
-    forces[3 * (size_t)m] = fx;
-    forces[3 * (size_t)m + 1] = fy;
-    forces[3 * (size_t)m + 2] = fz;
+    const size_t o = perm ? (size_t)perm[m] : (size_t)m;
+    forces[3 * o] = fx;
+    forces[3 * o + 1] = fy;
+    forces[3 * o + 2] = fz;
 }
 
 // Fused packing: F_m = (terms of centre m) + plane e of m for every row
 // position e whose centre keeps m (kmask[m]), in increasing e; the centre at
 // row position e of m wrote its force on m there (or zero when m was beyond
-// its slots).  Partials as k_gather_forces.
+// its slots).  Partials and perm as k_gather_forces.
 template <typename T>
 __global__ __launch_bounds__(kGatherThreads) void k_gather_rows(const unsigned long long *__restrict__ kmask,
                                                                 const T *__restrict__ planes,
                                                                 const double *__restrict__ own, int n,
                                                                 int plane_stride, double *__restrict__ forces,
-                                                                FinalizeArgs fin)
+                                                                const int *__restrict__ perm, FinalizeArgs fin)
 {
     if (fin.partials && blockIdx.x == 0) {
         finalize_sums<kGatherThreads>(fin.partials, fin.counters, fin.grid, fin.out, fin.counts, fin.flags);
@@ -1918,9 +1922,10 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_rows(const unsigned l
             fz += (double)v[u][2];
         }
     }
-    forces[3 * (size_t)m] = fx;
-    forces[3 * (size_t)m + 1] = fy;
-    forces[3 * (size_t)m + 2] = fz;
+    const size_t o = perm ? (size_t)perm[m] : (size_t)m;
+    forces[3 * o] = fx;
+    forces[3 * o + 1] = fy;
+    forces[3 * o + 2] = fz;
 }
 
 // One thread per row entry (i, e): the position of i in the row of its
@@ -2159,31 +2164,32 @@ hipError_t launch_reduce_systems(const SysDesc *sys, const BatchDims *dims, int 
 }
 
 hipError_t launch_gather_forces(const int *pcount, int prec, const void *planes, const double *own, int n,
-                                const int *n_dev, int plane_stride, double *forces, int *drop_count,
-                                const FinalizeArgs &fin, hipStream_t s)
+                                const int *n_dev, int plane_stride, double *forces, const int *perm,
+                                int *drop_count, const FinalizeArgs &fin, hipStream_t s)
 {
     const int blocks = std::max(1, (n + kGatherThreads - 1) / kGatherThreads) + (fin.partials ? 1 : 0);
     const dim3 G(blocks), W(kGatherThreads);
     if (prec != kPrecFP64)
         hipLaunchKernelGGL(k_gather_forces<float>, G, W, 0, s, pcount, static_cast<const float *>(planes), own, n,
-                           n_dev, plane_stride, forces, drop_count, fin);
+                           n_dev, plane_stride, forces, perm, drop_count, fin);
     else
         hipLaunchKernelGGL(k_gather_forces<double>, G, W, 0, s, pcount, static_cast<const double *>(planes), own,
-                           n, n_dev, plane_stride, forces, drop_count, fin);
+                           n, n_dev, plane_stride, forces, perm, drop_count, fin);
     return hipGetLastError();
 }
 
 hipError_t launch_gather_rows(const unsigned long long *kmask, int prec, const void *planes, const double *own,
-                              int n, int plane_stride, double *forces, const FinalizeArgs &fin, hipStream_t s)
+                              int n, int plane_stride, double *forces, const int *perm, const FinalizeArgs &fin,
+                              hipStream_t s)
 {
     const int blocks = std::max(1, (n + kGatherThreads - 1) / kGatherThreads) + (fin.partials ? 1 : 0);
     const dim3 G(blocks), W(kGatherThreads);
     if (prec != kPrecFP64)
         hipLaunchKernelGGL(k_gather_rows<float>, G, W, 0, s, kmask, static_cast<const float *>(planes), own, n,
-                           plane_stride, forces, fin);
+                           plane_stride, forces, perm, fin);
     else
         hipLaunchKernelGGL(k_gather_rows<double>, G, W, 0, s, kmask, static_cast<const double *>(planes), own, n,
-                           plane_stride, forces, fin);
+                           plane_stride, forces, perm, fin);
     return hipGetLastError();
 }
 
@@ -2193,6 +2199,46 @@ hipError_t launch_reverse_index(const int *ell, const int *row_count, int cap, i
     const long long total = (long long)n * cap;
     const int grid = (int)std::max(1LL, std::min((total + 255) / 256, 8192LL));
     hipLaunchKernelGGL(k_reverse_index, dim3(grid), dim3(256), 0, s, ell, row_count, cap, n, rev, flags);
+    return hipGetLastError();
+}
+
+// Positions in the internal numbering: posp[t] = pos[perm[t]]; and back:
+// out[perm[t]] = in[t] (three doubles per atom each).
+__global__ void k_unpermute3(const double *__restrict__ in, const int *__restrict__ perm, int n,
+                             double *__restrict__ out)
+{
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const size_t i = (size_t)perm[t];
+        out[3 * i] = in[3 * (size_t)t];
+        out[3 * i + 1] = in[3 * (size_t)t + 1];
+        out[3 * i + 2] = in[3 * (size_t)t + 2];
+    }
+}
+
+hipError_t launch_unpermute3(const double *in, const int *perm, int n, double *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int grid = std::max(1, std::min((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_unpermute3, dim3(grid), dim3(256), 0, s, in, perm, n, out);
+    return hipGetLastError();
+}
+
+__global__ void k_permute_pos(const double *__restrict__ pos, const int *__restrict__ perm, int n,
+                              double *__restrict__ posp)
+{
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const size_t i = (size_t)perm[t];
+        posp[3 * (size_t)t] = pos[3 * i];
+        posp[3 * (size_t)t + 1] = pos[3 * i + 1];
+        posp[3 * (size_t)t + 2] = pos[3 * i + 2];
+    }
+}
+
+hipError_t launch_permute_pos(const double *pos, const int *perm, int n, double *posp, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int grid = std::max(1, std::min((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_permute_pos, dim3(grid), dim3(256), 0, s, pos, perm, n, posp);
     return hipGetLastError();
 }
 

@@ -134,10 +134,6 @@ struct PackLaunch {
     const double *pos_build;    // n x 3 positions of the last build (stale check)
     double stale_sq;            // (skin / 2)^2
     int atoms_per_batch;        // B: centre atoms per batch (<= kWave), shared with the compute kernel
-    // one system: the order in which centre atoms are taken (batch slot s is
-    // atom order[s], a permutation of 0 .. n-1; the build's cell order), or
-    // null for atom order
-    const int *order;
     // batches of systems (null for one system): atom count, box of each atom's system
     const int *n_dev;
     const SysDesc *sys;
@@ -158,7 +154,6 @@ struct ComputeLaunch {
     long long *counters;        // grid x 2 (pairs, triplets)
     int atoms_per_batch;        // nominal atoms per batch (<= kWave)
     int plane_stride;           // atoms per force plane (n, or the batch capacity)
-    const int *order;           // one system: centre atom of each batch slot (as PackLaunch), or null
     // batches of systems (null for one system): atom count; per-atom energy
     // and virial (8 doubles per atom) in place of the per-workgroup partials
     const int *n_dev;
@@ -223,9 +218,10 @@ constexpr int kGatherThreads = 256;
 // drop_count, when not null, is reset to 0 (the dropped-atom list is empty
 // for the next evaluation); fin.partials, when not null, adds the sum of the
 // partials (one extra workgroup).
+// perm, when not null: forces of atom m stored at the caller's index perm[m].
 hipError_t launch_gather_forces(const int *pcount, int prec, const void *planes, const double *own, int n,
-                                const int *n_dev, int plane_stride, double *forces, int *drop_count,
-                                const FinalizeArgs &fin, hipStream_t s);
+                                const int *n_dev, int plane_stride, double *forces, const int *perm,
+                                int *drop_count, const FinalizeArgs &fin, hipStream_t s);
 // Per-system sums of the per-atom energy / virial of a batch and status bits
 // (1: a neighbour row over capacity, 2: an atom over the record capacity):
 // out[8 s + c] = E, Wxx, Wyy, Wzz, Wxy, Wxz, Wyz, status.
@@ -236,7 +232,11 @@ hipError_t launch_fill_zero_int(int *p, size_t count, hipStream_t s);
 // Fused packing: the force on each atom m from the planes its row's kept
 // centres wrote (kmask[m], in row order) plus its own; fin as above.
 hipError_t launch_gather_rows(const unsigned long long *kmask, int prec, const void *planes, const double *own,
-                              int n, int plane_stride, double *forces, const FinalizeArgs &fin, hipStream_t s);
+                              int n, int plane_stride, double *forces, const int *perm, const FinalizeArgs &fin,
+                              hipStream_t s);
+// posp[t] = pos[perm[t]]; out[perm[t]] = in[t] (n atoms, 3 doubles each).
+hipError_t launch_permute_pos(const double *pos, const int *perm, int n, double *posp, hipStream_t s);
+hipError_t launch_unpermute3(const double *in, const int *perm, int n, double *out, hipStream_t s);
 // rev[i cap + e] = position of i in the row of its neighbour ell[i cap + e],
 // for the rows of n atoms (row_count, at most cap <= 256 entries each,
 // sorted); kFlagAsym into *flags when a neighbour's row lacks i.
@@ -250,6 +250,13 @@ hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntyp
 // Consecutive atoms (i, i + 1) in the same or adjacent cells, added into
 // *count: how coherent in space the caller's atom order is.
 hipError_t launch_order_locality(const int *cell_of, int n, const CellGrid &g, int *count, hipStream_t s);
+// The resident list in the internal numbering (atom = its cell-order slot):
+// row t of ell_s / row_count_s is the row of atom cell_atoms[t] with its
+// neighbours' slots in ascending order, types_s[t] its type; inv (n ints)
+// receives each atom's slot.  Rows at stride cap.
+hipError_t launch_renumber_rows(const int *ell, const int *row_count, int cap, const int *cell_atoms,
+                                const int *types, int n, int *inv, int *ell_s, int *row_count_s, int *types_s,
+                                hipStream_t s);
 // Cell-order copies of the atoms (ids, FP64 positions, wrapped FP32
 // positions with the id in the fourth word).  Batches: dims and the
 // per-atom system set, n the capacity the grid is sized for.

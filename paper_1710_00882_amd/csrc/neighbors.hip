@@ -652,6 +652,60 @@ hipError_t launch_order_locality(const int *cell_of, int n, const CellGrid &g, i
     return hipGetLastError();
 }
 
+// slot of each atom: inv[cell_atoms[t]] = t
+__global__ void k_slot_inverse(const int *__restrict__ cell_atoms, int n, int *__restrict__ inv)
+{
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) inv[cell_atoms[t]] = t;
+}
+
+// Row t of the renumbered list: the row of atom cell_atoms[t] with each
+// neighbour named by its slot, in ascending order (rows of up to kLRow
+// entries sorted in registers; a longer row places each entry by the count
+// of entries below it -- slots are distinct); the type of slot t.
+__global__ __launch_bounds__(256) void k_renumber_rows(const int *__restrict__ ell, const int *__restrict__ row_count,
+                                                       int cap, const int *__restrict__ cell_atoms,
+                                                       const int *__restrict__ inv, const int *__restrict__ types,
+                                                       int n, int *__restrict__ ell_s, int *__restrict__ row_count_s,
+                                                       int *__restrict__ types_s)
+{
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const int i = cell_atoms[t];
+        const int rc = row_count[i];
+        row_count_s[t] = rc;
+        types_s[t] = types[i];
+        const int *row = ell + (size_t)i * cap;
+        int *out = ell_s + (size_t)t * cap;
+        if (rc <= kLRow) {
+            int v[kLRow];
+#pragma unroll
+            for (int k = 0; k < kLRow; ++k) v[k] = k < rc ? inv[row[k]] : INT_MAX;
+            bitonic32(v);
+#pragma unroll
+            for (int k = 0; k < kLRow; ++k)
+                if (k < rc) out[k] = v[k];
+        } else {
+            for (int e = 0; e < rc; ++e) {
+                const int u = inv[row[e]];
+                int below = 0;
+                for (int f = 0; f < rc; ++f) below += inv[row[f]] < u ? 1 : 0;
+                out[below] = u;
+            }
+        }
+    }
+}
+
+hipError_t launch_renumber_rows(const int *ell, const int *row_count, int cap, const int *cell_atoms,
+                                const int *types, int n, int *inv, int *ell_s, int *row_count_s, int *types_s,
+                                hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int grid = std::max(1, std::min(blocks_for(n, 256), 4096));
+    hipLaunchKernelGGL(k_slot_inverse, dim3(grid), dim3(256), 0, s, cell_atoms, n, inv);
+    hipLaunchKernelGGL(k_renumber_rows, dim3(grid), dim3(256), 0, s, ell, row_count, cap, cell_atoms, inv, types, n,
+                       ell_s, row_count_s, types_s);
+    return hipGetLastError();
+}
+
 hipError_t launch_bin_systems(const double *pos, const int *sys_of, const SysDesc *sys, const BatchDims *dims,
                               int max_atoms, int *cell_of, int *rank_in_cell, int *cell_count, hipStream_t s)
 {

@@ -462,7 +462,7 @@ hipError_t enqueue_batch(Server &S, Lane &L, int prec)
     SRV_TRY(launch_fixup_dropped(L.ell.p, S.cap, L.row_count.p, L.kept.p, pk.kept_more, L.drop_list.p,
                                  L.ctl.p + 1, S.max_atoms, prec, L.planes.p, s));
     SRV_TRY(launch_gather_forces(L.pcount.p, prec, L.planes.p, L.own.p, S.max_atoms, n_dev, S.max_atoms, L.forces.p,
-                                 nullptr, FinalizeArgs{}, s));
+                                 nullptr, nullptr, FinalizeArgs{}, s));
     SRV_TRY(launch_reduce_systems(L.desc.p, L.dims.p, S.max_sys, L.eatom.p, L.drop_list.p, L.ctl.p + 1,
                                   L.ctl.p + 3, L.out.p, s));
     return hipSuccess;

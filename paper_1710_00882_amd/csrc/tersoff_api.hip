@@ -67,7 +67,9 @@ struct tersoff_ctx {
     int packing = 0;                // 0: separate packing kernel; 1: fused into the compute kernel where rows allow
     bool fused_ok = false;          // the resident list supports the fused packing (rows <= kFusedRowCap)
     bool rev_ready = false;         // rev holds the reverse row positions of the resident list
-    bool cell_order = false;        // centre atoms taken in the build's cell order (caller's order incoherent)
+    bool cell_order = false;        // the caller's order is incoherent in space: atoms renumbered in the
+                                    // build's cell order (ell_s, row_count_s, types_s) or, in the comparison
+                                    // modes, centre atoms taken in that order
     int grid[kNumPrec][4] = {};   // [precision] x {pack, compute, fixup, fused compute}
 
     DevBuf<double> pos_build;
@@ -80,6 +82,8 @@ struct tersoff_ctx {
     DevBuf<float4> cell_posf;
     DevBuf<int> long_rows;
     DevBuf<int> ell, row_count, scan_tmp, misc;   // misc: [0] flags, [1] max row, [2] check flags
+    DevBuf<int> ell_s, row_count_s, types_s, slot_of;   // the list in the internal numbering (cell_order)
+    DevBuf<double> pos_s;                               // positions in the internal numbering (per evaluation)
     DevBuf<unsigned char> rev;                     // reverse row positions (fused packing)
     DevBuf<unsigned long long> kmask;              // kept row positions per atom (fused packing)
     DevBuf<double> partials, force_scratch;
@@ -195,6 +199,7 @@ struct EvalBuffers {
     double *partials;    // 8 x compute grid
     long long *counters; // 2 x compute grid
     unsigned long long *kmask;   // n, or null: no fused packing (records, kept lists, pcount used instead)
+    double *pos_s;       // 3 n: positions in the internal numbering (used when cell_order)
 };
 
 // Packing, compute, dropped-atom fixup and force gather of one evaluation on
@@ -203,11 +208,26 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
                       const EvalBuffers &b, bool profile)
 {
     const int *grid = c->grid[prec];
+    // internal numbering: when the caller's order is incoherent in space,
+    // every atom is named by its slot in the build's cell order -- positions
+    // permuted in, the build's renumbered rows, types and positions
+    // (cell_pos), forces stored back at the caller's indices by the gather
+    // (the atomic scatter: summed in cell order, then moved) -- so that the
+    // atoms of a batch, their neighbours, kept lists and force planes lie
+    // together in memory.  An order that already is coherent, such as a
+    // lattice's, is kept: it packs a batch more tightly than the cell
+    // order's lines of cells.
+    const bool slots = c->cell_order;
+    const int *perm = slots ? c->cell_atoms.p : nullptr;
+    const int *types = slots ? c->types_s.p : c->types.p;
+    const int *ell = slots ? c->ell_s.p : c->ell.p;
+    const int *row_count = slots ? c->row_count_s.p : c->row_count.p;
+    const double *pos_build = slots ? c->cell_pos.p : c->pos_build.p;
     PackLaunch pk{};
-    pk.pos = pos;
-    pk.types = c->types.p;
-    pk.row_count = c->row_count.p;
-    pk.ell = c->ell.p;
+    pk.pos = slots ? b.pos_s : pos;
+    pk.types = types;
+    pk.row_count = row_count;
+    pk.ell = ell;
     pk.cap = c->list_cap;
     pk.n = c->n;
     for (int d = 0; d < 3; ++d) {
@@ -223,19 +243,12 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     pk.flags = c->misc.p;
     pk.drop_list = b.drop_list;
     pk.drop_count = c->misc.p + 3;
-    pk.pos_build = c->pos_build.p;
+    pk.pos_build = pos_build;
     pk.stale_sq = 0.25 * c->skin * c->skin;
     pk.atoms_per_batch = c->atoms_per_batch;
-    // centre atoms in the build's cell order when the caller's order is not
-    // coherent in space: the atoms of a batch, and of the batches one XCD
-    // takes, then lie close together, so their neighbours' positions and
-    // kept lists are shared in the caches (an order that already is coherent,
-    // such as a lattice's, is kept: it packs a batch more tightly than the
-    // cell order's lines of cells)
-    pk.order = c->cell_order ? c->cell_atoms.p : nullptr;
 
     ComputeLaunch a{};
-    a.types = c->types.p;
+    a.types = types;
     a.recs = b.recs;
     a.rlo = pk.rlo;
     a.pcount = b.pcount;
@@ -247,22 +260,21 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     a.counters = b.counters;
     a.atoms_per_batch = c->atoms_per_batch;
     a.plane_stride = c->n;
-    a.order = pk.order;
 
     // fused packing: the compute kernel packs the rows itself (no records,
     // kept lists or counts in memory); planes indexed by row position
     const bool fused = b.kmask && c->fused_ok && c->packing == 1 && c->mapping == 0 && c->force_sum == 0;
     if (fused) {
         if (!c->rev_ready) {
-            HIP_TRY(c, launch_reverse_index(c->ell.p, c->row_count.p, c->list_cap, c->n, c->rev.p, c->misc.p, s));
+            HIP_TRY(c, launch_reverse_index(ell, row_count, c->list_cap, c->n, c->rev.p, c->misc.p, s));
             c->rev_ready = true;
         }
-        a.rows = c->ell.p;
+        a.rows = ell;
         a.rev = c->rev.p;
-        a.row_count = c->row_count.p;
+        a.row_count = row_count;
         a.cap = c->list_cap;
-        a.pos = pos;
-        a.pos_build = c->pos_build.p;
+        a.pos = pk.pos;
+        a.pos_build = pos_build;
         for (int d = 0; d < 3; ++d) {
             a.L[d] = pk.L[d];
             a.invL[d] = pk.invL[d];
@@ -273,9 +285,11 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     }
 
     // atomic scatter (comparison point): forces summed with FP64 atomics
-    // into the zeroed output; no planes, no gather, only the partial sums
+    // into the zeroed output (in the internal numbering: into the unused
+    // plane buffer, then moved to the caller's indices); no planes, no
+    // gather, only the partial sums
     const bool atomic = c->force_sum == 1;
-    if (atomic) a.forces_atomic = f;
+    if (atomic) a.forces_atomic = slots ? b.planes : f;
 
     // event pairs (profiling only): pack (with the zeroing of the forces in
     // the atomic scatter; none with the fused packing), main kernel, fixup +
@@ -284,7 +298,8 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     if (profile)
         for (int q = fused ? 2 : 0; q < 6; ++q) HIP_TRY(c, take_event(c, &ev[q]));
     if (ev[0]) HIP_TRY(c, hipEventRecord(ev[0], s));
-    if (atomic) HIP_TRY(c, launch_fill_zero(f, 3 * (size_t)c->n, s));
+    if (slots) HIP_TRY(c, launch_permute_pos(pos, perm, c->n, b.pos_s, s));
+    if (atomic) HIP_TRY(c, launch_fill_zero(a.forces_atomic, 3 * (size_t)c->n, s));
     if (!fused) HIP_TRY(c, launch_pack(pk, c->tab, prec, grid[0], s));
     if (ev[1]) HIP_TRY(c, hipEventRecord(ev[1], s));
     if (ev[2]) HIP_TRY(c, hipEventRecord(ev[2], s));
@@ -295,15 +310,17 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     if (ev[4]) HIP_TRY(c, hipEventRecord(ev[4], s));
     const FinalizeArgs fin{b.partials, b.counters, compute_grid, energy_virial, c->counts.p, c->misc.p};
     if (fused) {
-        HIP_TRY(c, launch_gather_rows(b.kmask, prec, b.planes, b.own, c->n, c->n, f, fin, s));
+        HIP_TRY(c, launch_gather_rows(b.kmask, prec, b.planes, b.own, c->n, c->n, f, perm, fin, s));
     } else if (atomic) {
         // the partial sums alone (no rows to gather); resets the dropped count
-        HIP_TRY(c, launch_gather_forces(b.pcount, prec, b.planes, b.own, 0, nullptr, c->n, f, c->misc.p + 3, fin, s));
+        HIP_TRY(c, launch_gather_forces(b.pcount, prec, b.planes, b.own, 0, nullptr, c->n, f, nullptr, c->misc.p + 3,
+                                        fin, s));
+        if (slots) HIP_TRY(c, launch_unpermute3(b.planes, perm, c->n, f, s));
     } else {
-        HIP_TRY(c, launch_fixup_dropped(c->ell.p, c->list_cap, c->row_count.p, b.kept, pk.kept_more, b.drop_list,
+        HIP_TRY(c, launch_fixup_dropped(ell, c->list_cap, row_count, b.kept, pk.kept_more, b.drop_list,
                                         c->misc.p + 3, c->n, prec, b.planes, s));
-        HIP_TRY(c, launch_gather_forces(b.pcount, prec, b.planes, b.own, c->n, nullptr, c->n, f, c->misc.p + 3, fin,
-                                        s));
+        HIP_TRY(c, launch_gather_forces(b.pcount, prec, b.planes, b.own, c->n, nullptr, c->n, f, perm,
+                                        c->misc.p + 3, fin, s));
     }
     if (ev[5]) HIP_TRY(c, hipEventRecord(ev[5], s));
     if (profile) {
@@ -338,7 +355,7 @@ constexpr size_t kStaticIntBytes = align256(kStaticAtoms * sizeof(int));
 constexpr size_t kStaticKeptBytes = align256((size_t)(kKeptFast + kRecCap) * kStaticAtoms * sizeof(int));
 constexpr size_t kStaticPartialBytes = align256(8 * kStaticGrid * sizeof(double));
 constexpr size_t kStaticCounterBytes = align256(2 * kStaticGrid * sizeof(long long));
-constexpr size_t kStaticBytes = kStaticRecBytes + kStaticPlaneBytes + 2 * kStaticOwnBytes + 2 * kStaticIntBytes +
+constexpr size_t kStaticBytes = kStaticRecBytes + kStaticPlaneBytes + 3 * kStaticOwnBytes + 2 * kStaticIntBytes +
                                 kStaticKeptBytes + kStaticPartialBytes + kStaticCounterBytes;
 }  // namespace
 
@@ -494,6 +511,7 @@ void tersoff_destroy(tersoff_ctx *c)
     (void)hipDeviceSynchronize();
     c->pos_build.release(); c->types.release(); c->offsets.release(); c->jn.release();
     c->kept.release(); c->own.release(); c->planes.release(); c->rev.release(); c->kmask.release();
+    c->ell_s.release(); c->row_count_s.release(); c->types_s.release(); c->slot_of.release(); c->pos_s.release();
     c->pcount.release(); c->drop_list.release(); c->recs.release();
     c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
     c->cell_atoms.release(); c->slot_cell.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
@@ -728,6 +746,15 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     // the caller's order is kept when at least half of its consecutive atoms
     // share or neighbour a cell
     c->cell_order = 2LL * host[6] < (long long)N - 1;
+    if (c->cell_order) {
+        // the list in the internal numbering (cell-order slots)
+        HIP_TRY(c, c->ell_s.ensure((size_t)N * c->list_cap));
+        HIP_TRY(c, c->row_count_s.ensure(N));
+        HIP_TRY(c, c->types_s.ensure(N));
+        HIP_TRY(c, c->slot_of.ensure(N));
+        HIP_TRY(c, launch_renumber_rows(c->ell.p, c->row_count.p, c->list_cap, c->cell_atoms.p, c->types.p, N,
+                                        c->slot_of.p, c->ell_s.p, c->row_count_s.p, c->types_s.p, s));
+    }
 
     c->n = N;
     for (int a = 0; a < 3; ++a) c->box[a] = box[a];
@@ -772,6 +799,10 @@ int tersoff_compute(tersoff_ctx *c, const double *pos, int32_t precision, double
     b.drop_list = c->drop_list.p;
     b.partials = c->partials.p;
     b.counters = c->counters.p;
+    if (c->cell_order) {
+        HIP_TRY(c, c->pos_s.ensure(3 * (size_t)c->n));
+        b.pos_s = c->pos_s.p;
+    }
     if (c->fused_ok && c->packing == 1) {
         HIP_TRY(c, c->rev.ensure((size_t)c->n * c->list_cap));
         HIP_TRY(c, c->kmask.ensure(c->n));
@@ -804,6 +835,7 @@ int tersoff_compute_static(tersoff_ctx *c, const double *pos, int32_t precision,
     b.planes = reinterpret_cast<double *>(take(kStaticPlaneBytes));
     b.own = reinterpret_cast<double *>(take(kStaticOwnBytes));
     double *force_scratch = reinterpret_cast<double *>(take(kStaticOwnBytes));
+    b.pos_s = reinterpret_cast<double *>(take(kStaticOwnBytes));
     b.pcount = reinterpret_cast<int *>(take(kStaticIntBytes));
     b.drop_list = reinterpret_cast<int *>(take(kStaticIntBytes));
     b.kept = reinterpret_cast<int *>(take(kStaticKeptBytes));

@@ -490,10 +490,11 @@ def test_overflow_reported_both_packings(natoms):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", ["si512", "two_species"])
 def test_atom_order_does_not_matter(case, precision):
-    """The same configuration with its atoms in a random order (the kernels
-    then take the centre atoms in the build's cell order instead of the
-    caller's): the same energy and virial, and the permuted forces, to the
-    stated tolerances; both orders at parity with the oracle."""
+    """The same configuration with its atoms in a random order (the library
+    then renumbers the atoms in the build's cell order and writes the forces
+    back at the caller's indices): the same energy and virial, and the
+    permuted forces, to the stated tolerances; both orders at parity with the
+    oracle."""
     from paper_1710_00882_amd import workloads as Wl
     sysf, tabf = CASES[case]
     s, table = sysf(), tabf()
