@@ -244,12 +244,12 @@ hipError_t launch_reverse_index(const int *ell, const int *row_count, int cap, i
                                 int *flags, hipStream_t s);
 
 // Neighbour build (neighbors.hip)
+// Cells and in-cell ranks of the atoms; types copied to types_out; into
+// *near_count, the consecutive atoms (i, i + 1), i mod 64 != 63, in the same
+// or adjacent cells (how coherent in space the caller's atom order is).
 hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,
                             int *cell_of, int *rank_in_cell, int *cell_count, int *flags, int *types_out,
-                            hipStream_t s);
-// Consecutive atoms (i, i + 1) in the same or adjacent cells, added into
-// *count: how coherent in space the caller's atom order is.
-hipError_t launch_order_locality(const int *cell_of, int n, const CellGrid &g, int *count, hipStream_t s);
+                            int *near_count, hipStream_t s);
 // The resident list in the internal numbering (atom = its cell-order slot):
 // row t of ell_s / row_count_s is the row of atom cell_atoms[t] with its
 // neighbours' slots in ascending order, types_s[t] its type; inv (n ints)

@@ -34,28 +34,57 @@ __device__ inline int cell_index(double x, double L, double w, int nc)
 
 // Cell of every atom (positions wrapped into the box for binning only) and
 // its rank within the cell; non-finite positions raise flag 1 and types
-// outside [0, ntypes) flag 2.  The types are copied to types_out.
-__global__ void k_bin(const double *__restrict__ pos, const int *__restrict__ types, int n, int ntypes,
-                      CellGrid g, int *__restrict__ cell_of, int *__restrict__ rank,
-                      int *__restrict__ count, int *flags, int *__restrict__ types_out)
+// outside [0, ntypes) flag 2.  The types are copied to types_out.  Also adds
+// into *near_count the consecutive atoms (i, i + 1) of one wavefront (i not
+// the last atom of a 64-atom group) whose cells are the same or adjacent
+// (periodically) along every axis: how coherent in space the caller's atom
+// order is.  Blocks of kBinThreads threads.
+constexpr int kBinThreads = 256;
+__global__ __launch_bounds__(kBinThreads) void k_bin(const double *__restrict__ pos, const int *__restrict__ types,
+                                                     int n, int ntypes, CellGrid g, int *__restrict__ cell_of,
+                                                     int *__restrict__ rank, int *__restrict__ count, int *flags,
+                                                     int *__restrict__ types_out, int *__restrict__ near_count)
 {
+    __shared__ int part[kBinThreads / kWave];
+    auto near = [](int u, int v, int m) {
+        const int d = u > v ? u - v : v - u;
+        return d <= 1 || d == m - 1;
+    };
+    const int lane = threadIdx.x % kWave;
+    int nc = 0;   // this thread's near pairs
     const ItemRange r = xcd_items((n + blockDim.x - 1) / blockDim.x);
-    for (int it = r.begin; it < r.end; it += r.stride) {
+    for (int it = r.begin; it < r.end; it += r.stride) {   // the same trip count in every lane of a block
         const int i = it * blockDim.x + threadIdx.x;
-        if (i >= n) continue;
-        const double *p = pos + 3 * (size_t)i;
-        int f = 0;
-        if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) f |= 1;
-        const int t = types[i];
-        types_out[i] = t;
-        if (t < 0 || t >= ntypes) f |= 2;
-        if (f) atomicOr(flags, f);
-        int cx = cell_index(p[0], g.L[0], g.cell_w[0], g.nc[0]);
-        int cy = cell_index(p[1], g.L[1], g.cell_w[1], g.nc[1]);
-        int cz = cell_index(p[2], g.L[2], g.cell_w[2], g.nc[2]);
-        int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
-        cell_of[i] = c;
-        rank[i] = atomicAdd(&count[c], 1);
+        const bool valid = i < n;
+        int cx = 0, cy = 0, cz = 0;
+        if (valid) {
+            const double *p = pos + 3 * (size_t)i;
+            int f = 0;
+            if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2])) f |= 1;
+            const int t = types[i];
+            types_out[i] = t;
+            if (t < 0 || t >= ntypes) f |= 2;
+            if (f) atomicOr(flags, f);
+            cx = cell_index(p[0], g.L[0], g.cell_w[0], g.nc[0]);
+            cy = cell_index(p[1], g.L[1], g.cell_w[1], g.nc[1]);
+            cz = cell_index(p[2], g.L[2], g.cell_w[2], g.nc[2]);
+            const int c = (cx * g.nc[1] + cy) * g.nc[2] + cz;
+            cell_of[i] = c;
+            rank[i] = atomicAdd(&count[c], 1);
+        }
+        // the cell of atom i + 1: the next lane's
+        const int nx = __shfl_down(cx, 1, kWave), ny = __shfl_down(cy, 1, kWave), nz = __shfl_down(cz, 1, kWave);
+        if (valid && i + 1 < n && lane != kWave - 1)
+            nc += near(cx, nx, g.nc[0]) && near(cy, ny, g.nc[1]) && near(cz, nz, g.nc[2]) ? 1 : 0;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) nc += __shfl_xor(nc, off, kWave);
+    if (lane == 0) part[threadIdx.x / kWave] = nc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kBinThreads / kWave; ++w) t += part[w];
+        if (t) atomicAdd(near_count, t);
     }
 }
 
@@ -610,45 +639,13 @@ hipError_t launch_compact_list(const int *ell, int cap, const int *row_count, co
 
 hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,
                             int *cell_of, int *rank_in_cell, int *cell_count, int *flags, int *types_out,
-                            hipStream_t s)
+                            int *near_count, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin, dim3(blocks_for(n, 256)), dim3(256), 0, s, pos, types, n, ntypes, g, cell_of,
-                       rank_in_cell, cell_count, flags, types_out);
-    return hipGetLastError();
-}
-
-// How spatially coherent the caller's atom order is: the number of
-// consecutive atoms (i, i + 1) whose cells are the same or adjacent
-// (periodic), added into *count (one atomic per workgroup).
-__global__ void k_order_locality(const int *__restrict__ cell_of, int n, CellGrid g, int *count)
-{
-    __shared__ int part[256 / kWave];
-    int c = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i + 1 < n; i += gridDim.x * blockDim.x) {
-        const int a = cell_of[i], b = cell_of[i + 1];
-        const int az = a % g.nc[2], ay = (a / g.nc[2]) % g.nc[1], ax = a / (g.nc[2] * g.nc[1]);
-        const int bz = b % g.nc[2], by = (b / g.nc[2]) % g.nc[1], bx = b / (g.nc[2] * g.nc[1]);
-        auto near = [](int u, int v, int m) {
-            const int d = u > v ? u - v : v - u;
-            return d <= 1 || d == m - 1;
-        };
-        c += near(ax, bx, g.nc[0]) && near(ay, by, g.nc[1]) && near(az, bz, g.nc[2]);
-    }
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
-    if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < (int)blockDim.x / kWave; ++w) t += part[w];
-        atomicAdd(count, t);
-    }
-}
-
-hipError_t launch_order_locality(const int *cell_of, int n, const CellGrid &g, int *count, hipStream_t s)
-{
-    const int grid = std::max(1, std::min(blocks_for(n, 256), 1024));
-    hipLaunchKernelGGL(k_order_locality, dim3(grid), dim3(256), 0, s, cell_of, n, g, count);
+    // at most 1024 workgroups (each adds its near count with one atomic on a
+    // single address; the grid strides over the atoms)
+    const int grid = std::max(1, std::min(blocks_for(n, kBinThreads), 1024));
+    hipLaunchKernelGGL(k_bin, dim3(grid), dim3(kBinThreads), 0, s, pos, types, n, ntypes, g, cell_of, rank_in_cell,
+                       cell_count, flags, types_out, near_count);
     return hipGetLastError();
 }
 
@@ -676,9 +673,20 @@ __global__ __launch_bounds__(256) void k_renumber_rows(const int *__restrict__ e
         const int *row = ell + (size_t)i * cap;
         int *out = ell_s + (size_t)t * cap;
         if (rc <= kLRow) {
+            // the row in 16-byte words (cap is a multiple of 8, so a word
+            // starting below cap lies in the row; words past it re-read the
+            // last one), then every slot lookup at once (entries past the
+            // row's end look up atom 0)
             int v[kLRow];
 #pragma unroll
-            for (int k = 0; k < kLRow; ++k) v[k] = k < rc ? inv[row[k]] : INT_MAX;
+            for (int k = 0; k < kLRow; k += 4) {
+                const int4 w = *reinterpret_cast<const int4 *>(row + min(k, cap - 4));
+                v[k] = w.x; v[k + 1] = w.y; v[k + 2] = w.z; v[k + 3] = w.w;
+            }
+#pragma unroll
+            for (int k = 0; k < kLRow; ++k) v[k] = inv[k < rc ? v[k] : 0];
+#pragma unroll
+            for (int k = 0; k < kLRow; ++k) v[k] = k < rc ? v[k] : INT_MAX;
             bitonic32(v);
 #pragma unroll
             for (int k = 0; k < kLRow; ++k)

@@ -675,8 +675,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     HIP_TRY(c, hipMemsetAsync(c->misc.p, 0, 8 * sizeof(int), s));
     HIP_TRY(c, hipMemsetAsync(c->cell_count.p, 0, sizeof(int) * ncell, s));
     HIP_TRY(c, launch_bin_atoms(pos, types, N, c->ntypes, g, c->cell_of.p, c->rank.p, c->cell_count.p,
-                                c->misc.p + 2, c->types.p, s));
-    HIP_TRY(c, launch_order_locality(c->cell_of.p, N, g, c->misc.p + 6, s));
+                                c->misc.p + 2, c->types.p, c->misc.p + 6, s));
     HIP_TRY(c, launch_exclusive_scan(c->cell_count.p, c->cell_start.p, (int)ncell, c->scan_tmp.p, nullptr, s));
     ScatterLaunch sca{};
     sca.pos = pos;
@@ -744,8 +743,10 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     c->fused_ok = c->list_cap <= kFusedRowCap;
     c->rev_ready = false;
     // the caller's order is kept when at least half of its consecutive atoms
-    // share or neighbour a cell
-    c->cell_order = 2LL * host[6] < (long long)N - 1;
+    // (the pairs i, i + 1 with i mod 64 != 63 that the binning examines) share
+    // or neighbour a cell
+    const long long examined = (long long)N - 1 - ((long long)N - 1) / 64;
+    c->cell_order = 2LL * host[6] < examined;
     if (c->cell_order) {
         // the list in the internal numbering (cell-order slots)
         HIP_TRY(c, c->ell_s.ensure((size_t)N * c->list_cap));
