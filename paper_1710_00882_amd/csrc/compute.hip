@@ -412,7 +412,13 @@ constexpr int kThirdBit = 27;
 static_assert(kMaxTypes <= 4, "two type bits and four third-atom bits per record");
 __device__ __forceinline__ int rec_type(int jm) { return (jm >> kTypeShift) & 3; }
 
-constexpr int kChunks = 8;     // 64-entry chunks whose loads are issued together
+// 64-entry chunks of the packing kernel whose loads are issued together: 8,
+// and 4 for the several-species float records, whose tables and types take
+// registers enough that 8 would cost two wavefronts per SIMD (2M-atom
+// silicon: 4 and 8 equal in mixed, FP64 252 against 227 us; 256k-atom two
+// species, mixed: 40 against 44 us)
+template <typename real, bool ONE>
+constexpr int pack_chunks() { return (!ONE && sizeof(real) == 4) ? 4 : 8; }
 constexpr int kOwnerCap = 1024;   // batch entries whose atom is looked up in a table (the rest: binary search)
 static_assert(kKeptFast == 8, "the first block of a kept list is two 16-byte words");
 
@@ -501,6 +507,7 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
     // has to wait behind the record stores
     __shared__ double psq_s[ONE ? 1 : kMaxTypes * kMaxTypes];
     __shared__ double cut_s[ONE ? 1 : kMaxTypes * kMaxTypes * kMaxTypes];
+    constexpr int kCh = pack_chunks<real, ONE>();
     const int lane = threadIdx.x;
     Rec<real> *recs = static_cast<Rec<real> *>(a.recs);
     const int B = a.atoms_per_batch;
@@ -569,16 +576,16 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
         __syncthreads();
         const int e_begin = eoff[0], e_end = eoff[nb];
         int npacked = 0;   // kept entries of the batch so far (records beyond an atom's cap excluded)
-        for (int eb = e_begin; eb < e_end; eb += kWave * kChunks) {
-            // All loads of the kChunks chunks are issued unconditionally (lanes
+        for (int eb = e_begin; eb < e_end; eb += kWave * kCh) {
+            // All loads of the kCh chunks are issued unconditionally (lanes
             // past the batch's last entry re-read that entry and are masked
             // below): a load inside a branch is waited for at the branch's end,
             // which would serialise the chunks' gathers.
-            int jv[kChunks], tv[kChunks];
-            double xv[kChunks], yv[kChunks], zv[kChunks];
-            int alv[kChunks];
+            int jv[kCh], tv[kCh];
+            double xv[kCh], yv[kCh], zv[kCh];
+            int alv[kCh];
 #pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
+            for (int c = 0; c < kCh; ++c) {
                 const int ec = min(eb + c * kWave + lane, e_end - 1);
                 const int al = ec < kOwnerCap ? (int)owner[ec] : find_seg(eoff, nb, ec);
                 alv[c] = al;
@@ -586,13 +593,13 @@ __global__ __launch_bounds__(kWave) void k_pack(PackLaunch a, DeviceTable tab)
                 jv[c] = a.ell[(size_t)cid[al] * a.cap + (ec - eoff[al])];
             }
 #pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
+            for (int c = 0; c < kCh; ++c) {
                 const double *pj = a.pos + 3 * (size_t)jv[c];
                 xv[c] = pj[0]; yv[c] = pj[1]; zv[c] = pj[2];
                 tv[c] = ONE ? 0 : a.types[jv[c]];
             }
 #pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
+            for (int c = 0; c < kCh; ++c) {
                 const int e0 = eb + c * kWave;
                 if (e0 >= e_end) break;
                 const int e = e0 + lane;
