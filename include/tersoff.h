@@ -102,7 +102,12 @@ void tersoff_destroy(tersoff_ctx *ctx);
  *   R + D of the table; skin >= 0.
  * stream: hipStream_t or NULL.  The call synchronises that stream (it reads
  *   back the list length).  pos and types are copied; the list and the copies
- *   stay resident in the context until the next build.
+ *   stay resident in the context until the next build.  When fewer than half
+ *   of the consecutive atoms of the caller's order lie in the same or
+ *   adjacent cells, the context also keeps the list in the cell order's
+ *   numbering, and tersoff_compute works in that numbering (positions
+ *   permuted in, forces written back at the caller's indices): results do
+ *   not depend on the caller's order beyond floating-point summation order.
  * Errors: E_INVALID (n < 1 or > 2^24, cutoff too small, type out of range,
  *   non-finite position), E_BOX (a box length < 2 (cutoff + skin)),
  *   E_OVERFLOW (an atom has more than 256 neighbours within cutoff + skin),
