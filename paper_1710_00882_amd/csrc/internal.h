@@ -250,13 +250,15 @@ hipError_t launch_reverse_index(const int *ell, const int *row_count, int cap, i
 hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntypes, const CellGrid &g,
                             int *cell_of, int *rank_in_cell, int *cell_count, int *flags, int *types_out,
                             int *near_count, hipStream_t s);
-// The resident list in the internal numbering (atom = its cell-order slot):
-// row t of ell_s / row_count_s is the row of atom cell_atoms[t] with its
-// neighbours' slots in ascending order, types_s[t] its type; inv (n ints)
-// receives each atom's slot.  Rows at stride cap.
+// The internal numbering: perm[t] = the atom of slot t, the cell order
+// (cell_atoms, cells at cell_start with cell_count atoms) with each cell's
+// atoms in ascending index order; inv (n ints) receives each atom's slot;
+// row t of ell_s / row_count_s is the row of atom perm[t] with its
+// neighbours' slots in ascending order, types_s[t] its type.  Rows at
+// stride cap.
 hipError_t launch_renumber_rows(const int *ell, const int *row_count, int cap, const int *cell_atoms,
-                                const int *types, int n, int *inv, int *ell_s, int *row_count_s, int *types_s,
-                                hipStream_t s);
+                                const int *cell_start, const int *cell_count, int ncell, const int *types, int n,
+                                int *perm, int *inv, int *ell_s, int *row_count_s, int *types_s, hipStream_t s);
 // Cell-order copies of the atoms (ids, FP64 positions, wrapped FP32
 // positions with the id in the fourth word).  Batches: dims and the
 // per-atom system set, n the capacity the grid is sized for.

@@ -83,6 +83,8 @@ struct tersoff_ctx {
     DevBuf<int> long_rows;
     DevBuf<int> ell, row_count, scan_tmp, misc;   // misc: [0] flags, [1] max row, [2] check flags
     DevBuf<int> ell_s, row_count_s, types_s, slot_of;   // the list in the internal numbering (cell_order)
+    DevBuf<int> perm_s;                                 // atom of each slot of the internal numbering
+    DevBuf<double> pos_build_s;                         // positions of the build in that numbering
     DevBuf<double> pos_s;                               // positions in the internal numbering (per evaluation)
     DevBuf<unsigned char> rev;                     // reverse row positions (fused packing)
     DevBuf<unsigned long long> kmask;              // kept row positions per atom (fused packing)
@@ -211,18 +213,18 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
     // internal numbering: when the caller's order is incoherent in space,
     // every atom is named by its slot in the build's cell order -- positions
     // permuted in, the build's renumbered rows, types and positions
-    // (cell_pos), forces stored back at the caller's indices by the gather
+    // (pos_build_s), forces stored back at the caller's indices by the gather
     // (the atomic scatter: summed in cell order, then moved) -- so that the
     // atoms of a batch, their neighbours, kept lists and force planes lie
     // together in memory.  An order that already is coherent, such as a
     // lattice's, is kept: it packs a batch more tightly than the cell
     // order's lines of cells.
     const bool slots = c->cell_order;
-    const int *perm = slots ? c->cell_atoms.p : nullptr;
+    const int *perm = slots ? c->perm_s.p : nullptr;
     const int *types = slots ? c->types_s.p : c->types.p;
     const int *ell = slots ? c->ell_s.p : c->ell.p;
     const int *row_count = slots ? c->row_count_s.p : c->row_count.p;
-    const double *pos_build = slots ? c->cell_pos.p : c->pos_build.p;
+    const double *pos_build = slots ? c->pos_build_s.p : c->pos_build.p;
     PackLaunch pk{};
     pk.pos = slots ? b.pos_s : pos;
     pk.types = types;
@@ -512,6 +514,7 @@ void tersoff_destroy(tersoff_ctx *c)
     c->pos_build.release(); c->types.release(); c->offsets.release(); c->jn.release();
     c->kept.release(); c->own.release(); c->planes.release(); c->rev.release(); c->kmask.release();
     c->ell_s.release(); c->row_count_s.release(); c->types_s.release(); c->slot_of.release(); c->pos_s.release();
+    c->perm_s.release(); c->pos_build_s.release();
     c->pcount.release(); c->drop_list.release(); c->recs.release();
     c->cell_of.release(); c->rank.release(); c->cell_count.release(); c->cell_start.release();
     c->cell_atoms.release(); c->slot_cell.release(); c->cell_pos.release(); c->ell.release(); c->row_count.release();
@@ -753,8 +756,12 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
         HIP_TRY(c, c->row_count_s.ensure(N));
         HIP_TRY(c, c->types_s.ensure(N));
         HIP_TRY(c, c->slot_of.ensure(N));
-        HIP_TRY(c, launch_renumber_rows(c->ell.p, c->row_count.p, c->list_cap, c->cell_atoms.p, c->types.p, N,
-                                        c->slot_of.p, c->ell_s.p, c->row_count_s.p, c->types_s.p, s));
+        HIP_TRY(c, c->perm_s.ensure(N));
+        HIP_TRY(c, c->pos_build_s.ensure(3 * (size_t)N));
+        HIP_TRY(c, launch_renumber_rows(c->ell.p, c->row_count.p, c->list_cap, c->cell_atoms.p, c->cell_start.p,
+                                        c->cell_count.p, (int)ncell, c->types.p, N, c->perm_s.p, c->slot_of.p,
+                                        c->ell_s.p, c->row_count_s.p, c->types_s.p, s));
+        HIP_TRY(c, launch_permute_pos(c->pos_build.p, c->perm_s.p, N, c->pos_build_s.p, s));
     }
 
     c->n = N;
