@@ -65,10 +65,10 @@ RECORD_BYTES = {"mixed": 16, "single": 16, "fp64": 32}
 # reads 0.5 of the bytes a copy moves, WRITE_SIZE 1.0).  Valid only for the
 # compute source it was measured on (its SHA-256 prefix).
 TRAFFIC_PROFILE = {
-    "source": "dfb790ab40d3c9e1",
-    "fetch_kib": 140591.2, "fetch_factor": 2.0,
-    "write_kib": 229957.6, "write_factor": 1.0,
-    "bytes_per_launch": 140591.2 * 1024 * 2.0 + 229957.6 * 1024 * 1.0,
+    "source": "f267cfdb3d72ebea",
+    "fetch_kib": 140405.2, "fetch_factor": 2.0,
+    "write_kib": 230022.7, "write_factor": 1.0,
+    "bytes_per_launch": 140405.2 * 1024 * 2.0 + 230022.7 * 1024 * 1.0,
 }
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1710_00882_amd", "csrc", "compute.hip")
 
