@@ -710,9 +710,11 @@ __global__ __launch_bounds__(256) void k_renumber_rows(const int *__restrict__ e
 #pragma unroll
             for (int k = 0; k < kLRow; ++k) v[k] = k < rc ? v[k] : INT_MAX;
             bitonic32(v);
+            // 16-byte stores, words starting below cap only (entries past
+            // row_count are padding, never read)
 #pragma unroll
-            for (int k = 0; k < kLRow; ++k)
-                if (k < rc) out[k] = v[k];
+            for (int k = 0; k < kLRow; k += 4)
+                if (k < rc && k < cap) *reinterpret_cast<int4 *>(out + k) = make_int4(v[k], v[k + 1], v[k + 2], v[k + 3]);
         } else {
             for (int e = 0; e < rc; ++e) {
                 const int u = inv[row[e]];
