@@ -68,8 +68,7 @@ struct tersoff_ctx {
     bool fused_ok = false;          // the resident list supports the fused packing (rows <= kFusedRowCap)
     bool rev_ready = false;         // rev holds the reverse row positions of the resident list
     bool cell_order = false;        // the caller's order is incoherent in space: atoms renumbered in the
-                                    // build's cell order (ell_s, row_count_s, types_s) or, in the comparison
-                                    // modes, centre atoms taken in that order
+                                    // build's cell order (perm_s, ell_s, row_count_s, types_s, pos_build_s)
     int grid[kNumPrec][4] = {};   // [precision] x {pack, compute, fixup, fused compute}
 
     DevBuf<double> pos_build;
