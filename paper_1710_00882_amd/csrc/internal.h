@@ -254,11 +254,12 @@ hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntyp
 // (cell_atoms, cells at cell_start with cell_count atoms) with each cell's
 // atoms in ascending index order; inv (n ints) receives each atom's slot;
 // row t of ell_s / row_count_s is the row of atom perm[t] with its
-// neighbours' slots in ascending order, types_s[t] its type.  Rows at
-// stride cap.
+// neighbours' slots in ascending order, types_s[t] its type, pos_s[t] its
+// position in pos (3 doubles).  Rows at stride cap.
 hipError_t launch_renumber_rows(const int *ell, const int *row_count, int cap, const int *cell_atoms,
-                                const int *cell_start, const int *cell_count, int ncell, const int *types, int n,
-                                int *perm, int *inv, int *ell_s, int *row_count_s, int *types_s, hipStream_t s);
+                                const int *cell_start, const int *cell_count, int ncell, const int *types,
+                                const double *pos, int n, int *perm, int *inv, int *ell_s, int *row_count_s,
+                                int *types_s, double *pos_s, hipStream_t s);
 // Cell-order copies of the atoms (ids, FP64 positions, wrapped FP32
 // positions with the id in the fourth word).  Batches: dims and the
 // per-atom system set, n the capacity the grid is sized for.

@@ -653,11 +653,15 @@ hipError_t launch_bin_atoms(const double *pos, const int *types, int n, int ntyp
 // order's slots (cell c at cell_start[c], cell_count[c] atoms, in the order
 // the binning's atomics gave them); an insertion sort per cell, one thread
 // per cell.  The internal numbering then depends on the positions only.
+// Then, per slot t of the cell, inv[perm[t]] = t and pos_s[t] =
+// pos[perm[t]] (3 doubles).
 __global__ void k_sort_cells(const int *__restrict__ cell_start, const int *__restrict__ cell_count, int ncell,
-                             int *__restrict__ perm)
+                             const double *__restrict__ pos, int *__restrict__ perm, int *__restrict__ inv,
+                             double *__restrict__ pos_s)
 {
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x) {
-        int *seg = perm + cell_start[c];
+        const int t0 = cell_start[c];
+        int *seg = perm + t0;
         const int k = cell_count[c];
         for (int a = 1; a < k; ++a) {
             const int v = seg[a];
@@ -668,13 +672,14 @@ __global__ void k_sort_cells(const int *__restrict__ cell_start, const int *__re
             }
             seg[b + 1] = v;
         }
+        for (int a = 0; a < k; ++a) {
+            const int i = seg[a];
+            inv[i] = t0 + a;
+            pos_s[3 * (size_t)(t0 + a)] = pos[3 * (size_t)i];
+            pos_s[3 * (size_t)(t0 + a) + 1] = pos[3 * (size_t)i + 1];
+            pos_s[3 * (size_t)(t0 + a) + 2] = pos[3 * (size_t)i + 2];
+        }
     }
-}
-
-// slot of each atom: inv[cell_atoms[t]] = t
-__global__ void k_slot_inverse(const int *__restrict__ cell_atoms, int n, int *__restrict__ inv)
-{
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) inv[cell_atoms[t]] = t;
 }
 
 // Row t of the renumbered list: the row of atom cell_atoms[t] with each
@@ -727,16 +732,17 @@ __global__ __launch_bounds__(256) void k_renumber_rows(const int *__restrict__ e
 }
 
 hipError_t launch_renumber_rows(const int *ell, const int *row_count, int cap, const int *cell_atoms,
-                                const int *cell_start, const int *cell_count, int ncell, const int *types, int n,
-                                int *perm, int *inv, int *ell_s, int *row_count_s, int *types_s, hipStream_t s)
+                                const int *cell_start, const int *cell_count, int ncell, const int *types,
+                                const double *pos, int n, int *perm, int *inv, int *ell_s, int *row_count_s,
+                                int *types_s, double *pos_s, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipError_t e = hipMemcpyAsync(perm, cell_atoms, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     const int cgrid = std::max(1, std::min(blocks_for(ncell, 256), 4096));
-    hipLaunchKernelGGL(k_sort_cells, dim3(cgrid), dim3(256), 0, s, cell_start, cell_count, ncell, perm);
+    hipLaunchKernelGGL(k_sort_cells, dim3(cgrid), dim3(256), 0, s, cell_start, cell_count, ncell, pos, perm, inv,
+                       pos_s);
     const int grid = std::max(1, std::min(blocks_for(n, 256), 4096));
-    hipLaunchKernelGGL(k_slot_inverse, dim3(grid), dim3(256), 0, s, perm, n, inv);
     hipLaunchKernelGGL(k_renumber_rows, dim3(grid), dim3(256), 0, s, ell, row_count, cap, perm, inv, types, n,
                        ell_s, row_count_s, types_s);
     return hipGetLastError();

@@ -758,9 +758,9 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
         HIP_TRY(c, c->perm_s.ensure(N));
         HIP_TRY(c, c->pos_build_s.ensure(3 * (size_t)N));
         HIP_TRY(c, launch_renumber_rows(c->ell.p, c->row_count.p, c->list_cap, c->cell_atoms.p, c->cell_start.p,
-                                        c->cell_count.p, (int)ncell, c->types.p, N, c->perm_s.p, c->slot_of.p,
-                                        c->ell_s.p, c->row_count_s.p, c->types_s.p, s));
-        HIP_TRY(c, launch_permute_pos(c->pos_build.p, c->perm_s.p, N, c->pos_build_s.p, s));
+                                        c->cell_count.p, (int)ncell, c->types.p, c->pos_build.p, N, c->perm_s.p,
+                                        c->slot_of.p, c->ell_s.p, c->row_count_s.p, c->types_s.p,
+                                        c->pos_build_s.p, s));
     }
 
     c->n = N;
