@@ -60,6 +60,7 @@ struct tersoff_ctx {
     long long S = 0;
     int ell_cap = 32;        // row capacity for the next build (multiple of 8)
     int list_cap = 0;        // row stride of the resident list
+    int max_row = 0;         // longest row of the resident list
     int atoms_per_batch = 32;
     bool batch_atoms_set = false;   // tersoff_set_batch_atoms was called (else chosen by the build)
     int force_sum = 0;              // 0: force planes + gather; 1: FP64 atomic scatter (tersoff_set_force_sum)
@@ -318,8 +319,11 @@ int launch_evaluation(tersoff_ctx *c, const double *pos, int prec, double *energ
                                         fin, s));
         if (slots) HIP_TRY(c, launch_unpermute3(b.planes, perm, c->n, f, s));
     } else {
-        HIP_TRY(c, launch_fixup_dropped(ell, c->list_cap, row_count, b.kept, pk.kept_more, b.drop_list,
-                                        c->misc.p + 3, c->n, prec, b.planes, s));
+        // an atom is dropped only with more kept neighbours than its records
+        // hold, and its kept neighbours are part of its row
+        if (c->max_row > kRecCap)
+            HIP_TRY(c, launch_fixup_dropped(ell, c->list_cap, row_count, b.kept, pk.kept_more, b.drop_list,
+                                            c->misc.p + 3, c->n, prec, b.planes, s));
         HIP_TRY(c, launch_gather_forces(b.pcount, prec, b.planes, b.own, c->n, nullptr, c->n, f, perm,
                                         c->misc.p + 3, fin, s));
     }
@@ -735,6 +739,7 @@ int tersoff_build_neighbors(tersoff_ctx *c, const double *pos, const int32_t *ty
     if (evb1) c->ev_build.emplace_back(evb0, evb1);
     if (host[1] > c->ell_cap) return fail(c, TERSOFF_E_OVERFLOW, "row capacity retry failed");
     c->list_cap = c->ell_cap;
+    c->max_row = host[1];
     if (host[5] < 0) return fail(c, TERSOFF_E_INVALID, "list longer than 2^31 entries");
     c->S = host[5];
     // the next build starts from the capacity this list needed (plus a margin)
