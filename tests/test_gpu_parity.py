@@ -487,6 +487,29 @@ def test_overflow_reported_both_packings(natoms):
         m.close()
 
 
+def test_stale_list_detected_in_internal_numbering():
+    """With the atoms in a random order (evaluated in the library's cell-order
+    numbering), moving one atom by more than skin / 2 since the build is
+    reported as E_STALE, and a move below it is not."""
+    import torch
+    from paper_1710_00882_amd import Tersoff
+    s = W.diamond(4, 4, 4, jitter=0.05, seed=21)
+    p = np.random.default_rng(3).permutation(s.n)
+    sp = W.System(s.pos[p].copy(), s.types[p].copy(), s.box.copy())
+    m = Tersoff(W.si_table())
+    try:
+        pos, types = to_dev(sp)
+        m.build_neighbors(pos, types, sp.box)   # skin 1.0: stale beyond 0.5
+        for atom, dx, status in ((17, 0.45, 0), (17, 0.55, -5), (sp.n - 1, -0.6, -5)):
+            moved = pos.clone()
+            moved[atom, 1] += dx
+            m.compute(moved)
+            torch.cuda.synchronize()
+            assert m.check_status() == status, (atom, dx)
+    finally:
+        m.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", ["si512", "two_species", "disordered_small"])
 def test_rebuild_is_bit_identical(case, precision):
