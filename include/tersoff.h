@@ -134,7 +134,8 @@ int tersoff_compute(tersoff_ctx *ctx, const double *pos, int32_t precision,
  * harnesses that forbid hipMalloc.  The same evaluation as tersoff_compute
  * (the same kernels in the same launch configuration: results identical bit
  * for bit), with every per-evaluation buffer -- records, force planes,
- * per-atom forces and counts, kept-neighbour lists, partial sums, and the
+ * per-atom forces and counts, kept-neighbour lists, partial sums, the
+ * positions in the internal numbering (see tersoff_build_neighbors), and the
  * force output when forces is NULL -- taken from one fixed device array of
  * the library (about 34 MB on each GPU it runs on, held from the first use of
  * the library's device code on that GPU until the process ends) instead of
