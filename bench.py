@@ -66,9 +66,9 @@ RECORD_BYTES = {"mixed": 16, "single": 16, "fp64": 32}
 # compute source it was measured on (its SHA-256 prefix).
 TRAFFIC_PROFILE = {
     "source": "f267cfdb3d72ebea",
-    "fetch_kib": 140431.1, "fetch_factor": 2.0,
-    "write_kib": 229762.7, "write_factor": 1.0,
-    "bytes_per_launch": 140431.1 * 1024 * 2.0 + 229762.7 * 1024 * 1.0,
+    "fetch_kib": 140509.0, "fetch_factor": 2.0,
+    "write_kib": 229662.8, "write_factor": 1.0,
+    "bytes_per_launch": 140509.0 * 1024 * 2.0 + 229662.8 * 1024 * 1.0,
 }
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1710_00882_amd", "csrc", "compute.hip")
 
