@@ -462,6 +462,34 @@ def test_long_rows_fused_and_fallback(skin):
         m.close()
 
 
+def test_long_rows_in_internal_numbering():
+    """Rows of about 46 entries (skin 3.0) with the atoms in a random order, so
+    that the build renumbers a list whose rows exceed the 32-entry register
+    sort: the list handed back is the oracle's, and both packings are at
+    parity with it (box of 5 cells per axis, so that the random order is
+    found incoherent)."""
+    from paper_1710_00882_amd import Tersoff
+    skin = 3.0
+    s0, table = W.diamond(6, 6, 6, jitter=0.1, seed=33), W.si_table()
+    p = np.random.default_rng(9).permutation(s0.n)
+    s = W.System(s0.pos[p].copy(), s0.types[p].copy(), s0.box.copy())
+    Eo, Fo, Vo, off, idx = oracle_eval(s, table, skin=skin)
+    assert int(np.diff(off).max()) > 32
+    m = Tersoff(table)
+    try:
+        pos, types = to_dev(s)
+        m.build_neighbors(pos, types, s.box, skin=skin)
+        goff, gidx = m.neighbors()
+        assert np.array_equal(goff, off) and np.array_equal(gidx, idx)
+        for precision in ("fp64", "mixed"):
+            for mode in ("fused", "separate"):
+                say(f"[long rows, random order] longest row {int(np.diff(off).max())} {precision} {mode}")
+                o, F, _ = _eval_packing(m, pos, precision, mode)
+                assert_parity(float(o[0]), F, o[1:], Eo, Fo, Vo, s.n, precision, f"random order {mode}")
+    finally:
+        m.close()
+
+
 @pytest.mark.parametrize("natoms", [40, 80])
 def test_overflow_reported_both_packings(natoms):
     """Atoms with more kept neighbours than a batch slot range holds are
